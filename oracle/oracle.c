@@ -1,0 +1,679 @@
+/*
+ * ORACLE -- test infrastructure, not part of the product.
+ *
+ * A plain, slow, sequential CPU implementation of max-flow min-cut pair
+ * refinement as described in Section 4.1 of Sanders & Schulz, "Engineering
+ * Multilevel Graph Partitioning Algorithms" ("Using Max-Flow Min-Cut
+ * Computations for Local Improvement").  Only the test suite, the smoke check
+ * and the CPU-baseline leg of the benchmark may load it.  It shares no code,
+ * header or table with the GPU library.
+ *
+ * Everything is integer; flows, cuts and weights are int64.
+ *
+ * Steps, in the paper's order:
+ *   - boundary nodes delta_l / delta_r            (Sec. 4.1, notation)
+ *   - two bounded BFS growing the corridor B      (Sec. 4.1, construction)
+ *   - corridor border and the s-t network G'      (Sec. 4.1, construction)
+ *   - max flow (Dinic's blocking-flow algorithm, Dinic 1970: any exact
+ *     max-flow algorithm gives the same value and residual closure)
+ *   - smallest source set = vertices reachable from s in the residual graph
+ *     (Sec. 4.1.1, Ford-Fulkerson labelling)
+ *   - balance check and adaptive flow iterations  (Sec. 4.1, improvements)
+ *   - balance constraint L_max and cut objective  (Sec. 2.1)
+ *
+ * Readings where the paper is silent (all listed in the design notes):
+ *   R2  only blocks a and b matter: border and BFS work in G[A u B]
+ *   R3  BFS levels in ascending vertex id; a level is walked in that order
+ *       and the walk stops at the first vertex that would exceed the bound
+ *   R4  area bound U_x(alpha) = floor((1+alpha*eps) c(V)/k) - c(other block),
+ *       eps in parts per million, clamped at 0
+ *   R5  acceptance uses L_max with the original eps (plus max_v c(v))
+ *   R6  adaptive loop: start at the given alpha; apply => alpha=min(2a,amax);
+ *       reject => alpha=max(a/2,1) (stop if it was 1); feasible and not
+ *       improving => stop; at most max_iters solves
+ *   R8  the first block of the pair is the source side
+ *   R9  DEPTH mode includes BFS distance <= depth from the boundary
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+  int32_t n;
+  const int32_t *xadj;
+  const int32_t *adjncy;
+  const int32_t *vwgt;
+  const int32_t *adjwgt;
+} or_graph;
+
+typedef struct {
+  int32_t area_mode; /* 0 = weight bound (alpha), 1 = BFS depth */
+  int32_t depth;
+  int32_t alpha;
+  int32_t alpha_max;
+  int32_t adaptive;
+  int32_t max_iters;
+  int32_t eps_ppm;
+} or_params;
+
+/* one flow solve */
+typedef struct {
+  int32_t alpha;
+  int32_t decision; /* 1 apply, 2 infeasible, 3 feasible not improving, 4 not adjacent */
+  int64_t flow;
+  int64_t region_vertices;
+  int64_t region_edges;
+  int64_t source_side;   /* corridor vertices ending on the source side */
+  int64_t cut_before;    /* pair cut before this solve */
+  int64_t cut_candidate; /* pair cut of the candidate partition */
+  int64_t wa, wb;        /* block weights of the candidate */
+} or_solve;
+
+typedef struct {
+  int32_t status; /* 1 accepted, 2 rejected (imbalance), 3 no improvement, 4 not adjacent */
+  int32_t iters;
+  int32_t final_alpha;
+  int32_t applied;
+  int32_t iter_cap; /* 1 if the loop ended only because of max_iters */
+  int32_t pad;
+  int64_t flow_value;
+  int64_t cut_before, cut_after;
+  int64_t weight_a, weight_b;
+  int64_t region_vertices, region_edges;
+} or_result;
+
+enum { DEC_APPLY = 1, DEC_INFEASIBLE = 2, DEC_EQUAL = 3, DEC_NOT_ADJ = 4 };
+enum { ST_ACCEPTED = 1, ST_REJECTED = 2, ST_NO_IMPROVEMENT = 3, ST_NOT_ADJACENT = 4 };
+
+/* ------------------------------------------------------------------------ */
+/* graph validation                                                          */
+
+/* 0 ok; -1 bad graph.  Symmetric, positive edge weights, no self loops, no
+ * parallel arcs, non-negative vertex weights (Sec. 2.1: omega > 0, c >= 0). */
+int32_t or_validate_graph(const or_graph *g) {
+  if (g->n < 0 || g->xadj[0] != 0) return -1;
+  for (int32_t u = 0; u < g->n; u++) {
+    if (g->xadj[u + 1] < g->xadj[u]) return -1;
+    if (g->vwgt[u] < 0) return -1;
+  }
+  int32_t *mark = (int32_t *)malloc(sizeof(int32_t) * (size_t)(g->n ? g->n : 1));
+  if (!mark) return -1;
+  for (int32_t u = 0; u < g->n; u++) mark[u] = -1;
+  int32_t rc = 0;
+  for (int32_t u = 0; u < g->n && rc == 0; u++) {
+    for (int32_t e = g->xadj[u]; e < g->xadj[u + 1]; e++) {
+      int32_t v = g->adjncy[e];
+      if (v < 0 || v >= g->n || v == u || g->adjwgt[e] < 1 || mark[v] == u) { rc = -1; break; }
+      mark[v] = u;
+      /* the reverse arc must exist with the same weight */
+      int found = 0;
+      for (int32_t f = g->xadj[v]; f < g->xadj[v + 1]; f++)
+        if (g->adjncy[f] == u) { found = g->adjwgt[f] == g->adjwgt[e]; break; }
+      if (!found) { rc = -1; break; }
+    }
+  }
+  free(mark);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* generic max flow on a small directed network (Dinic)                      */
+
+typedef struct {
+  int32_t nn;      /* nodes */
+  int64_t na, cap; /* arcs used / allocated; arc i^1 is the reverse of arc i */
+  int32_t *tail, *head;
+  int64_t *res;    /* residual capacity */
+  int64_t *cap0;   /* original capacity */
+  int64_t *off;    /* [nn+1] arcs grouped by tail */
+  int64_t *byt;    /* arc ids grouped by tail */
+} or_net;
+
+static int net_init(or_net *N, int32_t nn, int64_t max_arcs) {
+  memset(N, 0, sizeof(*N));
+  N->nn = nn;
+  N->cap = max_arcs > 0 ? max_arcs : 1;
+  N->tail = (int32_t *)malloc(sizeof(int32_t) * (size_t)N->cap);
+  N->head = (int32_t *)malloc(sizeof(int32_t) * (size_t)N->cap);
+  N->res = (int64_t *)malloc(sizeof(int64_t) * (size_t)N->cap);
+  N->cap0 = (int64_t *)malloc(sizeof(int64_t) * (size_t)N->cap);
+  return (N->tail && N->head && N->res && N->cap0) ? 0 : -1;
+}
+
+static void net_free(or_net *N) {
+  free(N->tail); free(N->head); free(N->res); free(N->cap0); free(N->off); free(N->byt);
+  memset(N, 0, sizeof(*N));
+}
+
+/* add arc u->v with capacity c and its reverse v->u with capacity rc */
+static void net_add(or_net *N, int32_t u, int32_t v, int64_t c, int64_t rc) {
+  int64_t i = N->na;
+  N->tail[i] = u; N->head[i] = v; N->res[i] = c; N->cap0[i] = c;
+  N->tail[i + 1] = v; N->head[i + 1] = u; N->res[i + 1] = rc; N->cap0[i + 1] = rc;
+  N->na += 2;
+}
+
+static int net_finish(or_net *N) {
+  N->off = (int64_t *)calloc((size_t)N->nn + 1, sizeof(int64_t));
+  N->byt = (int64_t *)malloc(sizeof(int64_t) * (size_t)(N->na ? N->na : 1));
+  if (!N->off || !N->byt) return -1;
+  for (int64_t i = 0; i < N->na; i++) N->off[N->tail[i] + 1]++;
+  for (int32_t v = 0; v < N->nn; v++) N->off[v + 1] += N->off[v];
+  int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * ((size_t)N->nn + 1));
+  if (!fill) return -1;
+  memcpy(fill, N->off, sizeof(int64_t) * ((size_t)N->nn + 1));
+  for (int64_t i = 0; i < N->na; i++) N->byt[fill[N->tail[i]]++] = i;
+  free(fill);
+  return 0;
+}
+
+/* Dinic: repeat { BFS level graph from s over residual arcs; if t is not
+ * reached stop; find augmenting s-t paths along level-increasing residual
+ * arcs with current-arc pointers until none is left }.  Returns the flow. */
+static int64_t net_dinic(or_net *N, int32_t s, int32_t t) {
+  int32_t nn = N->nn;
+  int32_t *level = (int32_t *)malloc(sizeof(int32_t) * (size_t)nn);
+  int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)nn);
+  int64_t *it = (int64_t *)malloc(sizeof(int64_t) * (size_t)nn);
+  int64_t *path = (int64_t *)malloc(sizeof(int64_t) * (size_t)nn);
+  int64_t flow = 0;
+  if (!level || !queue || !it || !path) { flow = -1; goto done; }
+  if (s == t) goto done;
+  for (;;) {
+    for (int32_t v = 0; v < nn; v++) level[v] = -1;
+    int32_t qh = 0, qt = 0;
+    level[s] = 0;
+    queue[qt++] = s;
+    while (qh < qt) {
+      int32_t v = queue[qh++];
+      for (int64_t j = N->off[v]; j < N->off[v + 1]; j++) {
+        int64_t a = N->byt[j];
+        if (N->res[a] > 0 && level[N->head[a]] < 0) {
+          level[N->head[a]] = level[v] + 1;
+          queue[qt++] = N->head[a];
+        }
+      }
+    }
+    if (level[t] < 0) break;
+    for (int32_t v = 0; v < nn; v++) it[v] = N->off[v];
+    /* blocking flow: depth-first search for s-t paths in the level graph */
+    int32_t v = s;
+    int64_t plen = 0;
+    for (;;) {
+      if (v == t) {
+        int64_t b = N->res[path[0]];
+        for (int64_t i = 1; i < plen; i++) if (N->res[path[i]] < b) b = N->res[path[i]];
+        for (int64_t i = 0; i < plen; i++) { N->res[path[i]] -= b; N->res[path[i] ^ 1] += b; }
+        flow += b;
+        v = s;
+        plen = 0;
+        continue;
+      }
+      int advanced = 0;
+      while (it[v] < N->off[v + 1]) {
+        int64_t a = N->byt[it[v]];
+        int32_t w = N->head[a];
+        if (N->res[a] > 0 && level[w] == level[v] + 1) {
+          path[plen++] = a;
+          v = w;
+          advanced = 1;
+          break;
+        }
+        it[v]++;
+      }
+      if (advanced) continue;
+      /* dead end: v leaves the level graph; retreat one arc */
+      level[v] = -1;
+      if (v == s) break;
+      plen--;
+      v = N->tail[path[plen]];
+      it[v]++;
+    }
+  }
+done:
+  free(level); free(queue); free(it); free(path);
+  return flow;
+}
+
+/* reach[v] = 1 iff v is reachable from s over arcs with positive residual */
+static void net_reach(const or_net *N, int32_t s, uint8_t *reach, int32_t *queue) {
+  memset(reach, 0, (size_t)N->nn);
+  int32_t qh = 0, qt = 0;
+  reach[s] = 1;
+  queue[qt++] = s;
+  while (qh < qt) {
+    int32_t v = queue[qh++];
+    for (int64_t j = N->off[v]; j < N->off[v + 1]; j++) {
+      int64_t a = N->byt[j];
+      if (N->res[a] > 0 && !reach[N->head[a]]) { reach[N->head[a]] = 1; queue[qt++] = N->head[a]; }
+    }
+  }
+}
+
+/* Max flow on an explicit network given as arcs (tail, head, cap); every arc
+ * gets a zero-capacity reverse.  Writes the flow value and, if reach != NULL,
+ * the smallest source set (nodes reachable from s in the final residual
+ * graph).  Returns 0, or -1 on bad input. */
+int32_t or_maxflow(int32_t nn, int64_t narcs, const int32_t *tails, const int32_t *heads,
+                   const int64_t *caps, int32_t s, int32_t t, int64_t *flow_out,
+                   uint8_t *reach) {
+  if (nn <= 0 || s < 0 || s >= nn || t < 0 || t >= nn || s == t) return -1;
+  or_net N;
+  if (net_init(&N, nn, 2 * narcs) != 0) { net_free(&N); return -1; }
+  for (int64_t i = 0; i < narcs; i++) {
+    if (tails[i] < 0 || tails[i] >= nn || heads[i] < 0 || heads[i] >= nn || caps[i] < 0) {
+      net_free(&N);
+      return -1;
+    }
+    net_add(&N, tails[i], heads[i], caps[i], 0);
+  }
+  if (net_finish(&N) != 0) { net_free(&N); return -1; }
+  *flow_out = net_dinic(&N, s, t);
+  if (reach) {
+    int32_t *q = (int32_t *)malloc(sizeof(int32_t) * (size_t)nn);
+    net_reach(&N, s, reach, q);
+    free(q);
+  }
+  net_free(&N);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* pair refinement                                                           */
+
+static int cmp_i32(const void *x, const void *y) {
+  int32_t a = *(const int32_t *)x, b = *(const int32_t *)y;
+  return (a > b) - (a < b);
+}
+
+/* pair cut omega(E_ab), each undirected edge counted once */
+static int64_t pair_cut(const or_graph *g, const int32_t *part, int32_t a, int32_t b) {
+  int64_t c = 0;
+  for (int32_t u = 0; u < g->n; u++) {
+    if (part[u] != a) continue;
+    for (int32_t e = g->xadj[u]; e < g->xadj[u + 1]; e++)
+      if (part[g->adjncy[e]] == b) c += g->adjwgt[e];
+  }
+  return c;
+}
+
+/* One bounded BFS (Sec. 4.1): seeds = boundary of block `blk` towards
+ * `other`, expanded only inside `blk`.  Vertices are taken level by level,
+ * each level in ascending id, while the running weight stays <= bound
+ * (FACTOR mode); the walk stops for good at the first vertex that would
+ * exceed it.  DEPTH mode takes every vertex at distance <= depth.
+ * Marks inB[v] = tag for every taken vertex. */
+static void area_bfs(const or_graph *g, const int32_t *part, int32_t blk, int32_t other,
+                     int32_t mode, int32_t depth, int64_t bound, uint8_t *inB, uint8_t tag,
+                     uint8_t *seen, int32_t *cur, int32_t *next) {
+  int32_t ncur = 0;
+  for (int32_t u = 0; u < g->n; u++) {
+    if (part[u] != blk) continue;
+    for (int32_t e = g->xadj[u]; e < g->xadj[u + 1]; e++)
+      if (part[g->adjncy[e]] == other) { cur[ncur++] = u; break; }
+  }
+  for (int32_t i = 0; i < ncur; i++) seen[cur[i]] = 1;
+  int64_t weight = 0;
+  int32_t lev = 0;
+  while (ncur > 0) {
+    qsort(cur, (size_t)ncur, sizeof(int32_t), cmp_i32);
+    if (mode == 1) {
+      if (lev > depth) return;
+      for (int32_t i = 0; i < ncur; i++) inB[cur[i]] = tag;
+    } else {
+      for (int32_t i = 0; i < ncur; i++) {
+        int32_t v = cur[i];
+        if (weight + g->vwgt[v] > bound) return; /* stop the whole search */
+        weight += g->vwgt[v];
+        inB[v] = tag;
+      }
+    }
+    int32_t nnext = 0;
+    for (int32_t i = 0; i < ncur; i++) {
+      int32_t u = cur[i];
+      for (int32_t e = g->xadj[u]; e < g->xadj[u + 1]; e++) {
+        int32_t v = g->adjncy[e];
+        if (part[v] == blk && !seen[v]) { seen[v] = 1; next[nnext++] = v; }
+      }
+    }
+    int32_t *t = cur; cur = next; next = t;
+    ncur = nnext;
+    lev++;
+  }
+}
+
+/* One flow solve for the pair (a = source side, b = sink side) at factor
+ * alpha.  Fills rec; if apply is set and the candidate is accepted, writes it
+ * into part.  side_out (optional, length n): -1 outside the corridor, 0/1
+ * corridor vertex ending in a / b, 2/3 border vertex pinned to s / t. */
+static int32_t solve_once(const or_graph *g, int32_t *part, int32_t k, int32_t a, int32_t b,
+                          const or_params *p, int32_t alpha, or_solve *rec, int8_t *side_out) {
+  int32_t n = g->n;
+  memset(rec, 0, sizeof(*rec));
+  rec->alpha = alpha;
+  /* Sec. 2.1: c(V), max c(v), block weights, L_max = (1+eps) c(V)/k + max c */
+  int64_t cV = 0, maxc = 0, cA = 0, cB = 0;
+  for (int32_t u = 0; u < n; u++) {
+    cV += g->vwgt[u];
+    if (g->vwgt[u] > maxc) maxc = g->vwgt[u];
+    if (part[u] == a) cA += g->vwgt[u];
+    if (part[u] == b) cB += g->vwgt[u];
+  }
+  int64_t lmax = (int64_t)(((__int128)(1000000 + (int64_t)p->eps_ppm) * cV) /
+                           ((__int128)1000000 * k)) + maxc;
+  int64_t cut = pair_cut(g, part, a, b);
+  rec->cut_before = cut;
+  if (side_out) for (int32_t u = 0; u < n; u++) side_out[u] = -1;
+  if (cut == 0) {
+    rec->decision = DEC_NOT_ADJ;
+    rec->cut_candidate = cut;
+    rec->wa = cA;
+    rec->wb = cB;
+    return 0;
+  }
+  /* R4: U_x(alpha) = floor((1 + alpha eps) c(V) / k) - c(other block) */
+  int64_t base = (int64_t)(((__int128)(1000000 + (int64_t)alpha * p->eps_ppm) * cV) /
+                           ((__int128)1000000 * k));
+  int64_t UA = base - cB, UB = base - cA;
+  if (UA < 0) UA = 0;
+  if (UB < 0) UB = 0;
+
+  uint8_t *inB = (uint8_t *)calloc((size_t)n, 1);
+  uint8_t *seen = (uint8_t *)calloc((size_t)n, 1);
+  int32_t *q1 = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t *q2 = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t *loc = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  if (!inB || !seen || !q1 || !q2 || !loc) { free(inB); free(seen); free(q1); free(q2); free(loc); return -1; }
+  area_bfs(g, part, a, b, p->area_mode, p->depth, UA, inB, 1, seen, q1, q2);
+  area_bfs(g, part, b, a, p->area_mode, p->depth, UB, inB, 2, seen, q1, q2);
+
+  /* corridor vertices in ascending id -> local ids; s = nb, t = nb + 1 */
+  int32_t nb = 0;
+  for (int32_t u = 0; u < n; u++) loc[u] = inB[u] ? nb++ : -1;
+  int32_t S = nb, T = nb + 1;
+  /* R2: border within G[A u B]: a corridor vertex with a neighbour in A u B
+   * outside the corridor */
+  uint8_t *border = (uint8_t *)calloc((size_t)(nb ? nb : 1), 1);
+  int64_t nedges = 0, sumw = 0, cin = 0;
+  for (int32_t u = 0; u < n; u++) {
+    if (!inB[u]) continue;
+    for (int32_t e = g->xadj[u]; e < g->xadj[u + 1]; e++) {
+      int32_t v = g->adjncy[e];
+      if (inB[v]) {
+        if (u < v) {
+          nedges++;
+          sumw += g->adjwgt[e];
+          if (inB[u] != inB[v]) cin += g->adjwgt[e];
+        }
+      } else if (part[v] == a || part[v] == b) {
+        border[loc[u]] = 1;
+      }
+    }
+  }
+  rec->region_vertices = nb;
+  rec->region_edges = nedges;
+  int64_t INF = 2 * sumw + 1; /* exceeds every finite cut */
+  or_net N;
+  int64_t nborder = 0;
+  for (int32_t i = 0; i < nb; i++) nborder += border[i];
+  if (net_init(&N, nb + 2, 2 * nedges + 2 * nborder) != 0) goto oom;
+  for (int32_t u = 0; u < n; u++) {
+    if (!inB[u]) continue;
+    for (int32_t e = g->xadj[u]; e < g->xadj[u + 1]; e++) {
+      int32_t v = g->adjncy[e];
+      if (inB[v] && u < v) net_add(&N, loc[u], loc[v], g->adjwgt[e], g->adjwgt[e]);
+    }
+    if (border[loc[u]]) {
+      if (inB[u] == 1) net_add(&N, S, loc[u], INF, 0); /* s -> left border */
+      else net_add(&N, loc[u], T, INF, 0);             /* right border -> t */
+    }
+  }
+  if (net_finish(&N) != 0) goto oom;
+  int64_t flow = net_dinic(&N, S, T);
+  rec->flow = flow;
+  uint8_t *reach = (uint8_t *)malloc((size_t)nb + 2);
+  int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * ((size_t)nb + 2));
+  if (!reach || !queue) { free(reach); free(queue); net_free(&N); goto oom; }
+  net_reach(&N, S, reach, queue);
+
+  /* candidate: corridor vertex -> a iff in the smallest source set */
+  int64_t wa = cA, wb = cB, src = 0;
+  for (int32_t u = 0; u < n; u++) {
+    if (!inB[u]) continue;
+    int in_s = reach[loc[u]];
+    src += in_s;
+    if (inB[u] == 1 && !in_s) { wa -= g->vwgt[u]; wb += g->vwgt[u]; }
+    if (inB[u] == 2 && in_s) { wb -= g->vwgt[u]; wa += g->vwgt[u]; }
+    if (side_out) side_out[u] = (int8_t)((border[loc[u]] ? 2 : 0) + (in_s ? 0 : 1));
+  }
+  rec->source_side = src;
+  rec->wa = wa;
+  rec->wb = wb;
+  /* edges with both ends in the corridor: C_in before, flow after */
+  int64_t cand = cut - cin + flow;
+  rec->cut_candidate = cand;
+  int feasible = wa <= lmax && wb <= lmax;
+  if (!feasible) rec->decision = DEC_INFEASIBLE;
+  else if (cand < cut) rec->decision = DEC_APPLY;
+  else rec->decision = DEC_EQUAL;
+  if (rec->decision == DEC_APPLY) {
+    for (int32_t u = 0; u < n; u++)
+      if (inB[u]) part[u] = reach[loc[u]] ? a : b;
+  }
+  free(reach);
+  free(queue);
+  net_free(&N);
+  free(border); free(inB); free(seen); free(q1); free(q2); free(loc);
+  return 0;
+oom:
+  free(border); free(inB); free(seen); free(q1); free(q2); free(loc);
+  return -1;
+}
+
+/* Adaptive flow iterations (Sec. 4.1) on one pair.  trace (optional) gets
+ * one record per solve, at most p->max_iters.  side_out: of the last solve. */
+int32_t or_refine_pair(const or_graph *g, int32_t *part, int32_t k, int32_t a, int32_t b,
+                       const or_params *p, or_result *res, int8_t *side_out, or_solve *trace) {
+  memset(res, 0, sizeof(*res));
+  if (a < 0 || b < 0 || a >= k || b >= k || a == b) return -3;
+  if (p->alpha < 1 || p->alpha_max < 1 || p->max_iters < 1 || p->eps_ppm < 0 ||
+      (p->area_mode != 0 && p->area_mode != 1) || p->depth < 0)
+    return -8;
+  int64_t w_a = 0, w_b = 0;
+  for (int32_t u = 0; u < g->n; u++) {
+    if (part[u] == a) w_a += g->vwgt[u];
+    if (part[u] == b) w_b += g->vwgt[u];
+  }
+  res->cut_before = pair_cut(g, part, a, b);
+  int32_t alpha = p->alpha < p->alpha_max ? p->alpha : p->alpha_max;
+  int32_t last = 0;
+  int stopped = 0;
+  for (int32_t it = 0; it < p->max_iters; it++) {
+    or_solve rec;
+    if (solve_once(g, part, k, a, b, p, alpha, &rec, side_out) != 0) return -7;
+    if (trace) trace[it] = rec;
+    res->iters++;
+    res->final_alpha = alpha;
+    res->flow_value = rec.flow;
+    res->region_vertices += rec.region_vertices;
+    res->region_edges += rec.region_edges;
+    last = rec.decision;
+    if (rec.decision == DEC_APPLY) {
+      res->applied++;
+      if (!p->adaptive) { stopped = 1; break; }
+      alpha = 2 * alpha < p->alpha_max ? 2 * alpha : p->alpha_max;
+    } else if (rec.decision == DEC_INFEASIBLE) {
+      if (!p->adaptive || alpha == 1) { stopped = 1; break; }
+      alpha = alpha / 2 > 1 ? alpha / 2 : 1;
+    } else {
+      stopped = 1; /* feasible and not improving, or not adjacent */
+      break;
+    }
+  }
+  res->iter_cap = !stopped;
+  if (last == DEC_NOT_ADJ && res->applied == 0) res->status = ST_NOT_ADJACENT;
+  else if (res->applied > 0) res->status = ST_ACCEPTED;
+  else if (last == DEC_INFEASIBLE) res->status = ST_REJECTED;
+  else res->status = ST_NO_IMPROVEMENT;
+  res->cut_after = pair_cut(g, part, a, b);
+  res->weight_a = 0;
+  res->weight_b = 0;
+  for (int32_t u = 0; u < g->n; u++) {
+    if (part[u] == a) res->weight_a += g->vwgt[u];
+    if (part[u] == b) res->weight_b += g->vwgt[u];
+  }
+  (void)w_a; (void)w_b;
+  return 0;
+}
+
+/* Pairs of one quotient-graph matching, one after the other.  The pairs must
+ * be block-disjoint, so the order does not change the outcome. */
+int32_t or_refine_batch(const or_graph *g, int32_t *part, int32_t k, const int32_t *pairs,
+                        int32_t npairs, const or_params *p, or_result *res, or_solve *trace) {
+  uint8_t *used = (uint8_t *)calloc((size_t)(k > 0 ? k : 1), 1);
+  if (!used) return -7;
+  for (int32_t i = 0; i < npairs; i++) {
+    int32_t a = pairs[2 * i], b = pairs[2 * i + 1];
+    if (a < 0 || b < 0 || a >= k || b >= k || a == b) { free(used); return -3; }
+    if (used[a] || used[b]) { free(used); return -4; }
+    used[a] = used[b] = 1;
+  }
+  free(used);
+  for (int32_t i = 0; i < npairs; i++) {
+    int32_t rc = or_refine_pair(g, part, k, pairs[2 * i], pairs[2 * i + 1], p, &res[i], NULL,
+                                trace ? trace + (size_t)i * p->max_iters : NULL);
+    if (rc != 0) return rc;
+  }
+  return 0;
+}
+
+/* Quotient graph (Sec. 2.1): one edge {a,b}, a < b, per pair of blocks that
+ * share a cut edge, sorted by (a,b).  Greedy edge colouring: in that order,
+ * each edge takes the smallest colour free at both ends, so every colour
+ * class is a matching.  Returns the number of edges (or -1). */
+int32_t or_quotient_colouring(const or_graph *g, const int32_t *part, int32_t k,
+                              int32_t *edges, int32_t *colour, int32_t max_edges) {
+  uint8_t *adj = (uint8_t *)calloc((size_t)k * k, 1);
+  if (!adj) return -1;
+  for (int32_t u = 0; u < g->n; u++)
+    for (int32_t e = g->xadj[u]; e < g->xadj[u + 1]; e++) {
+      int32_t x = part[u], y = part[g->adjncy[e]];
+      if (x < y) adj[(size_t)x * k + y] = 1;
+    }
+  int32_t ne = 0;
+  for (int32_t x = 0; x < k; x++)
+    for (int32_t y = x + 1; y < k; y++)
+      if (adj[(size_t)x * k + y]) {
+        if (ne >= max_edges) { free(adj); return -1; }
+        edges[2 * ne] = x;
+        edges[2 * ne + 1] = y;
+        ne++;
+      }
+  free(adj);
+  /* used[c*k + block] */
+  int32_t maxc = 2 * k + 1;
+  uint8_t *used = (uint8_t *)calloc((size_t)maxc * k, 1);
+  if (!used) return -1;
+  for (int32_t i = 0; i < ne; i++) {
+    int32_t x = edges[2 * i], y = edges[2 * i + 1], c = 0;
+    while (used[(size_t)c * k + x] || used[(size_t)c * k + y]) c++;
+    used[(size_t)c * k + x] = used[(size_t)c * k + y] = 1;
+    colour[i] = c;
+  }
+  free(used);
+  return ne;
+}
+
+/* Total cut sum_{i<j} omega(E_ij) (Sec. 2.1). */
+int64_t or_total_cut(const or_graph *g, const int32_t *part) {
+  int64_t c = 0;
+  for (int32_t u = 0; u < g->n; u++)
+    for (int32_t e = g->xadj[u]; e < g->xadj[u + 1]; e++)
+      if (part[u] != part[g->adjncy[e]]) c += g->adjwgt[e];
+  return c / 2;
+}
+
+/* Refinement sweep: build and colour the quotient graph, refine the pairs of
+ * each colour class in colour order, repeat until a sweep applies nothing or
+ * max_sweeps is reached.  Returns 0; stats[0] = sweeps run, stats[1] = flow
+ * solves, stats[2] = pairs with an applied change, stats[3] = region edges. */
+int32_t or_sweep(const or_graph *g, int32_t *part, int32_t k, const or_params *p,
+                 int32_t max_sweeps, int64_t *total_cut_out, int64_t *stats) {
+  int32_t maxe = k * (k - 1) / 2 + 1;
+  int32_t *edges = (int32_t *)malloc(sizeof(int32_t) * 2 * (size_t)maxe);
+  int32_t *colour = (int32_t *)malloc(sizeof(int32_t) * (size_t)maxe);
+  int32_t *pairs = (int32_t *)malloc(sizeof(int32_t) * 2 * (size_t)maxe);
+  or_result *res = (or_result *)malloc(sizeof(or_result) * (size_t)maxe);
+  if (!edges || !colour || !pairs || !res) { free(edges); free(colour); free(pairs); free(res); return -7; }
+  memset(stats, 0, sizeof(int64_t) * 4);
+  int32_t rc = 0;
+  for (int32_t s = 0; s < max_sweeps; s++) {
+    int32_t ne = or_quotient_colouring(g, part, k, edges, colour, maxe);
+    if (ne < 0) { rc = -7; break; }
+    int32_t ncol = 0;
+    for (int32_t i = 0; i < ne; i++) if (colour[i] + 1 > ncol) ncol = colour[i] + 1;
+    int64_t changed = 0;
+    for (int32_t c = 0; c < ncol; c++) {
+      int32_t np = 0;
+      for (int32_t i = 0; i < ne; i++)
+        if (colour[i] == c) { pairs[2 * np] = edges[2 * i]; pairs[2 * np + 1] = edges[2 * i + 1]; np++; }
+      rc = or_refine_batch(g, part, k, pairs, np, p, res, NULL);
+      if (rc != 0) break;
+      for (int32_t i = 0; i < np; i++) {
+        stats[1] += res[i].iters;
+        stats[3] += res[i].region_edges;
+        if (res[i].applied) changed++;
+      }
+    }
+    if (rc != 0) break;
+    stats[0]++;
+    stats[2] += changed;
+    if (changed == 0) break;
+  }
+  *total_cut_out = or_total_cut(g, part);
+  free(edges); free(colour); free(pairs); free(res);
+  return rc;
+}
+
+/* Per-pair input features for the learned area factor (no counterpart in the
+ * paper): boundary sizes, block weights, pair cut, slacks to L_max and the
+ * alpha = 1 area bound relative to the boundary weight.  f[0..7]:
+ *   log2(1+|dA|), log2(1+|dB|), c(A)/W, c(B)/W, log2(1+cut_AB),
+ *   (Lmax-c(A))/W, (Lmax-c(B))/W, log2(1 + U_A(1)/max(1,c(dA)))
+ * with W = c(V)/k.  Double precision. */
+int32_t or_pair_features(const or_graph *g, const int32_t *part, int32_t k, int32_t a,
+                         int32_t b, int32_t eps_ppm, double *f) {
+  if (a < 0 || b < 0 || a >= k || b >= k || a == b) return -3;
+  int64_t cV = 0, maxc = 0, cA = 0, cB = 0, nda = 0, ndb = 0, wda = 0, cut = 0;
+  for (int32_t u = 0; u < g->n; u++) {
+    cV += g->vwgt[u];
+    if (g->vwgt[u] > maxc) maxc = g->vwgt[u];
+    if (part[u] != a && part[u] != b) continue;
+    int32_t other = part[u] == a ? b : a;
+    int hit = 0;
+    for (int32_t e = g->xadj[u]; e < g->xadj[u + 1]; e++)
+      if (part[g->adjncy[e]] == other) {
+        hit = 1;
+        if (part[u] == a) cut += g->adjwgt[e];
+      }
+    if (part[u] == a) { cA += g->vwgt[u]; if (hit) { nda++; wda += g->vwgt[u]; } }
+    else { cB += g->vwgt[u]; if (hit) ndb++; }
+  }
+  int64_t lmax = (int64_t)(((__int128)(1000000 + (int64_t)eps_ppm) * cV) /
+                           ((__int128)1000000 * k)) + maxc;
+  int64_t u1 = (int64_t)(((__int128)(1000000 + (int64_t)eps_ppm) * cV) /
+                         ((__int128)1000000 * k)) - cB;
+  if (u1 < 0) u1 = 0;
+  double W = (double)cV / (double)k;
+  if (W <= 0) W = 1;
+  f[0] = log2(1.0 + (double)nda);
+  f[1] = log2(1.0 + (double)ndb);
+  f[2] = (double)cA / W;
+  f[3] = (double)cB / W;
+  f[4] = log2(1.0 + (double)cut);
+  f[5] = (double)(lmax - cA) / W;
+  f[6] = (double)(lmax - cB) / W;
+  f[7] = log2(1.0 + (double)u1 / (double)(wda > 1 ? wda : 1));
+  return 0;
+}
