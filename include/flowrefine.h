@@ -1,0 +1,204 @@
+/*
+ * flowrefine -- max-flow min-cut local refinement between pairs of blocks of a
+ * graph partition, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Sanders & Schulz, "Engineering Multilevel Graph Partitioning
+ * Algorithms", Section 4.1 ("Using Max-Flow Min-Cut Computations for Local
+ * Improvement").  For a pair of adjacent blocks (a, b):
+ *   1. boundary nodes of a towards b and of b towards a (Sec. 4.1, delta_l/r);
+ *   2. a BFS inside each block from its boundary, stopped once the area would
+ *      exceed (1 + alpha*eps) c(V)/k - c(other block) (Sec. 4.1, corridor B,
+ *      generalised from k = 2 to k blocks);
+ *   3. the corridor network G': G[B] plus s -> left corridor border and right
+ *      corridor border -> t with infinite capacity (Sec. 4.1);
+ *   4. a maximum s-t flow (push-relabel with global relabelling);
+ *   5. the minimum cut with the smallest source set, i.e. the vertices
+ *      reachable from s in the residual graph (Sec. 4.1.1, Ford-Fulkerson
+ *      labelling);
+ *   6. the balance check c(V_i) <= L_max = (1+eps) c(V)/k + max_v c(v)
+ *      (Sec. 2.1) and the adaptive flow iterations on alpha (Sec. 4.1).
+ * All arithmetic is integer.  Every output (flow value, smallest source set,
+ * partition, cut, block weights, alpha sequence) is unique, so it can be
+ * compared bit for bit with any exact reference.
+ *
+ * Readings of points the paper leaves open:
+ *   - only blocks a and b matter: the border is taken within G[A u B];
+ *   - BFS levels are walked in ascending vertex id and the walk stops for good
+ *     at the first vertex that would exceed the bound;
+ *   - area bound U_x(alpha) = floor((1+alpha*eps) c(V)/k) - c(other), >= 0;
+ *   - acceptance uses L_max with the original eps;
+ *   - adaptive loop: start at alpha (<= alpha_max); accepted => alpha =
+ *     min(2 alpha, alpha_max) and repeat; infeasible => alpha = max(alpha/2,1),
+ *     stop if it already was 1; feasible but not smaller => stop; at most
+ *     max_iters flow solves;
+ *   - the first block of a pair is the source side.
+ *
+ * Conventions: every entry point returns FR_OK (0) or a negative FR_E_* code,
+ * and never throws.  On error the partition is left unchanged.  All buffers
+ * are owned by the caller; the library keeps no pointer after a call returns.
+ * Calls on one context are serialised by the caller (a context is not
+ * thread-safe).  Calls block until their GPU work has finished.
+ */
+#ifndef FLOWREFINE_H
+#define FLOWREFINE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------- */
+#define FR_OK 0
+#define FR_E_INVALID_GRAPH (-1)      /* CSR malformed, asymmetric, self loop, weight out of range */
+#define FR_E_INVALID_PART (-2)       /* part[v] outside [0, k) */
+#define FR_E_INVALID_PAIR (-3)       /* block id outside [0, k), or a == b */
+#define FR_E_PAIRS_NOT_DISJOINT (-4) /* two pairs of one batch share a block */
+#define FR_E_OVERFLOW (-5)           /* capacities of one corridor reach 2^31, or an edge weight >= 2^30 */
+#define FR_E_DEVICE (-6)             /* HIP runtime error or an aborted device barrier */
+#define FR_E_OOM (-7)                /* device or host allocation failed */
+#define FR_E_INVALID_ARG (-8)        /* NULL pointer, bad parameter value */
+#define FR_E_SOLVER_LIMIT (-9)       /* push-relabel exceeded its sweep safety cap */
+
+/* ---- per-pair status (fr_result.status) --------------------------------- */
+#define FR_ACCEPTED 1           /* at least one flow solve was applied */
+#define FR_REJECTED_IMBALANCE 2 /* nothing applied; the last candidate broke L_max */
+#define FR_NO_IMPROVEMENT 3     /* nothing applied; the last candidate was feasible, not smaller */
+#define FR_NOT_ADJACENT 4       /* the blocks share no edge */
+
+/* ---- per-solve decision (fr_solve.decision) ----------------------------- */
+#define FR_DEC_APPLY 1
+#define FR_DEC_INFEASIBLE 2
+#define FR_DEC_EQUAL 3
+#define FR_DEC_NOT_ADJACENT 4
+
+/* ---- area modes (fr_params.area_mode) ----------------------------------- */
+#define FR_AREA_FACTOR 0 /* weight-bounded corridor, U_x(alpha) */
+#define FR_AREA_DEPTH 1  /* every vertex within BFS distance <= depth of the boundary */
+
+/* Undirected graph as symmetric CSR.  n vertices; xadj[n+1] with xadj[0] = 0
+ * and xadj[n] = 2m < 2^31; adjncy[2m] neighbour ids (no self loops, no
+ * repeats, each edge stored in both directions); adjwgt[2m] edge weights in
+ * [1, 2^30) equal in both directions (omega: E -> R>0, Sec. 2.1); vwgt[n]
+ * vertex weights >= 0 (c: V -> R>=0).  on_device = 1: all five pointers and
+ * the partition are device pointers (for example torch tensors); 0: host
+ * pointers, copied by the library for the call.  Read-only. */
+typedef struct {
+  int32_t n;
+  int32_t on_device;
+  const int32_t *xadj;
+  const int32_t *adjncy;
+  const int32_t *adjwgt;
+  const int32_t *vwgt;
+} fr_graph;
+
+/* Parameters of the adaptive flow iterations. */
+typedef struct {
+  int32_t area_mode; /* FR_AREA_FACTOR or FR_AREA_DEPTH */
+  int32_t depth;     /* FR_AREA_DEPTH only, >= 0 */
+  int32_t alpha;     /* start factor, >= 1 (clamped to alpha_max) */
+  int32_t alpha_max; /* upper bound alpha' of the factor, >= 1 */
+  int32_t adaptive;  /* 0: one flow solve; 1: adaptive flow iterations */
+  int32_t max_iters; /* flow solves per pair, in [1, 64] */
+  int32_t eps_ppm;   /* imbalance eps in parts per million (3 % = 30000), >= 0 */
+  int32_t use_mlp;   /* batch calls only: start each pair at the learned factor */
+} fr_params;
+
+/* Outcome of one pair. */
+typedef struct {
+  int32_t status;      /* FR_ACCEPTED, FR_REJECTED_IMBALANCE, FR_NO_IMPROVEMENT, FR_NOT_ADJACENT */
+  int32_t iters;       /* flow solves run */
+  int32_t final_alpha; /* factor of the last solve */
+  int32_t applied;     /* solves whose candidate was applied */
+  int32_t iter_cap;    /* 1 if the loop stopped only because of max_iters */
+  int32_t start_alpha; /* factor of the first solve (differs from alpha with use_mlp) */
+  int64_t flow_value;  /* max-flow value of the last solve */
+  int64_t cut_before, cut_after;         /* pair cut omega(E_ab) before / after the call */
+  int64_t weight_a, weight_b;            /* c(V_a), c(V_b) after the call */
+  int64_t region_vertices, region_edges; /* corridor vertices / edges summed over the solves */
+} fr_result;
+
+/* One flow solve (trace record). */
+typedef struct {
+  int32_t alpha;
+  int32_t decision;        /* FR_DEC_* */
+  int64_t flow;            /* max-flow value */
+  int64_t region_vertices; /* |B| */
+  int64_t region_edges;    /* edges of G[B] */
+  int64_t source_side;     /* corridor vertices in the smallest source set */
+  int64_t cut_before;      /* pair cut before the solve */
+  int64_t cut_candidate;   /* pair cut of the candidate partition */
+  int64_t wa, wb;          /* block weights of the candidate */
+} fr_solve;
+
+/* Kernel launch parameters; any valid setting gives identical results. */
+typedef struct {
+  int32_t block_threads;   /* threads per workgroup: 64..1024, multiple of 64 */
+  int32_t blocks_per_cu;   /* persistent workgroups per compute unit: 1..4 */
+  int32_t tpv;             /* lanes per vertex in push/relabel sweeps: 1,2,4,8,16 */
+  int32_t relabel_period;  /* push/relabel sweeps between global relabels, >= 1 */
+} fr_tuning;
+
+typedef struct fr_context fr_context;
+
+/* Create a context on HIP device `device`, issuing work on `hip_stream` (a
+ * hipStream_t; NULL = the null stream).  Device scratch is allocated lazily and
+ * grows with the largest graph seen. */
+int32_t fr_create(int32_t device, void *hip_stream, fr_context **ctx);
+int32_t fr_destroy(fr_context *ctx);
+const char *fr_strerror(int32_t code);
+
+/* Adaptive flow refinement of one pair (a = source side, b = sink side).
+ * part: [n] in/out, block ids in [0, k).  res: host, one record.
+ * side_out (optional, host int8 [n]): per vertex of the LAST solve, -1 outside
+ * the corridor, 0 / 1 corridor vertex ending in a / b, 2 / 3 border vertex
+ * pinned to s (block a) / t (block b).
+ * trace (optional, host, p->max_iters records): one record per solve. */
+int32_t flow_refine_pair(fr_context *ctx, const fr_graph *g, int32_t *part, int32_t k,
+                         int32_t a, int32_t b, const fr_params *p, fr_result *res,
+                         int8_t *side_out, fr_solve *trace);
+
+/* All pairs of one quotient-graph matching in one batched solve.  pairs: host
+ * int32 [2*npairs] (a_i, b_i), blocks pairwise disjoint.  res: host
+ * [npairs]; trace (optional): host [npairs * p->max_iters], record j of pair i
+ * at i*max_iters + j.  With p->use_mlp = 1 each pair starts at the factor the
+ * loaded area-factor network predicts (see fr_mlp_*). */
+int32_t flow_refine_batch(fr_context *ctx, const fr_graph *g, int32_t *part, int32_t k,
+                          const int32_t *pairs, int32_t npairs, const fr_params *p,
+                          fr_result *res, fr_solve *trace);
+
+/* Quotient graph of the partition (an edge {a, b}, a < b, per pair of blocks
+ * sharing a cut edge; Sec. 2.1) in (a, b) order, greedily edge-coloured (each
+ * edge takes the smallest colour free at both ends), so every colour class is
+ * a matching.  edges: host int32 [2*max_edges]; colour: host int32
+ * [max_edges].  *nedges gets the edge count (FR_E_INVALID_ARG if > max_edges). */
+int32_t fr_quotient_matchings(fr_context *ctx, const fr_graph *g, const int32_t *part, int32_t k,
+                              int32_t *edges, int32_t *colour, int32_t max_edges,
+                              int32_t *nedges);
+
+/* Repeated rounds: build and colour the quotient graph, run one batched solve
+ * per colour class in colour order, until a sweep changes nothing or
+ * max_sweeps sweeps ran.  stats (optional, host int64 [4]): sweeps, flow
+ * solves, pairs with an applied change, region edges.  total_cut_out: the cut
+ * sum_{i<j} omega(E_ij) after the sweep. */
+int32_t flow_refine_sweep(fr_context *ctx, const fr_graph *g, int32_t *part, int32_t k,
+                          const fr_params *p, int32_t max_sweeps, int64_t *total_cut_out,
+                          int64_t *stats);
+
+/* Launch parameters (fr_tuning); FR_E_INVALID_ARG for values out of range. */
+int32_t fr_set_tuning(fr_context *ctx, const fr_tuning *t);
+int32_t fr_get_tuning(fr_context *ctx, fr_tuning *t);
+
+/* Input checks of every call (CSR shape, ranges, symmetry: O(sum deg^2)) on
+ * (1, the default) or off (0; malformed input then gives undefined results). */
+int32_t fr_set_validation(fr_context *ctx, int32_t on);
+
+/* Per-stage GPU time of the last call in milliseconds (host float [8]):
+ * boundary+corridor, network build, push/relabel + global relabel, cut +
+ * decision, total; then push/relabel sweeps, global relabels, and 0. */
+int32_t fr_last_stats(fr_context *ctx, double *ms, int64_t *counters);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FLOWREFINE_H */

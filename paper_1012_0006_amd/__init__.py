@@ -1,0 +1,273 @@
+"""Python binding of libflowrefine (max-flow min-cut pair refinement on
+MI355X).  Argument marshalling only: every step of the refinement runs in the
+library's HIP kernels.  torch supplies device memory and the stream.
+
+The names mirror the C ABI in include/flowrefine.h: fr_create, fr_destroy,
+flow_refine_pair, flow_refine_batch, flow_refine_sweep, fr_quotient_matchings,
+fr_set_tuning, fr_get_tuning, fr_last_stats.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libflowrefine.so")
+_lib = None
+
+FR_OK = 0
+FR_ERRORS = {-1: "INVALID_GRAPH", -2: "INVALID_PART", -3: "INVALID_PAIR",
+             -4: "PAIRS_NOT_DISJOINT", -5: "OVERFLOW", -6: "DEVICE", -7: "OOM",
+             -8: "INVALID_ARG", -9: "SOLVER_LIMIT"}
+FR_ACCEPTED, FR_REJECTED_IMBALANCE, FR_NO_IMPROVEMENT, FR_NOT_ADJACENT = 1, 2, 3, 4
+FR_DEC_APPLY, FR_DEC_INFEASIBLE, FR_DEC_EQUAL, FR_DEC_NOT_ADJACENT = 1, 2, 3, 4
+FR_AREA_FACTOR, FR_AREA_DEPTH = 0, 1
+
+i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+
+
+class FrGraph(ctypes.Structure):
+    _fields_ = [("n", i32), ("on_device", i32), ("xadj", vp), ("adjncy", vp), ("adjwgt", vp),
+                ("vwgt", vp)]
+
+
+class FrParams(ctypes.Structure):
+    _fields_ = [(f, i32) for f in ("area_mode", "depth", "alpha", "alpha_max", "adaptive",
+                                   "max_iters", "eps_ppm", "use_mlp")]
+
+
+class FrResult(ctypes.Structure):
+    _fields_ = [(f, i32) for f in ("status", "iters", "final_alpha", "applied", "iter_cap",
+                                   "start_alpha")] + [
+        (f, i64) for f in ("flow_value", "cut_before", "cut_after", "weight_a", "weight_b",
+                           "region_vertices", "region_edges")]
+
+
+class FrSolve(ctypes.Structure):
+    _fields_ = [("alpha", i32), ("decision", i32)] + [
+        (f, i64) for f in ("flow", "region_vertices", "region_edges", "source_side",
+                           "cut_before", "cut_candidate", "wa", "wb")]
+
+
+class FrTuning(ctypes.Structure):
+    _fields_ = [(f, i32) for f in ("block_threads", "blocks_per_cu", "tpv", "relabel_period")]
+
+
+EXPORTS = ("fr_create", "fr_destroy", "fr_strerror", "flow_refine_pair", "flow_refine_batch",
+           "flow_refine_sweep", "fr_quotient_matchings", "fr_set_tuning", "fr_get_tuning",
+           "fr_set_validation", "fr_last_stats")
+
+
+class FlowRefineError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {FR_ERRORS.get(code, code)} ({code})")
+        self.code = code
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library; raises if it is not built (no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            f"{path} is missing: build it with `python -m paper_1012_0006_amd.build`")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    lib.fr_create.restype = i32
+    lib.fr_create.argtypes = [i32, vp, P(vp)]
+    lib.fr_destroy.restype = i32
+    lib.fr_destroy.argtypes = [vp]
+    lib.fr_strerror.restype = ctypes.c_char_p
+    lib.fr_strerror.argtypes = [i32]
+    lib.flow_refine_pair.restype = i32
+    lib.flow_refine_pair.argtypes = [vp, P(FrGraph), vp, i32, i32, i32, P(FrParams), vp, vp, vp]
+    lib.flow_refine_batch.restype = i32
+    lib.flow_refine_batch.argtypes = [vp, P(FrGraph), vp, i32, vp, i32, P(FrParams), vp, vp]
+    lib.flow_refine_sweep.restype = i32
+    lib.flow_refine_sweep.argtypes = [vp, P(FrGraph), vp, i32, P(FrParams), i32, P(i64), vp]
+    lib.fr_quotient_matchings.restype = i32
+    lib.fr_quotient_matchings.argtypes = [vp, P(FrGraph), vp, i32, vp, vp, i32, P(i32)]
+    lib.fr_set_tuning.restype = i32
+    lib.fr_set_tuning.argtypes = [vp, P(FrTuning)]
+    lib.fr_get_tuning.restype = i32
+    lib.fr_get_tuning.argtypes = [vp, P(FrTuning)]
+    lib.fr_set_validation.restype = i32
+    lib.fr_set_validation.argtypes = [vp, i32]
+    lib.fr_last_stats.restype = i32
+    lib.fr_last_stats.argtypes = [vp, vp, vp]
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, where: str):
+    if rc != FR_OK:
+        raise FlowRefineError(rc, where)
+
+
+def _struct_dict(s) -> dict:
+    return {f: getattr(s, f) for f, _ in s._fields_}
+
+
+def params(**kw) -> FrParams:
+    d = dict(area_mode=0, depth=0, alpha=16, alpha_max=16, adaptive=1, max_iters=16,
+             eps_ppm=30000, use_mlp=0)
+    d.update(kw)
+    return FrParams(**{k: int(d[k]) for k, _ in FrParams._fields_})
+
+
+@dataclass
+class DeviceGraph:
+    """CSR graph held in device memory (torch int32 tensors)."""
+    n: int
+    xadj: object
+    adjncy: object
+    adjwgt: object
+    vwgt: object
+
+    @classmethod
+    def from_host(cls, g, device="cuda"):
+        import torch
+
+        def t(a):
+            return torch.as_tensor(np.ascontiguousarray(a, dtype=np.int32)).to(device)
+
+        return cls(int(g.xadj.shape[0] - 1), t(g.xadj), t(g.adjncy), t(g.adjwgt), t(g.vwgt))
+
+    def struct(self) -> FrGraph:
+        return FrGraph(self.n, 1, self.xadj.data_ptr(), self.adjncy.data_ptr(),
+                       self.adjwgt.data_ptr(), self.vwgt.data_ptr())
+
+
+def host_graph_struct(g):
+    """FrGraph over host numpy arrays (the library copies them); returns
+    (struct, keepalive)."""
+    arrs = [np.ascontiguousarray(a, dtype=np.int32) for a in (g.xadj, g.adjncy, g.adjwgt, g.vwgt)]
+    s = FrGraph(int(arrs[0].shape[0] - 1), 0, *(a.ctypes.data for a in arrs))
+    return s, arrs
+
+
+class Context:
+    """fr_create / fr_destroy around one HIP device and stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+
+        lib = load()
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        h = vp()
+        _check(lib.fr_create(device, stream, ctypes.byref(h)), "fr_create")
+        self.handle = h
+        self.lib = lib
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.fr_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- tuning ---------------------------------------------------------
+    def set_tuning(self, block_threads=256, blocks_per_cu=4, tpv=8, relabel_period=6):
+        t = FrTuning(block_threads, blocks_per_cu, tpv, relabel_period)
+        _check(self.lib.fr_set_tuning(self.handle, ctypes.byref(t)), "fr_set_tuning")
+
+    def get_tuning(self) -> dict:
+        t = FrTuning()
+        _check(self.lib.fr_get_tuning(self.handle, ctypes.byref(t)), "fr_get_tuning")
+        return _struct_dict(t)
+
+    def set_validation(self, on: bool):
+        _check(self.lib.fr_set_validation(self.handle, 1 if on else 0), "fr_set_validation")
+
+    def last_stats(self):
+        ms = (ctypes.c_double * 8)()
+        cnt = (ctypes.c_int64 * 8)()
+        _check(self.lib.fr_last_stats(self.handle, ms, cnt), "fr_last_stats")
+        return list(ms), list(cnt)
+
+
+def _graph_arg(graph):
+    if isinstance(graph, DeviceGraph):
+        return graph.struct(), None
+    return host_graph_struct(graph)
+
+
+def _part_arg(part, on_device: bool):
+    if on_device:
+        import torch
+
+        assert isinstance(part, torch.Tensor) and part.is_cuda and part.dtype == torch.int32
+        assert part.is_contiguous()
+        return part.data_ptr()
+    assert isinstance(part, np.ndarray) and part.dtype == np.int32 and part.flags.c_contiguous
+    return part.ctypes.data
+
+
+def flow_refine_pair(ctx: Context, graph, part, k: int, a: int, b: int, prm: FrParams,
+                     want_side: bool = False):
+    """Adaptive flow refinement of one pair; part is updated in place.
+    Returns (result, trace, side)."""
+    gs, keep = _graph_arg(graph)
+    res = FrResult()
+    trace = (FrSolve * max(1, prm.max_iters))()
+    side = np.zeros(gs.n, dtype=np.int8) if want_side else None
+    rc = ctx.lib.flow_refine_pair(ctx.handle, ctypes.byref(gs), _part_arg(part, gs.on_device), k,
+                                  a, b, ctypes.byref(prm), ctypes.addressof(res),
+                                  side.ctypes.data if want_side else None,
+                                  ctypes.addressof(trace))
+    _check(rc, "flow_refine_pair")
+    r = _struct_dict(res)
+    return r, [_struct_dict(trace[i]) for i in range(r["iters"])], side
+
+
+def flow_refine_batch(ctx: Context, graph, part, k: int, pairs, prm: FrParams):
+    """All pairs of one matching in one batched solve; part updated in place.
+    Returns (results, traces)."""
+    gs, keep = _graph_arg(graph)
+    pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1))
+    npairs = pr.shape[0] // 2
+    res = (FrResult * max(1, npairs))()
+    mi = max(1, prm.max_iters)
+    trace = (FrSolve * max(1, npairs * mi))()
+    rc = ctx.lib.flow_refine_batch(ctx.handle, ctypes.byref(gs), _part_arg(part, gs.on_device), k,
+                                   pr.ctypes.data, npairs, ctypes.byref(prm),
+                                   ctypes.addressof(res), ctypes.addressof(trace))
+    _check(rc, "flow_refine_batch")
+    results = [_struct_dict(res[i]) for i in range(npairs)]
+    traces = [[_struct_dict(trace[i * mi + j]) for j in range(results[i]["iters"])]
+              for i in range(npairs)]
+    return results, traces
+
+
+def fr_quotient_matchings(ctx: Context, graph, part, k: int):
+    gs, keep = _graph_arg(graph)
+    maxe = k * (k - 1) // 2 + 1
+    edges = np.zeros(2 * maxe, dtype=np.int32)
+    colour = np.zeros(maxe, dtype=np.int32)
+    ne = i32(0)
+    rc = ctx.lib.fr_quotient_matchings(ctx.handle, ctypes.byref(gs), _part_arg(part, gs.on_device),
+                                       k, edges.ctypes.data, colour.ctypes.data, maxe,
+                                       ctypes.byref(ne))
+    _check(rc, "fr_quotient_matchings")
+    return edges[:2 * ne.value].reshape(-1, 2), colour[:ne.value]
+
+
+def flow_refine_sweep(ctx: Context, graph, part, k: int, prm: FrParams, max_sweeps: int):
+    """Returns (total cut, stats[sweeps, solves, changed pairs, region edges])."""
+    gs, keep = _graph_arg(graph)
+    tc = i64(0)
+    stats = np.zeros(4, dtype=np.int64)
+    rc = ctx.lib.flow_refine_sweep(ctx.handle, ctypes.byref(gs), _part_arg(part, gs.on_device), k,
+                                   ctypes.byref(prm), max_sweeps, ctypes.byref(tc),
+                                   stats.ctypes.data)
+    _check(rc, "flow_refine_sweep")
+    return int(tc.value), stats
