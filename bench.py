@@ -1,0 +1,260 @@
+"""Benchmark of max-flow min-cut pair refinement on one MI355X.
+
+A step is one adaptive flow refinement of the bisection of a 2D random
+geometric graph (n = 2^18, mean degree 8, edge weights 1..10, median-x split
+with 2 % boundary noise, eps = 3 %, alpha 16 adaptive): boundary, bounded BFS
+corridor, network, max preflow, smallest source set, balance check, adaptive
+factor, write-back -- every solve of the loop.  Inputs are resident in device
+memory before the timed region; each step starts from the same partition.
+
+Printed: one JSON line with region edges/s (corridor edges summed over all
+flow solves, divided by wall time), the roofline of the solve kernel, the CPU
+oracle on the same input, and a batched-vs-plain comparison on one
+quotient-graph matching round of a 3D random geometric graph (n = 2^20,
+k = 16).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "flow-refinement region edges/s + %HBM peak, batched vs plain, bit-exact cut"
+HBM_PEAK_GBS = 8000.0
+
+# algorithmic bytes per unit of work (4-byte ints; what each phase must read
+# or write, not what the caches do)
+BYTES = {
+    "bnd_verts": 16, "bnd_arcs": 8,        # list + part + xadj pair; neighbour id + its block
+    "bfs_items": 16, "bfs_arcs": 12,       # + corridor mark of the neighbour
+    "net_verts": 29, "net_arcs": 24,       # two passes (count, fill) over the global arcs
+    "sweep_items": 20, "sweep_arcs": 12,   # list, label, excess, offsets; head, residual, label
+    "gr_items": 12, "gr_arcs": 16,         # list, offsets; head, reverse arc, its residual, label
+    "cl_items": 12, "cl_arcs": 12,         # list, offsets; residual, head, mark
+}
+CORRIDOR_ARC_BYTES = 36  # reverse-arc search and writes of head / reverse / residual
+
+
+def algorithmic_bytes(stats: dict, region_edges: int) -> int:
+    b = sum(stats[k] * v for k, v in BYTES.items())
+    return int(b + CORRIDOR_ARC_BYTES * 2 * region_edges)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("fr_kernels.h", "fr_internal.h", "flowrefine.hip"):
+        with open(os.path.join(ROOT, "paper_1012_0006_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"k_solve_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def c2_params(fr, w):
+    return fr.params(**{k: w.params[k] for k in ("area_mode", "depth", "alpha", "alpha_max",
+                                                  "adaptive", "max_iters", "eps_ppm")})
+
+
+def run_plain(args, fr, torch, gen):
+    w = gen.config("C2")
+    ctx = fr.Context()
+    ctx.set_validation(False)  # inputs are generated valid; validation is O(sum deg^2)
+    dg = fr.DeviceGraph.from_host(w.graph)
+    part0 = torch.as_tensor(w.part).cuda()
+    dpart = part0.clone()
+    prm = c2_params(fr, w)
+    for _ in range(args.warmup):
+        dpart.copy_(part0)
+        fr.flow_refine_pair(ctx, dg, dpart, w.k, 0, 1, prm)
+    torch.cuda.synchronize()
+    edges, kern_ms, byts = 0, 0.0, 0
+    results = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dpart.copy_(part0)
+        res, trace, _ = fr.flow_refine_pair(ctx, dg, dpart, w.k, 0, 1, prm)
+        st = fr.stats_dict(ctx)
+        edges += res["region_edges"]
+        kern_ms += st["solve_kernel_ms"]
+        byts += algorithmic_bytes(st, res["region_edges"])
+        results.append((res, trace))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    final_part = dpart.cpu().numpy()
+    ctx.close()
+    return dict(w=w, edges=edges, wall=wall, kern_ms=kern_ms, bytes=byts, result=results[-1][0],
+                trace=results[-1][1], part=final_part, stats=st)
+
+
+def run_cpu_baseline(w):
+    import oracle
+
+    t0 = time.perf_counter()
+    o = oracle.refine_pair(w.graph, w.part, w.k, 0, 1, w.params, want_side=False)
+    dt = time.perf_counter() - t0
+    return o, dt
+
+
+def run_batched(args, fr, torch, gen):
+    """One matching round of C3 (3D RGG n=2^20, mean degree 12, k=16 RCB +
+    2 % noise): all pairs in one batched launch vs the pairs one by one."""
+    w = gen.config("C3")
+    ctx = fr.Context()
+    ctx.set_validation(False)
+    dg = fr.DeviceGraph.from_host(w.graph)
+    part0 = torch.as_tensor(w.part).cuda()
+    edges_q, colour = fr.fr_quotient_matchings(ctx, dg, part0, w.k)
+    counts = np.bincount(colour)
+    c = int(np.argmax(counts))
+    pairs = [tuple(e) for e, cc in zip(edges_q.tolist(), colour.tolist()) if cc == c]
+    prm = fr.params(**{k: w.params[k] for k in ("area_mode", "depth", "alpha", "alpha_max",
+                                                 "adaptive", "max_iters", "eps_ppm")})
+    dpart = part0.clone()
+    reps = max(1, args.batch_reps)
+    # batched
+    dpart.copy_(part0)
+    fr.flow_refine_batch(ctx, dg, dpart, w.k, pairs, prm)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dpart.copy_(part0)
+        res_b, _ = fr.flow_refine_batch(ctx, dg, dpart, w.k, pairs, prm)
+    torch.cuda.synchronize()
+    t_b = (time.perf_counter() - t0) / reps
+    part_b = dpart.cpu().numpy()
+    # plain: one pair call after the other on the same partition
+    dpart.copy_(part0)
+    for a, b in pairs[:1]:
+        fr.flow_refine_pair(ctx, dg, dpart, w.k, a, b, prm)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dpart.copy_(part0)
+        res_p = [fr.flow_refine_pair(ctx, dg, dpart, w.k, a, b, prm)[0] for a, b in pairs]
+    torch.cuda.synchronize()
+    t_p = (time.perf_counter() - t0) / reps
+    part_p = dpart.cpu().numpy()
+    ctx.close()
+    e_b = sum(r["region_edges"] for r in res_b)
+    e_p = sum(r["region_edges"] for r in res_p)
+    same = bool(np.array_equal(part_b, part_p)) and all(
+        rb["cut_after"] == rp["cut_after"] for rb, rp in zip(res_b, res_p))
+    return {
+        "workload": "C3: 3D RGG n=2^20 mean degree 12 unit weights, k=16 RCB + 2% noise, "
+                    f"largest matching round ({len(pairs)} pairs), eps 3%, alpha 16 adaptive",
+        "pairs": len(pairs),
+        "batched_region_edges_per_s": e_b / t_b,
+        "plain_region_edges_per_s": e_p / t_p,
+        "batched_ms": t_b * 1e3,
+        "plain_ms": t_p * 1e3,
+        "speedup": t_p / t_b,
+        "equal_result": same,
+        "region_edges": e_b,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-reps", type=int, default=3)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    import gen
+    import paper_1012_0006_amd as fr
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    fr.load()  # fails loudly when the HIP library is not built
+
+    plain = run_plain(args, fr, torch, gen)
+    value = plain["edges"] / plain["wall"]
+    launches = args.steps
+    avg_kern_s = plain["kern_ms"] / 1e3 / launches
+    bytes_per_launch = plain["bytes"] / launches
+    achieved = bytes_per_launch / avg_kern_s / 1e9
+    traffic = load_traffic("C2")
+    tune = None
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "region edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": plain["wall"] * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": "C2: 2D RGG n=2^18 mean degree 8, edge weights 1..10, median-x bisection "
+                        "+ 2% boundary noise, eps 3%, alpha 16 adaptive (max 16 solves)",
+            "region_edges_per_step": plain["edges"] // args.steps,
+            "solves_per_step": plain["result"]["iters"],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_solve",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "avg_launch_ms": avg_kern_s * 1e3,
+        },
+    }
+    if not args.no_cpu_baseline:
+        o, dt = run_cpu_baseline(plain["w"])
+        exact = (o.result["cut_after"] == plain["result"]["cut_after"]
+                 and o.result["flow_value"] == plain["result"]["flow_value"]
+                 and o.trace == plain["trace"]
+                 and bool(np.array_equal(o.part, plain["part"])))
+        line["cpu_baseline"] = {
+            "value": o.result["region_edges"] / dt,
+            "unit": "region edges/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": "one full adaptive refinement of the same C2 pair "
+                      f"({o.result['iters']} flow solves, {o.result['region_edges']} region edges), "
+                      "single-threaded sequential Dinic oracle",
+            "seconds": dt,
+        }
+        line["bit_exact_vs_oracle"] = bool(exact)
+    if not args.no_batched:
+        line["batched"] = run_batched(args, fr, torch, gen)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

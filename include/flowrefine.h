@@ -193,9 +193,17 @@ int32_t fr_get_tuning(fr_context *ctx, fr_tuning *t);
  * (1, the default) or off (0; malformed input then gives undefined results). */
 int32_t fr_set_validation(fr_context *ctx, int32_t on);
 
-/* Per-stage GPU time of the last call in milliseconds (host float [8]):
- * boundary+corridor, network build, push/relabel + global relabel, cut +
- * decision, total; then push/relabel sweeps, global relabels, and 0. */
+/* Statistics of the last pair / batch call (host arrays, either may be NULL).
+ * ms[8]: setup (validation, weights, arenas), the batched solve kernel,
+ *   corridor phase, network build, whole call on the device, global
+ *   relabels, push/relabel sweeps, closure + decision; phases 2,3,5,6,7 are
+ *   device clock time summed over the pairs' workgroups.
+ * counters[32]: [0] push/relabel sweeps, [1] global relabels, [2] corridor
+ *   BFS levels, [3] relabel BFS levels, [4] closure levels, [5] workgroups
+ *   launched, [6] internal check that failed (0 = none); [16..27] vertices
+ *   and arcs touched: boundary scan, corridor BFS, network build,
+ *   push/relabel sweeps, global relabels, residual closure (vertices then
+ *   arcs for each); the rest 0. */
 int32_t fr_last_stats(fr_context *ctx, double *ms, int64_t *counters);
 
 #ifdef __cplusplus

@@ -176,7 +176,7 @@ class Context:
             pass
 
     # -- tuning ---------------------------------------------------------
-    def set_tuning(self, block_threads=256, blocks_per_cu=4, tpv=8, relabel_period=6):
+    def set_tuning(self, block_threads=1024, blocks_per_cu=2, tpv=4, relabel_period=200):
         t = FrTuning(block_threads, blocks_per_cu, tpv, relabel_period)
         _check(self.lib.fr_set_tuning(self.handle, ctypes.byref(t)), "fr_set_tuning")
 
@@ -190,9 +190,24 @@ class Context:
 
     def last_stats(self):
         ms = (ctypes.c_double * 8)()
-        cnt = (ctypes.c_int64 * 8)()
+        cnt = (ctypes.c_int64 * 32)()
         _check(self.lib.fr_last_stats(self.handle, ms, cnt), "fr_last_stats")
         return list(ms), list(cnt)
+
+
+WORK_KEYS = ("bnd_verts", "bnd_arcs", "bfs_items", "bfs_arcs", "net_verts", "net_arcs",
+             "sweep_items", "sweep_arcs", "gr_items", "gr_arcs", "cl_items", "cl_arcs")
+
+
+def stats_dict(ctx) -> dict:
+    """fr_last_stats as a dict: phase times (ms) and work counters."""
+    ms, cnt = ctx.last_stats()
+    d = dict(setup_ms=ms[0], solve_kernel_ms=ms[1], corridor_ms=ms[2], build_ms=ms[3],
+             call_ms=ms[4], relabel_ms=ms[5], push_ms=ms[6], closure_finish_ms=ms[7],
+             sweeps=cnt[0], relabels=cnt[1], bfs_levels=cnt[2], gr_levels=cnt[3],
+             cl_levels=cnt[4], workgroups=cnt[5], diag=cnt[6])
+    d.update({k: cnt[16 + i] for i, k in enumerate(WORK_KEYS)})
+    return d
 
 
 def _graph_arg(graph):

@@ -190,10 +190,10 @@ def test_sweep_matches_oracle(gpu_lib, ctx):
     assert np.array_equal(dpart.cpu().numpy(), opart)
 
 
-@pytest.mark.parametrize("tune", [dict(block_threads=64, blocks_per_cu=1, tpv=1, relabel_period=1),
+@pytest.mark.parametrize("tune", [dict(block_threads=256, blocks_per_cu=1, tpv=1, relabel_period=1),
                                   dict(block_threads=1024, blocks_per_cu=2, tpv=16, relabel_period=50),
                                   dict(block_threads=512, blocks_per_cu=4, tpv=4, relabel_period=3),
-                                  dict(block_threads=256, blocks_per_cu=3, tpv=2, relabel_period=12)])
+                                  dict(block_threads=256, blocks_per_cu=8, tpv=2, relabel_period=12)])
 def test_launch_parameters_do_not_change_results(gpu_lib, tune):
     c = gpu_lib.Context()
     try:
@@ -234,5 +234,5 @@ def test_error_paths(gpu_lib, ctx):
         gpu_lib.flow_refine_pair(ctx, dg, dpart, 2, 0, 1, gpu_lib.params(max_iters=0))
     assert e.value.code == -8
     with pytest.raises(gpu_lib.FlowRefineError) as e:
-        ctx.set_tuning(blocks_per_cu=8)
+        ctx.set_tuning(blocks_per_cu=9)
     assert e.value.code == -8
