@@ -101,7 +101,7 @@ typedef struct {
   int32_t adaptive;  /* 0: one flow solve; 1: adaptive flow iterations */
   int32_t max_iters; /* flow solves per pair, in [1, 64] */
   int32_t eps_ppm;   /* imbalance eps in parts per million (3 % = 30000), >= 0 */
-  int32_t use_mlp;   /* batch calls only: start each pair at the learned factor */
+  int32_t use_mlp;   /* start each pair at the learned factor (needs loaded weights) */
 } fr_params;
 
 /* Outcome of one pair. */
@@ -177,8 +177,9 @@ int32_t fr_quotient_matchings(fr_context *ctx, const fr_graph *g, const int32_t 
                               int32_t *nedges);
 
 /* Repeated rounds: build and colour the quotient graph, run one batched solve
- * per colour class in colour order, until a sweep changes nothing or
- * max_sweeps sweeps ran.  stats (optional, host int64 [4]): sweeps, flow
+ * per colour class in colour order (all rounds of a sweep recorded into one
+ * hipGraph and launched once), until a sweep changes nothing or max_sweeps
+ * sweeps ran.  stats (optional, host int64 [4]): sweeps, flow
  * solves, pairs with an applied change, region edges.  total_cut_out: the cut
  * sum_{i<j} omega(E_ij) after the sweep. */
 int32_t flow_refine_sweep(fr_context *ctx, const fr_graph *g, int32_t *part, int32_t k,
@@ -205,6 +206,45 @@ int32_t fr_set_validation(fr_context *ctx, int32_t on);
  *   push/relabel sweeps, global relabels, residual closure (vertices then
  *   arcs for each); the rest 0. */
 int32_t fr_last_stats(fr_context *ctx, double *ms, int64_t *counters);
+
+/* ---- learned area factor (no counterpart in the paper) -----------------
+ * A small network (8 features -> 64 -> 64 -> 5 classes, ReLU, softmax;
+ * FP32) proposes the start factor alpha in {1, 2, 4, 8, 16} of each pair;
+ * the adaptive flow iterations then run as usual from that factor, so every
+ * flow result stays exact.  Parameters: one float array of
+ * fr_mlp_num_params() values, W1[8][64], b1[64], W2[64][64], b2[64],
+ * W3[64][5], b3[5] (row-major [in][out]).  All arrays below are host arrays. */
+int32_t fr_mlp_num_params(void);
+/* He-normal initialisation from a seed; the network counts as loaded. */
+int32_t fr_mlp_init(fr_context *ctx, uint64_t seed);
+int32_t fr_mlp_set_weights(fr_context *ctx, const float *w, int32_t count);
+int32_t fr_mlp_get_weights(fr_context *ctx, float *w, int32_t count);
+/* probs[n*5] = softmax output for features x[n*8]. */
+int32_t fr_mlp_forward(fr_context *ctx, const float *x, int32_t n, float *probs);
+/* Mean cross-entropy of (x, labels in [0,5)) and its gradient grad[num_params]
+ * (either output may be NULL). */
+int32_t fr_mlp_loss_grad(fr_context *ctx, const float *x, const int32_t *labels, int32_t n,
+                         float *loss, float *grad);
+/* Minibatch Adam (beta 0.9 / 0.999) on the device; epoch_loss[epochs]
+ * (optional) = mean cross-entropy over all n samples after each epoch. */
+int32_t fr_mlp_train(fr_context *ctx, const float *x, const int32_t *labels, int32_t n,
+                     int32_t epochs, int32_t batch, float lr, uint64_t seed, float *epoch_loss);
+/* Features feats[npairs*8] of block-disjoint pairs: log2(1+|boundary a|),
+ * log2(1+|boundary b|), c(a)/W, c(b)/W, log2(1+pair cut), (L_max-c(a))/W,
+ * (L_max-c(b))/W, log2(1 + U_a(1)/c(boundary a)); W = c(V)/k. */
+int32_t fr_pair_features(fr_context *ctx, const fr_graph *g, const int32_t *part, int32_t k,
+                         const int32_t *pairs, int32_t npairs, int32_t eps_ppm, float *feats);
+
+/* ---- autotuner -----------------------------------------------------------
+ * Runs one batched round of `pairs` (graph and partition on the device; the
+ * partition is not modified) under each candidate tuning, reps timed runs
+ * after one warm-up, checks that all candidates give identical results
+ * (FR_E_DEVICE otherwise), stores the mean solve time per candidate in
+ * ms_out[ncand] (optional) and keeps the fastest as the context's tuning. */
+int32_t fr_autotune(fr_context *ctx, const fr_graph *g, const int32_t *part, int32_t k,
+                    const int32_t *pairs, int32_t npairs, const fr_params *p,
+                    const fr_tuning *candidates, int32_t ncand, int32_t reps, double *ms_out,
+                    int32_t *best);
 
 #ifdef __cplusplus
 }

@@ -58,7 +58,10 @@ class FrTuning(ctypes.Structure):
 
 EXPORTS = ("fr_create", "fr_destroy", "fr_strerror", "flow_refine_pair", "flow_refine_batch",
            "flow_refine_sweep", "fr_quotient_matchings", "fr_set_tuning", "fr_get_tuning",
-           "fr_set_validation", "fr_last_stats")
+           "fr_set_validation", "fr_last_stats", "fr_mlp_num_params", "fr_mlp_init",
+           "fr_mlp_set_weights", "fr_mlp_get_weights", "fr_mlp_forward", "fr_mlp_loss_grad",
+           "fr_mlp_train", "fr_pair_features", "fr_autotune")
+ALPHAS = (1, 2, 4, 8, 16)
 
 
 class FlowRefineError(RuntimeError):
@@ -99,6 +102,25 @@ def load(path: str = LIB_PATH):
     lib.fr_set_validation.argtypes = [vp, i32]
     lib.fr_last_stats.restype = i32
     lib.fr_last_stats.argtypes = [vp, vp, vp]
+    lib.fr_mlp_num_params.restype = i32
+    lib.fr_mlp_num_params.argtypes = []
+    lib.fr_mlp_init.restype = i32
+    lib.fr_mlp_init.argtypes = [vp, ctypes.c_uint64]
+    lib.fr_mlp_set_weights.restype = i32
+    lib.fr_mlp_set_weights.argtypes = [vp, vp, i32]
+    lib.fr_mlp_get_weights.restype = i32
+    lib.fr_mlp_get_weights.argtypes = [vp, vp, i32]
+    lib.fr_mlp_forward.restype = i32
+    lib.fr_mlp_forward.argtypes = [vp, vp, i32, vp]
+    lib.fr_mlp_loss_grad.restype = i32
+    lib.fr_mlp_loss_grad.argtypes = [vp, vp, vp, i32, vp, vp]
+    lib.fr_mlp_train.restype = i32
+    lib.fr_mlp_train.argtypes = [vp, vp, vp, i32, i32, i32, ctypes.c_float, ctypes.c_uint64, vp]
+    lib.fr_pair_features.restype = i32
+    lib.fr_pair_features.argtypes = [vp, P(FrGraph), vp, i32, vp, i32, i32, vp]
+    lib.fr_autotune.restype = i32
+    lib.fr_autotune.argtypes = [vp, P(FrGraph), vp, i32, vp, i32, P(FrParams), vp, i32, i32, vp,
+                                P(i32)]
     _lib = lib
     return lib
 
@@ -286,3 +308,98 @@ def flow_refine_sweep(ctx: Context, graph, part, k: int, prm: FrParams, max_swee
                                    stats.ctypes.data)
     _check(rc, "flow_refine_sweep")
     return int(tc.value), stats
+
+
+# ------------------------------------------------------ learned factor ---
+
+def _f32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def fr_mlp_num_params() -> int:
+    return int(load().fr_mlp_num_params())
+
+
+def mlp_unpack(w: np.ndarray) -> dict:
+    """Flat parameter array -> W1, b1, W2, b2, W3, b3 (row-major [in][out])."""
+    w = np.asarray(w, dtype=np.float32)
+    shapes = (("W1", (8, 64)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)),
+              ("W3", (64, 5)), ("b3", (5,)))
+    out, off = {}, 0
+    for k, sh in shapes:
+        cnt = int(np.prod(sh))
+        out[k] = w[off:off + cnt].reshape(sh)
+        off += cnt
+    return out
+
+
+def fr_mlp_init(ctx: Context, seed: int):
+    _check(ctx.lib.fr_mlp_init(ctx.handle, seed), "fr_mlp_init")
+
+
+def fr_mlp_set_weights(ctx: Context, w):
+    w = _f32(w)
+    _check(ctx.lib.fr_mlp_set_weights(ctx.handle, w.ctypes.data, w.size), "fr_mlp_set_weights")
+
+
+def fr_mlp_get_weights(ctx: Context) -> np.ndarray:
+    w = np.zeros(fr_mlp_num_params(), dtype=np.float32)
+    _check(ctx.lib.fr_mlp_get_weights(ctx.handle, w.ctypes.data, w.size), "fr_mlp_get_weights")
+    return w
+
+
+def fr_mlp_forward(ctx: Context, x) -> np.ndarray:
+    x = _f32(x).reshape(-1, 8)
+    p = np.zeros((x.shape[0], 5), dtype=np.float32)
+    _check(ctx.lib.fr_mlp_forward(ctx.handle, x.ctypes.data, x.shape[0], p.ctypes.data),
+           "fr_mlp_forward")
+    return p
+
+
+def fr_mlp_loss_grad(ctx: Context, x, labels):
+    x = _f32(x).reshape(-1, 8)
+    y = _i32(labels)
+    loss = np.zeros(1, dtype=np.float32)
+    g = np.zeros(fr_mlp_num_params(), dtype=np.float32)
+    _check(ctx.lib.fr_mlp_loss_grad(ctx.handle, x.ctypes.data, y.ctypes.data, x.shape[0],
+                                    loss.ctypes.data, g.ctypes.data), "fr_mlp_loss_grad")
+    return float(loss[0]), g
+
+
+def fr_mlp_train(ctx: Context, x, labels, epochs: int, batch: int, lr: float, seed: int):
+    x = _f32(x).reshape(-1, 8)
+    y = _i32(labels)
+    losses = np.zeros(epochs, dtype=np.float32)
+    _check(ctx.lib.fr_mlp_train(ctx.handle, x.ctypes.data, y.ctypes.data, x.shape[0], epochs,
+                                batch, lr, seed, losses.ctypes.data), "fr_mlp_train")
+    return losses
+
+
+def fr_pair_features(ctx: Context, graph, part, k: int, pairs, eps_ppm: int) -> np.ndarray:
+    gs, keep = _graph_arg(graph)
+    pr = _i32(pairs).reshape(-1)
+    npairs = pr.shape[0] // 2
+    f = np.zeros((npairs, 8), dtype=np.float32)
+    _check(ctx.lib.fr_pair_features(ctx.handle, ctypes.byref(gs), _part_arg(part, gs.on_device), k,
+                                    pr.ctypes.data, npairs, eps_ppm, f.ctypes.data),
+           "fr_pair_features")
+    return f
+
+
+def fr_autotune(ctx: Context, graph: DeviceGraph, part, k: int, pairs, prm: FrParams,
+                candidates, reps: int = 2):
+    """Times each candidate tuning (dicts of FrTuning fields); the fastest is
+    kept in the context.  Returns (best index, per-candidate ms)."""
+    gs = graph.struct()
+    pr = _i32(pairs).reshape(-1)
+    cand = (FrTuning * len(candidates))(*[FrTuning(**c) for c in candidates])
+    ms = (ctypes.c_double * len(candidates))()
+    best = i32(-1)
+    _check(ctx.lib.fr_autotune(ctx.handle, ctypes.byref(gs), _part_arg(part, True), k,
+                               pr.ctypes.data, pr.shape[0] // 2, ctypes.byref(prm), cand,
+                               len(candidates), reps, ms, ctypes.byref(best)), "fr_autotune")
+    return int(best.value), list(ms)

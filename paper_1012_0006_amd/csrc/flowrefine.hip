@@ -7,10 +7,12 @@
 
 #include <algorithm>
 #include <numeric>
+#include <random>
 #include <vector>
 
 #include "fr_internal.h"
 #include "fr_kernels.h"
+#include "fr_mlp.h"
 
 #define HIPCHK(x)                        \
   do {                                   \
@@ -23,12 +25,12 @@
 
 static thread_local hipError_t last_hip_error = hipSuccess;
 
-#define FR_MAX_PAIRS 4096
+#define FR_MAX_PAIRS 4096  // pairs of one round (one launch)
 #define FR_MAX_K 8192
 #define FR_MAX_BLOCKS_PER_CU 8
 
 struct DevBufs {
-  int64_t ncap = 0, acap = 0, kcap = 0;
+  int64_t ncap = 0, acap = 0, kcap = 0, pcap = 0;
   // per vertex
   int32_t *mark = nullptr, *vmap = nullptr, *uvert = nullptr, *lg = nullptr, *lo = nullptr,
           *ex = nullptr, *lab = nullptr, *ins = nullptr, *LA = nullptr, *LB = nullptr,
@@ -39,26 +41,35 @@ struct DevBufs {
   int32_t *lh = nullptr, *lr = nullptr, *rc = nullptr, *ga = nullptr, *gw = nullptr;
   // per block
   int32_t *blk2pair = nullptr;
-  int64_t *bstat = nullptr;  // [3k]: weight, vertex count, arc count per block
-  uint8_t *qadj = nullptr;   // k*k
-  // per pair (fixed maximum)
+  int64_t *bstat = nullptr;  // [3k]
+  uint8_t *qadj = nullptr;   // [k*k]
+  // per pair of a call (all rounds of a sweep): grows with pcap
   PairState *ps = nullptr;
+  int32_t *pairs = nullptr, *alpha0 = nullptr, *order = nullptr;
+  // per round (at most FR_MAX_PAIRS pairs)
   fr_solve *trace = nullptr;
-  int32_t *pairs = nullptr, *order = nullptr, *ucnt = nullptr;
-  int64_t *voff = nullptr, *aoff = nullptr, *base = nullptr, *scal = nullptr;
+  int32_t *ucnt = nullptr;
+  int64_t *voff = nullptr, *aoff = nullptr, *fstat = nullptr;
+  float *feats = nullptr, *probs = nullptr;
+  int64_t *base = nullptr, *scal = nullptr;
   Ctl *ctl = nullptr;
+  // learned factor: parameters, Adam moments, gradient
+  float *mlp = nullptr, *mlp_m = nullptr, *mlp_v = nullptr, *mlp_g = nullptr;
 };
 
 struct fr_context {
   int device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t user_stream = nullptr;
+  hipStream_t cs = nullptr;  // the library's own stream (graph capture needs a non-null one)
   int num_cus = 0;
   fr_tuning tune{1024, 2, 4, 200};
   int validate = 1;
+  int mlp_loaded = 0;
   DevBufs d;
   Ctl *h_ctl = nullptr;  // pinned
   int32_t stamp = 2;
   double wall_khz = 100000.0;  // device constant-rate clock
+  int64_t graph_launches = 0;
   // stats of the last call
   double ms[8] = {0};
   int64_t counters[32] = {0};
@@ -130,10 +141,32 @@ static int32_t ensure_capacity(fr_context *c, int64_t n, int64_t narcs, int64_t 
       return FR_E_OOM;
     d.kcap = k;
   }
-  if (c->stamp > (1 << 29)) {  // corridor marks are compared against a growing stamp
-    if (hipMemset(d.mark, 0, sizeof(int32_t) * (size_t)d.ncap) != hipSuccess) return FR_E_DEVICE;
+  return FR_OK;
+}
+
+static int32_t ensure_pairs(fr_context *c, int64_t npairs) {
+  DevBufs &d = c->d;
+  if (npairs <= d.pcap) return FR_OK;
+  const int64_t pc = std::max<int64_t>(npairs, 2 * d.pcap);
+  dfree(d.ps); dfree(d.pairs); dfree(d.alpha0); dfree(d.order);
+  d.ps = nullptr;
+  d.pairs = d.alpha0 = d.order = nullptr;
+  if (dalloc(&d.ps, pc) != hipSuccess || dalloc(&d.pairs, 2 * pc) != hipSuccess ||
+      dalloc(&d.alpha0, pc) != hipSuccess || dalloc(&d.order, pc) != hipSuccess)
+    return FR_E_OOM;
+  d.pcap = pc;
+  return FR_OK;
+}
+
+// Corridor marks are compared against a stamp that grows by 2 per solve;
+// clear them well before int32 wraps.
+static int32_t reserve_stamps(fr_context *c, int64_t count, int32_t *first) {
+  if ((int64_t)c->stamp + 2 * count + 4 > (1 << 30)) {
+    HIPCHK(hipMemsetAsync(c->d.mark, 0, sizeof(int32_t) * (size_t)c->d.ncap, c->cs));
     c->stamp = 2;
   }
+  *first = c->stamp;
+  c->stamp += (int32_t)(2 * count + 2);
   return FR_OK;
 }
 
@@ -162,7 +195,7 @@ extern "C" int32_t fr_create(int32_t device, void *hip_stream, fr_context **out)
   fr_context *c = new (std::nothrow) fr_context();
   if (!c) return FR_E_OOM;
   c->device = device;
-  c->stream = (hipStream_t)hip_stream;
+  c->user_stream = (hipStream_t)hip_stream;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
     delete c;
@@ -173,16 +206,22 @@ extern "C" int32_t fr_create(int32_t device, void *hip_stream, fr_context **out)
   if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, device) == hipSuccess && rate > 0)
     c->wall_khz = rate;
   DevBufs &d = c->d;
-  hipError_t e = hipSuccess;
+  hipError_t e = hipStreamCreateWithFlags(&c->cs, hipStreamNonBlocking);
 #define A_(p, cnt) \
   if (e == hipSuccess) e = dalloc(&d.p, cnt)
-  A_(ps, FR_MAX_PAIRS); A_(trace, (int64_t)FR_MAX_PAIRS * FR_MAX_ITERS); A_(pairs, 2 * FR_MAX_PAIRS);
-  A_(order, FR_MAX_PAIRS); A_(ucnt, FR_MAX_PAIRS); A_(voff, FR_MAX_PAIRS + 1);
-  A_(aoff, FR_MAX_PAIRS + 1); A_(base, FR_MAX_ALPHA + 1); A_(scal, 8); A_(ctl, 1);
+  A_(trace, (int64_t)FR_MAX_PAIRS * FR_MAX_ITERS); A_(ucnt, FR_MAX_PAIRS);
+  A_(voff, FR_MAX_PAIRS + 1); A_(aoff, FR_MAX_PAIRS + 1); A_(fstat, 4 * FR_MAX_PAIRS);
+  A_(feats, MLP_IN * FR_MAX_PAIRS); A_(probs, MLP_OUT * FR_MAX_PAIRS);
+  A_(base, FR_MAX_ALPHA + 1); A_(scal, 8); A_(ctl, 1);
+  A_(mlp, MLP_NPARAMS); A_(mlp_m, MLP_NPARAMS); A_(mlp_v, MLP_NPARAMS); A_(mlp_g, MLP_NPARAMS);
 #undef A_
   if (e == hipSuccess) e = hipHostMalloc((void **)&c->h_ctl, sizeof(Ctl), hipHostMallocDefault);
   for (int i = 0; i < 4 && e == hipSuccess; i++) e = hipEventCreate(&c->ev[i]);
   if (e != hipSuccess) {
+    fr_destroy(c);
+    return FR_E_OOM;
+  }
+  if (ensure_pairs(c, FR_MAX_PAIRS) != FR_OK) {
     fr_destroy(c);
     return FR_E_OOM;
   }
@@ -193,15 +232,17 @@ extern "C" int32_t fr_create(int32_t device, void *hip_stream, fr_context **out)
 extern "C" int32_t fr_destroy(fr_context *c) {
   if (!c) return FR_E_INVALID_ARG;
   (void)hipSetDevice(c->device);
-  (void)hipDeviceSynchronize();
+  if (c->cs) (void)hipStreamSynchronize(c->cs);
   free_vertex_arc(c->d);
   DevBufs &d = c->d;
-  dfree(d.blk2pair); dfree(d.bstat); dfree(d.qadj); dfree(d.ps); dfree(d.trace); dfree(d.pairs);
-  dfree(d.order); dfree(d.ucnt); dfree(d.voff); dfree(d.aoff); dfree(d.base); dfree(d.scal);
-  dfree(d.ctl);
+  void *ptrs[] = {d.blk2pair, d.bstat, d.qadj, d.ps,    d.pairs, d.alpha0, d.order,
+                  d.trace,    d.ucnt,  d.voff, d.aoff,  d.fstat, d.feats,  d.probs,
+                  d.base,     d.scal,  d.ctl,  d.mlp,   d.mlp_m, d.mlp_v,  d.mlp_g};
+  for (void *q : ptrs) dfree(q);
   if (c->h_ctl) (void)hipHostFree(c->h_ctl);
   for (int i = 0; i < 4; i++)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  if (c->cs) (void)hipStreamDestroy(c->cs);
   delete c;
   return FR_OK;
 }
@@ -265,8 +306,8 @@ static solve_fn solve_kernel(int tpb) {
 static int32_t graph_narcs(fr_context *c, const fr_graph *g, int64_t *narcs) {
   int32_t na = 0;
   if (g->on_device) {
-    HIPCHK(hipMemcpyAsync(&na, g->xadj + g->n, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpyAsync(&na, g->xadj + g->n, sizeof(int32_t), hipMemcpyDeviceToHost, c->cs));
+    HIPCHK(hipStreamSynchronize(c->cs));
   } else {
     na = g->xadj[g->n];
   }
@@ -275,47 +316,32 @@ static int32_t graph_narcs(fr_context *c, const fr_graph *g, int64_t *narcs) {
   return FR_OK;
 }
 
-// Shared driver of the pair, batch and sweep entry points.  The graph is on
-// the device (staged by the caller for host graphs); dpart is a device array
-// that receives the result only on success.
-static int32_t run_batch_dev(fr_context *c, const fr_graph *g, int64_t narcs, int32_t *dpart,
-                             int32_t k, const int32_t *pairs, int32_t npairs, const fr_params *p,
-                             const int32_t *alpha_start, fr_result *res, int8_t *side_out,
-                             fr_solve *trace) {
-  hipStream_t st = c->stream;
+// Kernel arguments common to every round of a call: graph, partition,
+// parameters, scratch.  Per-round fields are set by round_args.
+static KArgs call_args(fr_context *c, const fr_graph *g, int32_t *dpart, int32_t k,
+                       const fr_params *p) {
   DevBufs &d = c->d;
-  const int64_t n = g->n;
-  HIPCHK(hipMemcpyAsync(d.partw, dpart, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
-  std::vector<int32_t> b2p((size_t)k, -1);
-  for (int i = 0; i < npairs; i++) b2p[pairs[2 * i]] = b2p[pairs[2 * i + 1]] = i;
-  HIPCHK(hipMemcpyAsync(d.blk2pair, b2p.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(d.pairs, pairs, sizeof(int32_t) * 2 * npairs, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemsetAsync(d.bstat, 0, sizeof(int64_t) * 3 * k, st));
-  memset(c->h_ctl, 0, sizeof(Ctl));
-  HIPCHK(hipMemcpyAsync(d.ctl, c->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
-
   KArgs A;
   memset(&A, 0, sizeof(A));
-  A.n = (int32_t)n;
+  A.n = g->n;
   A.k = k;
   A.xadj = g->xadj;
   A.adjncy = g->adjncy;
   A.adjwgt = g->adjwgt;
   A.vwgt = g->vwgt;
-  A.part = d.partw;
-  A.P = npairs;
-  A.pairs = d.pairs;
-  A.order = d.order;
+  A.part = dpart;
   A.blk2pair = d.blk2pair;
-  A.ps = d.ps;
-  A.trace = d.trace;
+  A.bstat = d.bstat;
+  A.queue = &d.ctl->queue;
   A.base = d.base;
-  A.area_mode = p->area_mode;
-  A.depth = p->depth;
-  A.alpha_max = p->alpha_max;
-  A.adaptive = p->adaptive;
-  A.max_iters = p->max_iters;
-  A.eps_ppm = p->eps_ppm;
+  if (p) {
+    A.area_mode = p->area_mode;
+    A.depth = p->depth;
+    A.alpha_max = p->alpha_max;
+    A.adaptive = p->adaptive;
+    A.max_iters = p->max_iters;
+    A.eps_ppm = p->eps_ppm;
+  }
   A.mark = d.mark;
   A.vmap = d.vmap;
   A.voff = d.voff;
@@ -337,157 +363,149 @@ static int32_t run_batch_dev(fr_context *c, const fr_graph *g, int64_t narcs, in
   A.ctl = d.ctl;
   A.tpv = c->tune.tpv;
   A.relabel_period = c->tune.relabel_period;
-  A.max_sweeps = 4 * (n + 16) + 1000000;
+  A.max_sweeps = 4 * ((int64_t)g->n + 16) + 1000000;
   A.side_out = d.side;
+  return A;
+}
 
+// Per-call constants: input checks, c(V), max c(v), L_max and the area
+// bases floor((1 + alpha eps) c(V) / k) for alpha = 0..alpha_max (exact, in
+// 128-bit arithmetic on the host).  One host synchronisation.
+static int32_t call_constants(fr_context *c, KArgs &A, int64_t narcs, const fr_params *p) {
+  DevBufs &d = c->d;
+  hipStream_t st = c->cs;
+  memset(c->h_ctl, 0, sizeof(Ctl));
+  HIPCHK(hipMemcpyAsync(d.ctl, c->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
   const int sblocks = std::min(4 * c->num_cus, 8192);
-  (void)hipEventRecord(c->ev[0], st);
   if (c->validate) {
     hipLaunchKernelGGL(k_validate, dim3(sblocks), dim3(256), 0, st, A, narcs);
     HIPCHK(hipGetLastError());
   }
-  int64_t *bw = d.bstat, *bcnt = d.bstat + k, *barc = d.bstat + 2 * k;
-  hipLaunchKernelGGL(k_setup, dim3(sblocks), dim3(256), 0, st, A, bw, bcnt, barc);
+  hipLaunchKernelGGL(k_graph_stats, dim3(sblocks), dim3(256), 0, st, A);
   HIPCHK(hipGetLastError());
-  std::vector<int64_t> hb((size_t)3 * k);
-  HIPCHK(hipMemcpyAsync(hb.data(), d.bstat, sizeof(int64_t) * 3 * k, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(c->h_ctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (c->h_ctl->bad_graph) return FR_E_INVALID_GRAPH;
   if (c->h_ctl->bad_part) return FR_E_INVALID_PART;
   const int64_t cV = c->h_ctl->cV, maxc = c->h_ctl->maxc;
-  // L_max = (1+eps) c(V)/k + max c(v) (Sec. 2.1) and the area bases
-  // floor((1 + alpha eps) c(V) / k), exact in 128-bit arithmetic
-  const unsigned __int128 den = (unsigned __int128)1000000 * (unsigned)k;
+  const unsigned __int128 den = (unsigned __int128)1000000 * (unsigned)A.k;
+  // L_max = (1 + eps) c(V) / k + max c(v)  (Sec. 2.1)
   A.lmax = floor_div_u128((unsigned __int128)(1000000 + (int64_t)p->eps_ppm) * (uint64_t)cV, den) +
            maxc;
-  std::vector<int64_t> base((size_t)p->alpha_max + 1, 0);
-  for (int al = 0; al <= p->alpha_max; al++)
+  std::vector<int64_t> base((size_t)std::max(p->alpha_max, 1) + 1, 0);
+  for (size_t al = 0; al < base.size(); al++)
     base[al] = floor_div_u128(
         (unsigned __int128)(1000000 + (int64_t)al * p->eps_ppm) * (uint64_t)cV, den);
   HIPCHK(hipMemcpyAsync(d.base, base.data(), sizeof(int64_t) * base.size(), hipMemcpyHostToDevice,
                         st));
-  // arena slices and the largest-first order of the pairs
-  std::vector<int64_t> voff((size_t)npairs + 1, 0), aoff((size_t)npairs + 1, 0);
-  std::vector<PairState> ps((size_t)npairs);
-  for (int i = 0; i < npairs; i++) {
-    const int32_t a = pairs[2 * i], b = pairs[2 * i + 1];
-    voff[i + 1] = voff[i] + hb[k + a] + hb[k + b];
-    aoff[i + 1] = aoff[i] + hb[2 * k + a] + hb[2 * k + b];
-    PairState &s = ps[i];
-    memset(&s, 0, sizeof(s));
-    s.a = a;
-    s.b = b;
-    int al = alpha_start ? alpha_start[i] : p->alpha;
-    al = std::min(std::max(al, 1), p->alpha_max);
-    s.alpha = s.start_alpha = s.final_alpha = al;
-    s.cA = hb[a];
-    s.cB = hb[b];
-    s.cut = s.cut0 = -1;
+  HIPCHK(hipStreamSynchronize(st));
+  return FR_OK;
+}
+
+// Per-round view: pairs [off, off + P) of the call's pair arrays.
+static KArgs round_args(fr_context *c, const KArgs &base, int64_t off, int32_t P, int32_t stamp0,
+                        bool with_trace) {
+  DevBufs &d = c->d;
+  KArgs A = base;
+  A.P = P;
+  A.pairs = d.pairs + 2 * off;
+  A.alpha0 = d.alpha0 + off;
+  A.order = d.order + off;
+  A.ps = d.ps + off;
+  A.trace = with_trace ? d.trace : nullptr;
+  A.stamp0 = stamp0;
+  return A;
+}
+
+// All kernels of one matching round; device-only work, so a sequence of
+// rounds can be captured into a graph.
+static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t st) {
+  DevBufs &d = c->d;
+  const int sblocks = std::min(4 * c->num_cus, 8192);
+  A.fstat = use_mlp ? d.fstat : nullptr;
+  hipLaunchKernelGGL(k_round_init, dim3(1), dim3(1024), 0, st, A);
+  hipLaunchKernelGGL(k_block_stats, dim3(sblocks), dim3(256), 0, st, A);
+  if (use_mlp) {
+    hipLaunchKernelGGL(k_feature_stats, dim3(sblocks), dim3(256), 0, st, A, d.fstat);
+    hipLaunchKernelGGL(k_features, dim3((A.P + 255) / 256), dim3(256), 0, st, A,
+                       (const int64_t *)d.fstat, d.feats);
+    hipLaunchKernelGGL(k_mlp_forward,
+                       dim3((A.P + MLP_SAMPLES_PER_BLOCK - 1) / MLP_SAMPLES_PER_BLOCK), dim3(1024),
+                       0, st, (const float *)d.mlp, (const float *)d.feats, A.P, d.probs,
+                       (float *)nullptr);
+    hipLaunchKernelGGL(k_alpha_from_probs, dim3((A.P + 255) / 256), dim3(256), 0, st,
+                       (const float *)d.probs, A.P, A.alpha0);
   }
-  std::vector<int32_t> order((size_t)npairs);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-    return aoff[x + 1] - aoff[x] > aoff[y + 1] - aoff[y];
-  });
-  HIPCHK(hipMemcpyAsync(d.voff, voff.data(), sizeof(int64_t) * (npairs + 1), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(d.aoff, aoff.data(), sizeof(int64_t) * (npairs + 1), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(d.order, order.data(), sizeof(int32_t) * npairs, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(d.ps, ps.data(), sizeof(PairState) * npairs, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemsetAsync(d.ucnt, 0, sizeof(int32_t) * npairs, st));
+  hipLaunchKernelGGL(k_arena, dim3(1), dim3(1024), 0, st, A);
   hipLaunchKernelGGL(k_union, dim3(sblocks), dim3(256), 0, st, A);
-  HIPCHK(hipGetLastError());
-  A.stamp0 = c->stamp;
-  c->stamp += 2 * p->max_iters + 2;
   const int tpb = c->tune.block_threads;
   const int64_t slots = (int64_t)c->num_cus * c->tune.blocks_per_cu;
-  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(npairs, slots));
-  (void)hipEventRecord(c->ev[1], st);
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(A.P, slots));
   hipLaunchKernelGGL(solve_kernel(tpb), dim3(blocks), dim3(tpb), 0, st, A);
   HIPCHK(hipGetLastError());
-  (void)hipEventRecord(c->ev[2], st);
-  HIPCHK(hipMemcpyAsync(c->h_ctl, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  if (c->h_ctl->err) {
-    c->counters[6] = c->h_ctl->diag;
-    if (verbose())
-      fprintf(stderr, "flowrefine: device error %d (check %d)\n", c->h_ctl->err, c->h_ctl->diag);
-    return c->h_ctl->err;
-  }
-  if (side_out) {
-    hipLaunchKernelGGL(k_side_fill, dim3(sblocks), dim3(256), 0, st, A);
-    hipLaunchKernelGGL(k_side_scatter, dim3(sblocks), dim3(256), 0, st, A);
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(side_out, d.side, n, hipMemcpyDeviceToHost, st));
-  }
-  HIPCHK(hipMemcpyAsync(ps.data(), d.ps, sizeof(PairState) * npairs, hipMemcpyDeviceToHost, st));
-  std::vector<fr_solve> tr;
-  if (trace) {
-    tr.resize((size_t)npairs * p->max_iters);
-    HIPCHK(hipMemcpyAsync(tr.data(), d.trace, sizeof(fr_solve) * tr.size(), hipMemcpyDeviceToHost,
-                          st));
-  }
-  HIPCHK(hipMemcpyAsync(dpart, d.partw, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
-  (void)hipEventRecord(c->ev[3], st);
-  HIPCHK(hipStreamSynchronize(st));
-  float t01 = 0.f, t12 = 0.f, t03 = 0.f;
-  (void)hipEventElapsedTime(&t01, c->ev[0], c->ev[1]);
-  (void)hipEventElapsedTime(&t12, c->ev[1], c->ev[2]);
-  (void)hipEventElapsedTime(&t03, c->ev[0], c->ev[3]);
-  c->ms[0] = t01;  // validation, setup, arena
-  c->ms[1] = t12;  // the batched solve kernel
-  c->ms[4] = t03;  // whole call on the device
+  c->counters[5] = blocks;
+  return FR_OK;
+}
+
+static void fill_result(const PairState &s, fr_result &r) {
+  memset(&r, 0, sizeof(r));
+  r.iters = s.iters;
+  r.final_alpha = s.final_alpha;
+  r.start_alpha = s.start_alpha;
+  r.applied = s.applied;
+  r.iter_cap = s.iter_cap;
+  r.flow_value = s.flow_last;
+  r.cut_before = s.cut0;
+  r.cut_after = s.cut;
+  r.weight_a = s.cA;
+  r.weight_b = s.cB;
+  r.region_vertices = s.rv_sum;
+  r.region_edges = s.re_sum;
+  if (s.applied > 0) r.status = FR_ACCEPTED;
+  else if (s.last_dec == FR_DEC_NOT_ADJACENT) r.status = FR_NOT_ADJACENT;
+  else if (s.last_dec == FR_DEC_INFEASIBLE) r.status = FR_REJECTED_IMBALANCE;
+  else r.status = FR_NO_IMPROVEMENT;
+}
+
+static void collect_stats(fr_context *c, const std::vector<PairState> &ps) {
   int64_t sw = 0, rl = 0, bl = 0, gl = 0, cl = 0, wk[W_COUNT] = {0};
-  double ph_c = 0, ph_b = 0, ph_r = 0, ph_p = 0, ph_f = 0;
-  for (int i = 0; i < npairs; i++) {
-    const PairState &s = ps[i];
+  double ph[5] = {0, 0, 0, 0, 0};
+  for (const PairState &s : ps) {
     sw += s.sweeps;
     rl += s.relabels;
     bl += s.bfs_levels;
     gl += s.gr_levels;
     cl += s.cl_levels;
     for (int j = 0; j < W_COUNT; j++) wk[j] += s.work[j];
-    ph_c += s.t_corridor;
-    ph_b += s.t_build;
-    ph_r += s.t_relabel;
-    ph_p += s.t_push;
-    ph_f += s.t_closure + s.t_finish;
-    fr_result &r = res[i];
-    memset(&r, 0, sizeof(r));
-    r.iters = s.iters;
-    r.final_alpha = s.final_alpha;
-    r.start_alpha = s.start_alpha;
-    r.applied = s.applied;
-    r.iter_cap = s.iter_cap;
-    r.flow_value = s.flow_last;
-    r.cut_before = s.cut0;
-    r.cut_after = s.cut;
-    r.weight_a = s.cA;
-    r.weight_b = s.cB;
-    r.region_vertices = s.rv_sum;
-    r.region_edges = s.re_sum;
-    if (s.applied > 0) r.status = FR_ACCEPTED;
-    else if (s.last_dec == FR_DEC_NOT_ADJACENT) r.status = FR_NOT_ADJACENT;
-    else if (s.last_dec == FR_DEC_INFEASIBLE) r.status = FR_REJECTED_IMBALANCE;
-    else r.status = FR_NO_IMPROVEMENT;
-    if (trace)
-      for (int j = 0; j < s.iters; j++)
-        trace[(size_t)i * p->max_iters + j] = tr[(size_t)i * p->max_iters + j];
+    ph[0] += s.t_corridor;
+    ph[1] += s.t_build;
+    ph[2] += s.t_relabel;
+    ph[3] += s.t_push;
+    ph[4] += s.t_closure + s.t_finish;
   }
   c->counters[0] = sw;
   c->counters[1] = rl;
   c->counters[2] = bl;
   c->counters[3] = gl;
   c->counters[4] = cl;
-  c->counters[5] = blocks;
   c->counters[6] = 0;
   for (int j = 0; j < W_COUNT; j++) c->counters[16 + j] = wk[j];
-  // per-phase device time summed over the pairs' workgroups
-  c->ms[2] = ph_c / c->wall_khz;
-  c->ms[3] = ph_b / c->wall_khz;
-  c->ms[5] = ph_r / c->wall_khz;
-  c->ms[6] = ph_p / c->wall_khz;
-  c->ms[7] = ph_f / c->wall_khz;
+  c->ms[2] = ph[0] / c->wall_khz;
+  c->ms[3] = ph[1] / c->wall_khz;
+  c->ms[5] = ph[2] / c->wall_khz;
+  c->ms[6] = ph[3] / c->wall_khz;
+  c->ms[7] = ph[4] / c->wall_khz;
+}
+
+static int32_t device_error(fr_context *c) {
+  HIPCHK(hipMemcpyAsync(c->h_ctl, c->d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->cs));
+  HIPCHK(hipStreamSynchronize(c->cs));
+  if (c->h_ctl->err) {
+    c->counters[6] = c->h_ctl->diag;
+    if (verbose())
+      fprintf(stderr, "flowrefine: device error %d (check %d)\n", c->h_ctl->err, c->h_ctl->diag);
+    return c->h_ctl->err;
+  }
   return FR_OK;
 }
 
@@ -504,7 +522,7 @@ static int32_t stage(fr_context *c, const fr_graph *g, int32_t *part, int32_t k,
   if (rc) return rc;
   if ((rc = ensure_capacity(c, g->n, narcs, k))) return rc;
   DevBufs &d = c->d;
-  hipStream_t st = c->stream;
+  hipStream_t st = c->cs;
   s->g = *g;
   s->narcs = narcs;
   s->dpart = part;
@@ -525,11 +543,12 @@ static int32_t stage(fr_context *c, const fr_graph *g, int32_t *part, int32_t k,
   return FR_OK;
 }
 
-static int32_t unstage(fr_context *c, const fr_graph *g, int32_t *part, const Staged &s) {
-  if (!g->on_device) {
-    HIPCHK(hipMemcpyAsync(part, s.dpart, sizeof(int32_t) * g->n, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-  }
+// Make the library stream wait for the caller's stream (inputs it produced).
+static int32_t enter(fr_context *c) {
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipEventRecord(c->ev[3], c->user_stream));
+  HIPCHK(hipStreamWaitEvent(c->cs, c->ev[3], 0));
+  c->counters[6] = 0;
   return FR_OK;
 }
 
@@ -551,35 +570,80 @@ static int32_t check_batch_args(const fr_context *c, const fr_graph *g, const in
   return FR_OK;
 }
 
+// The pair and batch entry points: one round of disjoint pairs.
 static int32_t refine(fr_context *c, const fr_graph *g, int32_t *part, int32_t k,
-                      const int32_t *pairs, int32_t npairs, const fr_params *p,
-                      const int32_t *alpha_start, fr_result *res, int8_t *side_out,
-                      fr_solve *trace) {
+                      const int32_t *pairs, int32_t npairs, const fr_params *p, fr_result *res,
+                      int8_t *side_out, fr_solve *trace) {
   int32_t rc = check_batch_args(c, g, part, k, pairs, npairs, p);
   if (rc) return rc;
   if (!res) return FR_E_INVALID_ARG;
-  HIPCHK(hipSetDevice(c->device));
+  if (p->use_mlp && !c->mlp_loaded) return FR_E_INVALID_ARG;
+  if ((rc = enter(c))) return rc;
   Staged s;
   if ((rc = stage(c, g, part, k, &s))) return rc;
-  rc = run_batch_dev(c, &s.g, s.narcs, s.dpart, k, pairs, npairs, p, alpha_start, res, side_out,
-                     trace);
-  if (rc) return rc;
-  return unstage(c, g, part, s);
+  DevBufs &d = c->d;
+  hipStream_t st = c->cs;
+  const int64_t n = g->n;
+  (void)hipEventRecord(c->ev[0], st);
+  HIPCHK(hipMemcpyAsync(d.partw, s.dpart, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
+  KArgs A = call_args(c, &s.g, d.partw, k, p);
+  if ((rc = call_constants(c, A, s.narcs, p))) return rc;
+  std::vector<int32_t> a0((size_t)npairs, p->alpha);
+  HIPCHK(hipMemcpyAsync(d.pairs, pairs, sizeof(int32_t) * 2 * npairs, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d.alpha0, a0.data(), sizeof(int32_t) * npairs, hipMemcpyHostToDevice, st));
+  int32_t stamp0 = 0;
+  if ((rc = reserve_stamps(c, p->max_iters, &stamp0))) return rc;
+  const KArgs R = round_args(c, A, 0, npairs, stamp0, true);
+  (void)hipEventRecord(c->ev[1], st);
+  if ((rc = enqueue_round(c, R, p->use_mlp != 0, st))) return rc;
+  (void)hipEventRecord(c->ev[2], st);
+  if ((rc = device_error(c))) return rc;
+  if (side_out) {
+    const int sblocks = std::min(4 * c->num_cus, 8192);
+    hipLaunchKernelGGL(k_side_fill, dim3(sblocks), dim3(256), 0, st, R);
+    hipLaunchKernelGGL(k_side_scatter, dim3(sblocks), dim3(256), 0, st, R);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(side_out, d.side, n, hipMemcpyDeviceToHost, st));
+  }
+  std::vector<PairState> ps((size_t)npairs);
+  HIPCHK(hipMemcpyAsync(ps.data(), d.ps, sizeof(PairState) * npairs, hipMemcpyDeviceToHost, st));
+  std::vector<fr_solve> tr;
+  if (trace) {
+    tr.resize((size_t)npairs * p->max_iters);
+    HIPCHK(hipMemcpyAsync(tr.data(), d.trace, sizeof(fr_solve) * tr.size(), hipMemcpyDeviceToHost, st));
+  }
+  HIPCHK(hipMemcpyAsync(part, d.partw, sizeof(int32_t) * n,
+                        g->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+  (void)hipEventRecord(c->ev[3], st);
+  HIPCHK(hipStreamSynchronize(st));
+  float t01 = 0.f, t12 = 0.f, t03 = 0.f;
+  (void)hipEventElapsedTime(&t01, c->ev[0], c->ev[1]);
+  (void)hipEventElapsedTime(&t12, c->ev[1], c->ev[2]);
+  (void)hipEventElapsedTime(&t03, c->ev[0], c->ev[3]);
+  c->ms[0] = t01;  // validation, graph constants
+  c->ms[1] = t12;  // the round: setup kernels and the solve kernel
+  c->ms[4] = t03;  // whole call on the device
+  collect_stats(c, ps);
+  for (int i = 0; i < npairs; i++) {
+    fill_result(ps[i], res[i]);
+    if (trace)
+      for (int j = 0; j < ps[i].iters; j++)
+        trace[(size_t)i * p->max_iters + j] = tr[(size_t)i * p->max_iters + j];
+  }
+  return FR_OK;
 }
 
 extern "C" int32_t flow_refine_pair(fr_context *c, const fr_graph *g, int32_t *part, int32_t k,
                                     int32_t a, int32_t b, const fr_params *p, fr_result *res,
                                     int8_t *side_out, fr_solve *trace) {
   const int32_t pr[2] = {a, b};
-  if (p && p->use_mlp) return FR_E_INVALID_ARG;
-  return refine(c, g, part, k, pr, 1, p, nullptr, res, side_out, trace);
+  return refine(c, g, part, k, pr, 1, p, res, side_out, trace);
 }
 
 extern "C" int32_t flow_refine_batch(fr_context *c, const fr_graph *g, int32_t *part, int32_t k,
                                      const int32_t *pairs, int32_t npairs, const fr_params *p,
                                      fr_result *res, fr_solve *trace) {
-  if (p && p->use_mlp) return FR_E_INVALID_ARG;  // no area-factor network loaded
-  return refine(c, g, part, k, pairs, npairs, p, nullptr, res, nullptr, trace);
+  return refine(c, g, part, k, pairs, npairs, p, res, nullptr, trace);
 }
 
 // ---------------------------------------------------------------------------
@@ -591,7 +655,7 @@ extern "C" int32_t flow_refine_batch(fr_context *c, const fr_graph *g, int32_t *
 static int32_t quotient_dev(fr_context *c, const fr_graph *g, const int32_t *dpart, int32_t k,
                             std::vector<int32_t> &edges, std::vector<int32_t> &colour) {
   DevBufs &d = c->d;
-  hipStream_t st = c->stream;
+  hipStream_t st = c->cs;
   KArgs A;
   memset(&A, 0, sizeof(A));
   A.n = g->n;
@@ -632,10 +696,10 @@ extern "C" int32_t fr_quotient_matchings(fr_context *c, const fr_graph *g, const
                                          int32_t max_edges, int32_t *nedges) {
   if (!c || !g || !part || !edges || !colour || !nedges || k < 1 || k > FR_MAX_K || g->n < 1)
     return FR_E_INVALID_ARG;
-  HIPCHK(hipSetDevice(c->device));
-  Staged s;
-  int32_t rc = stage(c, g, const_cast<int32_t *>(part), k, &s);
+  int32_t rc = enter(c);
   if (rc) return rc;
+  Staged s;
+  if ((rc = stage(c, g, const_cast<int32_t *>(part), k, &s))) return rc;
   std::vector<int32_t> e, col;
   if ((rc = quotient_dev(c, &s.g, s.dpart, k, e, col))) return rc;
   *nedges = (int32_t)col.size();
@@ -645,6 +709,8 @@ extern "C" int32_t fr_quotient_matchings(fr_context *c, const fr_graph *g, const
   return FR_OK;
 }
 
+// One sweep = every colour class of the quotient graph, class after class;
+// the rounds are recorded once into a hipGraph and launched as one graph.
 extern "C" int32_t flow_refine_sweep(fr_context *c, const fr_graph *g, int32_t *part, int32_t k,
                                      const fr_params *p, int32_t max_sweeps,
                                      int64_t *total_cut_out, int64_t *stats) {
@@ -652,59 +718,92 @@ extern "C" int32_t flow_refine_sweep(fr_context *c, const fr_graph *g, int32_t *
     return FR_E_INVALID_ARG;
   int32_t rc = check_params(p);
   if (rc) return rc;
-  if (p->use_mlp) return FR_E_INVALID_ARG;
-  HIPCHK(hipSetDevice(c->device));
+  if (p->use_mlp && !c->mlp_loaded) return FR_E_INVALID_ARG;
+  if ((rc = enter(c))) return rc;
   Staged s;
   if ((rc = stage(c, g, part, k, &s))) return rc;
   DevBufs &d = c->d;
-  hipStream_t st = c->stream;
+  hipStream_t st = c->cs;
   // the caller's partition changes only on success: work on a copy
-  int32_t *work = d.parts;
-  if (g->on_device)
-    HIPCHK(hipMemcpyAsync(work, part, sizeof(int32_t) * g->n, hipMemcpyDeviceToDevice, st));
+  int32_t *work = d.partw;
+  HIPCHK(hipMemcpyAsync(work, s.dpart, sizeof(int32_t) * g->n, hipMemcpyDeviceToDevice, st));
+  KArgs A = call_args(c, &s.g, work, k, p);
+  if ((rc = call_constants(c, A, s.narcs, p))) return rc;
   int64_t acc[4] = {0, 0, 0, 0};
-  std::vector<int32_t> e, col, pairs;
-  std::vector<fr_result> res;
+  std::vector<int32_t> e, col, pairs, offs;
+  std::vector<PairState> ps;
   for (int32_t sw = 0; sw < max_sweeps; sw++) {
     if ((rc = quotient_dev(c, &s.g, work, k, e, col))) return rc;
     int32_t ncol = 0;
     for (int32_t x : col) ncol = std::max(ncol, x + 1);
-    int64_t changed = 0;
+    // pairs of all rounds, class by class, at most FR_MAX_PAIRS per round
+    pairs.clear();
+    offs.assign(1, 0);
     for (int32_t cc = 0; cc < ncol; cc++) {
-      pairs.clear();
+      int32_t in_round = 0;
       for (size_t i = 0; i < col.size(); i++)
         if (col[i] == cc) {
           pairs.push_back(e[2 * i]);
           pairs.push_back(e[2 * i + 1]);
+          if (++in_round == FR_MAX_PAIRS) {
+            offs.push_back((int32_t)(pairs.size() / 2));
+            in_round = 0;
+          }
         }
-      const int32_t np = (int32_t)(pairs.size() / 2);
-      res.assign((size_t)np, fr_result{});
-      for (int32_t off = 0; off < np; off += FR_MAX_PAIRS) {
-        const int32_t cnt = std::min(FR_MAX_PAIRS, np - off);
-        rc = run_batch_dev(c, &s.g, s.narcs, work, k, pairs.data() + 2 * off, cnt, p, nullptr,
-                           res.data() + off, nullptr, nullptr);
-        if (rc) return rc;
-      }
-      for (const fr_result &r : res) {
-        acc[1] += r.iters;
-        acc[3] += r.region_edges;
-        if (r.applied) changed++;
-      }
+      if (in_round) offs.push_back((int32_t)(pairs.size() / 2));
+    }
+    const int64_t total = (int64_t)pairs.size() / 2;
+    if (total == 0) break;
+    if ((rc = ensure_pairs(c, total))) return rc;
+    std::vector<int32_t> a0((size_t)total, p->alpha);
+    HIPCHK(hipMemcpyAsync(d.pairs, pairs.data(), sizeof(int32_t) * pairs.size(),
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.alpha0, a0.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice, st));
+    const int32_t nrounds = (int32_t)offs.size() - 1;
+    int32_t stamp0 = 0;
+    if ((rc = reserve_stamps(c, (int64_t)nrounds * (p->max_iters + 1), &stamp0))) return rc;
+    HIPCHK(hipStreamSynchronize(st));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    int32_t cap_rc = FR_OK;
+    for (int32_t r = 0; r < nrounds && cap_rc == FR_OK; r++) {
+      const KArgs R = round_args(c, A, offs[r], offs[r + 1] - offs[r],
+                                 stamp0 + r * (2 * p->max_iters + 2), false);
+      cap_rc = enqueue_round(c, R, p->use_mlp != 0, st);
+    }
+    hipError_t ce = hipStreamEndCapture(st, &graph);
+    if (cap_rc != FR_OK || ce != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return cap_rc != FR_OK ? cap_rc : FR_E_DEVICE;
+    }
+    ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ce == hipSuccess) ce = hipGraphLaunch(exec, st);
+    if (ce == hipSuccess) ce = hipStreamSynchronize(st);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    if (ce != hipSuccess) {
+      last_hip_error = ce;
+      return FR_E_DEVICE;
+    }
+    c->graph_launches++;
+    if ((rc = device_error(c))) return rc;
+    ps.resize((size_t)total);
+    HIPCHK(hipMemcpyAsync(ps.data(), d.ps, sizeof(PairState) * total, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int64_t changed = 0;
+    for (const PairState &q : ps) {
+      acc[1] += q.iters;
+      acc[3] += q.re_sum;
+      if (q.applied) changed++;
     }
     acc[0]++;
     acc[2] += changed;
     if (changed == 0) break;
   }
-  KArgs A;
-  memset(&A, 0, sizeof(A));
-  A.n = g->n;
-  A.k = k;
-  A.xadj = s.g.xadj;
-  A.adjncy = s.g.adjncy;
-  A.adjwgt = s.g.adjwgt;
-  A.part = work;
+  KArgs T = A;
   HIPCHK(hipMemsetAsync(d.scal, 0, sizeof(int64_t), st));
-  hipLaunchKernelGGL(k_total_cut, dim3(std::min(4 * c->num_cus, 8192)), dim3(256), 0, st, A, d.scal);
+  hipLaunchKernelGGL(k_total_cut, dim3(std::min(4 * c->num_cus, 8192)), dim3(256), 0, st, T, d.scal);
   HIPCHK(hipGetLastError());
   int64_t tc = 0;
   HIPCHK(hipMemcpyAsync(&tc, d.scal, sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -713,5 +812,242 @@ extern "C" int32_t flow_refine_sweep(fr_context *c, const fr_graph *g, int32_t *
   HIPCHK(hipStreamSynchronize(st));
   if (total_cut_out) *total_cut_out = tc;
   if (stats) memcpy(stats, acc, sizeof(acc));
+  return FR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// learned area factor
+
+extern "C" int32_t fr_mlp_num_params(void) { return MLP_NPARAMS; }
+
+extern "C" int32_t fr_mlp_set_weights(fr_context *c, const float *w, int32_t count) {
+  if (!c || !w || count != MLP_NPARAMS) return FR_E_INVALID_ARG;
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipMemcpyAsync(c->d.mlp, w, sizeof(float) * MLP_NPARAMS, hipMemcpyHostToDevice, c->cs));
+  HIPCHK(hipMemsetAsync(c->d.mlp_m, 0, sizeof(float) * MLP_NPARAMS, c->cs));
+  HIPCHK(hipMemsetAsync(c->d.mlp_v, 0, sizeof(float) * MLP_NPARAMS, c->cs));
+  HIPCHK(hipStreamSynchronize(c->cs));
+  c->mlp_loaded = 1;
+  return FR_OK;
+}
+
+extern "C" int32_t fr_mlp_get_weights(fr_context *c, float *w, int32_t count) {
+  if (!c || !w || count != MLP_NPARAMS || !c->mlp_loaded) return FR_E_INVALID_ARG;
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipMemcpyAsync(w, c->d.mlp, sizeof(float) * MLP_NPARAMS, hipMemcpyDeviceToHost, c->cs));
+  HIPCHK(hipStreamSynchronize(c->cs));
+  return FR_OK;
+}
+
+// He-normal weights, zero biases (host RNG, seeded).
+extern "C" int32_t fr_mlp_init(fr_context *c, uint64_t seed) {
+  if (!c) return FR_E_INVALID_ARG;
+  std::vector<float> w(MLP_NPARAMS, 0.f);
+  std::mt19937_64 rng(seed);
+  auto fill = [&](int off, int fan_in, int count) {
+    std::normal_distribution<float> nd(0.f, sqrtf(2.f / (float)fan_in));
+    for (int i = 0; i < count; i++) w[off + i] = nd(rng);
+  };
+  fill(MLP_W1, MLP_IN, MLP_IN * MLP_H);
+  fill(MLP_W2, MLP_H, MLP_H * MLP_H);
+  fill(MLP_W3, MLP_H, MLP_H * MLP_OUT);
+  return fr_mlp_set_weights(c, w.data(), MLP_NPARAMS);
+}
+
+// Scratch for n samples: x, labels, probs, activations (4*64), backward (5+2*64).
+struct MlpScratch {
+  float *x = nullptr, *probs = nullptr, *act = nullptr, *dact = nullptr, *loss = nullptr;
+  int32_t *labels = nullptr, *idx = nullptr;
+  float *xb = nullptr;
+  int32_t *lb = nullptr;
+  ~MlpScratch() {
+    dfree(x); dfree(probs); dfree(act); dfree(dact); dfree(loss); dfree(labels); dfree(idx);
+    dfree(xb); dfree(lb);
+  }
+};
+
+static int32_t mlp_alloc(MlpScratch &s, int64_t n, int64_t batch) {
+  const int64_t m = std::max(n, batch);
+  if (dalloc(&s.x, n * MLP_IN) || dalloc(&s.probs, m * MLP_OUT) || dalloc(&s.act, m * 4 * MLP_H) ||
+      dalloc(&s.dact, m * (MLP_OUT + 2 * MLP_H)) || dalloc(&s.loss, 1) || dalloc(&s.labels, n) ||
+      dalloc(&s.idx, std::max<int64_t>(batch, 1)) || dalloc(&s.xb, batch * MLP_IN) ||
+      dalloc(&s.lb, std::max<int64_t>(batch, 1)))
+    return FR_E_OOM;
+  return FR_OK;
+}
+
+static int32_t mlp_fwd_bwd(fr_context *c, const float *x, const int32_t *labels, int32_t n,
+                           MlpScratch &s, bool backward) {
+  hipStream_t st = c->cs;
+  const int fb = (n + MLP_SAMPLES_PER_BLOCK - 1) / MLP_SAMPLES_PER_BLOCK;
+  hipLaunchKernelGGL(k_mlp_forward, dim3(fb), dim3(1024), 0, st, (const float *)c->d.mlp, x, n,
+                     s.probs, s.act);
+  if (backward) {
+    hipLaunchKernelGGL(k_mlp_backward, dim3(fb), dim3(1024), 0, st, (const float *)c->d.mlp,
+                       (const float *)s.probs, labels, n, (const float *)s.act, s.dact);
+    hipLaunchKernelGGL(k_mlp_grad, dim3((MLP_NPARAMS + 255) / 256), dim3(256), 0, st, x,
+                       (const float *)s.act, (const float *)s.dact, n, c->d.mlp_g);
+  }
+  HIPCHK(hipGetLastError());
+  return FR_OK;
+}
+
+extern "C" int32_t fr_mlp_forward(fr_context *c, const float *x, int32_t n, float *probs) {
+  if (!c || !x || !probs || n < 1 || !c->mlp_loaded) return FR_E_INVALID_ARG;
+  HIPCHK(hipSetDevice(c->device));
+  MlpScratch s;
+  int32_t rc = mlp_alloc(s, n, 1);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(s.x, x, sizeof(float) * MLP_IN * n, hipMemcpyHostToDevice, c->cs));
+  if ((rc = mlp_fwd_bwd(c, s.x, nullptr, n, s, false))) return rc;
+  HIPCHK(hipMemcpyAsync(probs, s.probs, sizeof(float) * MLP_OUT * n, hipMemcpyDeviceToHost, c->cs));
+  HIPCHK(hipStreamSynchronize(c->cs));
+  return FR_OK;
+}
+
+extern "C" int32_t fr_mlp_loss_grad(fr_context *c, const float *x, const int32_t *labels, int32_t n,
+                                    float *loss, float *grad) {
+  if (!c || !x || !labels || n < 1 || !c->mlp_loaded) return FR_E_INVALID_ARG;
+  for (int32_t i = 0; i < n; i++)
+    if (labels[i] < 0 || labels[i] >= MLP_OUT) return FR_E_INVALID_ARG;
+  HIPCHK(hipSetDevice(c->device));
+  MlpScratch s;
+  int32_t rc = mlp_alloc(s, n, 1);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(s.x, x, sizeof(float) * MLP_IN * n, hipMemcpyHostToDevice, c->cs));
+  HIPCHK(hipMemcpyAsync(s.labels, labels, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->cs));
+  if ((rc = mlp_fwd_bwd(c, s.x, s.labels, n, s, true))) return rc;
+  hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(256), 0, c->cs, (const float *)s.probs,
+                     (const int32_t *)s.labels, n, s.loss);
+  if (loss) HIPCHK(hipMemcpyAsync(loss, s.loss, sizeof(float), hipMemcpyDeviceToHost, c->cs));
+  if (grad)
+    HIPCHK(hipMemcpyAsync(grad, c->d.mlp_g, sizeof(float) * MLP_NPARAMS, hipMemcpyDeviceToHost, c->cs));
+  HIPCHK(hipStreamSynchronize(c->cs));
+  return FR_OK;
+}
+
+// Minibatch Adam on the device; epoch_loss (optional, [epochs]) gets the mean
+// cross-entropy over all samples after each epoch.
+extern "C" int32_t fr_mlp_train(fr_context *c, const float *x, const int32_t *labels, int32_t n,
+                                int32_t epochs, int32_t batch, float lr, uint64_t seed,
+                                float *epoch_loss) {
+  if (!c || !x || !labels || n < 1 || epochs < 1 || batch < 1 || !(lr > 0.f) || !c->mlp_loaded)
+    return FR_E_INVALID_ARG;
+  for (int32_t i = 0; i < n; i++)
+    if (labels[i] < 0 || labels[i] >= MLP_OUT) return FR_E_INVALID_ARG;
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t st = c->cs;
+  batch = std::min(batch, n);
+  MlpScratch s;
+  int32_t rc = mlp_alloc(s, n, batch);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(s.x, x, sizeof(float) * MLP_IN * n, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(s.labels, labels, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+  std::vector<int32_t> perm((size_t)n);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::mt19937_64 rng(seed);
+  int32_t t = 0;
+  for (int32_t ep = 0; ep < epochs; ep++) {
+    std::shuffle(perm.begin(), perm.end(), rng);
+    for (int32_t b0 = 0; b0 + batch <= n; b0 += batch) {
+      HIPCHK(hipMemcpyAsync(s.idx, perm.data() + b0, sizeof(int32_t) * batch, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_gather_rows, dim3((batch * MLP_IN + 255) / 256), dim3(256), 0, st,
+                         (const float *)s.x, (const int32_t *)s.labels, (const int32_t *)s.idx,
+                         batch, s.xb, s.lb);
+      if ((rc = mlp_fwd_bwd(c, s.xb, s.lb, batch, s, true))) return rc;
+      hipLaunchKernelGGL(k_adam, dim3((MLP_NPARAMS + 255) / 256), dim3(256), 0, st, c->d.mlp,
+                         (const float *)c->d.mlp_g, c->d.mlp_m, c->d.mlp_v, lr, 0.9f, 0.999f, 1e-8f,
+                         ++t);
+      HIPCHK(hipStreamSynchronize(st));  // the host batch indices are reused
+    }
+    if (epoch_loss) {
+      if ((rc = mlp_fwd_bwd(c, s.x, s.labels, n, s, false))) return rc;
+      hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(256), 0, st, (const float *)s.probs,
+                         (const int32_t *)s.labels, n, s.loss);
+      HIPCHK(hipMemcpyAsync(&epoch_loss[ep], s.loss, sizeof(float), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
+  }
+  return FR_OK;
+}
+
+// The 8 input features of each pair (host [npairs * 8]).
+extern "C" int32_t fr_pair_features(fr_context *c, const fr_graph *g, const int32_t *part,
+                                    int32_t k, const int32_t *pairs, int32_t npairs,
+                                    int32_t eps_ppm, float *feats) {
+  fr_params p{FR_AREA_FACTOR, 0, 1, 1, 0, 1, eps_ppm, 0};
+  int32_t rc = check_batch_args(c, g, part, k, pairs, npairs, &p);
+  if (rc) return rc;
+  if (!feats) return FR_E_INVALID_ARG;
+  if ((rc = enter(c))) return rc;
+  Staged s;
+  if ((rc = stage(c, g, const_cast<int32_t *>(part), k, &s))) return rc;
+  DevBufs &d = c->d;
+  hipStream_t st = c->cs;
+  KArgs A = call_args(c, &s.g, s.dpart, k, &p);
+  if ((rc = call_constants(c, A, s.narcs, &p))) return rc;
+  HIPCHK(hipMemcpyAsync(d.pairs, pairs, sizeof(int32_t) * 2 * npairs, hipMemcpyHostToDevice, st));
+  KArgs R = round_args(c, A, 0, npairs, 0, false);
+  R.fstat = d.fstat;
+  const int sblocks = std::min(4 * c->num_cus, 8192);
+  hipLaunchKernelGGL(k_round_init, dim3(1), dim3(1024), 0, st, R);
+  hipLaunchKernelGGL(k_block_stats, dim3(sblocks), dim3(256), 0, st, R);
+  hipLaunchKernelGGL(k_feature_stats, dim3(sblocks), dim3(256), 0, st, R, d.fstat);
+  hipLaunchKernelGGL(k_features, dim3((npairs + 255) / 256), dim3(256), 0, st, R,
+                     (const int64_t *)d.fstat, d.feats);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(feats, d.feats, sizeof(float) * MLP_IN * npairs, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return FR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: times each candidate tuning on the same round (all must give
+// identical results) and keeps the fastest.
+
+extern "C" int32_t fr_autotune(fr_context *c, const fr_graph *g, const int32_t *part, int32_t k,
+                               const int32_t *pairs, int32_t npairs, const fr_params *p,
+                               const fr_tuning *cand, int32_t ncand, int32_t reps, double *ms_out,
+                               int32_t *best_out) {
+  if (!c || !g || !part || !pairs || !p || !cand || ncand < 1 || reps < 1) return FR_E_INVALID_ARG;
+  if (!g->on_device) return FR_E_INVALID_ARG;  // tune on device-resident inputs
+  int32_t rc = FR_OK;
+  const fr_tuning keep = c->tune;
+  int32_t *dpart = nullptr;
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipMalloc((void **)&dpart, sizeof(int32_t) * (size_t)g->n));
+  std::vector<fr_result> res((size_t)npairs), ref((size_t)npairs);
+  double best_ms = 1e300;
+  int32_t best = -1;
+  for (int32_t i = 0; i < ncand && rc == FR_OK; i++) {
+    if ((rc = fr_set_tuning(c, &cand[i]))) break;
+    double tot = 0;
+    for (int32_t r = 0; r < reps + 1 && rc == FR_OK; r++) {
+      if (hipMemcpy(dpart, part, sizeof(int32_t) * (size_t)g->n, hipMemcpyDeviceToDevice) != hipSuccess) {
+        rc = FR_E_DEVICE;
+        break;
+      }
+      rc = refine(c, g, dpart, k, pairs, npairs, p, res.data(), nullptr, nullptr);
+      if (rc) break;
+      if (r > 0) tot += c->ms[1];  // the first run warms up
+    }
+    if (rc) break;
+    if (i == 0) ref = res;
+    for (int32_t j = 0; j < npairs; j++)
+      if (memcmp(&res[j], &ref[j], sizeof(fr_result)) != 0) rc = FR_E_DEVICE;  // must not happen
+    const double ms = tot / reps;
+    if (ms_out) ms_out[i] = ms;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = i;
+    }
+  }
+  (void)hipFree(dpart);
+  if (rc) {
+    c->tune = keep;
+    return rc;
+  }
+  c->tune = cand[best];
+  if (best_out) *best_out = best;
   return FR_OK;
 }

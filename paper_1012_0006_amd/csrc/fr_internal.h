@@ -61,13 +61,17 @@ struct KArgs {
   int32_t n, k;
   const int32_t *xadj, *adjncy, *adjwgt, *vwgt;
   int32_t *part;
-  // pairs
+  // pairs of this round (one matching)
   int32_t P;
   const int32_t *pairs;     // [2P]
-  const int32_t *order;     // [P] pairs in the order workgroups take them
-  const int32_t *blk2pair;  // [k]
-  PairState *ps;
-  fr_solve *trace;          // [P * max_iters]
+  int32_t *order;           // [P] pairs in the order workgroups take them
+  int32_t *blk2pair;        // [k]
+  int32_t *alpha0;          // [P] start factor per pair
+  PairState *ps;            // [P]
+  fr_solve *trace;          // [P * max_iters] or null
+  int64_t *bstat;           // [3k] weight, vertex count, arc count per block
+  int32_t *queue;           // device counter of the pair queue of this round
+  int64_t *fstat;           // [4P] boundary statistics for the learned factor
   const int64_t *base;      // floor((1 + alpha eps) c(V) / k), alpha = 0..alpha_max
   int64_t lmax;
   // parameters
@@ -76,7 +80,7 @@ struct KArgs {
   // per vertex [n]
   int32_t *mark, *vmap;
   // per-pair arenas: vertex slots [voff[p], voff[p+1]), arc slots [aoff[p], aoff[p+1])
-  const int64_t *voff, *aoff;
+  int64_t *voff, *aoff;
   int32_t *ucnt;            // [P] fill counters of the union lists
   int32_t *uvert;           // vertices of blocks a and b of each pair
   int32_t *lg;              // corridor: local id -> global id

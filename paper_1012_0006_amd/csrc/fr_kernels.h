@@ -105,10 +105,45 @@ __device__ void block_sums(int64_t (&v)[N], int64_t *lds) {
 // ------------------------------------------------------------------------
 // setup kernels
 
-// c(V), max c(v), block weights, vertex and arc counts per block, range check
-// of the partition.
-__global__ void __launch_bounds__(256) k_setup(KArgs A, int64_t *bw, int64_t *bcnt,
-                                               int64_t *barc) {
+// Adds v into base[key * stride + slot] for the active lanes with key >= 0,
+// one atomic per distinct key of the wave (partitions of spatially ordered
+// vertices give one or two keys per wave).  Converged wave only.
+__device__ __forceinline__ void wave_add_by_key(unsigned long long *base, int stride, int slot,
+                                                int key, int64_t v) {
+  unsigned long long todo = __ballot(key >= 0);
+  while (todo) {
+    const int leader = __ffsll(todo) - 1;
+    const int k0 = __shfl(key, leader);
+    const bool mine = key == k0;
+    int64_t x = mine ? v : 0;
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    if (lane64() == leader && x != 0)
+      atomicAdd(&base[(int64_t)k0 * stride + slot], (unsigned long long)x);
+    todo &= ~__ballot(mine);
+  }
+}
+
+// Slot for every lane with key >= 0 in the list of its key: one atomic per
+// distinct key of the wave.  Converged wave only.
+__device__ __forceinline__ int wave_append_by_key(int32_t *counters, int key) {
+  unsigned long long todo = __ballot(key >= 0);
+  int slot = -1;
+  const int lane = lane64();
+  while (todo) {
+    const int leader = __ffsll(todo) - 1;
+    const int k0 = __shfl(key, leader);
+    const unsigned long long m = __ballot(key == k0);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&counters[k0], (int)__popcll(m));
+    base = __shfl(base, leader);
+    if (key == k0) slot = base + (int)__popcll(m & ((1ull << lane) - 1ull));
+    todo &= ~m;
+  }
+  return slot;
+}
+
+// c(V), max c(v) and the range check of the partition (once per call).
+__global__ void __launch_bounds__(256) k_graph_stats(KArgs A) {
   __shared__ int64_t s_red[16];
   int64_t sum = 0;
   int32_t mx = 0;
@@ -120,13 +155,7 @@ __global__ void __launch_bounds__(256) k_setup(KArgs A, int64_t *bw, int64_t *bc
     sum += w;
     mx = w > mx ? w : mx;
     if (w < 0) bad |= 2;
-    if (x < 0 || x >= A.k) {
-      bad |= 1;
-      continue;
-    }
-    atomicAdd((unsigned long long *)&bw[x], (unsigned long long)(int64_t)w);
-    atomicAdd((unsigned long long *)&bcnt[x], 1ull);
-    atomicAdd((unsigned long long *)&barc[x], (unsigned long long)(A.xadj[u + 1] - A.xadj[u]));
+    if (x < 0 || x >= A.k) bad |= 1;
   }
   int64_t v[1] = {sum};
   block_sums<1>(v, s_red);
@@ -138,6 +167,95 @@ __global__ void __launch_bounds__(256) k_setup(KArgs A, int64_t *bw, int64_t *bc
   if (lane64() == 0 && mx > 0) atomicMax((long long *)&A.ctl->maxc, (long long)mx);
   if (bad & 1) atomicOr(&A.ctl->bad_part, 1);
   if (bad & 2) atomicOr(&A.ctl->bad_graph, 1);
+}
+
+// Start of a round (one block): block -> pair map, cleared block statistics,
+// union fill counters and pair queue.
+__global__ void __launch_bounds__(1024) k_round_init(KArgs A) {
+  for (int i = threadIdx.x; i < A.k; i += blockDim.x) A.blk2pair[i] = -1;
+  for (int i = threadIdx.x; i < 3 * A.k; i += blockDim.x) A.bstat[i] = 0;
+  for (int i = threadIdx.x; i < A.P; i += blockDim.x) A.ucnt[i] = 0;
+  if (A.fstat)
+    for (int i = threadIdx.x; i < 4 * A.P; i += blockDim.x) A.fstat[i] = 0;
+  if (threadIdx.x == 0) *A.queue = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < A.P; i += blockDim.x) {
+    A.blk2pair[A.pairs[2 * i]] = i;
+    A.blk2pair[A.pairs[2 * i + 1]] = i;
+  }
+}
+
+// Weight, vertex count and arc count of every block in a pair of the round.
+__global__ void __launch_bounds__(256) k_block_stats(KArgs A) {
+  unsigned long long *bw = (unsigned long long *)A.bstat;
+  unsigned long long *bc = bw + A.k, *ba = bw + 2 * A.k;
+  for (int64_t b0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) & ~(int64_t)63;
+       b0 < A.n; b0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t u = b0 + lane64();
+    int key = -1;
+    int32_t w = 0, deg = 0;
+    if (u < A.n) {
+      const int32_t x = A.part[u];
+      if (A.blk2pair[x] >= 0) {
+        key = x;
+        w = A.vwgt[u];
+        deg = A.xadj[u + 1] - A.xadj[u];
+      }
+    }
+    wave_add_by_key(bw, 1, 0, key, w);
+    wave_add_by_key(bc, 1, 0, key, 1);
+    wave_add_by_key(ba, 1, 0, key, deg);
+  }
+}
+
+// Arena slices (prefix sums of the pairs' vertex and arc counts), the
+// largest-first order in which workgroups take the pairs, and the initial
+// pair states.  One block.
+__global__ void __launch_bounds__(1024) k_arena(KArgs A) {
+  __shared__ int64_t s_scan[17];
+  const int64_t *bw = A.bstat, *bc = A.bstat + A.k, *ba = A.bstat + 2 * A.k;
+  const int P = A.P;
+  const int per = (P + blockDim.x - 1) / blockDim.x;
+  const int lo = threadIdx.x * per, hi = min(lo + per, P);
+  int64_t sv = 0, sa = 0;
+  for (int i = lo; i < hi; i++) {
+    sv += bc[A.pairs[2 * i]] + bc[A.pairs[2 * i + 1]];
+    sa += ba[A.pairs[2 * i]] + ba[A.pairs[2 * i + 1]];
+  }
+  int64_t tv, ta;
+  int64_t rv = block_exscan64(sv, &tv, s_scan);
+  int64_t ra = block_exscan64(sa, &ta, s_scan);
+  for (int i = lo; i < hi; i++) {
+    A.voff[i] = rv;
+    A.aoff[i] = ra;
+    rv += bc[A.pairs[2 * i]] + bc[A.pairs[2 * i + 1]];
+    ra += ba[A.pairs[2 * i]] + ba[A.pairs[2 * i + 1]];
+  }
+  if (threadIdx.x == 0) {
+    A.voff[P] = tv;
+    A.aoff[P] = ta;
+  }
+  for (int i = threadIdx.x; i < P; i += blockDim.x) {
+    const int32_t a = A.pairs[2 * i], b = A.pairs[2 * i + 1];
+    const int64_t na = ba[a] + ba[b];
+    int rank = 0;
+    for (int q = 0; q < P; q++) {
+      const int64_t nq = ba[A.pairs[2 * q]] + ba[A.pairs[2 * q + 1]];
+      rank += (nq > na || (nq == na && q < i)) ? 1 : 0;
+    }
+    A.order[rank] = i;
+    PairState s;
+    memset(&s, 0, sizeof(s));
+    s.a = a;
+    s.b = b;
+    int al = A.alpha0 ? A.alpha0[i] : 1;
+    al = al < 1 ? 1 : (al > A.alpha_max ? A.alpha_max : al);
+    s.alpha = s.start_alpha = s.final_alpha = al;
+    s.cA = bw[a];
+    s.cB = bw[b];
+    s.cut = s.cut0 = -1;
+    A.ps[i] = s;
+  }
 }
 
 // CSR checks: offsets monotone, ids in range, no self loop, no repeated
@@ -175,12 +293,12 @@ __global__ void __launch_bounds__(256) k_validate(KArgs A, int64_t narcs) {
 
 // vertices of the two blocks of every pair, gathered into the pair's arena
 __global__ void __launch_bounds__(256) k_union(KArgs A) {
-  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < A.n;
-       u += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t p = A.blk2pair[A.part[u]];
-    if (p < 0) continue;
-    const int32_t pos = atomicAdd(&A.ucnt[p], 1);
-    if (A.voff[p] + pos < A.voff[p + 1]) A.uvert[A.voff[p] + pos] = (int32_t)u;
+  for (int64_t b0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) & ~(int64_t)63;
+       b0 < A.n; b0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t u = b0 + lane64();
+    const int32_t p = u < A.n ? A.blk2pair[A.part[u]] : -1;
+    const int pos = wave_append_by_key(A.ucnt, p);
+    if (p >= 0 && A.voff[p] + pos < A.voff[p + 1]) A.uvert[A.voff[p] + pos] = (int32_t)u;
   }
 }
 
@@ -980,7 +1098,7 @@ __global__ void __launch_bounds__(TPB) k_solve(KArgs A) {
   __shared__ SolveShared<TPB> sh;
   __shared__ PairState st;
   for (;;) {
-    if (threadIdx.x == 0) sh.pair = atomicAdd(&A.ctl->queue, 1);
+    if (threadIdx.x == 0) sh.pair = atomicAdd(A.queue, 1);
     __syncthreads();
     const int32_t q = sh.pair;
     __syncthreads();
@@ -1013,7 +1131,7 @@ __global__ void __launch_bounds__(TPB) k_solve(KArgs A) {
         const fr_solve rec = sh.rec;
         bool stop = A.ctl->err != 0;
         if (!stop) {
-          A.trace[(int64_t)p * A.max_iters + st.iters] = rec;
+          if (A.trace) A.trace[(int64_t)p * A.max_iters + st.iters] = rec;
           st.iters++;
           if (rec.decision == FR_DEC_APPLY) {
             st.applied++;

@@ -1,0 +1,160 @@
+"""GPU checks of the learned area factor: the HIP feature, forward, backward
+and Adam kernels against the float64 oracle (and finite differences), the
+batched solve started at the predicted factor against the oracle run from
+the same start factors, and the autotuner's result invariance."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("status", "iters", "final_alpha", "applied", "iter_cap", "flow_value", "cut_before",
+        "cut_after", "weight_a", "weight_b", "region_vertices", "region_edges")
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu_lib):
+    c = gpu_lib.Context()
+    yield c
+    c.close()
+
+
+def _case(seed=71, n=1 << 15, k=16):
+    g = gen.rgg(n, 2, 8.0, seed=seed, wlo=1, whi=10)
+    part = gen.rcb(g, k)
+    gen.global_noise(g, part, 0.02, seed)
+    return g, part, k
+
+
+def test_pair_features_match_oracle(gpu_lib, ctx):
+    g, part, k = _case()
+    edges, colour = oracle.quotient_colouring(g, part, k)
+    pairs = [tuple(e) for e, c in zip(edges.tolist(), colour.tolist()) if c == 0]
+    f = gpu_lib.fr_pair_features(ctx, g, part.copy(), k, pairs, 30000)
+    for i, (a, b) in enumerate(pairs):
+        ref = oracle.pair_features(g, part, k, a, b, 30000)
+        # computed in float64 on the device and rounded once to float32
+        assert np.allclose(f[i], ref.astype(np.float32), rtol=2e-7, atol=1e-7), (i, f[i], ref)
+
+
+def _oracle_params(fr, w):
+    return {k: v.astype(np.float64) for k, v in fr.mlp_unpack(w).items()}
+
+
+def test_forward_and_gradient_match_oracle(gpu_lib, ctx):
+    gpu_lib.fr_mlp_init(ctx, 123)
+    w = gpu_lib.fr_mlp_get_weights(ctx)
+    rng = np.random.default_rng(5)
+    x = rng.normal(0, 1.5, (301, 8)).astype(np.float32)  # several blocks and a ragged tail
+    y = rng.integers(0, 5, 301).astype(np.int32)
+    P = _oracle_params(gpu_lib, w)
+    p_ref, _ = oracle.mlp_forward(P, x.astype(np.float64))
+    p_gpu = gpu_lib.fr_mlp_forward(ctx, x)
+    assert np.allclose(p_gpu, p_ref, rtol=1e-5, atol=1e-6)
+    loss, grad = gpu_lib.fr_mlp_loss_grad(ctx, x, y)
+    l_ref, g_ref = oracle.mlp_loss_grad(P, x.astype(np.float64), y)
+    assert abs(loss - l_ref) <= 1e-5 * abs(l_ref) + 1e-6
+    g_ref_flat = np.concatenate([g_ref[k].reshape(-1) for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+    scale = np.abs(g_ref_flat).max()
+    assert np.allclose(grad, g_ref_flat, rtol=1e-3, atol=1e-5 * scale)
+
+
+def test_gradient_finite_differences(gpu_lib, ctx):
+    gpu_lib.fr_mlp_init(ctx, 7)
+    w = gpu_lib.fr_mlp_get_weights(ctx).astype(np.float64)
+    rng = np.random.default_rng(6)
+    x = rng.normal(0, 1.0, (64, 8)).astype(np.float32)
+    y = rng.integers(0, 5, 64).astype(np.int32)
+    _, grad = gpu_lib.fr_mlp_loss_grad(ctx, x, y)
+    h = 2e-3
+    for idx in np.argsort(-np.abs(grad))[:12]:
+        wp, wm = w.copy(), w.copy()
+        wp[idx] += h
+        wm[idx] -= h
+        gpu_lib.fr_mlp_set_weights(ctx, wp)
+        lp, _ = gpu_lib.fr_mlp_loss_grad(ctx, x, y)
+        gpu_lib.fr_mlp_set_weights(ctx, wm)
+        lm, _ = gpu_lib.fr_mlp_loss_grad(ctx, x, y)
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - grad[idx]) <= 5e-2 * abs(grad[idx]) + 2e-4, (idx, fd, grad[idx])
+    gpu_lib.fr_mlp_set_weights(ctx, w)
+
+
+def test_adam_step_matches_numpy(gpu_lib, ctx):
+    gpu_lib.fr_mlp_init(ctx, 9)
+    w0 = gpu_lib.fr_mlp_get_weights(ctx)
+    rng = np.random.default_rng(8)
+    x = rng.normal(0, 1.0, (32, 8)).astype(np.float32)
+    y = rng.integers(0, 5, 32).astype(np.int32)
+    _, g = gpu_lib.fr_mlp_loss_grad(ctx, x, y)
+    lr = 1e-3
+    gpu_lib.fr_mlp_train(ctx, x, y, epochs=1, batch=32, lr=lr, seed=0)  # one full-batch step
+    w1 = gpu_lib.fr_mlp_get_weights(ctx)
+    # Adam step 1: m = 0.1 g, v = 0.001 g^2, bias-corrected m_hat = g, v_hat = g^2
+    step = lr * g / (np.abs(g) + 1e-8)
+    ok = np.abs(g) > 1e-5  # sign-stable entries
+    assert np.allclose((w0 - w1)[ok], step[ok], rtol=1e-3, atol=1e-7)
+    assert np.all(np.abs(w0 - w1) <= lr * 1.0001 + 1e-9)
+
+
+def test_training_reduces_loss(gpu_lib, ctx):
+    gpu_lib.fr_mlp_init(ctx, 11)
+    rng = np.random.default_rng(12)
+    x = rng.normal(0, 1.0, (2000, 8)).astype(np.float32)
+    y = (np.argmax(x[:, :5] + 0.3 * x[:, 5:6], axis=1)).astype(np.int32)  # learnable rule
+    losses = gpu_lib.fr_mlp_train(ctx, x, y, epochs=15, batch=128, lr=3e-3, seed=1)
+    assert losses[-1] < 0.5 * losses[0]
+    acc = np.mean(np.argmax(gpu_lib.fr_mlp_forward(ctx, x), axis=1) == y)
+    assert acc > 0.8
+
+
+def test_batch_with_learned_factor_matches_oracle(gpu_lib, ctx):
+    """Flows stay exact under the learned start factor: the oracle, started at
+    the factor the device chose for each pair, gives the same results."""
+    import torch
+
+    gpu_lib.fr_mlp_init(ctx, 21)
+    g, part, k = _case(seed=73)
+    edges, colour = oracle.quotient_colouring(g, part, k)
+    pairs = [tuple(e) for e, c in zip(edges.tolist(), colour.tolist()) if c == 0]
+    p = dict(area_mode=0, depth=0, alpha=16, alpha_max=16, adaptive=1, max_iters=16,
+             eps_ppm=30000)
+    dg = gpu_lib.DeviceGraph.from_host(g)
+    dpart = torch.as_tensor(part.copy()).cuda()
+    prm = gpu_lib.params(**p, use_mlp=1)
+    res, trace = gpu_lib.flow_refine_batch(ctx, dg, dpart, k, pairs, prm)
+    # the start factors are the argmax of the network on the pairs' features
+    feats = gpu_lib.fr_pair_features(ctx, g, part.copy(), k, pairs, 30000)
+    probs = gpu_lib.fr_mlp_forward(ctx, feats)
+    for i in range(len(pairs)):
+        assert res[i]["start_alpha"] == gpu_lib.ALPHAS[int(np.argmax(probs[i]))]
+    cur = part.copy()
+    for i, (a, b) in enumerate(pairs):
+        o = oracle.refine_pair(g, cur, k, a, b, dict(p, alpha=res[i]["start_alpha"]),
+                               want_side=False)
+        for key in KEYS:
+            assert res[i][key] == o.result[key], (i, key)
+        assert trace[i] == o.trace
+        cur = o.part
+    assert np.array_equal(dpart.cpu().numpy(), cur)
+
+
+def test_autotune_keeps_results(gpu_lib, ctx):
+    import torch
+
+    g, part, k = _case(seed=75, n=1 << 14, k=8)
+    edges, colour = oracle.quotient_colouring(g, part, k)
+    pairs = [tuple(e) for e, c in zip(edges.tolist(), colour.tolist()) if c == 0]
+    dg = gpu_lib.DeviceGraph.from_host(g)
+    dpart = torch.as_tensor(part.copy()).cuda()
+    cands = [dict(block_threads=1024, blocks_per_cu=2, tpv=4, relabel_period=200),
+             dict(block_threads=512, blocks_per_cu=4, tpv=8, relabel_period=50),
+             dict(block_threads=256, blocks_per_cu=8, tpv=2, relabel_period=400)]
+    prm = gpu_lib.params()
+    best, ms = gpu_lib.fr_autotune(ctx, dg, dpart, k, pairs, prm, cands, reps=1)
+    assert 0 <= best < 3 and all(m > 0 for m in ms)
+    assert ctx.get_tuning() == cands[best]
+    assert np.array_equal(dpart.cpu().numpy(), part)  # the partition is not modified
+    ctx.set_tuning()
