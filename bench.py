@@ -172,6 +172,48 @@ def run_batched(args, fr, torch, gen):
     }
 
 
+def run_learned(args, fr, torch, gen):
+    """One matching-round sweep of C4 (2D RGG n=2^22, mean degree 8, weights
+    1..10, k=64 RCB + 2 % noise): every colour class batched, once with the
+    plain adaptive search from alpha' = 16 and once starting at the learned
+    factor."""
+    w = gen.config("C4")
+    ctx = fr.Context()
+    ctx.set_validation(False)
+    report = fr.load_trained_mlp(ctx)
+    dg = fr.DeviceGraph.from_host(w.graph)
+    part0 = torch.as_tensor(w.part).cuda()
+    edges_q, colour = fr.fr_quotient_matchings(ctx, dg, part0, w.k)
+    classes = sorted(set(colour.tolist()))
+    out = {}
+    for use in (0, 1):
+        prm = fr.params(**{k: w.params[k] for k in ("area_mode", "depth", "alpha", "alpha_max",
+                                                     "adaptive", "max_iters", "eps_ppm")},
+                        use_mlp=use)
+        dpart = part0.clone()
+        solves = edges = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for c in classes:
+            pairs = [tuple(e) for e, cc in zip(edges_q.tolist(), colour.tolist()) if cc == c]
+            res, _ = fr.flow_refine_batch(ctx, dg, dpart, w.k, pairs, prm)
+            solves += sum(r["iters"] for r in res)
+            edges += sum(r["region_edges"] for r in res)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        import oracle  # cut accounting only (sum of cut edge weights)
+        out["learned" if use else "plain"] = {
+            "seconds": dt, "flow_solves": solves, "region_edges": edges,
+            "region_edges_per_s": edges / dt,
+            "total_cut": oracle.total_cut(w.graph, dpart.cpu().numpy())}
+    ctx.close()
+    out["workload"] = ("C4: 2D RGG n=2^22 mean degree 8, weights 1..10, k=64 RCB + 2% noise, "
+                       f"one sweep of {len(classes)} matching rounds, eps 3%, alpha' 16 adaptive")
+    out["validation_accuracy"] = report.get("validation_accuracy")
+    out["speedup"] = out["plain"]["seconds"] / out["learned"]["seconds"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -180,6 +222,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--no-learned", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -253,6 +296,8 @@ def main():
         line["bit_exact_vs_oracle"] = bool(exact)
     if not args.no_batched:
         line["batched"] = run_batched(args, fr, torch, gen)
+    if not args.no_learned:
+        line["learned_factor"] = run_learned(args, fr, torch, gen)
     print(json.dumps(line), flush=True)
 
 

@@ -403,3 +403,17 @@ def fr_autotune(ctx: Context, graph: DeviceGraph, part, k: int, pairs, prm: FrPa
                                pr.ctypes.data, pr.shape[0] // 2, ctypes.byref(prm), cand,
                                len(candidates), reps, ms, ctypes.byref(best)), "fr_autotune")
     return int(best.value), list(ms)
+
+
+TRAINED_WEIGHTS = os.path.join(_HERE, "mlp_area_factor.json")
+
+
+def load_trained_mlp(ctx: Context, path: str = TRAINED_WEIGHTS) -> dict:
+    """Loads the committed area-factor weights (written by train_mlp.py) into
+    the context; returns the training report."""
+    import json
+
+    with open(path) as fh:
+        d = json.load(fh)
+    fr_mlp_set_weights(ctx, np.asarray(d["weights"], dtype=np.float32))
+    return d["report"]

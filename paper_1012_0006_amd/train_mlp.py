@@ -1,0 +1,237 @@
+"""Train the learned area factor on the GPU.
+
+Training data: seeded 2D random geometric graphs (n = 2^18, mean degree 8,
+edge weights 1..10), k = 64 by recursive coordinate bisection plus 2 %
+boundary noise, eps = 3 %.  The colour classes of the quotient graph are
+visited in order, as one sweep does; for every pair of a class the plain
+adaptive search is run from each start factor in {1, 2, 4, 8, 16} (alpha_max
+16), and the label is the smallest start whose search ends at the smallest
+final pair cut of the five.  The partition then moves on with the result of
+the plain search from 16 before the next class.  The features are the
+library's 8 pair features, taken before the class is refined.  Training runs
+on the device (fr_mlp_train: Adam, softmax cross-entropy).
+
+    python -m paper_1012_0006_amd.train_mlp --graphs 200 --out weights.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "mlp_area_factor.json")
+
+
+def label_graph(fr, ctx, torch, gen, seed, n, k, eps_ppm, alpha_max=16):
+    """Features and best-start labels of all quotient-graph pairs of one graph."""
+    g = gen.rgg(n, 2, 8.0, seed=seed, wlo=1, whi=10)
+    part = gen.rcb(g, k)
+    gen.global_noise(g, part, 0.02, seed)
+    dg = fr.DeviceGraph.from_host(g)
+    cur = torch.as_tensor(part).cuda()
+    edges, colour = fr.fr_quotient_matchings(ctx, dg, cur, k)
+    feats, labels, finals, works = [], [], [], []
+    work = torch.empty_like(cur)
+    for c in sorted(set(colour.tolist())):
+        pairs = [tuple(e) for e, cc in zip(edges.tolist(), colour.tolist()) if cc == c]
+        f = fr.fr_pair_features(ctx, dg, cur, k, pairs, eps_ppm)
+        final = np.zeros((len(pairs), len(fr.ALPHAS)), dtype=np.int64)
+        work_e = np.zeros((len(pairs), len(fr.ALPHAS)), dtype=np.int64)
+        valid = np.ones(len(pairs), dtype=bool)
+        for j, al in enumerate(fr.ALPHAS):
+            work.copy_(cur)
+            prm = fr.params(alpha=al, alpha_max=alpha_max, adaptive=1, max_iters=16,
+                            eps_ppm=eps_ppm)
+            res, _ = fr.flow_refine_batch(ctx, dg, work, k, pairs, prm)
+            for i, r in enumerate(res):
+                if r["status"] == fr.FR_NOT_ADJACENT:
+                    valid[i] = False
+                final[i, j] = r["cut_after"]
+                work_e[i, j] = r["region_edges"]
+        cur.copy_(work)  # the last start is the plain search from alpha_max
+        for i in range(len(pairs)):
+            if valid[i]:
+                feats.append(f[i])
+                labels.append(int(np.argmin(final[i])))  # first minimum = smallest start
+                finals.append(final[i])
+                works.append(work_e[i])
+    return feats, labels, finals, works
+
+
+def one_sweep(fr, ctx, torch, gen, seed, n, k, use_mlp):
+    """One pass over the colour classes from the seeded start partition:
+    flow solves, corridor edges and the final total cut."""
+    g = gen.rgg(n, 2, 8.0, seed=seed, wlo=1, whi=10)
+    part = gen.rcb(g, k)
+    gen.global_noise(g, part, 0.02, seed)
+    dg = fr.DeviceGraph.from_host(g)
+    cur = torch.as_tensor(part).cuda()
+    edges, colour = fr.fr_quotient_matchings(ctx, dg, cur, k)
+    solves = region = 0
+    prm = fr.params(alpha=16, alpha_max=16, adaptive=1, max_iters=16, eps_ppm=30000,
+                    use_mlp=use_mlp)
+    for c in sorted(set(colour.tolist())):
+        pairs = [tuple(e) for e, cc in zip(edges.tolist(), colour.tolist()) if cc == c]
+        res, _ = fr.flow_refine_batch(ctx, dg, cur, k, pairs, prm)
+        solves += sum(r["iters"] for r in res)
+        region += sum(r["region_edges"] for r in res)
+    out = cur.cpu().numpy()
+    a, b = g.xadj, g.adjncy
+    src = np.repeat(np.arange(g.n), np.diff(a))
+    cut = int(g.adjwgt[out[src] != out[b]].sum()) // 2
+    return solves, region, cut
+
+
+OFF_W1, OFF_B1, OFF_B3 = 0, 8 * 64, 8 * 64 + 64 + 64 * 64 + 64 + 64 * 5
+
+
+def fold_normalisation(w, mu, sd):
+    """Trained on (x - mu) / sd; returns weights that take the raw features."""
+    w = w.astype(np.float64).copy()
+    W1 = w[OFF_W1:OFF_B1].reshape(8, 64)
+    b1 = w[OFF_B1:OFF_B1 + 64]
+    b1 -= (W1 * (mu / sd)[:, None]).sum(0)
+    W1 /= sd[:, None]
+    return w.astype(np.float32)
+
+
+def choose_offsets(logp, final, work, tol):
+    """Per-class logit offsets (a shift of the class priors toward larger
+    factors) that minimise the corridor edges of the predicted starts while
+    the summed final pair cut stays within (1 + tol) of the plain search from
+    the largest factor.  First the smallest linear shift beta * class that
+    meets the bound, then a coordinate refinement of each class offset."""
+    idx = np.arange(len(logp))
+    ncls = logp.shape[1]
+    plain_cut = final[:, -1].sum()
+    bound = (1 + tol) * plain_cut
+
+    def cost(c):
+        pick = np.argmax(logp + c, axis=1)
+        return work[idx, pick].sum(), final[idx, pick].sum()
+
+    best = np.arange(ncls) * 50.0  # every pair at the largest factor: the plain search
+    bw, bc = cost(best)
+    for beta in np.arange(0.0, 8.0, 0.05):
+        c = beta * np.arange(ncls)
+        wv, cv = cost(c)
+        if cv <= bound:
+            if wv < bw:
+                best, bw, bc = c, wv, cv
+            break
+    grid = np.arange(-1.0, 1.01, 0.1)
+    for _ in range(3):
+        for j in range(1, ncls):
+            base = best.copy()
+            for dv in grid:
+                c = base.copy()
+                c[j] += dv
+                wv, cv = cost(c)
+                if cv <= bound and wv < bw:
+                    best, bw, bc = c, wv, cv
+    return best, int(bw), int(bc), int(plain_cut), int(work[:, -1].sum())
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--graphs", type=int, default=200)
+    ap.add_argument("--first-seed", type=int, default=1000)
+    ap.add_argument("--n", type=int, default=1 << 18)
+    ap.add_argument("--k", type=int, default=64)
+    ap.add_argument("--epochs", type=int, default=80)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--cut-tolerance", type=float, default=0.0025)
+    ap.add_argument("--out", default=WEIGHTS)
+    ap.add_argument("--dump", default=None, help="also save the labelled samples (.npz)")
+    args = ap.parse_args()
+
+    import torch
+
+    import gen
+    import paper_1012_0006_amd as fr
+
+    ctx = fr.Context()
+    ctx.set_validation(False)
+    t0 = time.time()
+    X, Y, G, F, E = [], [], [], [], []
+    for gi in range(args.graphs):
+        f, y, fin, wk = label_graph(fr, ctx, torch, gen, args.first_seed + gi, args.n, args.k,
+                                    30000)
+        X += f
+        Y += y
+        F += fin
+        E += wk
+        G += [gi] * len(y)
+        if gi % 20 == 0:
+            print(f"graph {gi}: {len(Y)} samples, {time.time() - t0:.1f}s", flush=True)
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.int32)
+    G = np.asarray(G)
+    F = np.asarray(F, dtype=np.int64)
+    E = np.asarray(E, dtype=np.int64)
+    if args.dump:
+        np.savez_compressed(args.dump, X=X, Y=Y, G=G, F=F, E=E)
+    # 90/10 split by graph
+    val = G >= int(round(0.9 * args.graphs))
+    mu = X[~val].mean(0)
+    sd = X[~val].std(0) + 1e-6
+    Xn = ((X - mu) / sd).astype(np.float32)
+    fr.fr_mlp_init(ctx, 2024)
+    losses = fr.fr_mlp_train(ctx, Xn[~val], Y[~val], args.epochs, args.batch, args.lr, seed=7)
+    w = fold_normalisation(fr.fr_mlp_get_weights(ctx), mu, sd)
+    fr.fr_mlp_set_weights(ctx, w)
+    Xf = X.astype(np.float32)
+    probs = fr.fr_mlp_forward(ctx, Xf)
+    acc_tr = float(np.mean(np.argmax(probs[~val], 1) == Y[~val]))
+    acc_va = float(np.mean(np.argmax(probs[val], 1) == Y[val])) if val.any() else None
+    logp = np.log(np.maximum(probs.astype(np.float64), 1e-30))
+    # decision offsets are chosen on the training graphs and checked on the held-out ones
+    c, w_tr, cut_tr, plain_cut_tr, plain_w_tr = choose_offsets(logp[~val], F[~val], E[~val],
+                                                               args.cut_tolerance)
+    w[OFF_B3:OFF_B3 + 5] += c.astype(np.float32)
+    fr.fr_mlp_set_weights(ctx, w)
+    pick = np.argmax(fr.fr_mlp_forward(ctx, Xf[val]), 1)
+    iv = np.arange(int(val.sum()))
+    hist = np.bincount(Y, minlength=5).tolist()
+    ev = {0: [0, 0, 0], 1: [0, 0, 0]}
+    for gi in range(int(round(0.9 * args.graphs)), args.graphs):
+        for use in (0, 1):
+            r = one_sweep(fr, ctx, torch, gen, args.first_seed + gi, args.n, args.k, use)
+            ev[use] = [x + y for x, y in zip(ev[use], r)]
+    report = {
+        "graphs": args.graphs, "first_seed": args.first_seed, "n": args.n, "k": args.k,
+        "samples": int(len(Y)), "label_histogram_alpha_1_2_4_8_16": hist,
+        "majority_class_accuracy": float(max(hist) / max(1, len(Y))),
+        "train_accuracy": acc_tr, "validation_accuracy": acc_va,
+        "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
+        "loss_first_epoch": float(losses[0]), "loss_last_epoch": float(losses[-1]),
+        "class_offsets": [float(v) for v in c], "cut_tolerance": args.cut_tolerance,
+        "train_pairs": {"plain_edges": plain_w_tr, "learned_edges": w_tr,
+                        "plain_cut": plain_cut_tr, "learned_cut": cut_tr},
+        "validation_pairs": {"plain_edges": int(E[val][:, -1].sum()),
+                             "learned_edges": int(E[val][iv, pick].sum()),
+                             "plain_cut": int(F[val][:, -1].sum()),
+                             "learned_cut": int(F[val][iv, pick].sum()),
+                             "best_cut": int(F[val].min(1).sum()),
+                             "constant_start_edges": [int(v) for v in E[val].sum(0)],
+                             "constant_start_cut": [int(v) for v in F[val].sum(0)]},
+        "validation_sweep_plain": dict(zip(("solves", "region_edges", "cut"), ev[0])),
+        "validation_sweep_learned": dict(zip(("solves", "region_edges", "cut"), ev[1])),
+        "seconds": time.time() - t0,
+    }
+    with open(args.out, "w") as fh:
+        json.dump({"report": report, "weights": [float(v) for v in w]}, fh)
+    print(json.dumps(report), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -158,3 +158,36 @@ def test_autotune_keeps_results(gpu_lib, ctx):
     assert ctx.get_tuning() == cands[best]
     assert np.array_equal(dpart.cpu().numpy(), part)  # the partition is not modified
     ctx.set_tuning()
+
+
+def test_trained_factor_gain(gpu_lib, ctx):
+    """What the trained network gains over the plain adaptive search (start at
+    alpha' = 16) on held-out graphs of the training family (one sweep over the
+    colour classes): at least 20 % fewer corridor edges, with the total cut at
+    most 1 % above the plain search's.  The plain search stays the judge: both
+    runs are exact flow solves, only the start factor differs."""
+    import torch
+
+    gpu_lib.load_trained_mlp(ctx)
+    p = dict(alpha=16, alpha_max=16, adaptive=1, max_iters=16, eps_ppm=30000)
+    tot = {0: [0, 0, 0], 1: [0, 0, 0]}  # solves, region edges, final cut
+    for seed in (5001, 5002, 5003):
+        g = gen.rgg(1 << 18, 2, 8.0, seed=seed, wlo=1, whi=10)
+        part = gen.rcb(g, 64)
+        gen.global_noise(g, part, 0.02, seed)
+        dg = gpu_lib.DeviceGraph.from_host(g)
+        part0 = torch.as_tensor(part).cuda()
+        edges, colour = gpu_lib.fr_quotient_matchings(ctx, dg, part0, 64)
+        for use in (0, 1):
+            dpart = part0.clone()
+            for c in sorted(set(colour.tolist())):
+                pairs = [tuple(e) for e, cc in zip(edges.tolist(), colour.tolist()) if cc == c]
+                res, _ = gpu_lib.flow_refine_batch(ctx, dg, dpart, 64, pairs,
+                                                   gpu_lib.params(**p, use_mlp=use))
+                tot[use][0] += sum(r["iters"] for r in res)
+                tot[use][1] += sum(r["region_edges"] for r in res)
+            tot[use][2] += oracle.total_cut(g, dpart.cpu().numpy())
+    print(f"plain: solves {tot[0][0]} edges {tot[0][1]} cut {tot[0][2]} | "
+          f"learned: solves {tot[1][0]} edges {tot[1][1]} cut {tot[1][2]}", flush=True)
+    assert tot[1][1] <= 0.8 * tot[0][1]
+    assert tot[1][2] <= 1.01 * tot[0][2]
