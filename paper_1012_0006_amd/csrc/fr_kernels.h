@@ -22,6 +22,11 @@
 
 __device__ __forceinline__ int lane64() { return (int)__lane_id(); }
 
+// A value every lane holds the same copy of (read from LDS after a barrier),
+// moved to a scalar register so loop control and addresses built from it
+// stay scalar.
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // Append for lanes with want=true among the ACTIVE lanes of the wave: one
 // atomic per wave on *counter (LDS or global).  Returns the slot or -1.
 __device__ __forceinline__ int wave_append(int32_t *counter, bool want) {
@@ -306,9 +311,23 @@ __global__ void __launch_bounds__(256) k_union(KArgs A) {
 // per-pair solver
 
 // Shared-memory state of one workgroup.
+// LDS working set of the flow phases: two vertex bitmaps (visited marks of
+// the relabel and closure searches, queued marks of the sweeps) cover
+// corridors of up to 32 * FR_BM_WORDS vertices; larger corridors use the
+// global label / mark arrays instead.  The first FR_LDS_LIST entries of each
+// frontier list live in LDS, the rest in the pair's global list.
+#define FR_BM_WORDS 4096
+#define FR_LDS_LIST 2048
+
 template <int TPB>
 struct SolveShared {
-  unsigned long long hist[2048];  // radix select of the last BFS level
+  union {
+    unsigned long long hist[2048];  // radix select of the last BFS level
+    struct {
+      uint32_t bm[2][FR_BM_WORDS];
+      int32_t ls[2][FR_LDS_LIST];
+    } f;
+  } u;
   int64_t red[16 * 8];            // block reductions
   int64_t scan[TPB / 64 + 1];
   int64_t W[2], U[2];             // BFS: taken weight and bound per side
@@ -338,12 +357,12 @@ __device__ void cut_level(const KArgs &A, int32_t x, const int32_t *list, int32_
   for (int pass = 0; pass < 3; pass++) {
     const int shift = pass == 0 ? 20 : (pass == 1 ? 10 : 0);
     const int nbk = pass == 0 ? 2048 : 1024;
-    for (int i = threadIdx.x; i < nbk; i += TPB) sh.hist[i] = 0ull;
+    for (int i = threadIdx.x; i < nbk; i += TPB) sh.u.hist[i] = 0ull;
     __syncthreads();
     for (int i = threadIdx.x; i < cnt; i += TPB) {
       const int32_t u = list[i];
       if (A.part[u] == x && ((uint32_t)u & mask) == prefix)
-        atomicAdd(&sh.hist[((uint32_t)u >> shift) & (nbk - 1)],
+        atomicAdd(&sh.u.hist[((uint32_t)u >> shift) & (nbk - 1)],
                   (unsigned long long)(int64_t)A.vwgt[u]);
     }
     __syncthreads();
@@ -351,7 +370,7 @@ __device__ void cut_level(const KArgs &A, int32_t x, const int32_t *list, int32_
     int64_t mine = 0;
     for (int j = 0; j < per; j++) {
       const int d = threadIdx.x * per + j;
-      if (d < nbk) mine += (int64_t)sh.hist[d];
+      if (d < nbk) mine += (int64_t)sh.u.hist[d];
     }
     int64_t tot;
     int64_t before = block_exscan64(mine, &tot, sh.scan);
@@ -360,7 +379,7 @@ __device__ void cut_level(const KArgs &A, int32_t x, const int32_t *list, int32_
     for (int j = 0; j < per; j++) {
       const int d = threadIdx.x * per + j;
       if (d >= nbk) break;
-      const int64_t h = (int64_t)sh.hist[d];
+      const int64_t h = (int64_t)sh.u.hist[d];
       if (before <= rem && before + h > rem) {
         sh.digit = d;
         sh.before = before;
@@ -394,14 +413,39 @@ struct PairView {
   int32_t *lh, *lr, *rc;
 };
 
+// A frontier list: entries below ns in LDS (s), the rest in global memory (g).
+struct ListRef {
+  int32_t *g;
+  int32_t *s;
+  int32_t ns;
+};
+
+__device__ __forceinline__ int32_t lget(const ListRef &L, int32_t i) {
+  return i < L.ns ? L.s[i] : L.g[i];
+}
+
+__device__ __forceinline__ void lput(const ListRef &L, int pos, int64_t cap, int32_t v, Ctl *ctl) {
+  if (pos < L.ns) L.s[pos] = v;
+  else put_bounded(L.g, pos, cap, v, ctl);
+}
+
+// Marks bit v of an LDS bitmap; true for the lane that set it first.
+__device__ __forceinline__ bool bm_claim(uint32_t *bm, int32_t v) {
+  const uint32_t bit = 1u << (v & 31);
+  return (atomicOr(&bm[v >> 5], bit) & bit) == 0u;
+}
+
 // One push/relabel pass with T lanes per vertex over `cur` (lock-free:
 // residuals and excess change by atomics; labels are read without
 // synchronisation -- they only grow, and termination is decided by an exact
-// global relabel).  Newly activated and still-active vertices go to `next`.
+// global relabel).  Vertices that received flow and vertices still active go
+// to `next`, each once: with an LDS bitmap (qbm, cleared) the first lane to
+// mark a vertex queues it and every atomic is fire-and-forget; without one,
+// the returning excess update (old value 0) decides.
 template <int TPB, int T>
-__device__ void pr_sweep(const KArgs &A, const PairView &V, const int32_t *cur, int32_t cnt,
-                         int32_t *next, int32_t *next_cnt, int32_t NL,
-                         unsigned long long *wcnt) {
+__device__ void pr_sweep(const KArgs &A, const PairView &V, const ListRef &cur, int32_t cnt,
+                         const ListRef &next, int32_t *next_cnt, int32_t NL,
+                         unsigned long long *wcnt, uint32_t *qbm) {
   const int lane = lane64();
   const int gl = lane & (T - 1);
   const int gid = threadIdx.x / T;
@@ -410,60 +454,77 @@ __device__ void pr_sweep(const KArgs &A, const PairView &V, const int32_t *cur, 
   for (int base = wave_first; base < cnt; base += G) {
     const int item = base + (gid - wave_first);
     const bool valid = item < cnt;
-    const int32_t u = valid ? cur[item] : 0;
+    const int32_t u = valid ? lget(cur, item) : 0;
     // the group leader reads label and excess once: excess may grow
-    // concurrently, and every lane must push against the same value
+    // concurrently, and every lane must push against the same value; the
+    // arc range is read by all lanes at the same time
     int32_t d = NL, e = 0;
     if (valid && gl == 0) {
       d = V.lab[u];
       e = V.ex[u];
     }
+    int32_t ab = valid ? V.lo[u] : 0;
+    int32_t ae = valid ? V.lo[u + 1] : 0;
     if (T > 1) {
       d = __shfl(d, 0, T);
       e = __shfl(e, 0, T);
     }
     const bool work = valid && d < NL && e > 0;
+    if (!work) ab = ae = 0;
     int64_t erem = e, pushed = 0;
     int32_t minres = 0x7fffffff;
-    int32_t ab = 0, ae = 0;
-    if (work) {
-      ab = V.lo[u];
-      ae = V.lo[u + 1];
-      if (gl == 0) {
-        atomicAdd(&wcnt[W_SWEEP_ITEMS], 1ull);
-        atomicAdd(&wcnt[W_SWEEP_ARCS], (unsigned long long)(ae - ab));
-      }
+    if (work && gl == 0) {
+      atomicAdd(&wcnt[W_SWEEP_ITEMS], 1ull);
+      atomicAdd(&wcnt[W_SWEEP_ARCS], (unsigned long long)(ae - ab));
     }
-    for (int32_t a0 = ab; a0 < ae; a0 += T) {
-      const int32_t a = a0 + gl;
-      const bool in = a < ae;
-      const int32_t h = in ? V.lh[a] : 0;
-      const int32_t r = in ? V.rc[a] : 0;
-      const int32_t dh = (in && r > 0) ? V.lab[h] : 0x7fffffff;
-      const int64_t adm = (r > 0 && dh < d) ? (int64_t)r : 0;
-      int64_t inc = adm;
-      if (T > 1) {
-        for (int o = 1; o < T; o <<= 1) {
-          const int64_t t = __shfl_up(inc, o, T);
-          if (gl >= o) inc += t;
+    // K chunks of T arcs per step: their loads are in flight together
+    constexpr int K = T >= 8 ? 1 : 8 / T;
+    for (int32_t c0 = ab; c0 < ae; c0 += T * K) {
+      int32_t h[K], r[K], ra[K], dh[K];
+#pragma unroll
+      for (int k = 0; k < K; k++) {
+        const int32_t a = c0 + k * T + gl;
+        const bool in = a < ae;
+        h[k] = in ? V.lh[a] : 0;
+        r[k] = in ? V.rc[a] : 0;
+        ra[k] = in ? V.lr[a] : 0;
+      }
+#pragma unroll
+      for (int k = 0; k < K; k++) dh[k] = r[k] > 0 ? V.lab[h[k]] : 0x7fffffff;
+#pragma unroll
+      for (int k = 0; k < K; k++) {
+        const int32_t a = c0 + k * T + gl;
+        const int64_t adm = (r[k] > 0 && dh[k] < d) ? (int64_t)r[k] : 0;
+        int64_t inc = adm;
+        if (T > 1) {
+          for (int o = 1; o < T; o <<= 1) {
+            const int64_t t = __shfl_up(inc, o, T);
+            if (gl >= o) inc += t;
+          }
         }
-      }
-      const int64_t pre = inc - adm;
-      const int64_t tot = T > 1 ? __shfl(inc, T - 1, T) : inc;
-      int64_t amt = 0;
-      if (adm > 0 && erem > pre) amt = adm < erem - pre ? adm : erem - pre;
-      if (amt > 0) {
-        atomicSub(&V.rc[a], (int32_t)amt);
-        atomicAdd(&V.rc[V.lr[a]], (int32_t)amt);
-        const int32_t old = atomicAdd(&V.ex[h], (int32_t)amt);
-        const bool act = old == 0 && dh > 0;
+        const int64_t pre = inc - adm;
+        const int64_t tot = T > 1 ? __shfl(inc, T - 1, T) : inc;
+        int64_t amt = 0;
+        if (adm > 0 && erem > pre) amt = adm < erem - pre ? adm : erem - pre;
+        bool act = false;
+        if (amt > 0) {
+          atomicSub(&V.rc[a], (int32_t)amt);
+          atomicAdd(&V.rc[ra[k]], (int32_t)amt);
+          if (qbm) {
+            atomicAdd(&V.ex[h[k]], (int32_t)amt);
+            act = dh[k] > 0 && bm_claim(qbm, h[k]);
+          } else {
+            const int32_t old = atomicAdd(&V.ex[h[k]], (int32_t)amt);
+            act = old == 0 && dh[k] > 0;
+          }
+        }
         const int pos = wave_append(next_cnt, act);
-        if (act) put_bounded(next, pos, V.nv, h, A.ctl);
+        if (act) lput(next, pos, V.nv, h[k], A.ctl);
+        if (r[k] - amt > 0 && dh[k] < minres) minres = dh[k];
+        const int64_t used = tot < erem ? tot : erem;
+        erem -= used;
+        pushed += used;
       }
-      if (r - amt > 0 && dh < minres) minres = dh;
-      const int64_t used = tot < erem ? tot : erem;
-      erem -= used;
-      pushed += used;
     }
     if (T > 1) {
       for (int o = T >> 1; o > 0; o >>= 1) {
@@ -482,26 +543,29 @@ __device__ void pr_sweep(const KArgs &A, const PairView &V, const int32_t *cur, 
           V.lab[u] = nd;
         }
       }
-      int64_t left = e;
-      if (pushed > 0) left = (int64_t)atomicSub(&V.ex[u], (int32_t)pushed) - pushed;
-      again = left > 0 && nd < NL;
+      if (qbm) {
+        // flow pushed into u during this pass queued u already
+        if (pushed > 0) atomicSub(&V.ex[u], (int32_t)pushed);
+        again = e - pushed > 0 && nd < NL && bm_claim(qbm, u);
+      } else {
+        int64_t left = e;
+        if (pushed > 0) left = (int64_t)atomicSub(&V.ex[u], (int32_t)pushed) - pushed;
+        again = left > 0 && nd < NL;
+      }
     }
     const int pos = wave_append(next_cnt, again);
-    if (again) put_bounded(next, pos, V.nv, u, A.ctl);
+    if (again) lput(next, pos, V.nv, u, A.ctl);
   }
 }
 
 template <int TPB>
-__device__ void pr_sweep_any(const KArgs &A, const PairView &V, const int32_t *cur, int32_t cnt,
-                             int32_t *next, int32_t *next_cnt, int32_t NL,
-                             unsigned long long *wcnt) {
-  switch (A.tpv) {
-    case 1: pr_sweep<TPB, 1>(A, V, cur, cnt, next, next_cnt, NL, wcnt); break;
-    case 2: pr_sweep<TPB, 2>(A, V, cur, cnt, next, next_cnt, NL, wcnt); break;
-    case 4: pr_sweep<TPB, 4>(A, V, cur, cnt, next, next_cnt, NL, wcnt); break;
-    case 8: pr_sweep<TPB, 8>(A, V, cur, cnt, next, next_cnt, NL, wcnt); break;
-    default: pr_sweep<TPB, 16>(A, V, cur, cnt, next, next_cnt, NL, wcnt); break;
-  }
+__device__ void pr_sweep_any(const KArgs &A, const PairView &V, const ListRef &cur, int32_t cnt,
+                             const ListRef &next, int32_t *next_cnt, int32_t NL,
+                             unsigned long long *wcnt, uint32_t *qbm) {
+  // 1 and 16 lanes per vertex run as 2 and 8 (results do not depend on it)
+  if (A.tpv <= 2) pr_sweep<TPB, 2>(A, V, cur, cnt, next, next_cnt, NL, wcnt, qbm);
+  else if (A.tpv == 4) pr_sweep<TPB, 4>(A, V, cur, cnt, next, next_cnt, NL, wcnt, qbm);
+  else pr_sweep<TPB, 8>(A, V, cur, cnt, next, next_cnt, NL, wcnt, qbm);
 }
 
 template <int TPB>
@@ -520,6 +584,10 @@ struct Rot {
 // the other, so a level costs a few dependent memory latencies, not one per
 // arc.
 #define GT 8
+// The same for the searches of the flow phases (relabel, closure): GTF lanes
+// per item, each with KF arcs in flight.
+#define GTF 4
+#define KF 2
 
 // Calls f(item, valid, gl) for list items 0..N-1, one group of G lanes per
 // item; the trip count is uniform over each wave.
@@ -561,70 +629,124 @@ __device__ __forceinline__ int32_t group_exscan(int32_t v, int32_t *total) {
   return inc - v;
 }
 
+// Sets the bitmap words of vertices 0..nr-1 to the ballot of pred(i) (one
+// store per 32 vertices; words past nr come out 0).  All threads call it.
+template <typename P>
+__device__ __forceinline__ void bm_fill(uint32_t *bm, int32_t nr, P &&pred) {
+  BLOCK_WAVE_LOOP(i, nr) {
+    const bool on = i < nr && pred((int32_t)i);
+    const unsigned long long m = __ballot(on);
+    const int lane = lane64();
+    if (lane == 0) bm[i >> 5] = (uint32_t)m;
+    if (lane == 32) bm[i >> 5] = (uint32_t)(m >> 32);
+  }
+}
+
+// Frontier lists of the flow phases: slot k (0/1) pairs the global list
+// (LA/LB) with its LDS part when the bitmaps are in use.
+template <int TPB>
+__device__ __forceinline__ ListRef flist(const PairView &V, SolveShared<TPB> &sh, int k,
+                                         bool lds) {
+  ListRef L;
+  L.g = k ? V.LB : V.LA;
+  L.s = sh.u.f.ls[k];
+  L.ns = lds ? FR_LDS_LIST : 0;
+  return L;
+}
+
 // Exact distance labels: BFS from the sink border backwards over residual
 // arcs (v gets d+1 when the arc v -> w into a labelled w has residual
-// capacity); unreached vertices keep NL and are inactive.  Leaves the active
-// list (excess > 0, label < NL, not border) in LA and returns its size.
+// capacity); unreached vertices keep NL and are inactive.  With lds set the
+// visited marks are an LDS bitmap (bm[0]) and bm[1] is cleared for the
+// sweeps; otherwise labels are claimed by compare-and-swap.  Leaves the
+// active list (excess > 0, label < NL, not border) in list slot 0 and
+// returns its size.
 template <int TPB>
 __device__ int32_t global_relabel(const KArgs &A, const PairView &V, int32_t nr, int32_t NL,
-                                  SolveShared<TPB> &sh, Rot &R, int64_t &levels) {
+                                  SolveShared<TPB> &sh, Rot &R, int64_t &levels, bool lds) {
+  uint32_t *vis = sh.u.f.bm[0];
   BLOCK_WAVE_LOOP(i, nr) {
     if (i < nr) {
       const uint32_t f = V.fl[i];
       V.lab[i] = LF_SNK(f) ? 0 : (LF_SRC(f) ? NL + 1 : NL);
     }
   }
+  if (lds) {
+    bm_fill(vis, nr, [&](int32_t i) { return (V.fl[i] & LF_BORDER) != 0; });
+    bm_fill(sh.u.f.bm[1], nr, [&](int32_t) { return false; });
+  }
   if (threadIdx.x == 0) sh.cnt[(R.c + 1) % 3] = 0;
   __syncthreads();
-  const int32_t *cur = V.SNK;
-  int32_t cnt = min(sh.nsnk, (int32_t)V.nv);
+  ListRef cur;
+  cur.g = V.SNK;
+  cur.s = nullptr;
+  cur.ns = 0;
+  int32_t cnt = uni(min(sh.nsnk, (int32_t)V.nv));
   int32_t lev = 0;
-  int which = 0;  // next list: 0 -> LA, 1 -> LB
+  int which = 0;  // next list slot
   while (cnt > 0) {
-    int32_t *next = which ? V.LB : V.LA;
+    const ListRef next = flist(V, sh, which, lds);
     int32_t *ncnt = &sh.cnt[(R.c + 1) % 3];
     const int32_t nl = lev + 1;
-    for_groups<GT>(cnt, [&](int item, bool valid, int gl) {
-      const int32_t w = valid ? cur[item] : 0;
+    for_groups<GTF>(cnt, [&](int item, bool valid, int gl) {
+      const int32_t w = valid ? lget(cur, item) : 0;
       const int32_t e0 = valid ? V.lo[w] : 0, e1 = valid ? V.lo[w + 1] : 0;
       if (valid && gl == 0) {
         count_work(sh, W_GR_ITEMS, 1);
         count_work(sh, W_GR_ARCS, e1 - e0);
       }
-      for (int32_t a0 = e0; a0 < e1; a0 += GT) {
-        const int32_t a = a0 + gl;
-        bool claim = false;
-        int32_t v = 0;
-        if (a < e1) {
-          v = V.lh[a];
-          if (V.lab[v] == NL && V.rc[V.lr[a]] > 0) claim = atomicCAS(&V.lab[v], NL, nl) == NL;
+      for (int32_t c0 = e0; c0 < e1; c0 += GTF * KF) {
+        int32_t v[KF], rr[KF], r[KF];
+#pragma unroll
+        for (int k = 0; k < KF; k++) {
+          const int32_t a = c0 + k * GTF + gl;
+          v[k] = a < e1 ? V.lh[a] : 0;
+          rr[k] = a < e1 ? V.lr[a] : -1;
         }
-        const int pos = wave_append(ncnt, claim);
-        if (claim) put_bounded(next, pos, V.nv, v, A.ctl);
+#pragma unroll
+        for (int k = 0; k < KF; k++) r[k] = rr[k] >= 0 ? V.rc[rr[k]] : 0;
+#pragma unroll
+        for (int k = 0; k < KF; k++) {
+          bool claim = false;
+          if (r[k] > 0) {
+            if (lds) {
+              const bool seen = (vis[v[k] >> 5] >> (v[k] & 31)) & 1u;
+              if (!seen) {
+                claim = bm_claim(vis, v[k]);
+                if (claim) V.lab[v[k]] = nl;
+              }
+            } else if (V.lab[v[k]] == NL) {
+              claim = atomicCAS(&V.lab[v[k]], NL, nl) == NL;
+            }
+          }
+          const int pos = wave_append(ncnt, claim);
+          if (claim) lput(next, pos, V.nv, v[k], A.ctl);
+        }
       }
     });
     if (threadIdx.x == 0) sh.cnt[(R.c + 2) % 3] = 0;
     __syncthreads();
     R.c = (R.c + 1) % 3;
-    cnt = min(sh.cnt[R.c], (int32_t)V.nv);
+    cnt = uni(min(sh.cnt[R.c], (int32_t)V.nv));
     cur = next;
     which ^= 1;
     lev++;
   }
   levels += lev;
   {
+    const ListRef act_list = flist(V, sh, 0, lds);
     int32_t *ncnt = &sh.cnt[(R.c + 1) % 3];
     BLOCK_WAVE_LOOP(i, nr) {
       bool act = false;
       if (i < nr) act = !(V.fl[i] & LF_BORDER) && V.ex[i] > 0 && V.lab[i] < NL;
       const int pos = wave_append(ncnt, act);
-      if (act) put_bounded(V.LA, pos, V.nv, (int32_t)i, A.ctl);
+      if (act) lput(act_list, pos, V.nv, (int32_t)i, A.ctl);
     }
     if (threadIdx.x == 0) sh.cnt[(R.c + 2) % 3] = 0;
     __syncthreads();
     R.c = (R.c + 1) % 3;
   }
-  return min(sh.cnt[R.c], (int32_t)V.nv);
+  return uni(min(sh.cnt[R.c], (int32_t)V.nv));
 }
 
 // One flow solve of the pair at factor st.alpha; leaves its record in sh.rec
@@ -689,7 +811,7 @@ __device__ void solve_round(const KArgs &A, const PairView &V, PairState &st, in
     int32_t *cur = V.LA, *nxt = V.LB;
     int cc = 0;  // counter of the current list
     for (int32_t lev = 0;; lev++) {
-      const int32_t cnt = min(sh.cnt[cc], (int32_t)V.nv);
+      const int32_t cnt = uni(min(sh.cnt[cc], (int32_t)V.nv));
       if (threadIdx.x == 0) {
         for (int s = 0; s < 2; s++) {
           sh.mode[s] = 0;
@@ -773,7 +895,7 @@ __device__ void solve_round(const KArgs &A, const PairView &V, PairState &st, in
     }
   }
   __syncthreads();
-  const int32_t nr = min(sh.nr, (int32_t)V.nv);
+  const int32_t nr = uni(min(sh.nr, (int32_t)V.nv));
   int64_t t1 = wall_clock64();
   if (threadIdx.x == 0) st.t_corridor += t1 - t0;
   t0 = t1;
@@ -911,13 +1033,15 @@ __device__ void solve_round(const KArgs &A, const PairView &V, PairState &st, in
   t0 = t1;
   int64_t t_rel = 0, t_push = 0;
   const int32_t NL = nr + 2;
+  const bool lds = nr <= 32 * FR_BM_WORDS;
+  const int32_t nw = (nr + 31) >> 5;
   Rot R;
   int64_t gr_levels = 0, sweeps = 0, relabels = 1;
-  int32_t cnt = global_relabel<TPB>(A, V, nr, NL, sh, R, gr_levels);
+  int32_t cnt = global_relabel<TPB>(A, V, nr, NL, sh, R, gr_levels, lds);
   t1 = wall_clock64();
   t_rel += t1 - t0;
   t0 = t1;
-  int32_t *cur = V.LA, *nxt = V.LB;
+  ListRef cur = flist(V, sh, 0, lds), nxt = flist(V, sh, 1, lds);
   int since = 0;
   for (;;) {
     if (cnt == 0) {
@@ -925,13 +1049,13 @@ __device__ void solve_round(const KArgs &A, const PairView &V, PairState &st, in
       t1 = wall_clock64();
       t_push += t1 - t0;
       t0 = t1;
-      cnt = global_relabel<TPB>(A, V, nr, NL, sh, R, gr_levels);
+      cnt = global_relabel<TPB>(A, V, nr, NL, sh, R, gr_levels, lds);
       t1 = wall_clock64();
       t_rel += t1 - t0;
       t0 = t1;
       relabels++;
-      cur = V.LA;
-      nxt = V.LB;
+      cur = flist(V, sh, 0, lds);
+      nxt = flist(V, sh, 1, lds);
       since = 0;
       continue;
     }
@@ -942,12 +1066,21 @@ __device__ void solve_round(const KArgs &A, const PairView &V, PairState &st, in
       }
       break;
     }
-    pr_sweep_any<TPB>(A, V, cur, cnt, nxt, &sh.cnt[(R.c + 1) % 3], NL, sh.work);
+    // queued marks of this pass in bm[(since + 1) & 1]; the other bitmap (the
+    // previous pass's marks, or the relabel's visited marks) is cleared now
+    // and serves the next pass
+    uint32_t *qbm = nullptr;
+    if (lds) {
+      qbm = sh.u.f.bm[(since + 1) & 1];
+      uint32_t *old = sh.u.f.bm[since & 1];
+      for (int w = threadIdx.x; w < nw; w += TPB) old[w] = 0u;
+    }
+    pr_sweep_any<TPB>(A, V, cur, cnt, nxt, &sh.cnt[(R.c + 1) % 3], NL, sh.work, qbm);
     if (threadIdx.x == 0) sh.cnt[(R.c + 2) % 3] = 0;
     __syncthreads();
     R.c = (R.c + 1) % 3;
-    cnt = min(sh.cnt[R.c], (int32_t)V.nv);
-    int32_t *t = cur;
+    cnt = uni(min(sh.cnt[R.c], (int32_t)V.nv));
+    const ListRef t = cur;
     cur = nxt;
     nxt = t;
     sweeps++;
@@ -955,13 +1088,13 @@ __device__ void solve_round(const KArgs &A, const PairView &V, PairState &st, in
       t1 = wall_clock64();
       t_push += t1 - t0;
       t0 = t1;
-      cnt = global_relabel<TPB>(A, V, nr, NL, sh, R, gr_levels);
+      cnt = global_relabel<TPB>(A, V, nr, NL, sh, R, gr_levels, lds);
       t1 = wall_clock64();
       t_rel += t1 - t0;
       t0 = t1;
       relabels++;
-      cur = V.LA;
-      nxt = V.LB;
+      cur = flist(V, sh, 0, lds);
+      nxt = flist(V, sh, 1, lds);
       since = 0;
     }
   }
@@ -972,6 +1105,9 @@ __device__ void solve_round(const KArgs &A, const PairView &V, PairState &st, in
   //      of every vertex left with excess, over arcs with residual capacity
   int64_t cl_levels = 0;
   {
+    uint32_t *vis = sh.u.f.bm[0];
+    cur = flist(V, sh, 0, lds);
+    nxt = flist(V, sh, 1, lds);
     int32_t *ncnt = &sh.cnt[(R.c + 1) % 3];
     BLOCK_WAVE_LOOP(i, nr) {
       bool seed = false;
@@ -980,45 +1116,59 @@ __device__ void solve_round(const KArgs &A, const PairView &V, PairState &st, in
         seed = LF_SRC(f) || (!LF_SNK(f) && V.ex[i] > 0);
         if (seed) V.ins[i] = 1;
       }
+      if (lds) {
+        const unsigned long long m = __ballot(seed);
+        if (lane64() == 0) vis[i >> 5] = (uint32_t)m;
+        if (lane64() == 32) vis[i >> 5] = (uint32_t)(m >> 32);
+      }
       const int pos = wave_append(ncnt, seed);
-      if (seed) put_bounded(V.LA, pos, V.nv, (int32_t)i, A.ctl);
+      if (seed) lput(cur, pos, V.nv, (int32_t)i, A.ctl);
     }
     if (threadIdx.x == 0) sh.cnt[(R.c + 2) % 3] = 0;
     __syncthreads();
     R.c = (R.c + 1) % 3;
-    cnt = min(sh.cnt[R.c], (int32_t)V.nv);
-    cur = V.LA;
-    nxt = V.LB;
+    cnt = uni(min(sh.cnt[R.c], (int32_t)V.nv));
     while (cnt > 0) {
       int32_t *ncnt2 = &sh.cnt[(R.c + 1) % 3];
-      for_groups<GT>(cnt, [&](int item, bool valid, int gl) {
-        const int32_t u = valid ? cur[item] : 0;
+      for_groups<GTF>(cnt, [&](int item, bool valid, int gl) {
+        const int32_t u = valid ? lget(cur, item) : 0;
         const int32_t e0 = valid ? V.lo[u] : 0, e1 = valid ? V.lo[u + 1] : 0;
         if (valid && gl == 0) {
           count_work(sh, W_CL_ITEMS, 1);
           count_work(sh, W_CL_ARCS, e1 - e0);
         }
-        for (int32_t a0 = e0; a0 < e1; a0 += GT) {
-          const int32_t ar = a0 + gl;
-          bool claim = false;
-          int32_t v = 0;
-          if (ar < e1 && V.rc[ar] > 0) {
-            v = V.lh[ar];
-            if (V.ins[v] == 0) claim = atomicCAS(&V.ins[v], 0, 1) == 0;
+        for (int32_t c0 = e0; c0 < e1; c0 += GTF * KF) {
+          int32_t v[KF], r[KF];
+#pragma unroll
+          for (int k = 0; k < KF; k++) {
+            const int32_t ar = c0 + k * GTF + gl;
+            r[k] = ar < e1 ? V.rc[ar] : 0;
+            v[k] = ar < e1 ? V.lh[ar] : 0;
           }
-          if (claim && LF_SNK(V.fl[v])) {  // the preflow was not maximal
-            A.ctl->err = FR_E_DEVICE;
-            A.ctl->diag = DIAG_CLOSURE;
+#pragma unroll
+          for (int k = 0; k < KF; k++) {
+            bool claim = false;
+            if (r[k] > 0) {
+              if (lds) {
+                const bool seen = (vis[v[k] >> 5] >> (v[k] & 31)) & 1u;
+                if (!seen) {
+                  claim = bm_claim(vis, v[k]);
+                  if (claim) V.ins[v[k]] = 1;
+                }
+              } else if (V.ins[v[k]] == 0) {
+                claim = atomicCAS(&V.ins[v[k]], 0, 1) == 0;
+              }
+            }
+            const int pos = wave_append(ncnt2, claim);
+            if (claim) lput(nxt, pos, V.nv, v[k], A.ctl);
           }
-          const int pos = wave_append(ncnt2, claim);
-          if (claim) put_bounded(nxt, pos, V.nv, v, A.ctl);
         }
       });
       if (threadIdx.x == 0) sh.cnt[(R.c + 2) % 3] = 0;
       __syncthreads();
       R.c = (R.c + 1) % 3;
-      cnt = min(sh.cnt[R.c], (int32_t)V.nv);
-      int32_t *t = cur;
+      cnt = uni(min(sh.cnt[R.c], (int32_t)V.nv));
+      const ListRef t = cur;
       cur = nxt;
       nxt = t;
       cl_levels++;
@@ -1034,6 +1184,10 @@ __device__ void solve_round(const KArgs &A, const PairView &V, PairState &st, in
       const uint32_t f = V.fl[i];
       const int32_t w = A.vwgt[V.lg[i]];
       const bool in = V.ins[i] != 0;
+      if (in && LF_SNK(f)) {  // the closure reached the sink: the preflow was not maximal
+        A.ctl->err = FR_E_DEVICE;
+        A.ctl->diag = DIAG_CLOSURE;
+      }
       if (LF_SNK(f)) acc[0] += V.ex[i];
       if (!(f & LF_SIDE_B) && !in) acc[1] += w;
       if ((f & LF_SIDE_B) && in) acc[2] += w;
@@ -1100,15 +1254,15 @@ __global__ void __launch_bounds__(TPB) k_solve(KArgs A) {
   for (;;) {
     if (threadIdx.x == 0) sh.pair = atomicAdd(A.queue, 1);
     __syncthreads();
-    const int32_t q = sh.pair;
+    const int32_t q = uni(sh.pair);
     __syncthreads();
     if (q >= A.P) break;
-    const int32_t p = A.order[q];
+    const int32_t p = uni(A.order[q]);
     if (threadIdx.x == 0) st = A.ps[p];
     __syncthreads();
     PairView V;
-    V.a = st.a;
-    V.b = st.b;
+    V.a = uni(st.a);
+    V.b = uni(st.b);
     const int64_t vb = A.voff[p];
     V.nv = A.voff[p + 1] - vb;
     V.na = A.aoff[p + 1] - A.aoff[p];
