@@ -43,9 +43,19 @@ BYTES = {
 CORRIDOR_ARC_BYTES = 36  # reverse-arc search and writes of head / reverse / residual
 
 
+FLOW_KEYS = ("sweep_items", "sweep_arcs", "gr_items", "gr_arcs", "cl_items", "cl_arcs")
+
+
 def algorithmic_bytes(stats: dict, region_edges: int) -> int:
+    """Bytes the whole solve path must move (every phase)."""
     b = sum(stats[k] * v for k, v in BYTES.items())
     return int(b + CORRIDOR_ARC_BYTES * 2 * region_edges)
+
+
+def flow_bytes(stats: dict) -> int:
+    """Bytes the flow kernel must move: push/relabel sweeps, global relabels,
+    residual closure."""
+    return int(sum(stats[k] * BYTES[k] for k in FLOW_KEYS))
 
 
 def kernel_source_hash() -> str:
@@ -59,7 +69,7 @@ def kernel_source_hash() -> str:
 def load_traffic(workload: str):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
     taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"k_solve_{workload}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"k_flow_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -86,7 +96,7 @@ def run_plain(args, fr, torch, gen):
         dpart.copy_(part0)
         fr.flow_refine_pair(ctx, dg, dpart, w.k, 0, 1, prm)
     torch.cuda.synchronize()
-    edges, kern_ms, byts = 0, 0.0, 0
+    edges, kern_ms, byts, path_ms, path_bytes = 0, 0.0, 0, 0.0, 0
     results = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -94,15 +104,18 @@ def run_plain(args, fr, torch, gen):
         res, trace, _ = fr.flow_refine_pair(ctx, dg, dpart, w.k, 0, 1, prm)
         st = fr.stats_dict(ctx)
         edges += res["region_edges"]
-        kern_ms += st["solve_kernel_ms"]
-        byts += algorithmic_bytes(st, res["region_edges"])
+        kern_ms += st["flow_kernel_ms"]
+        byts += flow_bytes(st)
+        path_ms += st["round_ms"]
+        path_bytes += algorithmic_bytes(st, res["region_edges"])
         results.append((res, trace))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     final_part = dpart.cpu().numpy()
     ctx.close()
     return dict(w=w, edges=edges, wall=wall, kern_ms=kern_ms, bytes=byts, result=results[-1][0],
-                trace=results[-1][1], part=final_part, stats=st)
+                trace=results[-1][1], part=final_part, stats=st, path_ms=path_ms,
+                path_bytes=path_bytes, launches=args.steps * w.params["max_iters"])
 
 
 def run_cpu_baseline(w):
@@ -240,7 +253,7 @@ def main():
 
     plain = run_plain(args, fr, torch, gen)
     value = plain["edges"] / plain["wall"]
-    launches = args.steps
+    launches = plain["launches"]  # the flow kernel runs once per adaptive iteration slot
     avg_kern_s = plain["kern_ms"] / 1e3 / launches
     bytes_per_launch = plain["bytes"] / launches
     achieved = bytes_per_launch / avg_kern_s / 1e9
@@ -267,7 +280,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_solve",
+            "kernel": "k_flow",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -275,6 +288,8 @@ def main():
             "traffic": traffic,
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "avg_launch_ms": avg_kern_s * 1e3,
+            "launches_per_step": launches // args.steps,
+            "whole_path_gb_per_s": plain["path_bytes"] / (plain["path_ms"] / 1e3) / 1e9,
         },
     }
     if not args.no_cpu_baseline:

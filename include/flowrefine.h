@@ -195,16 +195,18 @@ int32_t fr_get_tuning(fr_context *ctx, fr_tuning *t);
 int32_t fr_set_validation(fr_context *ctx, int32_t on);
 
 /* Statistics of the last pair / batch call (host arrays, either may be NULL).
- * ms[8]: setup (validation, weights, arenas), the batched solve kernel,
- *   corridor phase, network build, whole call on the device, global
- *   relabels, push/relabel sweeps, closure + decision; phases 2,3,5,6,7 are
- *   device clock time summed over the pairs' workgroups.
+ * ms[8]: [0] setup (validation, weights, arenas), [1] the round (setup
+ *   kernels and every flow iteration), [2] corridor kernels (boundary and
+ *   BFS), [3] network-build kernels, [4] whole call on the device, [5]
+ *   global relabels and [6] push/relabel sweeps (device clock time summed
+ *   over the pairs' workgroups), [7] flow kernel (relabels, sweeps,
+ *   closure, decision); [1..3], [7] are HIP event times.
  * counters[32]: [0] push/relabel sweeps, [1] global relabels, [2] corridor
  *   BFS levels, [3] relabel BFS levels, [4] closure levels, [5] workgroups
- *   launched, [6] internal check that failed (0 = none); [16..27] vertices
- *   and arcs touched: boundary scan, corridor BFS, network build,
- *   push/relabel sweeps, global relabels, residual closure (vertices then
- *   arcs for each); the rest 0. */
+ *   of the per-pair kernels, [6] internal check that failed (0 = none);
+ *   [16..27] vertices and arcs touched: boundary scan, corridor BFS, network
+ *   build, push/relabel sweeps, global relabels, residual closure (vertices
+ *   then arcs for each); the rest 0. */
 int32_t fr_last_stats(fr_context *ctx, double *ms, int64_t *counters);
 
 /* ---- learned area factor (no counterpart in the paper) -----------------

@@ -224,8 +224,8 @@ WORK_KEYS = ("bnd_verts", "bnd_arcs", "bfs_items", "bfs_arcs", "net_verts", "net
 def stats_dict(ctx) -> dict:
     """fr_last_stats as a dict: phase times (ms) and work counters."""
     ms, cnt = ctx.last_stats()
-    d = dict(setup_ms=ms[0], solve_kernel_ms=ms[1], corridor_ms=ms[2], build_ms=ms[3],
-             call_ms=ms[4], relabel_ms=ms[5], push_ms=ms[6], closure_finish_ms=ms[7],
+    d = dict(setup_ms=ms[0], round_ms=ms[1], corridor_ms=ms[2], build_ms=ms[3],
+             call_ms=ms[4], relabel_ms=ms[5], push_ms=ms[6], flow_kernel_ms=ms[7],
              sweeps=cnt[0], relabels=cnt[1], bfs_levels=cnt[2], gr_levels=cnt[3],
              cl_levels=cnt[4], workgroups=cnt[5], diag=cnt[6])
     d.update({k: cnt[16 + i] for i, k in enumerate(WORK_KEYS)})

@@ -48,8 +48,8 @@ struct DevBufs {
   int32_t *pairs = nullptr, *alpha0 = nullptr, *order = nullptr;
   // per round (at most FR_MAX_PAIRS pairs)
   fr_solve *trace = nullptr;
-  int32_t *ucnt = nullptr;
-  int64_t *voff = nullptr, *aoff = nullptr, *fstat = nullptr;
+  int32_t *ucnt = nullptr, *qctr = nullptr, *pcnt = nullptr;
+  int64_t *voff = nullptr, *aoff = nullptr, *fstat = nullptr, *pacc = nullptr;
   float *feats = nullptr, *probs = nullptr;
   int64_t *base = nullptr, *scal = nullptr;
   Ctl *ctl = nullptr;
@@ -70,6 +70,8 @@ struct fr_context {
   int32_t stamp = 2;
   double wall_khz = 100000.0;  // device constant-rate clock
   int64_t graph_launches = 0;
+  hipEvent_t itev[4 * FR_MAX_ITERS] = {};
+  int32_t timed_iters = 0;
   // stats of the last call
   double ms[8] = {0};
   int64_t counters[32] = {0};
@@ -210,6 +212,7 @@ extern "C" int32_t fr_create(int32_t device, void *hip_stream, fr_context **out)
 #define A_(p, cnt) \
   if (e == hipSuccess) e = dalloc(&d.p, cnt)
   A_(trace, (int64_t)FR_MAX_PAIRS * FR_MAX_ITERS); A_(ucnt, FR_MAX_PAIRS);
+  A_(qctr, 2 * FR_MAX_ITERS); A_(pcnt, 2 * FR_MAX_PAIRS); A_(pacc, (int64_t)PA_N * FR_MAX_PAIRS);
   A_(voff, FR_MAX_PAIRS + 1); A_(aoff, FR_MAX_PAIRS + 1); A_(fstat, 4 * FR_MAX_PAIRS);
   A_(feats, MLP_IN * FR_MAX_PAIRS); A_(probs, MLP_OUT * FR_MAX_PAIRS);
   A_(base, FR_MAX_ALPHA + 1); A_(scal, 8); A_(ctl, 1);
@@ -217,6 +220,7 @@ extern "C" int32_t fr_create(int32_t device, void *hip_stream, fr_context **out)
 #undef A_
   if (e == hipSuccess) e = hipHostMalloc((void **)&c->h_ctl, sizeof(Ctl), hipHostMallocDefault);
   for (int i = 0; i < 4 && e == hipSuccess; i++) e = hipEventCreate(&c->ev[i]);
+  for (int i = 0; i < 4 * FR_MAX_ITERS && e == hipSuccess; i++) e = hipEventCreate(&c->itev[i]);
   if (e != hipSuccess) {
     fr_destroy(c);
     return FR_E_OOM;
@@ -237,11 +241,14 @@ extern "C" int32_t fr_destroy(fr_context *c) {
   DevBufs &d = c->d;
   void *ptrs[] = {d.blk2pair, d.bstat, d.qadj, d.ps,    d.pairs, d.alpha0, d.order,
                   d.trace,    d.ucnt,  d.voff, d.aoff,  d.fstat, d.feats,  d.probs,
-                  d.base,     d.scal,  d.ctl,  d.mlp,   d.mlp_m, d.mlp_v,  d.mlp_g};
+                  d.base,     d.scal,  d.ctl,  d.mlp,   d.mlp_m, d.mlp_v,  d.mlp_g,
+                  d.qctr,     d.pcnt,  d.pacc};
   for (void *q : ptrs) dfree(q);
   if (c->h_ctl) (void)hipHostFree(c->h_ctl);
   for (int i = 0; i < 4; i++)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  for (int i = 0; i < 4 * FR_MAX_ITERS; i++)
+    if (c->itev[i]) (void)hipEventDestroy(c->itev[i]);
   if (c->cs) (void)hipStreamDestroy(c->cs);
   delete c;
   return FR_OK;
@@ -293,13 +300,21 @@ static int32_t check_params(const fr_params *p) {
   return FR_OK;
 }
 
-typedef void (*solve_fn)(KArgs);
+typedef void (*iter_fn)(KArgs, int32_t);
 
-static solve_fn solve_kernel(int tpb) {
+static iter_fn corr_kernel(int tpb) {
   switch (tpb) {
-    case 256: return k_solve<256>;
-    case 512: return k_solve<512>;
-    default: return k_solve<1024>;
+    case 256: return k_corr<256>;
+    case 512: return k_corr<512>;
+    default: return k_corr<1024>;
+  }
+}
+
+static iter_fn flow_kernel(int tpb) {
+  switch (tpb) {
+    case 256: return k_flow<256>;
+    case 512: return k_flow<512>;
+    default: return k_flow<1024>;
   }
 }
 
@@ -332,7 +347,9 @@ static KArgs call_args(fr_context *c, const fr_graph *g, int32_t *dpart, int32_t
   A.part = dpart;
   A.blk2pair = d.blk2pair;
   A.bstat = d.bstat;
-  A.queue = &d.ctl->queue;
+  A.queue = d.qctr;
+  A.pacc = d.pacc;
+  A.pcnt = d.pcnt;
   A.base = d.base;
   if (p) {
     A.area_mode = p->area_mode;
@@ -419,7 +436,10 @@ static KArgs round_args(fr_context *c, const KArgs &base, int64_t off, int32_t P
 
 // All kernels of one matching round; device-only work, so a sequence of
 // rounds can be captured into a graph.
-static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t st) {
+// One round: setup kernels, then max_iters launches of the per-iteration
+// chain (pairs that stopped are skipped inside).  With timed set, events
+// around the phases of each iteration give the per-phase times.
+static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t st, bool timed) {
   DevBufs &d = c->d;
   const int sblocks = std::min(4 * c->num_cus, 8192);
   A.fstat = use_mlp ? d.fstat : nullptr;
@@ -441,10 +461,36 @@ static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t s
   const int tpb = c->tune.block_threads;
   const int64_t slots = (int64_t)c->num_cus * c->tune.blocks_per_cu;
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(A.P, slots));
-  hipLaunchKernelGGL(solve_kernel(tpb), dim3(blocks), dim3(tpb), 0, st, A);
+  const iter_fn corr = corr_kernel(tpb), flow = flow_kernel(tpb);
+  for (int32_t it = 0; it < A.max_iters; it++) {
+    hipEvent_t *ev = c->itev + 4 * it;
+    if (timed) HIPCHK(hipEventRecord(ev[0], st));
+    hipLaunchKernelGGL(k_bnd, dim3(sblocks), dim3(256), 0, st, A, it);
+    hipLaunchKernelGGL(corr, dim3(blocks), dim3(tpb), 0, st, A, it);
+    if (timed) HIPCHK(hipEventRecord(ev[1], st));
+    hipLaunchKernelGGL(k_net_count, dim3(sblocks), dim3(256), 0, st, A, it);
+    hipLaunchKernelGGL(k_net_scan, dim3(A.P), dim3(1024), 0, st, A, it);
+    hipLaunchKernelGGL(k_net_fill, dim3(sblocks), dim3(256), 0, st, A, it);
+    hipLaunchKernelGGL(k_net_rev, dim3(sblocks), dim3(256), 0, st, A, it);
+    if (timed) HIPCHK(hipEventRecord(ev[2], st));
+    hipLaunchKernelGGL(flow, dim3(blocks), dim3(tpb), 0, st, A, it);
+    if (timed) HIPCHK(hipEventRecord(ev[3], st));
+  }
   HIPCHK(hipGetLastError());
   c->counters[5] = blocks;
+  c->timed_iters = timed ? A.max_iters : 0;
   return FR_OK;
+}
+
+// per-phase event times of the last timed round: corridor, build, flow kernel
+static void iteration_times(fr_context *c, double out[3]) {
+  out[0] = out[1] = out[2] = 0.0;
+  for (int it = 0; it < c->timed_iters; it++) {
+    float t = 0.f;
+    hipEvent_t *ev = c->itev + 4 * it;
+    for (int j = 0; j < 3; j++)
+      if (hipEventElapsedTime(&t, ev[j], ev[j + 1]) == hipSuccess) out[j] += t;
+  }
 }
 
 static void fill_result(const PairState &s, fr_result &r) {
@@ -490,11 +536,13 @@ static void collect_stats(fr_context *c, const std::vector<PairState> &ps) {
   c->counters[4] = cl;
   c->counters[6] = 0;
   for (int j = 0; j < W_COUNT; j++) c->counters[16 + j] = wk[j];
-  c->ms[2] = ph[0] / c->wall_khz;
-  c->ms[3] = ph[1] / c->wall_khz;
+  double ev[3];
+  iteration_times(c, ev);
+  c->ms[2] = ev[0];
+  c->ms[3] = ev[1];
   c->ms[5] = ph[2] / c->wall_khz;
   c->ms[6] = ph[3] / c->wall_khz;
-  c->ms[7] = ph[4] / c->wall_khz;
+  c->ms[7] = ev[2];
 }
 
 static int32_t device_error(fr_context *c) {
@@ -595,7 +643,7 @@ static int32_t refine(fr_context *c, const fr_graph *g, int32_t *part, int32_t k
   if ((rc = reserve_stamps(c, p->max_iters, &stamp0))) return rc;
   const KArgs R = round_args(c, A, 0, npairs, stamp0, true);
   (void)hipEventRecord(c->ev[1], st);
-  if ((rc = enqueue_round(c, R, p->use_mlp != 0, st))) return rc;
+  if ((rc = enqueue_round(c, R, p->use_mlp != 0, st, true))) return rc;
   (void)hipEventRecord(c->ev[2], st);
   if ((rc = device_error(c))) return rc;
   if (side_out) {
@@ -770,7 +818,7 @@ extern "C" int32_t flow_refine_sweep(fr_context *c, const fr_graph *g, int32_t *
     for (int32_t r = 0; r < nrounds && cap_rc == FR_OK; r++) {
       const KArgs R = round_args(c, A, offs[r], offs[r + 1] - offs[r],
                                  stamp0 + r * (2 * p->max_iters + 2), false);
-      cap_rc = enqueue_round(c, R, p->use_mlp != 0, st);
+      cap_rc = enqueue_round(c, R, p->use_mlp != 0, st, false);
     }
     hipError_t ce = hipStreamEndCapture(st, &graph);
     if (cap_rc != FR_OK || ce != hipSuccess) {

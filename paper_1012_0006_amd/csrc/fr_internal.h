@@ -15,6 +15,8 @@ struct PairState {
   int32_t iters, applied, last_dec, iter_cap;
   int32_t start_alpha, final_alpha;
   int32_t last_nr;      // corridor vertices of the last solve
+  int32_t nr;           // corridor vertices of the current solve
+  int32_t done;         // the adaptive loop has stopped
   int64_t cA, cB;       // current block weights
   int64_t cut;          // current pair cut
   int64_t cut0;         // pair cut at call start
@@ -40,6 +42,19 @@ enum {
   W_CL_ITEMS,       // vertices expanded by the residual closure
   W_CL_ARCS,        // their corridor arcs
   W_COUNT
+};
+
+// per-pair sums of the current solve (int64 [P][PA_N]), cleared for the next
+enum {
+  PA_CUT = 0,  // pair cut
+  PA_BW0,      // boundary weight, side a / side b
+  PA_BW1,
+  PA_BC0,      // boundary vertex count, side a / side b
+  PA_BC1,
+  PA_RARCS,    // corridor arcs
+  PA_RCAP,     // their capacity sum
+  PA_RCIN,     // weight of old a-b edges inside the corridor
+  PA_N
 };
 
 struct Ctl {
@@ -70,7 +85,9 @@ struct KArgs {
   PairState *ps;            // [P]
   fr_solve *trace;          // [P * max_iters] or null
   int64_t *bstat;           // [3k] weight, vertex count, arc count per block
-  int32_t *queue;           // device counter of the pair queue of this round
+  int32_t *queue;           // [2 * max_iters] pair-queue counters: corridor and flow kernels
+  int64_t *pacc;            // [P * PA_N] per-pair sums of the current solve
+  int32_t *pcnt;            // [2P] boundary-list and sink-list counters
   int64_t *fstat;           // [4P] boundary statistics for the learned factor
   const int64_t *base;      // floor((1 + alpha eps) c(V) / k), alpha = 0..alpha_max
   int64_t lmax;

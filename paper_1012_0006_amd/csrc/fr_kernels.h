@@ -14,6 +14,7 @@
 // of a shared arena sized by the pair's vertex and arc counts.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "fr_internal.h"
@@ -175,14 +176,16 @@ __global__ void __launch_bounds__(256) k_graph_stats(KArgs A) {
 }
 
 // Start of a round (one block): block -> pair map, cleared block statistics,
-// union fill counters and pair queue.
+// union fill counters, pair queues, per-pair sums and list counters.
 __global__ void __launch_bounds__(1024) k_round_init(KArgs A) {
   for (int i = threadIdx.x; i < A.k; i += blockDim.x) A.blk2pair[i] = -1;
   for (int i = threadIdx.x; i < 3 * A.k; i += blockDim.x) A.bstat[i] = 0;
   for (int i = threadIdx.x; i < A.P; i += blockDim.x) A.ucnt[i] = 0;
   if (A.fstat)
     for (int i = threadIdx.x; i < 4 * A.P; i += blockDim.x) A.fstat[i] = 0;
-  if (threadIdx.x == 0) *A.queue = 0;
+  for (int i = threadIdx.x; i < 2 * A.max_iters; i += blockDim.x) A.queue[i] = 0;
+  for (int i = threadIdx.x; i < A.P * PA_N; i += blockDim.x) A.pacc[i] = 0;
+  for (int i = threadIdx.x; i < 2 * A.P; i += blockDim.x) A.pcnt[i] = 0;
   __syncthreads();
   for (int i = threadIdx.x; i < A.P; i += blockDim.x) {
     A.blk2pair[A.pairs[2 * i]] = i;
@@ -749,65 +752,174 @@ __device__ int32_t global_relabel(const KArgs &A, const PairView &V, int32_t nr,
   return uni(min(sh.cnt[R.c], (int32_t)V.nv));
 }
 
-// One flow solve of the pair at factor st.alpha; leaves its record in sh.rec
-// and applies an accepted candidate to the partition.
-template <int TPB>
-__device__ void solve_round(const KArgs &A, const PairView &V, PairState &st, int32_t S,
-                            SolveShared<TPB> &sh) {
-  const int32_t a = V.a, b = V.b;
-  int64_t t0 = wall_clock64();
-  // ---- boundary nodes (BFS level 0) and the pair cut (Sec. 4.1)
-  if (threadIdx.x == 0) {
-    sh.cnt[0] = sh.cnt[1] = sh.cnt[2] = 0;
-    sh.nr = 0;
-    sh.nsnk = 0;
+// ------------------------------------------------------------------------
+// One adaptive flow iteration of every pair of a round is a chain of
+// kernels: pair boundary (grid-wide), bounded BFS corridor (one workgroup
+// per pair), network build (grid-wide, with a per-pair offset scan), then
+// flow, closure, decision and factor update (one workgroup per pair).  The
+// host enqueues the chain max_iters times; launch `it` performs solve `it` of
+// every pair still iterating (all pairs start together and each solves once
+// per launch), pairs that stopped are skipped.  Bulk scans over all vertices
+// of the two blocks or of the corridor use the whole chip; the latency-bound
+// searches stay inside one workgroup and its LDS.
+
+// pair owning arena vertex slot i: voff[p] <= i < voff[p + 1]
+__device__ __forceinline__ int32_t pair_of(const int64_t *voff, int32_t P, int64_t i) {
+  int32_t lo = 0, hi = P;
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (voff[mid] <= i) lo = mid;
+    else hi = mid;
   }
-  if (threadIdx.x < W_COUNT) sh.work[threadIdx.x] = 0ull;
-  __syncthreads();
-  {
-    int64_t acc[5] = {0, 0, 0, 0, 0};  // cut, weight a, weight b, count a, count b
-    for_groups<GT>((int32_t)V.nv, [&](int item, bool valid, int gl) {
-      const int32_t u = valid ? V.uv[item] : 0;
-      const int side = valid && A.part[u] == b;
-      const int32_t y = side ? a : b;
-      const int32_t e0 = valid ? A.xadj[u] : 0, e1 = valid ? A.xadj[u + 1] : 0;
-      bool bnd = false;
-      int64_t cw = 0;
-      for (int32_t a0 = e0; a0 < e1; a0 += GT) {
-        const int32_t e = a0 + gl;
-        if (e < e1 && A.part[A.adjncy[e]] == y) {
-          bnd = true;
-          if (!side) cw += A.adjwgt[e];
-        }
+  return lo;
+}
+
+__device__ __forceinline__ PairView make_view(const KArgs &A, int32_t p) {
+  PairView V;
+  V.a = A.pairs[2 * p];
+  V.b = A.pairs[2 * p + 1];
+  const int64_t vb = A.voff[p];
+  const int64_t ab = A.aoff[p];
+  V.nv = A.voff[p + 1] - vb;
+  V.na = A.aoff[p + 1] - ab;
+  V.uv = A.uvert + vb;
+  V.lg = A.lg + vb;
+  V.lo = A.lo + vb + p;
+  V.ex = A.ex + vb;
+  V.lab = A.lab + vb;
+  V.ins = A.ins + vb;
+  V.LA = A.LA + vb;
+  V.LB = A.LB + vb;
+  V.SNK = A.SNK + vb;
+  V.fl = A.lflag + vb;
+  V.lh = A.lh + ab;
+  V.lr = A.lr + ab;
+  V.rc = A.rc + ab;
+  return V;
+}
+
+// Grid-wide version of for_groups: G lanes per item over 0..N-1, the trip
+// count uniform over each wave.
+template <int G, typename F>
+__device__ __forceinline__ void grid_groups(int64_t N, F &&f) {
+  const int gl = lane64() & (G - 1);
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t wf = (gt & ~(int64_t)63) / G;
+  const int64_t gid = gt / G;
+  const int64_t step = (int64_t)gridDim.x * blockDim.x / G;
+  for (int64_t base = wf; base < N; base += step) {
+    const int64_t item = base + (gid - wf);
+    f(item, item < N, gl);
+  }
+}
+
+// corridor item of arena slot i for a pair still iterating, else -1 (p = -1)
+__device__ __forceinline__ int64_t corridor_item(const KArgs &A, int64_t i, bool valid,
+                                                 int32_t &p) {
+  p = -1;
+  if (!valid) return -1;
+  const int32_t q = pair_of(A.voff, A.P, i);
+  if (A.ps[q].done) return -1;
+  const int64_t item = i - A.voff[q];
+  if (item >= A.ps[q].nr) return -1;
+  p = q;
+  return item;
+}
+
+#define PS_WORDS ((int)(sizeof(PairState) / 8))
+#define PS_WORK (((int)offsetof(PairState, work)) / 8)
+static_assert(sizeof(PairState) % 8 == 0, "PairState is summed as 8-byte words");
+
+// ---- pair boundary (Sec. 4.1): vertices of a with a neighbour in b and vice
+//      versa become BFS level 0 (marked with the stamp S); also the pair cut
+//      and the boundary weight and size per side
+__global__ void __launch_bounds__(256) k_bnd(KArgs A, int32_t it) {
+  const int32_t S = A.stamp0 + 2 * it;
+  unsigned long long *acc = (unsigned long long *)A.pacc;
+  unsigned long long *psw = (unsigned long long *)A.ps;
+  grid_groups<GT>(A.voff[A.P], [&](int64_t i, bool valid, int gl) {
+    int32_t p = valid ? pair_of(A.voff, A.P, i) : -1;
+    if (p >= 0 && A.ps[p].done) p = -1;
+    const bool on = p >= 0;
+    const int32_t a = on ? A.pairs[2 * p] : 0, b = on ? A.pairs[2 * p + 1] : 0;
+    const int32_t u = on ? A.uvert[i] : 0;
+    const int side = on && A.part[u] == b;
+    const int32_t y = side ? a : b;
+    const int32_t e0 = on ? A.xadj[u] : 0, e1 = on ? A.xadj[u + 1] : 0;
+    bool bnd = false;
+    int64_t cw = 0;
+    for (int32_t a0 = e0; a0 < e1; a0 += GT) {
+      const int32_t e = a0 + gl;
+      if (e < e1 && A.part[A.adjncy[e]] == y) {
+        bnd = true;
+        if (!side) cw += A.adjwgt[e];
       }
-      bnd = group_any<GT>(bnd);
-      acc[0] += cw;
-      if (valid && gl == 0) {
-        count_work(sh, W_BND_VERTS, 1);
-        count_work(sh, W_BND_ARCS, e1 - e0);
-      }
-      const bool lead = bnd && gl == 0;
-      if (lead) {
-        A.mark[u] = S;
-        acc[1 + side] += A.vwgt[u];
-        acc[3 + side] += 1;
-      }
-      const int pos = wave_append(&sh.cnt[0], lead);
-      if (lead) put_bounded(V.LA, pos, V.nv, u, A.ctl);
-    });
-    block_sums<5>(acc, sh.red);
-    int64_t Lw[2] = {acc[1], acc[2]}, Lc[2] = {acc[3], acc[4]};
+    }
+    bnd = group_any<GT>(bnd);
+    cw = group_sum<GT>(cw);
+    const bool lead = on && gl == 0;
+    const bool bl = lead && bnd;
+    const int64_t w = bl ? A.vwgt[u] : 0;
+    if (bl) A.mark[u] = S;
+    wave_add_by_key(acc, PA_N, PA_CUT, lead ? p : -1, cw);
+    wave_add_by_key(acc, PA_N, PA_BW0, (bl && !side) ? p : -1, w);
+    wave_add_by_key(acc, PA_N, PA_BW1, (bl && side) ? p : -1, w);
+    wave_add_by_key(acc, PA_N, PA_BC0, (bl && !side) ? p : -1, 1);
+    wave_add_by_key(acc, PA_N, PA_BC1, (bl && side) ? p : -1, 1);
+    wave_add_by_key(psw, PS_WORDS, PS_WORK + W_BND_VERTS, lead ? p : -1, 1);
+    wave_add_by_key(psw, PS_WORDS, PS_WORK + W_BND_ARCS, lead ? p : -1, e1 - e0);
+    const int pos = wave_append_by_key(A.pcnt, bl ? p : -1);
+    if (bl) put_bounded(A.LA + A.voff[p], pos, A.voff[p + 1] - A.voff[p], u, A.ctl);
+  });
+}
+
+// Takes the next pair of the queue for launch `it`; -1 when the queue is
+// empty.  Pairs that stopped are skipped.  All threads call it.
+template <int TPB>
+__device__ __forceinline__ int32_t next_pair(const KArgs &A, int32_t *queue,
+                                             SolveShared<TPB> &sh) {
+  for (;;) {
+    if (threadIdx.x == 0) sh.pair = atomicAdd(queue, 1);
+    __syncthreads();
+    const int32_t q = uni(sh.pair);
+    __syncthreads();
+    if (q >= A.P) return -1;
+    const int32_t p = uni(A.order[q]);
+    if (!A.ps[p].done) return p;
+  }
+}
+
+// ---- bounded BFS corridor (Sec. 4.1): level-synchronous on both sides from
+//      the boundary; a level that crosses the side's area bound is cut in
+//      ascending vertex id.  Taken vertices get local ids (lg, vmap).
+template <int TPB>
+__global__ void __launch_bounds__(TPB) k_corr(KArgs A, int32_t it) {
+  __shared__ SolveShared<TPB> sh;
+  __shared__ PairState st;
+  const int32_t S = A.stamp0 + 2 * it;
+  for (;;) {
+    const int32_t p = next_pair<TPB>(A, A.queue + 2 * it, sh);
+    if (p < 0) break;
+    const PairView V = make_view(A, p);
+    const int32_t a = V.a, b = V.b;
+    const int64_t *pa = A.pacc + (int64_t)p * PA_N;
+    int64_t t0 = wall_clock64();
     if (threadIdx.x == 0) {
+      st = A.ps[p];
+      sh.cnt[0] = min(A.pcnt[p], (int32_t)V.nv);
+      sh.cnt[1] = sh.cnt[2] = 0;
+      sh.nr = 0;
       sh.W[0] = sh.W[1] = 0;
       sh.state[0] = sh.state[1] = 1;
       const int64_t base = A.base[st.alpha];
       sh.U[0] = base - st.cB > 0 ? base - st.cB : 0;
       sh.U[1] = base - st.cA > 0 ? base - st.cA : 0;
-      if (st.cut0 < 0) st.cut0 = acc[0];
-      st.cut = acc[0];
+      if (st.cut0 < 0) st.cut0 = pa[PA_CUT];
+      st.cut = pa[PA_CUT];
     }
+    if (threadIdx.x < W_COUNT) sh.work[threadIdx.x] = 0ull;
     __syncthreads();
-    // ---- bounded BFS on both sides, level by level (Sec. 4.1)
+    int64_t Lw[2] = {pa[PA_BW0], pa[PA_BW1]}, Lc[2] = {pa[PA_BC0], pa[PA_BC1]};
     int32_t *cur = V.LA, *nxt = V.LB;
     int cc = 0;  // counter of the current list
     for (int32_t lev = 0;; lev++) {
@@ -893,75 +1005,119 @@ __device__ void solve_round(const KArgs &A, const PairView &V, PairState &st, in
       nxt = t;
       cc = (cc + 1) % 3;
     }
-  }
-  __syncthreads();
-  const int32_t nr = uni(min(sh.nr, (int32_t)V.nv));
-  int64_t t1 = wall_clock64();
-  if (threadIdx.x == 0) st.t_corridor += t1 - t0;
-  t0 = t1;
-  // ---- corridor network G' (Sec. 4.1): edges of G[B] with capacity omega in
-  //      both directions; border vertices stand for s (side a) and t (side b)
-  {
-    int64_t acc[3] = {0, 0, 0};  // arcs, capacity sum, C_in
-    for_groups<GT>(nr, [&](int item, bool valid, int gl) {
-      const int32_t u = valid ? V.lg[item] : 0;
-      const int side = valid && A.part[u] == b;
-      const int32_t e0 = valid ? A.xadj[u] : 0, e1 = valid ? A.xadj[u + 1] : 0;
-      int64_t cnt = 0;
-      bool border = false;
-      for (int32_t a0 = e0; a0 < e1; a0 += GT) {
-        const int32_t e = a0 + gl;
-        if (e >= e1) continue;
-        const int32_t v = A.adjncy[e];
-        const int32_t xv = A.part[v];
-        if (xv != a && xv != b) continue;
-        if (A.mark[v] == S) {
-          cnt++;
-          acc[1] += A.adjwgt[e];
-          if (!side && xv == b) acc[2] += A.adjwgt[e];
-        } else {
-          border = true;
-        }
-      }
-      border = group_any<GT>(border);
-      cnt = group_sum<GT>(cnt);
-      if (valid && gl == 0) {
-        count_work(sh, W_NET_VERTS, 1);
-        count_work(sh, W_NET_ARCS, e1 - e0);
-        acc[0] += cnt;
-        V.lo[item + 1] = (int32_t)cnt;
-        V.fl[item] = (uint8_t)((side ? LF_SIDE_B : 0u) | (border ? LF_BORDER : 0u));
-      }
-    });
-    block_sums<3>(acc, sh.red);
+    __syncthreads();
     if (threadIdx.x == 0) {
-      V.lo[0] = 0;
-      sh.rarcs = acc[0];
-      sh.rcap = acc[1];
-      sh.rcin = acc[2];
-      st.re_sum += acc[0] / 2;
-      st.rv_sum += nr;
-      st.last_nr = nr;
-    }
-    // offsets: each thread scans a contiguous chunk
-    const int32_t per = (nr + TPB - 1) / TPB;
-    const int32_t lo0 = threadIdx.x * per;
-    const int32_t hi0 = min(lo0 + per, nr);
-    int64_t mine = 0;
-    for (int32_t i = lo0; i < hi0; i++) mine += V.lo[i + 1];
-    int64_t tot;
-    int64_t run = block_exscan64(mine, &tot, sh.scan);
-    for (int32_t i = lo0; i < hi0; i++) {
-      run += V.lo[i + 1];
-      V.lo[i + 1] = (int32_t)run;
+      st.nr = min(sh.nr, (int32_t)V.nv);
+      for (int j = 0; j < W_COUNT; j++) st.work[j] += (int64_t)sh.work[j];
+      st.t_corridor += wall_clock64() - t0;
+      A.ps[p] = st;
     }
     __syncthreads();
   }
-  // arcs: local head and capacity, in the order of the global adjacency
-  for_groups<GT>(nr, [&](int item, bool valid, int gl) {
-    const int32_t u = valid ? V.lg[item] : 0;
-    const int32_t e0 = valid ? A.xadj[u] : 0, e1 = valid ? A.xadj[u + 1] : 0;
-    int32_t k = valid ? V.lo[item] : 0;
+}
+
+// ---- corridor network G' (Sec. 4.1), pass 1: arcs of each corridor vertex
+//      inside the corridor (edges of G[B], capacity omega both ways), border
+//      flag (a neighbour in A u B outside the corridor: merged into s or t)
+__global__ void __launch_bounds__(256) k_net_count(KArgs A, int32_t it) {
+  const int32_t S = A.stamp0 + 2 * it;
+  unsigned long long *acc = (unsigned long long *)A.pacc;
+  unsigned long long *psw = (unsigned long long *)A.ps;
+  grid_groups<GT>(A.voff[A.P], [&](int64_t i, bool valid, int gl) {
+    int32_t p;
+    const int64_t item = corridor_item(A, i, valid, p);
+    const bool on = p >= 0;
+    const int32_t a = on ? A.pairs[2 * p] : 0, b = on ? A.pairs[2 * p + 1] : 0;
+    const int32_t u = on ? A.lg[i] : 0;
+    const int side = on && A.part[u] == b;
+    const int32_t e0 = on ? A.xadj[u] : 0, e1 = on ? A.xadj[u + 1] : 0;
+    int64_t cnt = 0, cap = 0, cin = 0;
+    bool border = false;
+    for (int32_t a0 = e0; a0 < e1; a0 += GT) {
+      const int32_t e = a0 + gl;
+      if (e >= e1) continue;
+      const int32_t v = A.adjncy[e];
+      const int32_t xv = A.part[v];
+      if (xv != a && xv != b) continue;
+      if (A.mark[v] == S) {
+        cnt++;
+        cap += A.adjwgt[e];
+        if (!side && xv == b) cin += A.adjwgt[e];
+      } else {
+        border = true;
+      }
+    }
+    border = group_any<GT>(border);
+    cnt = group_sum<GT>(cnt);
+    cap = group_sum<GT>(cap);
+    cin = group_sum<GT>(cin);
+    const bool lead = on && gl == 0;
+    if (lead) {
+      A.lo[i + p + 1] = (int32_t)cnt;  // the pair's offsets start at voff[p] + p
+      A.lflag[i] = (uint8_t)((side ? LF_SIDE_B : 0u) | (border ? LF_BORDER : 0u));
+    }
+    const int key = lead ? p : -1;
+    wave_add_by_key(acc, PA_N, PA_RARCS, key, cnt);
+    wave_add_by_key(acc, PA_N, PA_RCAP, key, cap);
+    wave_add_by_key(acc, PA_N, PA_RCIN, key, cin);
+    wave_add_by_key(psw, PS_WORDS, PS_WORK + W_NET_VERTS, key, 1);
+    wave_add_by_key(psw, PS_WORDS, PS_WORK + W_NET_ARCS, key, e1 - e0);
+    (void)item;
+  });
+}
+
+// pass 2 (one block per pair): inclusive scan of the arc counts into CSR
+// offsets, 4 values per thread per tile
+__global__ void __launch_bounds__(1024) k_net_scan(KArgs A, int32_t it) {
+  __shared__ int64_t s_scan[17];
+  (void)it;
+  const int32_t p = blockIdx.x;
+  if (p >= A.P || A.ps[p].done) return;
+  const int32_t nr = uni(A.ps[p].nr);
+  int32_t *lo = A.lo + A.voff[p] + p;
+  int64_t carry = 0;
+  const int tile = 4 * (int)blockDim.x;
+  for (int32_t t0 = 0; t0 < nr; t0 += tile) {
+    const int32_t i0 = t0 + 4 * (int)threadIdx.x;
+    int32_t v[4];
+    int64_t mine = 0;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      v[j] = i0 + j < nr ? lo[i0 + j + 1] : 0;
+      mine += v[j];
+    }
+    int64_t tot;
+    int64_t run = carry + block_exscan64(mine, &tot, s_scan);
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      run += v[j];
+      if (i0 + j < nr) lo[i0 + j + 1] = (int32_t)run;
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    lo[0] = 0;
+    PairState &s = A.ps[p];
+    const int64_t *pa = A.pacc + (int64_t)p * PA_N;
+    s.re_sum += pa[PA_RARCS] / 2;
+    s.rv_sum += nr;
+    s.last_nr = nr;
+  }
+}
+
+// pass 3: arcs (local head and capacity) in the order of the global adjacency
+__global__ void __launch_bounds__(256) k_net_fill(KArgs A, int32_t it) {
+  const int32_t S = A.stamp0 + 2 * it;
+  grid_groups<GT>(A.voff[A.P], [&](int64_t i, bool valid, int gl) {
+    int32_t p;
+    const int64_t item = corridor_item(A, i, valid, p);
+    const bool on = p >= 0;
+    const int32_t a = on ? A.pairs[2 * p] : 0, b = on ? A.pairs[2 * p + 1] : 0;
+    const int32_t u = on ? A.lg[i] : 0;
+    const int32_t e0 = on ? A.xadj[u] : 0, e1 = on ? A.xadj[u + 1] : 0;
+    const int64_t ab = on ? A.aoff[p] : 0;
+    const int64_t na = on ? A.aoff[p + 1] - ab : 0;
+    int32_t k = on ? A.lo[i + p] : 0;
     for (int32_t a0 = e0; a0 < e1; a0 += GT) {
       const int32_t e = a0 + gl;
       int32_t v = 0;
@@ -973,346 +1129,347 @@ __device__ void solve_round(const KArgs &A, const PairView &V, PairState &st, in
       }
       int32_t tot;
       const int32_t off = group_exscan<GT>(in ? 1 : 0, &tot);
-      if (in && k + off < V.na) {
-        V.lh[k + off] = A.vmap[v];
-        V.rc[k + off] = A.adjwgt[e];
+      if (in && k + off < na) {
+        A.lh[ab + k + off] = A.vmap[v];
+        A.rc[ab + k + off] = A.adjwgt[e];
       }
       k += tot;
     }
+    (void)item;
   });
-  __syncthreads();
-  const bool overflow = sh.rcap >= 0x7fffffffLL;
-  // reverse arcs, initial preflow (every arc out of the source border is
-  // saturated), closure marks, sink list
-  for_groups<GT>(nr, [&](int item, bool valid, int gl) {
-    const uint32_t f = valid ? V.fl[item] : 0u;
-    const bool src = valid && LF_SRC(f);
-    const bool snk = valid && LF_SNK(f);
-    const int32_t b0 = valid ? V.lo[item] : 0, e0 = valid ? V.lo[item + 1] : 0;
+}
+
+// pass 4: reverse arcs, the initial preflow (every arc out of the source
+// border is saturated), cleared closure marks, the sink list
+__global__ void __launch_bounds__(256) k_net_rev(KArgs A, int32_t it) {
+  (void)it;
+  grid_groups<GT>(A.voff[A.P], [&](int64_t i, bool valid, int gl) {
+    int32_t p;
+    const int64_t item64 = corridor_item(A, i, valid, p);
+    const bool on = p >= 0;
+    const int32_t item = (int32_t)item64;
+    bool overflow = false;
+    int64_t vb = 0, ab = 0;
+    if (on) {
+      overflow = A.pacc[(int64_t)p * PA_N + PA_RCAP] >= 0x7fffffffLL;
+      vb = A.voff[p];
+      ab = A.aoff[p];
+    }
+    const int32_t *lo = A.lo + vb + (on ? p : 0);
+    int32_t *lh = A.lh + ab, *lr = A.lr + ab, *rc = A.rc + ab;
+    const uint8_t *fl = A.lflag + vb;
+    const uint32_t f = on ? fl[item] : 0u;
+    const bool src = on && LF_SRC(f);
+    const bool snk = on && LF_SNK(f);
+    const int32_t b0 = on ? lo[item] : 0, e0 = on ? lo[item + 1] : 0;
     int64_t ex = 0;
     for (int32_t a0 = b0; a0 < e0; a0 += GT) {
       const int32_t ar = a0 + gl;
       if (ar >= e0) continue;
-      const int32_t j = V.lh[ar];
-      const int32_t je = V.lo[j + 1];
-      int32_t r = V.lo[j];
-      while (r < je && V.lh[r] != item) r++;
+      const int32_t j = lh[ar];
+      const int32_t je = lo[j + 1];
+      int32_t r = lo[j];
+      while (r < je && lh[r] != item) r++;
       if (r == je) {  // asymmetric input slipped past validation
         A.ctl->err = FR_E_INVALID_GRAPH;
         A.ctl->diag = DIAG_REV;
         r = ar;
       }
-      V.lr[ar] = r;
-      if (!src && LF_SRC(V.fl[j]) && !overflow) {
-        const int32_t c = V.rc[ar];
+      lr[ar] = r;
+      if (!src && LF_SRC(fl[j]) && !overflow) {
+        const int32_t c = rc[ar];
         ex += c;
-        V.rc[ar] = 2 * c;
-        V.rc[r] = 0;
+        rc[ar] = 2 * c;
+        rc[r] = 0;
       }
     }
     ex = group_sum<GT>(ex);
-    if (valid && gl == 0) {
-      V.ex[item] = src ? 0 : (int32_t)ex;
-      V.ins[item] = 0;
+    if (on && gl == 0) {
+      A.ex[vb + item] = src ? 0 : (int32_t)ex;
+      A.ins[vb + item] = 0;
+      if (overflow) {
+        A.ctl->err = FR_E_OVERFLOW;
+        A.ctl->diag = DIAG_OVERFLOW;
+      }
     }
     const bool lead = snk && gl == 0;
-    const int pos = wave_append(&sh.nsnk, lead);
-    if (lead) put_bounded(V.SNK, pos, V.nv, item, A.ctl);
+    const int pos = wave_append_by_key(A.pcnt + A.P, lead ? p : -1);
+    if (lead) put_bounded(A.SNK + vb, pos, A.voff[p + 1] - vb, item, A.ctl);
   });
-  __syncthreads();
-  if (overflow) {
-    if (threadIdx.x == 0) {
-      A.ctl->err = FR_E_OVERFLOW;
-      A.ctl->diag = DIAG_OVERFLOW;
-    }
-    return;
-  }
-  // ---- maximum preflow: push/relabel sweeps with periodic global relabels
-  t1 = wall_clock64();
-  if (threadIdx.x == 0) st.t_build += t1 - t0;
-  t0 = t1;
-  int64_t t_rel = 0, t_push = 0;
-  const int32_t NL = nr + 2;
-  const bool lds = nr <= 32 * FR_BM_WORDS;
-  const int32_t nw = (nr + 31) >> 5;
-  Rot R;
-  int64_t gr_levels = 0, sweeps = 0, relabels = 1;
-  int32_t cnt = global_relabel<TPB>(A, V, nr, NL, sh, R, gr_levels, lds);
-  t1 = wall_clock64();
-  t_rel += t1 - t0;
-  t0 = t1;
-  ListRef cur = flist(V, sh, 0, lds), nxt = flist(V, sh, 1, lds);
-  int since = 0;
-  for (;;) {
-    if (cnt == 0) {
-      if (since == 0) break;  // an exact relabel found no active vertex
-      t1 = wall_clock64();
-      t_push += t1 - t0;
-      t0 = t1;
-      cnt = global_relabel<TPB>(A, V, nr, NL, sh, R, gr_levels, lds);
-      t1 = wall_clock64();
-      t_rel += t1 - t0;
-      t0 = t1;
-      relabels++;
-      cur = flist(V, sh, 0, lds);
-      nxt = flist(V, sh, 1, lds);
-      since = 0;
-      continue;
-    }
-    if (sweeps >= A.max_sweeps) {
-      if (threadIdx.x == 0) {
-        A.ctl->err = FR_E_SOLVER_LIMIT;
-        A.ctl->diag = DIAG_SWEEPS;
-      }
-      break;
-    }
-    // queued marks of this pass in bm[(since + 1) & 1]; the other bitmap (the
-    // previous pass's marks, or the relabel's visited marks) is cleared now
-    // and serves the next pass
-    uint32_t *qbm = nullptr;
-    if (lds) {
-      qbm = sh.u.f.bm[(since + 1) & 1];
-      uint32_t *old = sh.u.f.bm[since & 1];
-      for (int w = threadIdx.x; w < nw; w += TPB) old[w] = 0u;
-    }
-    pr_sweep_any<TPB>(A, V, cur, cnt, nxt, &sh.cnt[(R.c + 1) % 3], NL, sh.work, qbm);
-    if (threadIdx.x == 0) sh.cnt[(R.c + 2) % 3] = 0;
-    __syncthreads();
-    R.c = (R.c + 1) % 3;
-    cnt = uni(min(sh.cnt[R.c], (int32_t)V.nv));
-    const ListRef t = cur;
-    cur = nxt;
-    nxt = t;
-    sweeps++;
-    if (++since >= A.relabel_period) {
-      t1 = wall_clock64();
-      t_push += t1 - t0;
-      t0 = t1;
-      cnt = global_relabel<TPB>(A, V, nr, NL, sh, R, gr_levels, lds);
-      t1 = wall_clock64();
-      t_rel += t1 - t0;
-      t0 = t1;
-      relabels++;
-      cur = flist(V, sh, 0, lds);
-      nxt = flist(V, sh, 1, lds);
-      since = 0;
-    }
-  }
-  t1 = wall_clock64();
-  t_push += t1 - t0;
-  t0 = t1;
-  // ---- smallest source set (Sec. 4.1.1): closure of the source border and
-  //      of every vertex left with excess, over arcs with residual capacity
-  int64_t cl_levels = 0;
-  {
-    uint32_t *vis = sh.u.f.bm[0];
-    cur = flist(V, sh, 0, lds);
-    nxt = flist(V, sh, 1, lds);
-    int32_t *ncnt = &sh.cnt[(R.c + 1) % 3];
-    BLOCK_WAVE_LOOP(i, nr) {
-      bool seed = false;
-      if (i < nr) {
-        const uint32_t f = V.fl[i];
-        seed = LF_SRC(f) || (!LF_SNK(f) && V.ex[i] > 0);
-        if (seed) V.ins[i] = 1;
-      }
-      if (lds) {
-        const unsigned long long m = __ballot(seed);
-        if (lane64() == 0) vis[i >> 5] = (uint32_t)m;
-        if (lane64() == 32) vis[i >> 5] = (uint32_t)(m >> 32);
-      }
-      const int pos = wave_append(ncnt, seed);
-      if (seed) lput(cur, pos, V.nv, (int32_t)i, A.ctl);
-    }
-    if (threadIdx.x == 0) sh.cnt[(R.c + 2) % 3] = 0;
-    __syncthreads();
-    R.c = (R.c + 1) % 3;
-    cnt = uni(min(sh.cnt[R.c], (int32_t)V.nv));
-    while (cnt > 0) {
-      int32_t *ncnt2 = &sh.cnt[(R.c + 1) % 3];
-      for_groups<GTF>(cnt, [&](int item, bool valid, int gl) {
-        const int32_t u = valid ? lget(cur, item) : 0;
-        const int32_t e0 = valid ? V.lo[u] : 0, e1 = valid ? V.lo[u + 1] : 0;
-        if (valid && gl == 0) {
-          count_work(sh, W_CL_ITEMS, 1);
-          count_work(sh, W_CL_ARCS, e1 - e0);
-        }
-        for (int32_t c0 = e0; c0 < e1; c0 += GTF * KF) {
-          int32_t v[KF], r[KF];
-#pragma unroll
-          for (int k = 0; k < KF; k++) {
-            const int32_t ar = c0 + k * GTF + gl;
-            r[k] = ar < e1 ? V.rc[ar] : 0;
-            v[k] = ar < e1 ? V.lh[ar] : 0;
-          }
-#pragma unroll
-          for (int k = 0; k < KF; k++) {
-            bool claim = false;
-            if (r[k] > 0) {
-              if (lds) {
-                const bool seen = (vis[v[k] >> 5] >> (v[k] & 31)) & 1u;
-                if (!seen) {
-                  claim = bm_claim(vis, v[k]);
-                  if (claim) V.ins[v[k]] = 1;
-                }
-              } else if (V.ins[v[k]] == 0) {
-                claim = atomicCAS(&V.ins[v[k]], 0, 1) == 0;
-              }
-            }
-            const int pos = wave_append(ncnt2, claim);
-            if (claim) lput(nxt, pos, V.nv, v[k], A.ctl);
-          }
-        }
-      });
-      if (threadIdx.x == 0) sh.cnt[(R.c + 2) % 3] = 0;
-      __syncthreads();
-      R.c = (R.c + 1) % 3;
-      cnt = uni(min(sh.cnt[R.c], (int32_t)V.nv));
-      const ListRef t = cur;
-      cur = nxt;
-      nxt = t;
-      cl_levels++;
-    }
-  }
-  t1 = wall_clock64();
-  const int64_t t_cl = t1 - t0;
-  t0 = t1;
-  // ---- candidate partition and its balance check (Sec. 2.1)
-  int64_t acc[4] = {0, 0, 0, 0};  // flow, moved a->b, moved b->a, source side
-  BLOCK_WAVE_LOOP(i, nr) {
-    if (i < nr) {
-      const uint32_t f = V.fl[i];
-      const int32_t w = A.vwgt[V.lg[i]];
-      const bool in = V.ins[i] != 0;
-      if (in && LF_SNK(f)) {  // the closure reached the sink: the preflow was not maximal
-        A.ctl->err = FR_E_DEVICE;
-        A.ctl->diag = DIAG_CLOSURE;
-      }
-      if (LF_SNK(f)) acc[0] += V.ex[i];
-      if (!(f & LF_SIDE_B) && !in) acc[1] += w;
-      if ((f & LF_SIDE_B) && in) acc[2] += w;
-      acc[3] += in ? 1 : 0;
-    }
-  }
-  block_sums<4>(acc, sh.red);
-  if (threadIdx.x == 0) {
-    st.sweeps += sweeps;
-    st.relabels += relabels;
-    st.gr_levels += gr_levels;
-    st.cl_levels += cl_levels;
-    for (int j = 0; j < W_COUNT; j++) st.work[j] += (int64_t)sh.work[j];
-    st.t_relabel += t_rel;
-    st.t_push += t_push;
-    st.t_closure += t_cl;
-    fr_solve rec;
-    const int64_t cut = st.cut;
-    rec.alpha = st.alpha;
-    rec.flow = acc[0];
-    rec.region_vertices = nr;
-    rec.region_edges = sh.rarcs / 2;
-    rec.source_side = acc[3];
-    rec.cut_before = cut;
-    int64_t cand = cut - sh.rcin + acc[0];
-    int64_t wa = st.cA - acc[1] + acc[2];
-    int64_t wb = st.cB + acc[1] - acc[2];
-    int dec;
-    if (cut == 0) {
-      dec = FR_DEC_NOT_ADJACENT;
-      cand = 0;
-      wa = st.cA;
-      wb = st.cB;
-      rec.flow = 0;
-    } else {
-      const bool feas = wa <= A.lmax && wb <= A.lmax;
-      dec = !feas ? FR_DEC_INFEASIBLE : (cand < cut ? FR_DEC_APPLY : FR_DEC_EQUAL);
-    }
-    rec.cut_candidate = cand;
-    rec.wa = wa;
-    rec.wb = wb;
-    rec.decision = dec;
-    st.flow_last = rec.flow;
-    st.last_dec = dec;
-    st.final_alpha = st.alpha;
-    sh.rec = rec;
-  }
-  __syncthreads();
-  if (sh.rec.decision == FR_DEC_APPLY) {
-    BLOCK_WAVE_LOOP(i, nr) {
-      if (i < nr) A.part[V.lg[i]] = V.ins[i] ? a : b;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) st.t_finish += wall_clock64() - t0;
 }
 
-// Persistent workgroups, one pair at a time from the device queue; each pair
-// runs its adaptive flow iterations (Sec. 4.1) to the end.
+// ---- maximum preflow, smallest source set, balance check, write-back and
+//      the adaptive factor (Sec. 4.1), one workgroup per pair
 template <int TPB>
-__global__ void __launch_bounds__(TPB) k_solve(KArgs A) {
+__global__ void __launch_bounds__(TPB) k_flow(KArgs A, int32_t it) {
   __shared__ SolveShared<TPB> sh;
   __shared__ PairState st;
   for (;;) {
-    if (threadIdx.x == 0) sh.pair = atomicAdd(A.queue, 1);
-    __syncthreads();
-    const int32_t q = uni(sh.pair);
-    __syncthreads();
-    if (q >= A.P) break;
-    const int32_t p = uni(A.order[q]);
-    if (threadIdx.x == 0) st = A.ps[p];
-    __syncthreads();
-    PairView V;
-    V.a = uni(st.a);
-    V.b = uni(st.b);
-    const int64_t vb = A.voff[p];
-    V.nv = A.voff[p + 1] - vb;
-    V.na = A.aoff[p + 1] - A.aoff[p];
-    V.uv = A.uvert + vb;
-    V.lg = A.lg + vb;
-    V.lo = A.lo + vb + p;
-    V.ex = A.ex + vb;
-    V.lab = A.lab + vb;
-    V.ins = A.ins + vb;
-    V.LA = A.LA + vb;
-    V.LB = A.LB + vb;
-    V.SNK = A.SNK + vb;
-    V.fl = A.lflag + vb;
-    V.lh = A.lh + A.aoff[p];
-    V.lr = A.lr + A.aoff[p];
-    V.rc = A.rc + A.aoff[p];
-    for (int32_t it = 0; it < A.max_iters; it++) {
-      solve_round<TPB>(A, V, st, A.stamp0 + 2 * it, sh);
-      if (threadIdx.x == 0) {
-        const fr_solve rec = sh.rec;
-        bool stop = A.ctl->err != 0;
-        if (!stop) {
-          if (A.trace) A.trace[(int64_t)p * A.max_iters + st.iters] = rec;
-          st.iters++;
-          if (rec.decision == FR_DEC_APPLY) {
-            st.applied++;
-            st.cA = rec.wa;
-            st.cB = rec.wb;
-            st.cut = rec.cut_candidate;
-            if (!A.adaptive) stop = true;
-            else st.alpha = 2 * st.alpha < A.alpha_max ? 2 * st.alpha : A.alpha_max;
-          } else if (rec.decision == FR_DEC_INFEASIBLE) {
-            if (!A.adaptive || st.alpha == 1) stop = true;
-            else st.alpha = st.alpha / 2 > 1 ? st.alpha / 2 : 1;
-          } else {
-            stop = true;
-          }
-          if (!stop && st.iters >= A.max_iters) {
-            stop = true;
-            st.iter_cap = 1;
-          }
-        }
-        sh.stop = stop;
-      }
-      __syncthreads();
-      const bool stop = sh.stop != 0;
-      __syncthreads();
-      if (stop) break;
+    const int32_t p = next_pair<TPB>(A, A.queue + 2 * it + 1, sh);
+    if (p < 0) break;
+    const PairView V = make_view(A, p);
+    const int32_t a = V.a, b = V.b;
+    int64_t *pa = A.pacc + (int64_t)p * PA_N;
+    if (threadIdx.x == 0) {
+      st = A.ps[p];
+      sh.cnt[0] = sh.cnt[1] = sh.cnt[2] = 0;
+      sh.nsnk = min(A.pcnt[A.P + p], (int32_t)V.nv);
     }
-    if (threadIdx.x == 0) A.ps[p] = st;
+    if (threadIdx.x < W_COUNT) sh.work[threadIdx.x] = 0ull;
+    __syncthreads();
+    const int32_t nr = uni(st.nr);
+    int64_t t0 = wall_clock64(), t1;
+    int64_t t_rel = 0, t_push = 0;
+    const int32_t NL = nr + 2;
+    const bool lds = nr <= 32 * FR_BM_WORDS;
+    const int32_t nw = (nr + 31) >> 5;
+    const bool overflow = pa[PA_RCAP] >= 0x7fffffffLL;
+    Rot R;
+    int64_t gr_levels = 0, sweeps = 0, relabels = 0, cl_levels = 0;
+    if (!overflow) {
+      relabels = 1;
+      int32_t cnt = global_relabel<TPB>(A, V, nr, NL, sh, R, gr_levels, lds);
+      t1 = wall_clock64();
+      t_rel += t1 - t0;
+      t0 = t1;
+      ListRef cur = flist(V, sh, 0, lds), nxt = flist(V, sh, 1, lds);
+      int since = 0;
+      for (;;) {
+        if (cnt == 0) {
+          if (since == 0) break;  // an exact relabel found no active vertex
+          t1 = wall_clock64();
+          t_push += t1 - t0;
+          t0 = t1;
+          cnt = global_relabel<TPB>(A, V, nr, NL, sh, R, gr_levels, lds);
+          t1 = wall_clock64();
+          t_rel += t1 - t0;
+          t0 = t1;
+          relabels++;
+          cur = flist(V, sh, 0, lds);
+          nxt = flist(V, sh, 1, lds);
+          since = 0;
+          continue;
+        }
+        if (sweeps >= A.max_sweeps) {
+          if (threadIdx.x == 0) {
+            A.ctl->err = FR_E_SOLVER_LIMIT;
+            A.ctl->diag = DIAG_SWEEPS;
+          }
+          break;
+        }
+        // queued marks of this pass in bm[(since + 1) & 1]; the other bitmap
+        // (the previous pass's marks, or the relabel's visited marks) is
+        // cleared now and serves the next pass
+        uint32_t *qbm = nullptr;
+        if (lds) {
+          qbm = sh.u.f.bm[(since + 1) & 1];
+          uint32_t *old = sh.u.f.bm[since & 1];
+          for (int w = threadIdx.x; w < nw; w += TPB) old[w] = 0u;
+        }
+        pr_sweep_any<TPB>(A, V, cur, cnt, nxt, &sh.cnt[(R.c + 1) % 3], NL, sh.work, qbm);
+        if (threadIdx.x == 0) sh.cnt[(R.c + 2) % 3] = 0;
+        __syncthreads();
+        R.c = (R.c + 1) % 3;
+        cnt = uni(min(sh.cnt[R.c], (int32_t)V.nv));
+        const ListRef t = cur;
+        cur = nxt;
+        nxt = t;
+        sweeps++;
+        if (++since >= A.relabel_period) {
+          t1 = wall_clock64();
+          t_push += t1 - t0;
+          t0 = t1;
+          cnt = global_relabel<TPB>(A, V, nr, NL, sh, R, gr_levels, lds);
+          t1 = wall_clock64();
+          t_rel += t1 - t0;
+          t0 = t1;
+          relabels++;
+          cur = flist(V, sh, 0, lds);
+          nxt = flist(V, sh, 1, lds);
+          since = 0;
+        }
+      }
+      t1 = wall_clock64();
+      t_push += t1 - t0;
+      t0 = t1;
+      // ---- smallest source set (Sec. 4.1.1): closure of the source border
+      //      and of every vertex left with excess, over arcs with residual
+      //      capacity
+      {
+        uint32_t *vis = sh.u.f.bm[0];
+        cur = flist(V, sh, 0, lds);
+        nxt = flist(V, sh, 1, lds);
+        int32_t *ncnt = &sh.cnt[(R.c + 1) % 3];
+        BLOCK_WAVE_LOOP(i, nr) {
+          bool seed = false;
+          if (i < nr) {
+            const uint32_t f = V.fl[i];
+            seed = LF_SRC(f) || (!LF_SNK(f) && V.ex[i] > 0);
+            if (seed) V.ins[i] = 1;
+          }
+          if (lds) {
+            const unsigned long long m = __ballot(seed);
+            if (lane64() == 0) vis[i >> 5] = (uint32_t)m;
+            if (lane64() == 32) vis[i >> 5] = (uint32_t)(m >> 32);
+          }
+          const int pos = wave_append(ncnt, seed);
+          if (seed) lput(cur, pos, V.nv, (int32_t)i, A.ctl);
+        }
+        if (threadIdx.x == 0) sh.cnt[(R.c + 2) % 3] = 0;
+        __syncthreads();
+        R.c = (R.c + 1) % 3;
+        int32_t cnt2 = uni(min(sh.cnt[R.c], (int32_t)V.nv));
+        while (cnt2 > 0) {
+          int32_t *ncnt2 = &sh.cnt[(R.c + 1) % 3];
+          for_groups<GTF>(cnt2, [&](int item, bool valid, int gl) {
+            const int32_t u = valid ? lget(cur, item) : 0;
+            const int32_t e0 = valid ? V.lo[u] : 0, e1 = valid ? V.lo[u + 1] : 0;
+            if (valid && gl == 0) {
+              count_work(sh, W_CL_ITEMS, 1);
+              count_work(sh, W_CL_ARCS, e1 - e0);
+            }
+            for (int32_t c0 = e0; c0 < e1; c0 += GTF * KF) {
+              int32_t v[KF], r[KF];
+#pragma unroll
+              for (int k = 0; k < KF; k++) {
+                const int32_t ar = c0 + k * GTF + gl;
+                r[k] = ar < e1 ? V.rc[ar] : 0;
+                v[k] = ar < e1 ? V.lh[ar] : 0;
+              }
+#pragma unroll
+              for (int k = 0; k < KF; k++) {
+                bool claim = false;
+                if (r[k] > 0) {
+                  if (lds) {
+                    const bool seen = (vis[v[k] >> 5] >> (v[k] & 31)) & 1u;
+                    if (!seen) {
+                      claim = bm_claim(vis, v[k]);
+                      if (claim) V.ins[v[k]] = 1;
+                    }
+                  } else if (V.ins[v[k]] == 0) {
+                    claim = atomicCAS(&V.ins[v[k]], 0, 1) == 0;
+                  }
+                }
+                const int pos = wave_append(ncnt2, claim);
+                if (claim) lput(nxt, pos, V.nv, v[k], A.ctl);
+              }
+            }
+          });
+          if (threadIdx.x == 0) sh.cnt[(R.c + 2) % 3] = 0;
+          __syncthreads();
+          R.c = (R.c + 1) % 3;
+          cnt2 = uni(min(sh.cnt[R.c], (int32_t)V.nv));
+          const ListRef t = cur;
+          cur = nxt;
+          nxt = t;
+          cl_levels++;
+        }
+      }
+    }
+    t1 = wall_clock64();
+    const int64_t t_cl = t1 - t0;
+    t0 = t1;
+    // ---- candidate partition and its balance check (Sec. 2.1)
+    int64_t acc[4] = {0, 0, 0, 0};  // flow, moved a->b, moved b->a, source side
+    if (!overflow) {
+      BLOCK_WAVE_LOOP(i, nr) {
+        if (i < nr) {
+          const uint32_t f = V.fl[i];
+          const int32_t w = A.vwgt[V.lg[i]];
+          const bool in = V.ins[i] != 0;
+          if (in && LF_SNK(f)) {  // the closure reached the sink: the preflow was not maximal
+            A.ctl->err = FR_E_DEVICE;
+            A.ctl->diag = DIAG_CLOSURE;
+          }
+          if (LF_SNK(f)) acc[0] += V.ex[i];
+          if (!(f & LF_SIDE_B) && !in) acc[1] += w;
+          if ((f & LF_SIDE_B) && in) acc[2] += w;
+          acc[3] += in ? 1 : 0;
+        }
+      }
+    }
+    block_sums<4>(acc, sh.red);
+    if (threadIdx.x == 0) {
+      st.sweeps += sweeps;
+      st.relabels += relabels;
+      st.gr_levels += gr_levels;
+      st.cl_levels += cl_levels;
+      for (int j = 0; j < W_COUNT; j++) st.work[j] += (int64_t)sh.work[j];
+      st.t_relabel += t_rel;
+      st.t_push += t_push;
+      st.t_closure += t_cl;
+      fr_solve rec;
+      const int64_t cut = st.cut;
+      rec.alpha = st.alpha;
+      rec.flow = acc[0];
+      rec.region_vertices = nr;
+      rec.region_edges = pa[PA_RARCS] / 2;
+      rec.source_side = acc[3];
+      rec.cut_before = cut;
+      int64_t cand = cut - pa[PA_RCIN] + acc[0];
+      int64_t wa = st.cA - acc[1] + acc[2];
+      int64_t wb = st.cB + acc[1] - acc[2];
+      int dec;
+      if (cut == 0) {
+        dec = FR_DEC_NOT_ADJACENT;
+        cand = 0;
+        wa = st.cA;
+        wb = st.cB;
+        rec.flow = 0;
+      } else {
+        const bool feas = wa <= A.lmax && wb <= A.lmax;
+        dec = !feas ? FR_DEC_INFEASIBLE : (cand < cut ? FR_DEC_APPLY : FR_DEC_EQUAL);
+      }
+      rec.cut_candidate = cand;
+      rec.wa = wa;
+      rec.wb = wb;
+      rec.decision = dec;
+      st.flow_last = rec.flow;
+      st.last_dec = dec;
+      st.final_alpha = st.alpha;
+      sh.rec = rec;
+    }
+    __syncthreads();
+    if (sh.rec.decision == FR_DEC_APPLY && A.ctl->err == 0) {
+      BLOCK_WAVE_LOOP(i, nr) {
+        if (i < nr) A.part[V.lg[i]] = V.ins[i] ? a : b;
+      }
+    }
+    __syncthreads();
+    // ---- adaptive factor (Sec. 4.1): doubled after an applied solve,
+    //      halved after an infeasible one, stop when a feasible cut does not
+    //      improve; the sums of this solve are cleared for the next
+    if (threadIdx.x == 0) {
+      st.t_finish += wall_clock64() - t0;
+      const fr_solve rec = sh.rec;
+      bool stop = A.ctl->err != 0;
+      if (!stop) {
+        if (A.trace) A.trace[(int64_t)p * A.max_iters + st.iters] = rec;
+        st.iters++;
+        if (rec.decision == FR_DEC_APPLY) {
+          st.applied++;
+          st.cA = rec.wa;
+          st.cB = rec.wb;
+          st.cut = rec.cut_candidate;
+          if (!A.adaptive) stop = true;
+          else st.alpha = 2 * st.alpha < A.alpha_max ? 2 * st.alpha : A.alpha_max;
+        } else if (rec.decision == FR_DEC_INFEASIBLE) {
+          if (!A.adaptive || st.alpha == 1) stop = true;
+          else st.alpha = st.alpha / 2 > 1 ? st.alpha / 2 : 1;
+        } else {
+          stop = true;
+        }
+        if (!stop && st.iters >= A.max_iters) {
+          stop = true;
+          st.iter_cap = 1;
+        }
+      }
+      st.done = stop ? 1 : 0;
+      for (int j = 0; j < PA_N; j++) pa[j] = 0;
+      A.pcnt[p] = 0;
+      A.pcnt[A.P + p] = 0;
+      A.ps[p] = st;
+    }
     __syncthreads();
   }
 }
