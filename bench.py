@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "flow-refinement region edges/s + %HBM peak, batched vs plain, bit-exact cut"
 HBM_PEAK_GBS = 8000.0
+COPY_PROBE_BYTES = 512 << 20
 
 # algorithmic bytes per unit of work (4-byte ints; what each phase must read
 # or write, not what the caches do)
@@ -236,6 +237,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one device copy of 512 MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -252,6 +255,13 @@ def main():
     fr.load()  # fails loudly when the HIP library is not built
 
     plain = run_plain(args, fr, torch, gen)
+    if args.copy_probe:
+        x = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     value = plain["edges"] / plain["wall"]
     launches = plain["launches"]  # the flow kernel runs once per adaptive iteration slot
     avg_kern_s = plain["kern_ms"] / 1e3 / launches
