@@ -38,7 +38,8 @@ struct DevBufs {
   uint8_t *lflag = nullptr;
   int8_t *side = nullptr;
   // per arc
-  int32_t *lh = nullptr, *lr = nullptr, *rc = nullptr, *ga = nullptr, *gw = nullptr;
+  int32_t *lh = nullptr, *lr = nullptr, *ga = nullptr, *gw = nullptr;
+  unsigned long long *rc = nullptr;  // residual pairs (own, reverse arc)
   // per block
   int32_t *blk2pair = nullptr;
   int64_t *bstat = nullptr;  // [3k]
@@ -98,12 +99,14 @@ static hipError_t dalloc(T **p, int64_t count) {
 
 static void free_vertex_arc(DevBufs &d) {
   int32_t **v32[] = {&d.mark, &d.vmap, &d.uvert, &d.lg, &d.lo, &d.ex, &d.lab, &d.ins, &d.LA,
-                     &d.LB, &d.SNK, &d.partw, &d.parts, &d.gx, &d.gv, &d.lh, &d.lr, &d.rc,
+                     &d.LB, &d.SNK, &d.partw, &d.parts, &d.gx, &d.gv, &d.lh, &d.lr,
                      &d.ga, &d.gw};
   for (auto pp : v32) {
     dfree(*pp);
     *pp = nullptr;
   }
+  dfree(d.rc);
+  d.rc = nullptr;
   dfree(d.lflag);
   d.lflag = nullptr;
   dfree(d.side);

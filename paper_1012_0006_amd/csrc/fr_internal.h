@@ -104,7 +104,8 @@ struct KArgs {
   int32_t *lo;              // local CSR offsets (n + P slots: nv_p + 1 per pair)
   int32_t *ex, *lab, *ins, *LA, *LB, *SNK;
   uint8_t *lflag;
-  int32_t *lh, *lr, *rc;    // local arcs: head, reverse arc, residual capacity
+  int32_t *lh, *lr;         // local arcs: head, reverse arc
+  unsigned long long *rc;   // residual capacity of the arc (low 32 bits) and of its reverse (high)
   Ctl *ctl;
   // launch
   int32_t tpv, relabel_period;

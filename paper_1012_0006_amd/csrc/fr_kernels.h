@@ -413,8 +413,20 @@ struct PairView {
   const int32_t *uv;
   int32_t *lg, *lo, *ex, *lab, *ins, *LA, *LB, *SNK;
   uint8_t *fl;
-  int32_t *lh, *lr, *rc;
+  int32_t *lh, *lr;
+  unsigned long long *rc;
 };
+
+// Residual pairs: each arc holds its own residual capacity in the low 32 bits
+// and that of its reverse arc in the high 32 bits, so the backward searches
+// read r(v -> w) at the arc w -> v.  A push of x along an arc adds
+// (x << 32) - x to its pair and x - (x << 32) to the reverse arc's pair: no
+// borrow or carry crosses the halves, as residuals stay in [0, 2^31).
+__device__ __forceinline__ int32_t res_own(unsigned long long p) { return (int32_t)(uint32_t)p; }
+__device__ __forceinline__ int32_t res_rev(unsigned long long p) { return (int32_t)(uint32_t)(p >> 32); }
+__device__ __forceinline__ unsigned long long res_pair(int32_t own, int32_t rev) {
+  return ((unsigned long long)(uint32_t)rev << 32) | (uint32_t)own;
+}
 
 // A frontier list: entries below ns in LDS (s), the rest in global memory (g).
 struct ListRef {
@@ -436,6 +448,13 @@ __device__ __forceinline__ void lput(const ListRef &L, int pos, int64_t cap, int
 __device__ __forceinline__ bool bm_claim(uint32_t *bm, int32_t v) {
   const uint32_t bit = 1u << (v & 31);
   return (atomicOr(&bm[v >> 5], bit) & bit) == 0u;
+}
+
+// Work counters: every lane of the wave calls it with its count (0 for none);
+// one LDS atomic per wave instead of one per item.
+__device__ __forceinline__ void count_work_wave(unsigned long long *work, int slot, int32_t v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if (lane64() == 0 && v) atomicAdd(&work[slot], (unsigned long long)v);
 }
 
 // One push/relabel pass with T lanes per vertex over `cur` (lock-free:
@@ -476,10 +495,8 @@ __device__ void pr_sweep(const KArgs &A, const PairView &V, const ListRef &cur, 
     if (!work) ab = ae = 0;
     int64_t erem = e, pushed = 0;
     int32_t minres = 0x7fffffff;
-    if (work && gl == 0) {
-      atomicAdd(&wcnt[W_SWEEP_ITEMS], 1ull);
-      atomicAdd(&wcnt[W_SWEEP_ARCS], (unsigned long long)(ae - ab));
-    }
+    count_work_wave(wcnt, W_SWEEP_ITEMS, (work && gl == 0) ? 1 : 0);
+    count_work_wave(wcnt, W_SWEEP_ARCS, (work && gl == 0) ? ae - ab : 0);
     // K chunks of T arcs per step: their loads are in flight together
     constexpr int K = T >= 8 ? 1 : 8 / T;
     for (int32_t c0 = ab; c0 < ae; c0 += T * K) {
@@ -489,7 +506,7 @@ __device__ void pr_sweep(const KArgs &A, const PairView &V, const ListRef &cur, 
         const int32_t a = c0 + k * T + gl;
         const bool in = a < ae;
         h[k] = in ? V.lh[a] : 0;
-        r[k] = in ? V.rc[a] : 0;
+        r[k] = in ? res_own(V.rc[a]) : 0;
         ra[k] = in ? V.lr[a] : 0;
       }
 #pragma unroll
@@ -511,8 +528,9 @@ __device__ void pr_sweep(const KArgs &A, const PairView &V, const ListRef &cur, 
         if (adm > 0 && erem > pre) amt = adm < erem - pre ? adm : erem - pre;
         bool act = false;
         if (amt > 0) {
-          atomicSub(&V.rc[a], (int32_t)amt);
-          atomicAdd(&V.rc[ra[k]], (int32_t)amt);
+          const unsigned long long x = (unsigned long long)amt;
+          atomicAdd(&V.rc[a], (x << 32) - x);
+          atomicAdd(&V.rc[ra[k]], x - (x << 32));
           if (qbm) {
             atomicAdd(&V.ex[h[k]], (int32_t)amt);
             act = dh[k] > 0 && bm_claim(qbm, h[k]);
@@ -572,8 +590,8 @@ __device__ void pr_sweep_any(const KArgs &A, const PairView &V, const ListRef &c
 }
 
 template <int TPB>
-__device__ __forceinline__ void count_work(SolveShared<TPB> &sh, int slot, int64_t v) {
-  if (v) atomicAdd(&sh.work[slot], (unsigned long long)v);
+__device__ __forceinline__ void count_work(SolveShared<TPB> &sh, int slot, int32_t v) {
+  count_work_wave(sh.work, slot, v);
 }
 
 // Rotating list counters: a phase appends into cnt[(c+1)%3] while thread 0
@@ -694,20 +712,16 @@ __device__ int32_t global_relabel(const KArgs &A, const PairView &V, int32_t nr,
     for_groups<GTF>(cnt, [&](int item, bool valid, int gl) {
       const int32_t w = valid ? lget(cur, item) : 0;
       const int32_t e0 = valid ? V.lo[w] : 0, e1 = valid ? V.lo[w + 1] : 0;
-      if (valid && gl == 0) {
-        count_work(sh, W_GR_ITEMS, 1);
-        count_work(sh, W_GR_ARCS, e1 - e0);
-      }
+      count_work(sh, W_GR_ITEMS, (valid && gl == 0) ? 1 : 0);
+      count_work(sh, W_GR_ARCS, (valid && gl == 0) ? e1 - e0 : 0);
       for (int32_t c0 = e0; c0 < e1; c0 += GTF * KF) {
-        int32_t v[KF], rr[KF], r[KF];
+        int32_t v[KF], r[KF];
 #pragma unroll
         for (int k = 0; k < KF; k++) {
           const int32_t a = c0 + k * GTF + gl;
           v[k] = a < e1 ? V.lh[a] : 0;
-          rr[k] = a < e1 ? V.lr[a] : -1;
+          r[k] = a < e1 ? res_rev(V.rc[a]) : 0;
         }
-#pragma unroll
-        for (int k = 0; k < KF; k++) r[k] = rr[k] >= 0 ? V.rc[rr[k]] : 0;
 #pragma unroll
         for (int k = 0; k < KF; k++) {
           bool claim = false;
@@ -975,10 +989,8 @@ __global__ void __launch_bounds__(TPB) k_corr(KArgs A, int32_t it) {
         const int s = x == b;
         const bool go = valid && sh.state[s];
         const int32_t e0 = go ? A.xadj[u] : 0, e1 = go ? A.xadj[u + 1] : 0;
-        if (go && gl == 0) {
-          count_work(sh, W_BFS_ITEMS, 1);
-          count_work(sh, W_BFS_ARCS, e1 - e0);
-        }
+        count_work(sh, W_BFS_ITEMS, (go && gl == 0) ? 1 : 0);
+        count_work(sh, W_BFS_ARCS, (go && gl == 0) ? e1 - e0 : 0);
         for (int32_t a0 = e0; a0 < e1; a0 += GT) {
           const int32_t e = a0 + gl;
           bool claim = false;
@@ -1131,7 +1143,7 @@ __global__ void __launch_bounds__(256) k_net_fill(KArgs A, int32_t it) {
       const int32_t off = group_exscan<GT>(in ? 1 : 0, &tot);
       if (in && k + off < na) {
         A.lh[ab + k + off] = A.vmap[v];
-        A.rc[ab + k + off] = A.adjwgt[e];
+        A.rc[ab + k + off] = res_pair(A.adjwgt[e], A.adjwgt[e]);
       }
       k += tot;
     }
@@ -1156,7 +1168,8 @@ __global__ void __launch_bounds__(256) k_net_rev(KArgs A, int32_t it) {
       ab = A.aoff[p];
     }
     const int32_t *lo = A.lo + vb + (on ? p : 0);
-    int32_t *lh = A.lh + ab, *lr = A.lr + ab, *rc = A.rc + ab;
+    int32_t *lh = A.lh + ab, *lr = A.lr + ab;
+    unsigned long long *rc = A.rc + ab;
     const uint8_t *fl = A.lflag + vb;
     const uint32_t f = on ? fl[item] : 0u;
     const bool src = on && LF_SRC(f);
@@ -1177,10 +1190,10 @@ __global__ void __launch_bounds__(256) k_net_rev(KArgs A, int32_t it) {
       }
       lr[ar] = r;
       if (!src && LF_SRC(fl[j]) && !overflow) {
-        const int32_t c = rc[ar];
+        const int32_t c = res_own(rc[ar]);
         ex += c;
-        rc[ar] = 2 * c;
-        rc[r] = 0;
+        rc[ar] = res_pair(2 * c, 0);
+        rc[r] = res_pair(0, 2 * c);
       }
     }
     ex = group_sum<GT>(ex);
@@ -1324,16 +1337,14 @@ __global__ void __launch_bounds__(TPB) k_flow(KArgs A, int32_t it) {
           for_groups<GTF>(cnt2, [&](int item, bool valid, int gl) {
             const int32_t u = valid ? lget(cur, item) : 0;
             const int32_t e0 = valid ? V.lo[u] : 0, e1 = valid ? V.lo[u + 1] : 0;
-            if (valid && gl == 0) {
-              count_work(sh, W_CL_ITEMS, 1);
-              count_work(sh, W_CL_ARCS, e1 - e0);
-            }
+            count_work(sh, W_CL_ITEMS, (valid && gl == 0) ? 1 : 0);
+            count_work(sh, W_CL_ARCS, (valid && gl == 0) ? e1 - e0 : 0);
             for (int32_t c0 = e0; c0 < e1; c0 += GTF * KF) {
               int32_t v[KF], r[KF];
 #pragma unroll
               for (int k = 0; k < KF; k++) {
                 const int32_t ar = c0 + k * GTF + gl;
-                r[k] = ar < e1 ? V.rc[ar] : 0;
+                r[k] = ar < e1 ? res_own(V.rc[ar]) : 0;
                 v[k] = ar < e1 ? V.lh[ar] : 0;
               }
 #pragma unroll
