@@ -49,8 +49,9 @@ struct DevBufs {
   int32_t *pairs = nullptr, *alpha0 = nullptr, *order = nullptr;
   // per round (at most FR_MAX_PAIRS pairs)
   fr_solve *trace = nullptr;
-  int32_t *ucnt = nullptr, *qctr = nullptr, *pcnt = nullptr;
-  int64_t *voff = nullptr, *aoff = nullptr, *fstat = nullptr, *pacc = nullptr;
+  int32_t *ucnt = nullptr, *qctr = nullptr, *pcnt = nullptr, *act = nullptr, *nact = nullptr;
+  int64_t *voff = nullptr, *aoff = nullptr, *fstat = nullptr, *pacc = nullptr, *vpre = nullptr,
+          *cpre = nullptr;
   float *feats = nullptr, *probs = nullptr;
   int64_t *base = nullptr, *scal = nullptr;
   Ctl *ctl = nullptr;
@@ -216,6 +217,7 @@ extern "C" int32_t fr_create(int32_t device, void *hip_stream, fr_context **out)
   if (e == hipSuccess) e = dalloc(&d.p, cnt)
   A_(trace, (int64_t)FR_MAX_PAIRS * FR_MAX_ITERS); A_(ucnt, FR_MAX_PAIRS);
   A_(qctr, 2 * FR_MAX_ITERS); A_(pcnt, 2 * FR_MAX_PAIRS); A_(pacc, (int64_t)PA_N * FR_MAX_PAIRS);
+  A_(act, FR_MAX_PAIRS); A_(nact, 1); A_(vpre, FR_MAX_PAIRS + 1); A_(cpre, FR_MAX_PAIRS + 1);
   A_(voff, FR_MAX_PAIRS + 1); A_(aoff, FR_MAX_PAIRS + 1); A_(fstat, 4 * FR_MAX_PAIRS);
   A_(feats, MLP_IN * FR_MAX_PAIRS); A_(probs, MLP_OUT * FR_MAX_PAIRS);
   A_(base, FR_MAX_ALPHA + 1); A_(scal, 8); A_(ctl, 1);
@@ -245,7 +247,7 @@ extern "C" int32_t fr_destroy(fr_context *c) {
   void *ptrs[] = {d.blk2pair, d.bstat, d.qadj, d.ps,    d.pairs, d.alpha0, d.order,
                   d.trace,    d.ucnt,  d.voff, d.aoff,  d.fstat, d.feats,  d.probs,
                   d.base,     d.scal,  d.ctl,  d.mlp,   d.mlp_m, d.mlp_v,  d.mlp_g,
-                  d.qctr,     d.pcnt,  d.pacc};
+                  d.qctr,     d.pcnt,  d.pacc, d.act,   d.nact,  d.vpre,   d.cpre};
   for (void *q : ptrs) dfree(q);
   if (c->h_ctl) (void)hipHostFree(c->h_ctl);
   for (int i = 0; i < 4; i++)
@@ -353,6 +355,10 @@ static KArgs call_args(fr_context *c, const fr_graph *g, int32_t *dpart, int32_t
   A.queue = d.qctr;
   A.pacc = d.pacc;
   A.pcnt = d.pcnt;
+  A.act = d.act;
+  A.nact = d.nact;
+  A.vpre = d.vpre;
+  A.cpre = d.cpre;
   A.base = d.base;
   if (p) {
     A.area_mode = p->area_mode;
@@ -468,8 +474,10 @@ static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t s
   for (int32_t it = 0; it < A.max_iters; it++) {
     hipEvent_t *ev = c->itev + 4 * it;
     if (timed) HIPCHK(hipEventRecord(ev[0], st));
+    hipLaunchKernelGGL(k_iter_begin, dim3(1), dim3(1024), 0, st, A, it);
     hipLaunchKernelGGL(k_bnd, dim3(sblocks), dim3(256), 0, st, A, it);
     hipLaunchKernelGGL(corr, dim3(blocks), dim3(tpb), 0, st, A, it);
+    hipLaunchKernelGGL(k_iter_mid, dim3(1), dim3(1024), 0, st, A, it);
     if (timed) HIPCHK(hipEventRecord(ev[1], st));
     hipLaunchKernelGGL(k_net_count, dim3(sblocks), dim3(256), 0, st, A, it);
     hipLaunchKernelGGL(k_net_scan, dim3(A.P), dim3(1024), 0, st, A, it);

@@ -88,6 +88,10 @@ struct KArgs {
   int32_t *queue;           // [2 * max_iters] pair-queue counters: corridor and flow kernels
   int64_t *pacc;            // [P * PA_N] per-pair sums of the current solve
   int32_t *pcnt;            // [2P] boundary-list and sink-list counters
+  // pairs still iterating in the current launch, compacted: act[0..nact),
+  // prefix sums of their union sizes (vpre) and corridor sizes (cpre)
+  int32_t *act, *nact;
+  int64_t *vpre, *cpre;
   int64_t *fstat;           // [4P] boundary statistics for the learned factor
   const int64_t *base;      // floor((1 + alpha eps) c(V) / k), alpha = 0..alpha_max
   int64_t lmax;

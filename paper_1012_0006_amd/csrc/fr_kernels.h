@@ -827,17 +827,94 @@ __device__ __forceinline__ void grid_groups(int64_t N, F &&f) {
   }
 }
 
-// corridor item of arena slot i for a pair still iterating, else -1 (p = -1)
-__device__ __forceinline__ int64_t corridor_item(const KArgs &A, int64_t i, bool valid,
-                                                 int32_t &p) {
+// Item i of the compacted range of the pairs still iterating: the pair p and
+// the item's offset inside that pair (pre = vpre or cpre); p = -1 past the end.
+__device__ __forceinline__ int64_t active_item(const KArgs &A, const int64_t *pre, int64_t i,
+                                               bool valid, int32_t &p) {
   p = -1;
   if (!valid) return -1;
-  const int32_t q = pair_of(A.voff, A.P, i);
-  if (A.ps[q].done) return -1;
-  const int64_t item = i - A.voff[q];
-  if (item >= A.ps[q].nr) return -1;
-  p = q;
-  return item;
+  const int32_t j = pair_of(pre, *A.nact, i);
+  p = A.act[j];
+  return i - pre[j];
+}
+
+// Per-lane running sums of N per-pair quantities, added to their per-pair
+// totals (dst[j][key * stride[j] + slot[j]]) only when the lane's pair
+// changes and at the end, so a kernel over many items of few pairs issues few
+// atomics.  Every lane of the wave calls add() and flush().
+template <int N>
+struct KeyedSums {
+  int key = -1;
+  int64_t v[N];
+  __device__ KeyedSums() {
+    for (int j = 0; j < N; j++) v[j] = 0;
+  }
+  template <typename Out>
+  __device__ __forceinline__ void add(int k, const int64_t (&x)[N], Out &&out) {
+    const bool change = key >= 0 && k >= 0 && k != key;
+    if (__ballot(change)) {
+      for (int j = 0; j < N; j++) out(j, change ? key : -1, v[j]);
+      if (change)
+        for (int j = 0; j < N; j++) v[j] = 0;
+    }
+    if (k >= 0) {
+      key = k;
+      for (int j = 0; j < N; j++) v[j] += x[j];
+    }
+  }
+  template <typename Out>
+  __device__ __forceinline__ void flush(Out &&out) {
+    for (int j = 0; j < N; j++) out(j, key, v[j]);
+  }
+};
+
+// Start of launch `it` (one block): the pairs still iterating, compacted in
+// pair order, and the prefix sums of their union sizes.
+__global__ void __launch_bounds__(1024) k_iter_begin(KArgs A, int32_t it) {
+  __shared__ int64_t s_scan[17];
+  (void)it;
+  const int P = A.P;
+  const int per = (P + blockDim.x - 1) / blockDim.x;
+  const int lo = threadIdx.x * per, hi = min(lo + per, P);
+  int64_t cnt = 0, sz = 0;
+  for (int i = lo; i < hi; i++)
+    if (!A.ps[i].done) {
+      cnt++;
+      sz += A.voff[i + 1] - A.voff[i];
+    }
+  int64_t tc, ts;
+  int64_t rc = block_exscan64(cnt, &tc, s_scan);
+  int64_t rs = block_exscan64(sz, &ts, s_scan);
+  for (int i = lo; i < hi; i++)
+    if (!A.ps[i].done) {
+      A.act[rc] = i;
+      A.vpre[rc] = rs;
+      rc++;
+      rs += A.voff[i + 1] - A.voff[i];
+    }
+  if (threadIdx.x == 0) {
+    *A.nact = (int32_t)tc;
+    A.vpre[tc] = ts;
+  }
+}
+
+// After the corridor kernel (one block): prefix sums of the active pairs'
+// corridor sizes.
+__global__ void __launch_bounds__(1024) k_iter_mid(KArgs A, int32_t it) {
+  __shared__ int64_t s_scan[17];
+  (void)it;
+  const int na = *A.nact;
+  const int per = (na + blockDim.x - 1) / blockDim.x;
+  const int lo = threadIdx.x * per, hi = min(lo + per, na);
+  int64_t sz = 0;
+  for (int j = lo; j < hi; j++) sz += A.ps[A.act[j]].nr;
+  int64_t ts;
+  int64_t rs = block_exscan64(sz, &ts, s_scan);
+  for (int j = lo; j < hi; j++) {
+    A.cpre[j] = rs;
+    rs += A.ps[A.act[j]].nr;
+  }
+  if (threadIdx.x == 0) A.cpre[na] = ts;
 }
 
 #define PS_WORDS ((int)(sizeof(PairState) / 8))
@@ -851,12 +928,18 @@ __global__ void __launch_bounds__(256) k_bnd(KArgs A, int32_t it) {
   const int32_t S = A.stamp0 + 2 * it;
   unsigned long long *acc = (unsigned long long *)A.pacc;
   unsigned long long *psw = (unsigned long long *)A.ps;
-  grid_groups<GT>(A.voff[A.P], [&](int64_t i, bool valid, int gl) {
-    int32_t p = valid ? pair_of(A.voff, A.P, i) : -1;
-    if (p >= 0 && A.ps[p].done) p = -1;
+  // pair cut, boundary weight a / b, boundary count a / b, vertices, arcs
+  KeyedSums<7> sums;
+  auto out = [&](int j, int key, int64_t v) {
+    if (j < 5) wave_add_by_key(acc, PA_N, PA_CUT + j, key, v);
+    else wave_add_by_key(psw, PS_WORDS, PS_WORK + (j == 5 ? W_BND_VERTS : W_BND_ARCS), key, v);
+  };
+  grid_groups<GT>(A.vpre[*A.nact], [&](int64_t i, bool valid, int gl) {
+    int32_t p;
+    const int64_t slot = active_item(A, A.vpre, i, valid, p);
     const bool on = p >= 0;
     const int32_t a = on ? A.pairs[2 * p] : 0, b = on ? A.pairs[2 * p + 1] : 0;
-    const int32_t u = on ? A.uvert[i] : 0;
+    const int32_t u = on ? A.uvert[A.voff[p] + slot] : 0;
     const int side = on && A.part[u] == b;
     const int32_t y = side ? a : b;
     const int32_t e0 = on ? A.xadj[u] : 0, e1 = on ? A.xadj[u + 1] : 0;
@@ -875,16 +958,13 @@ __global__ void __launch_bounds__(256) k_bnd(KArgs A, int32_t it) {
     const bool bl = lead && bnd;
     const int64_t w = bl ? A.vwgt[u] : 0;
     if (bl) A.mark[u] = S;
-    wave_add_by_key(acc, PA_N, PA_CUT, lead ? p : -1, cw);
-    wave_add_by_key(acc, PA_N, PA_BW0, (bl && !side) ? p : -1, w);
-    wave_add_by_key(acc, PA_N, PA_BW1, (bl && side) ? p : -1, w);
-    wave_add_by_key(acc, PA_N, PA_BC0, (bl && !side) ? p : -1, 1);
-    wave_add_by_key(acc, PA_N, PA_BC1, (bl && side) ? p : -1, 1);
-    wave_add_by_key(psw, PS_WORDS, PS_WORK + W_BND_VERTS, lead ? p : -1, 1);
-    wave_add_by_key(psw, PS_WORDS, PS_WORK + W_BND_ARCS, lead ? p : -1, e1 - e0);
+    const int64_t x[7] = {cw, bl && !side ? w : 0, bl && side ? w : 0, bl && !side ? 1 : 0,
+                          bl && side ? 1 : 0, 1, e1 - e0};
+    sums.add(lead ? p : -1, x, out);
     const int pos = wave_append_by_key(A.pcnt, bl ? p : -1);
     if (bl) put_bounded(A.LA + A.voff[p], pos, A.voff[p + 1] - A.voff[p], u, A.ctl);
   });
+  sums.flush(out);
 }
 
 // Takes the next pair of the queue for launch `it`; -1 when the queue is
@@ -1035,9 +1115,16 @@ __global__ void __launch_bounds__(256) k_net_count(KArgs A, int32_t it) {
   const int32_t S = A.stamp0 + 2 * it;
   unsigned long long *acc = (unsigned long long *)A.pacc;
   unsigned long long *psw = (unsigned long long *)A.ps;
-  grid_groups<GT>(A.voff[A.P], [&](int64_t i, bool valid, int gl) {
+  // corridor arcs, capacity sum, old a-b weight inside, vertices, arcs scanned
+  KeyedSums<5> sums;
+  auto out = [&](int j, int key, int64_t v) {
+    if (j < 3) wave_add_by_key(acc, PA_N, PA_RARCS + j, key, v);
+    else wave_add_by_key(psw, PS_WORDS, PS_WORK + (j == 3 ? W_NET_VERTS : W_NET_ARCS), key, v);
+  };
+  grid_groups<GT>(A.cpre[*A.nact], [&](int64_t i0, bool valid, int gl) {
     int32_t p;
-    const int64_t item = corridor_item(A, i, valid, p);
+    const int64_t item = active_item(A, A.cpre, i0, valid, p);
+    const int64_t i = p >= 0 ? A.voff[p] + item : 0;  // arena slot
     const bool on = p >= 0;
     const int32_t a = on ? A.pairs[2 * p] : 0, b = on ? A.pairs[2 * p + 1] : 0;
     const int32_t u = on ? A.lg[i] : 0;
@@ -1068,14 +1155,11 @@ __global__ void __launch_bounds__(256) k_net_count(KArgs A, int32_t it) {
       A.lo[i + p + 1] = (int32_t)cnt;  // the pair's offsets start at voff[p] + p
       A.lflag[i] = (uint8_t)((side ? LF_SIDE_B : 0u) | (border ? LF_BORDER : 0u));
     }
-    const int key = lead ? p : -1;
-    wave_add_by_key(acc, PA_N, PA_RARCS, key, cnt);
-    wave_add_by_key(acc, PA_N, PA_RCAP, key, cap);
-    wave_add_by_key(acc, PA_N, PA_RCIN, key, cin);
-    wave_add_by_key(psw, PS_WORDS, PS_WORK + W_NET_VERTS, key, 1);
-    wave_add_by_key(psw, PS_WORDS, PS_WORK + W_NET_ARCS, key, e1 - e0);
+    const int64_t x[5] = {cnt, cap, cin, 1, e1 - e0};
+    sums.add(lead ? p : -1, x, out);
     (void)item;
   });
+  sums.flush(out);
 }
 
 // pass 2 (one block per pair): inclusive scan of the arc counts into CSR
@@ -1120,9 +1204,10 @@ __global__ void __launch_bounds__(1024) k_net_scan(KArgs A, int32_t it) {
 // pass 3: arcs (local head and capacity) in the order of the global adjacency
 __global__ void __launch_bounds__(256) k_net_fill(KArgs A, int32_t it) {
   const int32_t S = A.stamp0 + 2 * it;
-  grid_groups<GT>(A.voff[A.P], [&](int64_t i, bool valid, int gl) {
+  grid_groups<GT>(A.cpre[*A.nact], [&](int64_t i0, bool valid, int gl) {
     int32_t p;
-    const int64_t item = corridor_item(A, i, valid, p);
+    const int64_t item = active_item(A, A.cpre, i0, valid, p);
+    const int64_t i = p >= 0 ? A.voff[p] + item : 0;  // arena slot
     const bool on = p >= 0;
     const int32_t a = on ? A.pairs[2 * p] : 0, b = on ? A.pairs[2 * p + 1] : 0;
     const int32_t u = on ? A.lg[i] : 0;
@@ -1155,9 +1240,9 @@ __global__ void __launch_bounds__(256) k_net_fill(KArgs A, int32_t it) {
 // border is saturated), cleared closure marks, the sink list
 __global__ void __launch_bounds__(256) k_net_rev(KArgs A, int32_t it) {
   (void)it;
-  grid_groups<GT>(A.voff[A.P], [&](int64_t i, bool valid, int gl) {
+  grid_groups<GT>(A.cpre[*A.nact], [&](int64_t i0, bool valid, int gl) {
     int32_t p;
-    const int64_t item64 = corridor_item(A, i, valid, p);
+    const int64_t item64 = active_item(A, A.cpre, i0, valid, p);
     const bool on = p >= 0;
     const int32_t item = (int32_t)item64;
     bool overflow = false;
