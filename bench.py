@@ -128,10 +128,11 @@ def run_cpu_baseline(w):
     return o, dt
 
 
-def run_batched(args, fr, torch, gen):
-    """One matching round of C3 (3D RGG n=2^20, mean degree 12, k=16 RCB +
-    2 % noise): all pairs in one batched launch vs the pairs one by one."""
-    w = gen.config("C3")
+def run_batched(args, fr, torch, gen, cid="C3"):
+    """The largest matching round of a workload (C3: 3D RGG n=2^20, mean
+    degree 12, k=16 RCB + 2 % noise; C5: 2D RGG n=2^24, k=256): all pairs in
+    one batched launch vs the pairs one by one."""
+    w = gen.config(cid)
     ctx = fr.Context()
     ctx.set_validation(False)
     dg = fr.DeviceGraph.from_host(w.graph)
@@ -172,9 +173,11 @@ def run_batched(args, fr, torch, gen):
     e_p = sum(r["region_edges"] for r in res_p)
     same = bool(np.array_equal(part_b, part_p)) and all(
         rb["cut_after"] == rp["cut_after"] for rb, rp in zip(res_b, res_p))
+    desc = {"C3": "C3: 3D RGG n=2^20 mean degree 12 unit weights, k=16 RCB + 2% noise",
+            "C5": "C5: 2D RGG n=2^24 mean degree 6 unit weights, k=256 RCB + 1% noise"}[cid]
     return {
-        "workload": "C3: 3D RGG n=2^20 mean degree 12 unit weights, k=16 RCB + 2% noise, "
-                    f"largest matching round ({len(pairs)} pairs), eps 3%, alpha 16 adaptive",
+        "workload": f"{desc}, largest matching round ({len(pairs)} pairs), eps 3%, "
+                    "alpha 16 adaptive",
         "pairs": len(pairs),
         "batched_region_edges_per_s": e_b / t_b,
         "plain_region_edges_per_s": e_p / t_p,
@@ -353,6 +356,8 @@ def main():
         line["bit_exact_vs_oracle"] = bool(exact)
     if not args.no_batched:
         line["batched"] = run_batched(args, fr, torch, gen)
+        line["batched_c5_round"] = run_batched(argparse.Namespace(batch_reps=1), fr, torch, gen,
+                                               "C5")
     if not args.no_learned:
         line["learned_factor"] = run_learned(args, fr, torch, gen)
     if not args.no_sweep:
