@@ -163,6 +163,10 @@ class DeviceGraph:
         return FrGraph(self.n, 1, self.xadj.data_ptr(), self.adjncy.data_ptr(),
                        self.adjwgt.data_ptr(), self.vwgt.data_ptr())
 
+    @property
+    def narcs(self) -> int:
+        return int(self.adjncy.shape[0])
+
 
 def host_graph_struct(g):
     """FrGraph over host numpy arrays (the library copies them); returns
@@ -403,6 +407,57 @@ def fr_autotune(ctx: Context, graph: DeviceGraph, part, k: int, pairs, prm: FrPa
                                pr.ctypes.data, pr.shape[0] // 2, ctypes.byref(prm), cand,
                                len(candidates), reps, ms, ctypes.byref(best)), "fr_autotune")
     return int(best.value), list(ms)
+
+
+DEFAULT_CANDIDATES = (
+    dict(block_threads=1024, blocks_per_cu=2, tpv=4, relabel_period=200),
+    dict(block_threads=1024, blocks_per_cu=2, tpv=4, relabel_period=100),
+    dict(block_threads=1024, blocks_per_cu=2, tpv=8, relabel_period=100),
+    dict(block_threads=1024, blocks_per_cu=2, tpv=2, relabel_period=200),
+    dict(block_threads=512, blocks_per_cu=4, tpv=4, relabel_period=200),
+    dict(block_threads=256, blocks_per_cu=8, tpv=4, relabel_period=200),
+)
+
+
+def tuning_key(arch: str, n: int, narcs: int, npairs: int) -> str:
+    """Cache key of a workload: GPU architecture, log2 bucket of the vertex
+    count, mean-degree bucket and log2 bucket of the pairs per round."""
+    deg = narcs / max(1, n)
+    return (f"{arch}|n2^{max(0, int(n).bit_length() - 1)}|deg{int(round(deg))}"
+            f"|pairs2^{max(0, int(npairs).bit_length() - 1)}")
+
+
+def autotune_cached(ctx: Context, graph: "DeviceGraph", part, k: int, pairs, prm: FrParams,
+                    cache_path: str | None = None, candidates=DEFAULT_CANDIDATES, reps: int = 2,
+                    arch: str | None = None) -> dict:
+    """Tuning for this workload from a JSON cache keyed by tuning_key, or
+    found by fr_autotune (and stored) on a miss; the tuning is set on the
+    context and returned."""
+    import json
+
+    if arch is None:
+        import torch
+
+        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    if cache_path is None:
+        cache_path = os.path.join(os.path.expanduser("~"), ".cache", "flowrefine", "tuning.json")
+    key = tuning_key(arch, graph.n, graph.narcs, len(pairs))
+    cache = {}
+    if os.path.exists(cache_path):
+        with open(cache_path) as fh:
+            cache = json.load(fh)
+    if key in cache:
+        ctx.set_tuning(**cache[key]["tuning"])
+        return cache[key]["tuning"]
+    best, ms = fr_autotune(ctx, graph, part, k, pairs, prm, list(candidates), reps)
+    tuning = dict(candidates[best])
+    cache[key] = {"tuning": tuning, "ms": ms}
+    os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)
+    tmp = cache_path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(cache, fh, indent=1)
+    os.replace(tmp, cache_path)
+    return tuning
 
 
 TRAINED_WEIGHTS = os.path.join(_HERE, "mlp_area_factor.json")

@@ -64,3 +64,38 @@ def test_mlp_parameter_count():
     if not os.path.exists(fr.LIB_PATH):
         pytest.skip("library not built")
     assert fr.fr_mlp_num_params() == 8 * 64 + 64 + 64 * 64 + 64 + 64 * 5 + 5
+
+
+def test_tuning_cache_roundtrip(tmp_path, monkeypatch):
+    """The JSON tuning cache: a miss runs the autotuner once and stores the
+    winner under the workload's key; a hit sets it without timing."""
+    import paper_1012_0006_amd as fr
+
+    class FakeCtx:
+        def __init__(self):
+            self.set = []
+
+        def set_tuning(self, **kw):
+            self.set.append(kw)
+
+    class G:
+        n, narcs = 1 << 18, 2_097_152
+
+    calls = []
+
+    def fake_autotune(ctx, graph, part, k, pairs, prm, candidates, reps):
+        calls.append(len(candidates))
+        return 2, [3.0, 2.0, 1.0] + [9.0] * (len(candidates) - 3)
+
+    monkeypatch.setattr(fr, "fr_autotune", fake_autotune)
+    path = str(tmp_path / "tune.json")
+    ctx = FakeCtx()
+    t1 = fr.autotune_cached(ctx, G(), None, 2, [(0, 1)], None, cache_path=path, arch="gfx950")
+    assert t1 == fr.DEFAULT_CANDIDATES[2] and calls == [len(fr.DEFAULT_CANDIDATES)]
+    t2 = fr.autotune_cached(ctx, G(), None, 2, [(0, 1)], None, cache_path=path, arch="gfx950")
+    assert t2 == t1 and len(calls) == 1 and ctx.set == [t1]
+    assert fr.tuning_key("gfx950", 1 << 18, 2_097_152, 1) == "gfx950|n2^18|deg8|pairs2^0"
+    # another size bucket misses
+    fr.autotune_cached(ctx, type("H", (), {"n": 1 << 20, "narcs": 12 << 20})(), None, 16,
+                       [(0, 1)] * 8, None, cache_path=path, arch="gfx950")
+    assert len(calls) == 2
