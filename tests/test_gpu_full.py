@@ -97,3 +97,25 @@ def test_c5_sweep_properties(gpu_lib, ctx):
     bw1 = np.bincount(out, weights=w.graph.vwgt, minlength=w.k)
     assert np.all(bw1[bw0 <= lmax] <= lmax)
     assert out.min() >= 0 and out.max() < w.k
+
+
+def test_corridor_beyond_lds_bitmaps(gpu_lib, ctx):
+    """A corridor of more than 131,072 vertices (2D RGG n=2^19, alpha 16):
+    the flow phases run on the global label and mark arrays instead of the
+    LDS bitmaps; flow, smallest source side and decision still match."""
+    import torch
+
+    w = gen.config("C2", n_override=1 << 19)
+    p = {k: w.params[k] for k in ("area_mode", "depth", "alpha", "alpha_max", "eps_ppm")}
+    p.update(adaptive=0, max_iters=1)
+    o = oracle.refine_pair(w.graph, w.part, 2, 0, 1, p, want_side=True)
+    assert o.result["region_vertices"] > 131072
+    dg = gpu_lib.DeviceGraph.from_host(w.graph)
+    dpart = torch.as_tensor(w.part.copy()).cuda()
+    res, trace, side = gpu_lib.flow_refine_pair(ctx, dg, dpart, 2, 0, 1, gpu_lib.params(**p),
+                                                want_side=True)
+    for key in KEYS:
+        assert res[key] == o.result[key], key
+    assert trace == o.trace
+    assert np.array_equal(side, o.side)
+    assert np.array_equal(dpart.cpu().numpy(), o.part)
