@@ -190,6 +190,18 @@ int32_t flow_refine_sweep(fr_context *ctx, const fr_graph *g, int32_t *part, int
 int32_t fr_set_tuning(fr_context *ctx, const fr_tuning *t);
 int32_t fr_get_tuning(fr_context *ctx, fr_tuning *t);
 
+/* Speculative adaptive iterations (Sec. 4.1, the adaptive factor) on (1, the
+ * default) or off (0).  An infeasible candidate halves alpha and solves the
+ * same partition again, so each pair can solve its halving chain alpha,
+ * alpha/2, ..., 1 at once, one workgroup per factor, and the rule then walks
+ * the finished solves in order: the recorded solves, the trace, the result
+ * and the partition are those of the sequential loop; solves past the walk
+ * are discarded (counted in the work counters, not in region_vertices /
+ * region_edges).  Used for pair and batch calls with adaptive iterations and
+ * without the learned factor, as far as every factor of every pair gets a
+ * workgroup slot; fr_last_stats counters[7] reports the factors per pair. */
+int32_t fr_set_speculation(fr_context *ctx, int32_t on);
+
 /* Input checks of every call (CSR shape, ranges, symmetry: O(sum deg^2)) on
  * (1, the default) or off (0; malformed input then gives undefined results). */
 int32_t fr_set_validation(fr_context *ctx, int32_t on);
@@ -203,7 +215,8 @@ int32_t fr_set_validation(fr_context *ctx, int32_t on);
  *   closure, decision); [1..3], [7] are HIP event times.
  * counters[32]: [0] push/relabel sweeps, [1] global relabels, [2] corridor
  *   BFS levels, [3] relabel BFS levels, [4] closure levels, [5] workgroups
- *   of the per-pair kernels, [6] internal check that failed (0 = none);
+ *   of the per-pair kernels, [6] internal check that failed (0 = none),
+ *   [7] speculative factors per pair (1 = none);
  *   [16..27] vertices and arcs touched: boundary scan, corridor BFS, network
  *   build, push/relabel sweeps, global relabels, residual closure (vertices
  *   then arcs for each); the rest 0. */

@@ -48,7 +48,7 @@ struct DevBufs {
   PairState *ps = nullptr;
   int32_t *pairs = nullptr, *alpha0 = nullptr, *order = nullptr;
   // per round (at most FR_MAX_PAIRS pairs)
-  fr_solve *trace = nullptr;
+  fr_solve *trace = nullptr, *srec = nullptr;
   int32_t *ucnt = nullptr, *qctr = nullptr, *pcnt = nullptr, *act = nullptr, *nact = nullptr;
   int64_t *voff = nullptr, *aoff = nullptr, *fstat = nullptr, *pacc = nullptr, *vpre = nullptr,
           *cpre = nullptr;
@@ -74,6 +74,7 @@ struct fr_context {
   int64_t graph_launches = 0;
   hipEvent_t itev[4 * FR_MAX_ITERS] = {};
   int32_t timed_iters = 0;
+  int speculate = 1;
   // stats of the last call
   double ms[8] = {0};
   int64_t counters[32] = {0};
@@ -218,6 +219,7 @@ extern "C" int32_t fr_create(int32_t device, void *hip_stream, fr_context **out)
   A_(trace, (int64_t)FR_MAX_PAIRS * FR_MAX_ITERS); A_(ucnt, FR_MAX_PAIRS);
   A_(qctr, 2 * FR_MAX_ITERS); A_(pcnt, 2 * FR_MAX_PAIRS); A_(pacc, (int64_t)PA_N * FR_MAX_PAIRS);
   A_(act, FR_MAX_PAIRS); A_(nact, 1); A_(vpre, FR_MAX_PAIRS + 1); A_(cpre, FR_MAX_PAIRS + 1);
+  A_(srec, FR_MAX_PAIRS);
   A_(voff, FR_MAX_PAIRS + 1); A_(aoff, FR_MAX_PAIRS + 1); A_(fstat, 4 * FR_MAX_PAIRS);
   A_(feats, MLP_IN * FR_MAX_PAIRS); A_(probs, MLP_OUT * FR_MAX_PAIRS);
   A_(base, FR_MAX_ALPHA + 1); A_(scal, 8); A_(ctl, 1);
@@ -247,7 +249,8 @@ extern "C" int32_t fr_destroy(fr_context *c) {
   void *ptrs[] = {d.blk2pair, d.bstat, d.qadj, d.ps,    d.pairs, d.alpha0, d.order,
                   d.trace,    d.ucnt,  d.voff, d.aoff,  d.fstat, d.feats,  d.probs,
                   d.base,     d.scal,  d.ctl,  d.mlp,   d.mlp_m, d.mlp_v,  d.mlp_g,
-                  d.qctr,     d.pcnt,  d.pacc, d.act,   d.nact,  d.vpre,   d.cpre};
+                  d.qctr,     d.pcnt,  d.pacc, d.act,   d.nact,  d.vpre,   d.cpre,
+                  d.srec};
   for (void *q : ptrs) dfree(q);
   if (c->h_ctl) (void)hipHostFree(c->h_ctl);
   for (int i = 0; i < 4; i++)
@@ -274,6 +277,12 @@ extern "C" int32_t fr_set_tuning(fr_context *c, const fr_tuning *t) {
 extern "C" int32_t fr_get_tuning(fr_context *c, fr_tuning *t) {
   if (!c || !t) return FR_E_INVALID_ARG;
   *t = c->tune;
+  return FR_OK;
+}
+
+extern "C" int32_t fr_set_speculation(fr_context *c, int32_t on) {
+  if (!c) return FR_E_INVALID_ARG;
+  c->speculate = on ? 1 : 0;
   return FR_OK;
 }
 
@@ -356,6 +365,9 @@ static KArgs call_args(fr_context *c, const fr_graph *g, int32_t *dpart, int32_t
   A.pacc = d.pacc;
   A.pcnt = d.pcnt;
   A.act = d.act;
+  A.W = 1;
+  A.mstride = 0;
+  A.srec = d.srec;
   A.nact = d.nact;
   A.vpre = d.vpre;
   A.cpre = d.cpre;
@@ -486,6 +498,7 @@ static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t s
     if (timed) HIPCHK(hipEventRecord(ev[2], st));
     hipLaunchKernelGGL(flow, dim3(blocks), dim3(tpb), 0, st, A, it);
     if (timed) HIPCHK(hipEventRecord(ev[3], st));
+    hipLaunchKernelGGL(k_select, dim3(A.P / A.W), dim3(1024), 0, st, A, it);
   }
   HIPCHK(hipGetLastError());
   c->counters[5] = blocks;
@@ -575,11 +588,13 @@ struct Staged {
   int64_t narcs;
 };
 
-static int32_t stage(fr_context *c, const fr_graph *g, int32_t *part, int32_t k, Staged *s) {
+// slots: arena and mark arrays for that many entries per vertex / arc
+static int32_t stage(fr_context *c, const fr_graph *g, int32_t *part, int32_t k, Staged *s,
+                     int32_t slots = 1) {
   int64_t narcs = 0;
   int32_t rc = graph_narcs(c, g, &narcs);
   if (rc) return rc;
-  if ((rc = ensure_capacity(c, g->n, narcs, k))) return rc;
+  if ((rc = ensure_capacity(c, (int64_t)slots * g->n, (int64_t)slots * narcs, k))) return rc;
   DevBufs &d = c->d;
   hipStream_t st = c->cs;
   s->g = *g;
@@ -630,6 +645,22 @@ static int32_t check_batch_args(const fr_context *c, const fr_graph *g, const in
 }
 
 // The pair and batch entry points: one round of disjoint pairs.
+// Speculative slots per pair: the length of the halving chain of alpha_max,
+// as far as every entry still gets its own workgroup slot and the arenas stay
+// within a fixed budget.  One slot without adaptive iterations, with the
+// learned factor or when switched off.
+static int32_t speculation_slots(const fr_context *c, const fr_params *p, int32_t npairs,
+                                 int64_t n, int64_t narcs) {
+  if (!c->speculate || !p->adaptive || p->max_iters < 2 || p->use_mlp) return 1;
+  int32_t W = 0;
+  for (int32_t a = p->alpha_max; a >= 1; a >>= 1) W++;
+  const int64_t slots = (int64_t)c->num_cus * c->tune.blocks_per_cu;
+  while (W > 1 && ((int64_t)npairs * W > slots || (int64_t)npairs * W > FR_MAX_PAIRS ||
+                   W * n > (1ll << 28) || W * narcs > (1ll << 29)))
+    W--;
+  return W;
+}
+
 static int32_t refine(fr_context *c, const fr_graph *g, int32_t *part, int32_t k,
                       const int32_t *pairs, int32_t npairs, const fr_params *p, fr_result *res,
                       int8_t *side_out, fr_solve *trace) {
@@ -638,21 +669,32 @@ static int32_t refine(fr_context *c, const fr_graph *g, int32_t *part, int32_t k
   if (!res) return FR_E_INVALID_ARG;
   if (p->use_mlp && !c->mlp_loaded) return FR_E_INVALID_ARG;
   if ((rc = enter(c))) return rc;
+  int64_t narcs0 = 0;
+  if ((rc = graph_narcs(c, g, &narcs0))) return rc;
+  const int32_t W = speculation_slots(c, p, npairs, g->n, narcs0);
+  if ((rc = ensure_pairs(c, (int64_t)npairs * W))) return rc;
   Staged s;
-  if ((rc = stage(c, g, part, k, &s))) return rc;
+  if ((rc = stage(c, g, part, k, &s, W))) return rc;
   DevBufs &d = c->d;
   hipStream_t st = c->cs;
   const int64_t n = g->n;
+  const int32_t V = npairs * W;
   (void)hipEventRecord(c->ev[0], st);
   HIPCHK(hipMemcpyAsync(d.partw, s.dpart, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
   KArgs A = call_args(c, &s.g, d.partw, k, p);
+  A.W = W;
+  A.mstride = W > 1 ? n : 0;
   if ((rc = call_constants(c, A, s.narcs, p))) return rc;
-  std::vector<int32_t> a0((size_t)npairs, p->alpha);
-  HIPCHK(hipMemcpyAsync(d.pairs, pairs, sizeof(int32_t) * 2 * npairs, hipMemcpyHostToDevice, st));
+  std::vector<int32_t> a0((size_t)npairs, p->alpha), vp((size_t)2 * V);
+  for (int32_t i = 0; i < V; i++) {
+    vp[2 * i] = pairs[2 * (i / W)];
+    vp[2 * i + 1] = pairs[2 * (i / W) + 1];
+  }
+  HIPCHK(hipMemcpyAsync(d.pairs, vp.data(), sizeof(int32_t) * 2 * V, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(d.alpha0, a0.data(), sizeof(int32_t) * npairs, hipMemcpyHostToDevice, st));
   int32_t stamp0 = 0;
   if ((rc = reserve_stamps(c, p->max_iters, &stamp0))) return rc;
-  const KArgs R = round_args(c, A, 0, npairs, stamp0, true);
+  const KArgs R = round_args(c, A, 0, V, stamp0, true);
   (void)hipEventRecord(c->ev[1], st);
   if ((rc = enqueue_round(c, R, p->use_mlp != 0, st, true))) return rc;
   (void)hipEventRecord(c->ev[2], st);
@@ -664,8 +706,8 @@ static int32_t refine(fr_context *c, const fr_graph *g, int32_t *part, int32_t k
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(side_out, d.side, n, hipMemcpyDeviceToHost, st));
   }
-  std::vector<PairState> ps((size_t)npairs);
-  HIPCHK(hipMemcpyAsync(ps.data(), d.ps, sizeof(PairState) * npairs, hipMemcpyDeviceToHost, st));
+  std::vector<PairState> ps((size_t)V);
+  HIPCHK(hipMemcpyAsync(ps.data(), d.ps, sizeof(PairState) * V, hipMemcpyDeviceToHost, st));
   std::vector<fr_solve> tr;
   if (trace) {
     tr.resize((size_t)npairs * p->max_iters);
@@ -680,13 +722,14 @@ static int32_t refine(fr_context *c, const fr_graph *g, int32_t *part, int32_t k
   (void)hipEventElapsedTime(&t12, c->ev[1], c->ev[2]);
   (void)hipEventElapsedTime(&t03, c->ev[0], c->ev[3]);
   c->ms[0] = t01;  // validation, graph constants
-  c->ms[1] = t12;  // the round: setup kernels and the solve kernel
+  c->ms[1] = t12;  // the round: setup kernels and every flow iteration
   c->ms[4] = t03;  // whole call on the device
   collect_stats(c, ps);
+  c->counters[7] = W;
   for (int i = 0; i < npairs; i++) {
-    fill_result(ps[i], res[i]);
+    fill_result(ps[(size_t)i * W], res[i]);
     if (trace)
-      for (int j = 0; j < ps[i].iters; j++)
+      for (int j = 0; j < ps[(size_t)i * W].iters; j++)
         trace[(size_t)i * p->max_iters + j] = tr[(size_t)i * p->max_iters + j];
   }
   return FR_OK;

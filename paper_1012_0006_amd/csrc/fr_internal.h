@@ -16,7 +16,9 @@ struct PairState {
   int32_t start_alpha, final_alpha;
   int32_t last_nr;      // corridor vertices of the last solve
   int32_t nr;           // corridor vertices of the current solve
-  int32_t done;         // the adaptive loop has stopped
+  int32_t done;         // the adaptive loop has stopped (a slot: not solved this launch)
+  int32_t last_slot;    // slot of the pair's last recorded solve
+  int32_t spare;
   int64_t cA, cB;       // current block weights
   int64_t cut;          // current pair cut
   int64_t cut0;         // pair cut at call start
@@ -88,6 +90,14 @@ struct KArgs {
   int32_t *queue;           // [2 * max_iters] pair-queue counters: corridor and flow kernels
   int64_t *pacc;            // [P * PA_N] per-pair sums of the current solve
   int32_t *pcnt;            // [2P] boundary-list and sink-list counters
+  // Speculative slots: every pair of the round owns W consecutive entries
+  // (pair p, slot s at index p * W + s) that solve the same partition at the
+  // factors alpha, alpha/2, ... of its halving chain at once; each slot has
+  // its own corridor marks (mark/vmap + (index % W) * mstride).  W = 1: one
+  // entry per pair, shared marks (mstride 0).
+  int32_t W;
+  int64_t mstride;
+  fr_solve *srec;           // [P] record of each entry's solve in the current launch
   // pairs still iterating in the current launch, compacted: act[0..nact),
   // prefix sums of their union sizes (vpre) and corridor sizes (cpre)
   int32_t *act, *nact;

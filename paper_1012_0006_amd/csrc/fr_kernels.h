@@ -188,6 +188,7 @@ __global__ void __launch_bounds__(1024) k_round_init(KArgs A) {
   for (int i = threadIdx.x; i < 2 * A.P; i += blockDim.x) A.pcnt[i] = 0;
   __syncthreads();
   for (int i = threadIdx.x; i < A.P; i += blockDim.x) {
+    if (i % A.W) continue;  // a pair's blocks map to its first entry
     A.blk2pair[A.pairs[2 * i]] = i;
     A.blk2pair[A.pairs[2 * i + 1]] = i;
   }
@@ -256,9 +257,11 @@ __global__ void __launch_bounds__(1024) k_arena(KArgs A) {
     memset(&s, 0, sizeof(s));
     s.a = a;
     s.b = b;
-    int al = A.alpha0 ? A.alpha0[i] : 1;
+    int al = A.alpha0 ? A.alpha0[i / A.W] : 1;  // start factor of the pair
     al = al < 1 ? 1 : (al > A.alpha_max ? A.alpha_max : al);
-    s.alpha = s.start_alpha = s.final_alpha = al;
+    s.start_alpha = s.final_alpha = al;
+    s.alpha = al >> (i % A.W);  // slot s solves at the s-th halving
+    s.done = s.alpha < 1 ? 1 : 0;
     s.cA = bw[a];
     s.cB = bw[b];
     s.cut = s.cut0 = -1;
@@ -353,8 +356,8 @@ struct SolveShared {
 // that side with id >= y0 as outside (S + 1).  Radix descent over the id bits
 // in three passes (11 + 10 + 10 bits) with an LDS histogram of weights.
 template <int TPB>
-__device__ void cut_level(const KArgs &A, int32_t x, const int32_t *list, int32_t cnt, int64_t R,
-                          int32_t S, SolveShared<TPB> &sh) {
+__device__ void cut_level(const KArgs &A, int32_t *mark, int32_t x, const int32_t *list,
+                          int32_t cnt, int64_t R, int32_t S, SolveShared<TPB> &sh) {
   uint32_t prefix = 0, mask = 0;
   int64_t rem = R;
   for (int pass = 0; pass < 3; pass++) {
@@ -401,7 +404,7 @@ __device__ void cut_level(const KArgs &A, int32_t x, const int32_t *list, int32_
   const int32_t y0 = (int32_t)prefix;
   for (int i = threadIdx.x; i < cnt; i += TPB) {
     const int32_t u = list[i];
-    if (A.part[u] == x && u >= y0) A.mark[u] = S + 1;
+    if (A.part[u] == x && u >= y0) mark[u] = S + 1;
   }
   __syncthreads();
 }
@@ -812,6 +815,14 @@ __device__ __forceinline__ PairView make_view(const KArgs &A, int32_t p) {
   return V;
 }
 
+// corridor marks and local ids of entry p (its slot's arrays)
+__device__ __forceinline__ int32_t *mark_of(const KArgs &A, int32_t p) {
+  return A.mark + (int64_t)(p % A.W) * A.mstride;
+}
+__device__ __forceinline__ int32_t *vmap_of(const KArgs &A, int32_t p) {
+  return A.vmap + (int64_t)(p % A.W) * A.mstride;
+}
+
 // Grid-wide version of for_groups: G lanes per item over 0..N-1, the trip
 // count uniform over each wave.
 template <int G, typename F>
@@ -939,7 +950,8 @@ __global__ void __launch_bounds__(256) k_bnd(KArgs A, int32_t it) {
     const int64_t slot = active_item(A, A.vpre, i, valid, p);
     const bool on = p >= 0;
     const int32_t a = on ? A.pairs[2 * p] : 0, b = on ? A.pairs[2 * p + 1] : 0;
-    const int32_t u = on ? A.uvert[A.voff[p] + slot] : 0;
+    // the union list is held by the pair's first entry
+    const int32_t u = on ? A.uvert[A.voff[A.blk2pair[a]] + slot] : 0;
     const int side = on && A.part[u] == b;
     const int32_t y = side ? a : b;
     const int32_t e0 = on ? A.xadj[u] : 0, e1 = on ? A.xadj[u + 1] : 0;
@@ -957,7 +969,7 @@ __global__ void __launch_bounds__(256) k_bnd(KArgs A, int32_t it) {
     const bool lead = on && gl == 0;
     const bool bl = lead && bnd;
     const int64_t w = bl ? A.vwgt[u] : 0;
-    if (bl) A.mark[u] = S;
+    if (bl) mark_of(A, p)[u] = S;
     const int64_t x[7] = {cw, bl && !side ? w : 0, bl && side ? w : 0, bl && !side ? 1 : 0,
                           bl && side ? 1 : 0, 1, e1 - e0};
     sums.add(lead ? p : -1, x, out);
@@ -996,6 +1008,7 @@ __global__ void __launch_bounds__(TPB) k_corr(KArgs A, int32_t it) {
     if (p < 0) break;
     const PairView V = make_view(A, p);
     const int32_t a = V.a, b = V.b;
+    int32_t *mk = mark_of(A, p), *vm = vmap_of(A, p);
     const int64_t *pa = A.pacc + (int64_t)p * PA_N;
     int64_t t0 = wall_clock64();
     if (threadIdx.x == 0) {
@@ -1043,7 +1056,7 @@ __global__ void __launch_bounds__(TPB) k_corr(KArgs A, int32_t it) {
       }
       __syncthreads();
       for (int s = 0; s < 2; s++)
-        if (sh.mode[s] == 2) cut_level<TPB>(A, s ? b : a, cur, cnt, sh.U[s] - sh.W[s], S, sh);
+        if (sh.mode[s] == 2) cut_level<TPB>(A, mk, s ? b : a, cur, cnt, sh.U[s] - sh.W[s], S, sh);
       // the taken part of this level joins the corridor
       BLOCK_WAVE_LOOP(i, cnt) {
         bool take = false;
@@ -1051,12 +1064,12 @@ __global__ void __launch_bounds__(TPB) k_corr(KArgs A, int32_t it) {
         if (i < cnt) {
           u = cur[i];
           const int s = A.part[u] == b;
-          take = sh.mode[s] == 1 || (sh.mode[s] == 2 && A.mark[u] == S);
+          take = sh.mode[s] == 1 || (sh.mode[s] == 2 && mk[u] == S);
         }
         const int pos = wave_append(&sh.nr, take);
         if (take) {
           put_bounded(V.lg, pos, V.nv, u, A.ctl);
-          A.vmap[u] = pos;
+          vm[u] = pos;
         }
       }
       if (!sh.state[0] && !sh.state[1]) break;
@@ -1077,7 +1090,7 @@ __global__ void __launch_bounds__(TPB) k_corr(KArgs A, int32_t it) {
           int32_t v = 0;
           if (e < e1) {
             v = A.adjncy[e];
-            if (A.part[v] == x && A.mark[v] < S) claim = atomicMax(&A.mark[v], S) < S;
+            if (A.part[v] == x && mk[v] < S) claim = atomicMax(&mk[v], S) < S;
           }
           const int pos = wave_append(ncnt, claim);
           if (claim) {
@@ -1129,6 +1142,7 @@ __global__ void __launch_bounds__(256) k_net_count(KArgs A, int32_t it) {
     const int32_t a = on ? A.pairs[2 * p] : 0, b = on ? A.pairs[2 * p + 1] : 0;
     const int32_t u = on ? A.lg[i] : 0;
     const int side = on && A.part[u] == b;
+    const int32_t *mk = on ? mark_of(A, p) : A.mark;
     const int32_t e0 = on ? A.xadj[u] : 0, e1 = on ? A.xadj[u + 1] : 0;
     int64_t cnt = 0, cap = 0, cin = 0;
     bool border = false;
@@ -1138,7 +1152,7 @@ __global__ void __launch_bounds__(256) k_net_count(KArgs A, int32_t it) {
       const int32_t v = A.adjncy[e];
       const int32_t xv = A.part[v];
       if (xv != a && xv != b) continue;
-      if (A.mark[v] == S) {
+      if (mk[v] == S) {
         cnt++;
         cap += A.adjwgt[e];
         if (!side && xv == b) cin += A.adjwgt[e];
@@ -1193,11 +1207,7 @@ __global__ void __launch_bounds__(1024) k_net_scan(KArgs A, int32_t it) {
   }
   if (threadIdx.x == 0) {
     lo[0] = 0;
-    PairState &s = A.ps[p];
-    const int64_t *pa = A.pacc + (int64_t)p * PA_N;
-    s.re_sum += pa[PA_RARCS] / 2;
-    s.rv_sum += nr;
-    s.last_nr = nr;
+    A.ps[p].last_nr = nr;
   }
 }
 
@@ -1211,6 +1221,8 @@ __global__ void __launch_bounds__(256) k_net_fill(KArgs A, int32_t it) {
     const bool on = p >= 0;
     const int32_t a = on ? A.pairs[2 * p] : 0, b = on ? A.pairs[2 * p + 1] : 0;
     const int32_t u = on ? A.lg[i] : 0;
+    const int32_t *mk = on ? mark_of(A, p) : A.mark;
+    const int32_t *vm = on ? vmap_of(A, p) : A.vmap;
     const int32_t e0 = on ? A.xadj[u] : 0, e1 = on ? A.xadj[u + 1] : 0;
     const int64_t ab = on ? A.aoff[p] : 0;
     const int64_t na = on ? A.aoff[p + 1] - ab : 0;
@@ -1222,12 +1234,12 @@ __global__ void __launch_bounds__(256) k_net_fill(KArgs A, int32_t it) {
       if (e < e1) {
         v = A.adjncy[e];
         const int32_t xv = A.part[v];
-        in = (xv == a || xv == b) && A.mark[v] == S;
+        in = (xv == a || xv == b) && mk[v] == S;
       }
       int32_t tot;
       const int32_t off = group_exscan<GT>(in ? 1 : 0, &tot);
       if (in && k + off < na) {
-        A.lh[ab + k + off] = A.vmap[v];
+        A.lh[ab + k + off] = vm[v];
         A.rc[ab + k + off] = res_pair(A.adjwgt[e], A.adjwgt[e]);
       }
       k += tot;
@@ -1485,6 +1497,8 @@ __global__ void __launch_bounds__(TPB) k_flow(KArgs A, int32_t it) {
       }
     }
     block_sums<4>(acc, sh.red);
+    // the record of this solve; the adaptive rule and the write-back run in
+    // k_select, over all slots of the pair
     if (threadIdx.x == 0) {
       st.sweeps += sweeps;
       st.relabels += relabels;
@@ -1520,47 +1534,8 @@ __global__ void __launch_bounds__(TPB) k_flow(KArgs A, int32_t it) {
       rec.wa = wa;
       rec.wb = wb;
       rec.decision = dec;
-      st.flow_last = rec.flow;
-      st.last_dec = dec;
-      st.final_alpha = st.alpha;
-      sh.rec = rec;
-    }
-    __syncthreads();
-    if (sh.rec.decision == FR_DEC_APPLY && A.ctl->err == 0) {
-      BLOCK_WAVE_LOOP(i, nr) {
-        if (i < nr) A.part[V.lg[i]] = V.ins[i] ? a : b;
-      }
-    }
-    __syncthreads();
-    // ---- adaptive factor (Sec. 4.1): doubled after an applied solve,
-    //      halved after an infeasible one, stop when a feasible cut does not
-    //      improve; the sums of this solve are cleared for the next
-    if (threadIdx.x == 0) {
+      A.srec[p] = rec;
       st.t_finish += wall_clock64() - t0;
-      const fr_solve rec = sh.rec;
-      bool stop = A.ctl->err != 0;
-      if (!stop) {
-        if (A.trace) A.trace[(int64_t)p * A.max_iters + st.iters] = rec;
-        st.iters++;
-        if (rec.decision == FR_DEC_APPLY) {
-          st.applied++;
-          st.cA = rec.wa;
-          st.cB = rec.wb;
-          st.cut = rec.cut_candidate;
-          if (!A.adaptive) stop = true;
-          else st.alpha = 2 * st.alpha < A.alpha_max ? 2 * st.alpha : A.alpha_max;
-        } else if (rec.decision == FR_DEC_INFEASIBLE) {
-          if (!A.adaptive || st.alpha == 1) stop = true;
-          else st.alpha = st.alpha / 2 > 1 ? st.alpha / 2 : 1;
-        } else {
-          stop = true;
-        }
-        if (!stop && st.iters >= A.max_iters) {
-          stop = true;
-          st.iter_cap = 1;
-        }
-      }
-      st.done = stop ? 1 : 0;
       for (int j = 0; j < PA_N; j++) pa[j] = 0;
       A.pcnt[p] = 0;
       A.pcnt[A.P + p] = 0;
@@ -1568,6 +1543,85 @@ __global__ void __launch_bounds__(TPB) k_flow(KArgs A, int32_t it) {
     }
     __syncthreads();
   }
+}
+
+// ---- the adaptive factor (Sec. 4.1), one block per pair: walk the slots
+//      solved in this launch in halving order as the sequential loop would
+//      (an applied solve doubles alpha, an infeasible one halves it and the
+//      next slot holds that solve, a feasible solve that does not improve
+//      stops), record the walked solves, write the applied candidate back and
+//      set every slot's factor for the next launch
+__global__ void __launch_bounds__(1024) k_select(KArgs A, int32_t it) {
+  __shared__ int32_t s_chosen, s_v0;
+  (void)it;
+  const int32_t p = blockIdx.x;  // pair of the round
+  const int32_t W = A.W;
+  const int32_t v0 = p * W;
+  if (A.ps[v0].done) return;
+  if (threadIdx.x == 0) {
+    PairState R = A.ps[v0];
+    bool stop = false;
+    int chosen = -1;
+    int32_t next_alpha = R.alpha;
+    for (int s = 0; s < W; s++) {
+      const int32_t v = v0 + s;
+      if (A.ps[v].done) break;  // not solved in this launch
+      if (A.ctl->err != 0) {
+        stop = true;
+        break;
+      }
+      const fr_solve rec = A.srec[v];
+      if (A.trace) A.trace[(int64_t)p * A.max_iters + R.iters] = rec;
+      R.iters++;
+      R.rv_sum += rec.region_vertices;
+      R.re_sum += rec.region_edges;
+      R.final_alpha = rec.alpha;
+      R.flow_last = rec.flow;
+      R.last_dec = rec.decision;
+      R.last_slot = s;
+      if (rec.decision == FR_DEC_APPLY) {
+        R.applied++;
+        R.cA = rec.wa;
+        R.cB = rec.wb;
+        R.cut = rec.cut_candidate;
+        chosen = s;
+        if (!A.adaptive) stop = true;
+        else next_alpha = 2 * rec.alpha < A.alpha_max ? 2 * rec.alpha : A.alpha_max;
+      } else if (rec.decision == FR_DEC_INFEASIBLE) {
+        if (!A.adaptive || rec.alpha == 1) stop = true;
+        else next_alpha = rec.alpha / 2 > 1 ? rec.alpha / 2 : 1;
+      } else {
+        stop = true;
+      }
+      if (!stop && R.iters >= A.max_iters) {
+        stop = true;
+        R.iter_cap = 1;
+      }
+      if (stop || rec.decision == FR_DEC_APPLY) break;
+    }
+    R.alpha = next_alpha;
+    R.done = stop ? 1 : 0;
+    A.ps[v0] = R;
+    for (int s = 1; s < W; s++) {
+      PairState &q = A.ps[v0 + s];
+      q.alpha = next_alpha >> s;
+      q.done = (stop || q.alpha < 1) ? 1 : 0;
+      q.cA = R.cA;
+      q.cB = R.cB;
+      q.cut = R.cut;
+    }
+    s_chosen = A.ctl->err == 0 ? chosen : -1;
+    s_v0 = v0;
+  }
+  __syncthreads();
+  const int chosen = s_chosen;
+  if (chosen < 0) return;
+  const int32_t vc = s_v0 + chosen;
+  const int32_t a = A.pairs[2 * vc], b = A.pairs[2 * vc + 1];
+  const int64_t vb = A.voff[vc];
+  const int32_t nr = A.ps[vc].nr;
+  for (int32_t i = threadIdx.x; i < nr; i += blockDim.x)
+    A.part[A.lg[vb + i]] = A.ins[vb + i] ? a : b;
 }
 
 // side codes of the last solve of pair 0 (single-pair calls)
@@ -1578,8 +1632,9 @@ __global__ void __launch_bounds__(256) k_side_fill(KArgs A) {
 }
 
 __global__ void __launch_bounds__(256) k_side_scatter(KArgs A) {
-  const int32_t nr = A.ps[0].last_nr;
-  const int64_t vb = A.voff[0];
+  const int32_t v = A.ps[0].last_slot;
+  const int32_t nr = A.ps[v].last_nr;
+  const int64_t vb = A.voff[v];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nr;
        i += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t f = A.lflag[vb + i];

@@ -236,3 +236,29 @@ def test_error_paths(gpu_lib, ctx):
     with pytest.raises(gpu_lib.FlowRefineError) as e:
         ctx.set_tuning(blocks_per_cu=9)
     assert e.value.code == -8
+
+
+@pytest.mark.parametrize("spec", [True, False])
+def test_speculation_on_off_match_oracle(gpu_lib, spec):
+    """The adaptive loop with every factor of the halving chain solved at once
+    (speculation) and one solve per launch give the oracle's trace, result and
+    partition; with speculation the C2 pair runs its 5 factors side by side."""
+    import torch
+
+    w = gen.config("C2", n_override=1 << 16)
+    o = oracle.refine_pair(w.graph, w.part, 2, 0, 1, w.params, want_side=True)
+    ctx = gpu_lib.Context()
+    try:
+        ctx.set_speculation(spec)
+        dg = gpu_lib.DeviceGraph.from_host(w.graph)
+        dpart = torch.as_tensor(w.part.copy()).cuda()
+        res, trace, side = gpu_lib.flow_refine_pair(ctx, dg, dpart, 2, 0, 1,
+                                                    gpu_lib.params(**w.params), want_side=True)
+        assert gpu_lib.stats_dict(ctx)["slots"] == (5 if spec else 1)
+        for key in RESULT_KEYS:
+            assert res[key] == o.result[key], key
+        assert trace == o.trace
+        assert np.array_equal(side, o.side)
+        assert np.array_equal(dpart.cpu().numpy(), o.part)
+    finally:
+        ctx.close()
