@@ -197,9 +197,10 @@ int32_t fr_get_tuning(fr_context *ctx, fr_tuning *t);
  * the finished solves in order: the recorded solves, the trace, the result
  * and the partition are those of the sequential loop; solves past the walk
  * are discarded (counted in the work counters, not in region_vertices /
- * region_edges).  Used for pair and batch calls with adaptive iterations and
- * without the learned factor, as far as every factor of every pair gets a
- * workgroup slot; fr_last_stats counters[7] reports the factors per pair. */
+ * region_edges).  Used for pair and batch calls with adaptive iterations (the
+ * chain starts at the learned factor when use_mlp is set), as far as every
+ * factor of every pair gets a workgroup slot; fr_last_stats counters[7]
+ * reports the factors per pair. */
 int32_t fr_set_speculation(fr_context *ctx, int32_t on);
 
 /* Input checks of every call (CSR shape, ranges, symmetry: O(sum deg^2)) on

@@ -651,7 +651,7 @@ static int32_t check_batch_args(const fr_context *c, const fr_graph *g, const in
 // learned factor or when switched off.
 static int32_t speculation_slots(const fr_context *c, const fr_params *p, int32_t npairs,
                                  int64_t n, int64_t narcs) {
-  if (!c->speculate || !p->adaptive || p->max_iters < 2 || p->use_mlp) return 1;
+  if (!c->speculate || !p->adaptive || p->max_iters < 2) return 1;
   int32_t W = 0;
   for (int32_t a = p->alpha_max; a >= 1; a >>= 1) W++;
   const int64_t slots = (int64_t)c->num_cus * c->tune.blocks_per_cu;
@@ -685,13 +685,13 @@ static int32_t refine(fr_context *c, const fr_graph *g, int32_t *part, int32_t k
   A.W = W;
   A.mstride = W > 1 ? n : 0;
   if ((rc = call_constants(c, A, s.narcs, p))) return rc;
-  std::vector<int32_t> a0((size_t)npairs, p->alpha), vp((size_t)2 * V);
+  std::vector<int32_t> a0((size_t)V, p->alpha), vp((size_t)2 * V);
   for (int32_t i = 0; i < V; i++) {
     vp[2 * i] = pairs[2 * (i / W)];
     vp[2 * i + 1] = pairs[2 * (i / W) + 1];
   }
   HIPCHK(hipMemcpyAsync(d.pairs, vp.data(), sizeof(int32_t) * 2 * V, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(d.alpha0, a0.data(), sizeof(int32_t) * npairs, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d.alpha0, a0.data(), sizeof(int32_t) * V, hipMemcpyHostToDevice, st));
   int32_t stamp0 = 0;
   if ((rc = reserve_stamps(c, p->max_iters, &stamp0))) return rc;
   const KArgs R = round_args(c, A, 0, V, stamp0, true);

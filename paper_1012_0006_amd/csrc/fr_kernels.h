@@ -257,7 +257,7 @@ __global__ void __launch_bounds__(1024) k_arena(KArgs A) {
     memset(&s, 0, sizeof(s));
     s.a = a;
     s.b = b;
-    int al = A.alpha0 ? A.alpha0[i / A.W] : 1;  // start factor of the pair
+    int al = A.alpha0 ? A.alpha0[i - i % A.W] : 1;  // start factor: the pair's first entry
     al = al < 1 ? 1 : (al > A.alpha_max ? A.alpha_max : al);
     s.start_alpha = s.final_alpha = al;
     s.alpha = al >> (i % A.W);  // slot s solves at the s-th halving
