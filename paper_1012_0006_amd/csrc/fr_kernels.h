@@ -502,22 +502,15 @@ __device__ void pr_sweep(const KArgs &A, const PairView &V, const ListRef &cur, 
     count_work_wave(wcnt, W_SWEEP_ARCS, (work && gl == 0) ? ae - ab : 0);
     // K chunks of T arcs per step: their loads are in flight together
     constexpr int K = T >= 8 ? 1 : 8 / T;
-    for (int32_t c0 = ab; c0 < ae; c0 += T * K) {
-      int32_t h[K], r[K], ra[K], dh[K];
+    int32_t h[K], r[K], ra[K], dh[K];
+    // pushes along the arcs of the chunk at c0 that are admissible for label
+    // dcur (residual left, head label below dcur), in arc order, until the
+    // excess is used up; r[] keeps the residual left
+    auto push_chunk = [&](int32_t c0, int32_t dcur) {
 #pragma unroll
       for (int k = 0; k < K; k++) {
         const int32_t a = c0 + k * T + gl;
-        const bool in = a < ae;
-        h[k] = in ? V.lh[a] : 0;
-        r[k] = in ? res_own(V.rc[a]) : 0;
-        ra[k] = in ? V.lr[a] : 0;
-      }
-#pragma unroll
-      for (int k = 0; k < K; k++) dh[k] = r[k] > 0 ? V.lab[h[k]] : 0x7fffffff;
-#pragma unroll
-      for (int k = 0; k < K; k++) {
-        const int32_t a = c0 + k * T + gl;
-        const int64_t adm = (r[k] > 0 && dh[k] < d) ? (int64_t)r[k] : 0;
+        const int64_t adm = (r[k] > 0 && dh[k] < dcur) ? (int64_t)r[k] : 0;
         int64_t inc = adm;
         if (T > 1) {
           for (int o = 1; o < T; o <<= 1) {
@@ -544,11 +537,27 @@ __device__ void pr_sweep(const KArgs &A, const PairView &V, const ListRef &cur, 
         }
         const int pos = wave_append(next_cnt, act);
         if (act) lput(next, pos, V.nv, h[k], A.ctl);
-        if (r[k] - amt > 0 && dh[k] < minres) minres = dh[k];
+        r[k] -= (int32_t)amt;
         const int64_t used = tot < erem ? tot : erem;
         erem -= used;
         pushed += used;
       }
+    };
+    for (int32_t c0 = ab; c0 < ae; c0 += T * K) {
+#pragma unroll
+      for (int k = 0; k < K; k++) {
+        const int32_t a = c0 + k * T + gl;
+        const bool in = a < ae;
+        h[k] = in ? V.lh[a] : 0;
+        r[k] = in ? res_own(V.rc[a]) : 0;
+        ra[k] = in ? V.lr[a] : 0;
+      }
+#pragma unroll
+      for (int k = 0; k < K; k++) dh[k] = r[k] > 0 ? V.lab[h[k]] : 0x7fffffff;
+      push_chunk(c0, d);
+#pragma unroll
+      for (int k = 0; k < K; k++)
+        if (r[k] > 0 && dh[k] < minres) minres = dh[k];
     }
     if (T > 1) {
       for (int o = T >> 1; o > 0; o >>= 1) {
@@ -556,17 +565,20 @@ __device__ void pr_sweep(const KArgs &A, const PairView &V, const ListRef &cur, 
         minres = t < minres ? t : minres;
       }
     }
+    // relabel to one above the lowest residual neighbour
+    int32_t nd = d;
+    if (work && erem > 0) {
+      int64_t cand = minres == 0x7fffffff ? (int64_t)NL : (int64_t)minres + 1;
+      if (cand > NL) cand = NL;
+      if (cand > d) nd = (int32_t)cand;
+    }
+    if (work && gl == 0 && nd > d) V.lab[u] = nd;
+    // discharge on: after a relabel the arcs to the lowest neighbours are
+    // admissible; a vertex whose arcs fit one chunk still holds them
+    const bool second = work && erem > 0 && nd > d && nd < NL && ae - ab <= T * K;
+    if (__any(second)) push_chunk(ab, second ? nd : INT32_MIN);
     bool again = false;
     if (work && gl == 0) {
-      int32_t nd = d;
-      if (erem > 0) {
-        int64_t cand = minres == 0x7fffffff ? (int64_t)NL : (int64_t)minres + 1;
-        if (cand > NL) cand = NL;
-        if (cand > d) {
-          nd = (int32_t)cand;
-          V.lab[u] = nd;
-        }
-      }
       if (qbm) {
         // flow pushed into u during this pass queued u already
         if (pushed > 0) atomicSub(&V.ex[u], (int32_t)pushed);
