@@ -143,6 +143,13 @@ def run_batched(args, fr, torch, gen, cid="C3"):
     pairs = [tuple(e) for e, cc in zip(edges_q.tolist(), colour.tolist()) if cc == c]
     prm = fr.params(**{k: w.params[k] for k in ("area_mode", "depth", "alpha", "alpha_max",
                                                  "adaptive", "max_iters", "eps_ppm")})
+    tuning = None
+    if cid == "C3":  # the round's launch parameters come from the autotuner
+        import tempfile
+
+        with tempfile.TemporaryDirectory() as tmp:
+            tuning = fr.autotune_cached(ctx, dg, part0, w.k, pairs, prm,
+                                        cache_path=os.path.join(tmp, "tuning.json"), reps=1)
     dpart = part0.clone()
     reps = max(1, args.batch_reps)
     # batched
@@ -185,6 +192,7 @@ def run_batched(args, fr, torch, gen, cid="C3"):
         "plain_ms": t_p * 1e3,
         "speedup": t_p / t_b,
         "equal_result": same,
+        "tuning": tuning,
         "region_edges": e_b,
     }
 

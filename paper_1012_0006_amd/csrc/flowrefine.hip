@@ -38,8 +38,8 @@ struct DevBufs {
   uint8_t *lflag = nullptr;
   int8_t *side = nullptr;
   // per arc
-  int32_t *lh = nullptr, *lr = nullptr, *ga = nullptr, *gw = nullptr;
-  unsigned long long *rc = nullptr;  // residual pairs (own, reverse arc)
+  int32_t *ga = nullptr, *gw = nullptr;
+  Arc *arc = nullptr;  // corridor arcs
   // per block
   int32_t *blk2pair = nullptr;
   int64_t *bstat = nullptr;  // [3k]
@@ -101,14 +101,14 @@ static hipError_t dalloc(T **p, int64_t count) {
 
 static void free_vertex_arc(DevBufs &d) {
   int32_t **v32[] = {&d.mark, &d.vmap, &d.uvert, &d.lg, &d.lo, &d.ex, &d.lab, &d.ins, &d.LA,
-                     &d.LB, &d.SNK, &d.partw, &d.parts, &d.gx, &d.gv, &d.lh, &d.lr,
+                     &d.LB, &d.SNK, &d.partw, &d.parts, &d.gx, &d.gv,
                      &d.ga, &d.gw};
   for (auto pp : v32) {
     dfree(*pp);
     *pp = nullptr;
   }
-  dfree(d.rc);
-  d.rc = nullptr;
+  dfree(d.arc);
+  d.arc = nullptr;
   dfree(d.lflag);
   d.lflag = nullptr;
   dfree(d.side);
@@ -127,7 +127,7 @@ static int32_t ensure_capacity(fr_context *c, int64_t n, int64_t narcs, int64_t 
     A_(mark, nc); A_(vmap, nc); A_(uvert, nc); A_(lg, nc); A_(lo, nc + FR_MAX_PAIRS + 1);
     A_(ex, nc); A_(lab, nc); A_(ins, nc); A_(LA, nc); A_(LB, nc); A_(SNK, nc); A_(partw, nc);
     A_(parts, nc); A_(gx, nc + 1); A_(gv, nc); A_(lflag, nc); A_(side, nc);
-    A_(lh, ac); A_(lr, ac); A_(rc, ac); A_(ga, ac); A_(gw, ac);
+    A_(arc, ac); A_(ga, ac); A_(gw, ac);
 #undef A_
     if (e != hipSuccess) {
       free_vertex_arc(d);
@@ -395,9 +395,7 @@ static KArgs call_args(fr_context *c, const fr_graph *g, int32_t *dpart, int32_t
   A.LB = d.LB;
   A.SNK = d.SNK;
   A.lflag = d.lflag;
-  A.lh = d.lh;
-  A.lr = d.lr;
-  A.rc = d.rc;
+  A.arc = d.arc;
   A.ctl = d.ctl;
   A.tpv = c->tune.tpv;
   A.relabel_period = c->tune.relabel_period;

@@ -7,6 +7,15 @@
 #define FR_MAX_ALPHA 1024
 #define FR_MAX_ITERS 64
 
+// A corridor arc: local head, index of its reverse arc, and the residual
+// pair -- the arc's own residual capacity in the low 32 bits, the reverse
+// arc's in the high 32 bits.  One record is one 16-byte load.
+struct __attribute__((aligned(16))) Arc {
+  int32_t lh;
+  int32_t lr;
+  unsigned long long rc;
+};
+
 // Per-pair state of the adaptive flow iterations, kept in device memory
 // across the solves of one call.
 struct PairState {
@@ -118,8 +127,7 @@ struct KArgs {
   int32_t *lo;              // local CSR offsets (n + P slots: nv_p + 1 per pair)
   int32_t *ex, *lab, *ins, *LA, *LB, *SNK;
   uint8_t *lflag;
-  int32_t *lh, *lr;         // local arcs: head, reverse arc
-  unsigned long long *rc;   // residual capacity of the arc (low 32 bits) and of its reverse (high)
+  Arc *arc;                 // local arcs (one 16-byte record each)
   Ctl *ctl;
   // launch
   int32_t tpv, relabel_period;

@@ -416,8 +416,7 @@ struct PairView {
   const int32_t *uv;
   int32_t *lg, *lo, *ex, *lab, *ins, *LA, *LB, *SNK;
   uint8_t *fl;
-  int32_t *lh, *lr;
-  unsigned long long *rc;
+  Arc *arc;
 };
 
 // Residual pairs: each arc holds its own residual capacity in the low 32 bits
@@ -525,8 +524,8 @@ __device__ void pr_sweep(const KArgs &A, const PairView &V, const ListRef &cur, 
         bool act = false;
         if (amt > 0) {
           const unsigned long long x = (unsigned long long)amt;
-          atomicAdd(&V.rc[a], (x << 32) - x);
-          atomicAdd(&V.rc[ra[k]], x - (x << 32));
+          atomicAdd(&V.arc[a].rc, (x << 32) - x);
+          atomicAdd(&V.arc[ra[k]].rc, x - (x << 32));
           if (qbm) {
             atomicAdd(&V.ex[h[k]], (int32_t)amt);
             act = dh[k] > 0 && bm_claim(qbm, h[k]);
@@ -548,9 +547,11 @@ __device__ void pr_sweep(const KArgs &A, const PairView &V, const ListRef &cur, 
       for (int k = 0; k < K; k++) {
         const int32_t a = c0 + k * T + gl;
         const bool in = a < ae;
-        h[k] = in ? V.lh[a] : 0;
-        r[k] = in ? res_own(V.rc[a]) : 0;
-        ra[k] = in ? V.lr[a] : 0;
+        Arc x = {0, 0, 0ull};
+        if (in) x = V.arc[a];
+        h[k] = x.lh;
+        r[k] = res_own(x.rc);
+        ra[k] = x.lr;
       }
 #pragma unroll
       for (int k = 0; k < K; k++) dh[k] = r[k] > 0 ? V.lab[h[k]] : 0x7fffffff;
@@ -734,8 +735,10 @@ __device__ int32_t global_relabel(const KArgs &A, const PairView &V, int32_t nr,
 #pragma unroll
         for (int k = 0; k < KF; k++) {
           const int32_t a = c0 + k * GTF + gl;
-          v[k] = a < e1 ? V.lh[a] : 0;
-          r[k] = a < e1 ? res_rev(V.rc[a]) : 0;
+          Arc x = {0, 0, 0ull};
+          if (a < e1) x = V.arc[a];
+          v[k] = x.lh;
+          r[k] = res_rev(x.rc);
         }
 #pragma unroll
         for (int k = 0; k < KF; k++) {
@@ -821,9 +824,7 @@ __device__ __forceinline__ PairView make_view(const KArgs &A, int32_t p) {
   V.LB = A.LB + vb;
   V.SNK = A.SNK + vb;
   V.fl = A.lflag + vb;
-  V.lh = A.lh + ab;
-  V.lr = A.lr + ab;
-  V.rc = A.rc + ab;
+  V.arc = A.arc + ab;
   return V;
 }
 
@@ -1251,8 +1252,9 @@ __global__ void __launch_bounds__(256) k_net_fill(KArgs A, int32_t it) {
       int32_t tot;
       const int32_t off = group_exscan<GT>(in ? 1 : 0, &tot);
       if (in && k + off < na) {
-        A.lh[ab + k + off] = vm[v];
-        A.rc[ab + k + off] = res_pair(A.adjwgt[e], A.adjwgt[e]);
+        Arc &x = A.arc[ab + k + off];
+        x.lh = vm[v];
+        x.rc = res_pair(A.adjwgt[e], A.adjwgt[e]);
       }
       k += tot;
     }
@@ -1277,8 +1279,7 @@ __global__ void __launch_bounds__(256) k_net_rev(KArgs A, int32_t it) {
       ab = A.aoff[p];
     }
     const int32_t *lo = A.lo + vb + (on ? p : 0);
-    int32_t *lh = A.lh + ab, *lr = A.lr + ab;
-    unsigned long long *rc = A.rc + ab;
+    Arc *arc = A.arc + ab;
     const uint8_t *fl = A.lflag + vb;
     const uint32_t f = on ? fl[item] : 0u;
     const bool src = on && LF_SRC(f);
@@ -1288,21 +1289,21 @@ __global__ void __launch_bounds__(256) k_net_rev(KArgs A, int32_t it) {
     for (int32_t a0 = b0; a0 < e0; a0 += GT) {
       const int32_t ar = a0 + gl;
       if (ar >= e0) continue;
-      const int32_t j = lh[ar];
+      const int32_t j = arc[ar].lh;
       const int32_t je = lo[j + 1];
       int32_t r = lo[j];
-      while (r < je && lh[r] != item) r++;
+      while (r < je && arc[r].lh != item) r++;
       if (r == je) {  // asymmetric input slipped past validation
         A.ctl->err = FR_E_INVALID_GRAPH;
         A.ctl->diag = DIAG_REV;
         r = ar;
       }
-      lr[ar] = r;
+      arc[ar].lr = r;
       if (!src && LF_SRC(fl[j]) && !overflow) {
-        const int32_t c = res_own(rc[ar]);
+        const int32_t c = res_own(arc[ar].rc);
         ex += c;
-        rc[ar] = res_pair(2 * c, 0);
-        rc[r] = res_pair(0, 2 * c);
+        arc[ar].rc = res_pair(2 * c, 0);
+        arc[r].rc = res_pair(0, 2 * c);
       }
     }
     ex = group_sum<GT>(ex);
@@ -1453,8 +1454,10 @@ __global__ void __launch_bounds__(TPB) k_flow(KArgs A, int32_t it) {
 #pragma unroll
               for (int k = 0; k < KF; k++) {
                 const int32_t ar = c0 + k * GTF + gl;
-                r[k] = ar < e1 ? res_own(V.rc[ar]) : 0;
-                v[k] = ar < e1 ? V.lh[ar] : 0;
+                Arc x = {0, 0, 0ull};
+                if (ar < e1) x = V.arc[ar];
+                r[k] = res_own(x.rc);
+                v[k] = x.lh;
               }
 #pragma unroll
               for (int k = 0; k < KF; k++) {

@@ -262,3 +262,42 @@ def test_speculation_on_off_match_oracle(gpu_lib, spec):
         assert np.array_equal(dpart.cpu().numpy(), o.part)
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_batches_vs_oracle(gpu_lib, ctx, seed):
+    """Randomised whole rounds: RGG or random graphs, k in 4..16, a factor cap
+    that may not be a power of two, iteration caps 1..16, eps 0..10 %; the
+    batched call (speculative factor chains on) against the oracle pair by
+    pair."""
+    import torch
+
+    rng = np.random.default_rng(1000 + seed)
+    if seed % 2:
+        g = gen.rgg(int(rng.integers(2000, 12000)), 2, float(rng.choice([6.0, 8.0])),
+                    seed=seed, wlo=1, whi=int(rng.choice([1, 10])))
+    else:
+        g = random_graph(int(rng.integers(60, 160)), 0.06, seed, wmax=5,
+                         vwmax=2 if seed % 4 == 0 else 1)
+    k = int(rng.choice([4, 8, 16]))
+    part = gen.rcb(g, k) if g.coords is not None else rng.integers(0, k, g.n).astype(np.int32)
+    amax = int(rng.choice([1, 2, 6, 12, 16]))
+    p = dict(area_mode=0, depth=0, alpha=int(rng.integers(1, amax + 1)), alpha_max=amax,
+             adaptive=int(rng.random() < 0.85), max_iters=int(rng.choice([1, 2, 3, 16])),
+             eps_ppm=int(rng.choice([0, 10000, 30000, 100000])))
+    edges, colour = oracle.quotient_colouring(g, part, k)
+    if len(edges) == 0:
+        pytest.skip("no adjacent blocks")
+    cls = int(rng.integers(0, colour.max() + 1))
+    pairs = [tuple(e) for e, c in zip(edges.tolist(), colour.tolist()) if c == cls]
+    dg = gpu_lib.DeviceGraph.from_host(g)
+    dpart = torch.as_tensor(part.copy()).cuda()
+    res, trace = gpu_lib.flow_refine_batch(ctx, dg, dpart, k, pairs, gpu_lib.params(**p))
+    cur = part.copy()
+    for i, (a, b) in enumerate(pairs):
+        o = oracle.refine_pair(g, cur, k, a, b, p, want_side=False)
+        for key in RESULT_KEYS:
+            assert res[i][key] == o.result[key], (seed, (a, b), key, p)
+        assert trace[i] == o.trace, (seed, (a, b))
+        cur = o.part
+    assert np.array_equal(dpart.cpu().numpy(), cur)
