@@ -30,7 +30,8 @@ static thread_local hipError_t last_hip_error = hipSuccess;
 #define FR_MAX_BLOCKS_PER_CU 8
 
 struct DevBufs {
-  int64_t ncap = 0, acap = 0, kcap = 0, pcap = 0;
+  int64_t ncap = 0, acap = 0, kcap = 0, pcap = 0;  // graph copies: n, arcs
+  int64_t sncap = 0, sacap = 0;                      // arenas and marks: slots * n, slots * arcs
   // per vertex
   int32_t *mark = nullptr, *vmap = nullptr, *uvert = nullptr, *lg = nullptr, *lo = nullptr,
           *ex = nullptr, *lab = nullptr, *ins = nullptr, *LA = nullptr, *LB = nullptr,
@@ -113,29 +114,38 @@ static void free_vertex_arc(DevBufs &d) {
   d.lflag = nullptr;
   dfree(d.side);
   d.side = nullptr;
-  d.ncap = d.acap = 0;
+  d.ncap = d.acap = d.sncap = d.sacap = 0;
 }
 
-static int32_t ensure_capacity(fr_context *c, int64_t n, int64_t narcs, int64_t k) {
+// Graph-sized buffers (staged copies, partitions, side codes) for n vertices
+// and narcs arcs; arena-sized ones (per-entry slices, corridor marks) for
+// `slots` entries per vertex and per arc.
+static int32_t ensure_capacity(fr_context *c, int64_t n, int64_t narcs, int64_t k,
+                               int64_t slots = 1) {
   DevBufs &d = c->d;
-  if (n > d.ncap || narcs > d.acap) {
+  const int64_t sn = slots * n, sa = slots * narcs;
+  if (n > d.ncap || narcs > d.acap || sn > d.sncap || sa > d.sacap) {
     const int64_t nc = std::max(n, d.ncap), ac = std::max(narcs, d.acap);
+    const int64_t snc = std::max(sn, d.sncap), sac = std::max(sa, d.sacap);
     free_vertex_arc(d);
     hipError_t e = hipSuccess;
 #define A_(p, cnt) \
   if (e == hipSuccess) e = dalloc(&d.p, cnt)
-    A_(mark, nc); A_(vmap, nc); A_(uvert, nc); A_(lg, nc); A_(lo, nc + FR_MAX_PAIRS + 1);
-    A_(ex, nc); A_(lab, nc); A_(ins, nc); A_(LA, nc); A_(LB, nc); A_(SNK, nc); A_(partw, nc);
-    A_(parts, nc); A_(gx, nc + 1); A_(gv, nc); A_(lflag, nc); A_(side, nc);
-    A_(arc, ac); A_(ga, ac); A_(gw, ac);
+    A_(mark, snc); A_(vmap, snc); A_(uvert, snc); A_(lg, snc); A_(lo, snc + FR_MAX_PAIRS + 1);
+    A_(ex, snc); A_(lab, snc); A_(ins, snc); A_(LA, snc); A_(LB, snc); A_(SNK, snc);
+    A_(lflag, snc); A_(arc, sac);
+    A_(partw, nc); A_(parts, nc); A_(gx, nc + 1); A_(gv, nc); A_(side, nc);
+    A_(ga, ac); A_(gw, ac);
 #undef A_
     if (e != hipSuccess) {
       free_vertex_arc(d);
       return FR_E_OOM;
     }
-    if (hipMemset(d.mark, 0, sizeof(int32_t) * (size_t)nc) != hipSuccess) return FR_E_DEVICE;
+    if (hipMemset(d.mark, 0, sizeof(int32_t) * (size_t)snc) != hipSuccess) return FR_E_DEVICE;
     d.ncap = nc;
     d.acap = ac;
+    d.sncap = snc;
+    d.sacap = sac;
     c->stamp = 2;
   }
   if (k > d.kcap) {
@@ -169,7 +179,7 @@ static int32_t ensure_pairs(fr_context *c, int64_t npairs) {
 // clear them well before int32 wraps.
 static int32_t reserve_stamps(fr_context *c, int64_t count, int32_t *first) {
   if ((int64_t)c->stamp + 2 * count + 4 > (1 << 30)) {
-    HIPCHK(hipMemsetAsync(c->d.mark, 0, sizeof(int32_t) * (size_t)c->d.ncap, c->cs));
+    HIPCHK(hipMemsetAsync(c->d.mark, 0, sizeof(int32_t) * (size_t)c->d.sncap, c->cs));
     c->stamp = 2;
   }
   *first = c->stamp;
@@ -592,7 +602,7 @@ static int32_t stage(fr_context *c, const fr_graph *g, int32_t *part, int32_t k,
   int64_t narcs = 0;
   int32_t rc = graph_narcs(c, g, &narcs);
   if (rc) return rc;
-  if ((rc = ensure_capacity(c, (int64_t)slots * g->n, (int64_t)slots * narcs, k))) return rc;
+  if ((rc = ensure_capacity(c, g->n, narcs, k, slots))) return rc;
   DevBufs &d = c->d;
   hipStream_t st = c->cs;
   s->g = *g;
@@ -820,14 +830,19 @@ extern "C" int32_t flow_refine_sweep(fr_context *c, const fr_graph *g, int32_t *
   if (rc) return rc;
   if (p->use_mlp && !c->mlp_loaded) return FR_E_INVALID_ARG;
   if ((rc = enter(c))) return rc;
+  // arenas for the longest factor chain a round may speculate on
+  int64_t narcs0 = 0;
+  if ((rc = graph_narcs(c, g, &narcs0))) return rc;
+  const int32_t Wmax = speculation_slots(c, p, 1, g->n, narcs0);
   Staged s;
-  if ((rc = stage(c, g, part, k, &s))) return rc;
+  if ((rc = stage(c, g, part, k, &s, Wmax))) return rc;
   DevBufs &d = c->d;
   hipStream_t st = c->cs;
   // the caller's partition changes only on success: work on a copy
   int32_t *work = d.partw;
   HIPCHK(hipMemcpyAsync(work, s.dpart, sizeof(int32_t) * g->n, hipMemcpyDeviceToDevice, st));
   KArgs A = call_args(c, &s.g, work, k, p);
+  A.mstride = g->n;
   if ((rc = call_constants(c, A, s.narcs, p))) return rc;
   int64_t acc[4] = {0, 0, 0, 0};
   std::vector<int32_t> e, col, pairs, offs;
@@ -836,16 +851,27 @@ extern "C" int32_t flow_refine_sweep(fr_context *c, const fr_graph *g, int32_t *
     if ((rc = quotient_dev(c, &s.g, work, k, e, col))) return rc;
     int32_t ncol = 0;
     for (int32_t x : col) ncol = std::max(ncol, x + 1);
-    // pairs of all rounds, class by class, at most FR_MAX_PAIRS per round
+    std::vector<int32_t> per_class((size_t)ncol, 0);
+    for (int32_t x : col) per_class[x]++;
+    int32_t largest = 1;
+    for (int32_t v : per_class) largest = std::max(largest, v);
+    // speculative factors per pair, sized for the largest round
+    const int32_t W = std::min(Wmax, speculation_slots(c, p, largest, g->n, narcs0));
+    A.W = W;
+    // entries of all rounds (each pair W times), class by class, at most
+    // FR_MAX_PAIRS entries per round
+    const int32_t per_round = FR_MAX_PAIRS / W;
     pairs.clear();
     offs.assign(1, 0);
     for (int32_t cc = 0; cc < ncol; cc++) {
       int32_t in_round = 0;
       for (size_t i = 0; i < col.size(); i++)
         if (col[i] == cc) {
-          pairs.push_back(e[2 * i]);
-          pairs.push_back(e[2 * i + 1]);
-          if (++in_round == FR_MAX_PAIRS) {
+          for (int32_t sl = 0; sl < W; sl++) {
+            pairs.push_back(e[2 * i]);
+            pairs.push_back(e[2 * i + 1]);
+          }
+          if (++in_round == per_round) {
             offs.push_back((int32_t)(pairs.size() / 2));
             in_round = 0;
           }
@@ -892,7 +918,8 @@ extern "C" int32_t flow_refine_sweep(fr_context *c, const fr_graph *g, int32_t *
     HIPCHK(hipMemcpyAsync(ps.data(), d.ps, sizeof(PairState) * total, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     int64_t changed = 0;
-    for (const PairState &q : ps) {
+    for (int64_t i = 0; i < total; i += W) {  // the pair's record is its first entry
+      const PairState &q = ps[(size_t)i];
       acc[1] += q.iters;
       acc[3] += q.re_sum;
       if (q.applied) changed++;
