@@ -7,11 +7,13 @@ corridor, network, max preflow, smallest source set, balance check, adaptive
 factor, write-back -- every solve of the loop.  Inputs are resident in device
 memory before the timed region; each step starts from the same partition.
 
-Printed: one JSON line with region edges/s (corridor edges summed over all
-flow solves, divided by wall time), the roofline of the solve kernel, the CPU
-oracle on the same input, and a batched-vs-plain comparison on one
-quotient-graph matching round of a 3D random geometric graph (n = 2^20,
-k = 16).
+Printed: one JSON line with region edges/s (corridor edges summed over the
+solves the adaptive loop records, divided by wall time), the roofline of the
+flow kernel (k_flow: relabels, push/relabel passes, closure), the CPU oracle
+on the same input, and beside it: batched vs plain on the largest matching
+round of C3 (3D RGG n = 2^20, k = 16, autotuned launch) and of C5 (2D RGG
+n = 2^24, k = 256), plain vs learned start factor on one sweep of C4 (2D RGG
+n = 2^22, k = 64), and a C5 sweep to convergence.
 """
 from __future__ import annotations
 

@@ -1,17 +1,28 @@
 // Device code of libflowrefine: max-flow min-cut pair refinement
 // (Sanders & Schulz, Section 4.1) for gfx950.
 //
-// One workgroup solves one pair of blocks from start to end: boundary,
-// bounded BFS corridor, local network, push/relabel with global relabels,
-// residual closure, balance check, adaptive factor loop, write-back.  Phases
-// are separated by workgroup barriers only, so every step stays inside one
-// CU and its L1; no cross-XCD cache maintenance is ever needed.  A batch is
-// one launch of persistent workgroups that take pairs from a device queue,
-// largest first, so pairs of uneven size balance over the CUs.
+// A round refines the pairs of one quotient-graph matching.  Each pair owns
+// W consecutive entries ("slots") that solve the current partition at the
+// factors alpha, alpha/2, ... of its halving chain at once; an adaptive
+// iteration of every entry is a chain of kernels:
+//   k_iter_begin   compact the entries still iterating
+//   k_bnd          pair boundary and cut (grid-wide over the pairs' unions)
+//   k_corr         bounded BFS corridor (one workgroup per entry)
+//   k_iter_mid     prefix sums of the corridor sizes
+//   k_net_*        corridor network: arc counts, CSR offsets, arcs, reverse
+//                  arcs and the initial preflow (grid-wide)
+//   k_flow         global relabels, push/relabel passes, residual closure
+//                  and the candidate's record (one workgroup per entry)
+//   k_select       the adaptive rule over the finished slots, write-back of
+//                  the applied candidate, factors of the next iteration
+// Bulk scans use the whole chip; the latency-bound searches stay inside one
+// workgroup, its LDS and its L1.  Kernel boundaries order every step, so no
+// cross-XCD cache maintenance is needed.
 //
-// Pairs own disjoint blocks, hence disjoint vertices: their corridors,
-// corridor marks and flows never touch, and every per-pair buffer is a slice
-// of a shared arena sized by the pair's vertex and arc counts.
+// Pairs own disjoint blocks, hence disjoint vertices: their corridors and
+// flows never touch, and every per-entry buffer is a slice of a shared arena
+// sized by the pair's vertex and arc counts.  The slots of one pair share
+// vertices and keep separate corridor marks.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
