@@ -1100,27 +1100,40 @@ __global__ void __launch_bounds__(TPB) k_corr(KArgs A, int32_t it) {
       // expand the sides that go on
       int64_t acc2[4] = {0, 0, 0, 0};  // weight a, weight b, count a, count b
       int32_t *ncnt = &sh.cnt[(cc + 1) % 3];
-      for_groups<GT>(cnt, [&](int item, bool valid, int gl) {
+      // GTF lanes per frontier vertex, KF arcs per lane: the neighbours'
+      // block, mark and weight are loaded together, ahead of the claims
+      for_groups<GTF>(cnt, [&](int item, bool valid, int gl) {
         const int32_t u = valid ? cur[item] : 0;
         const int32_t x = valid ? A.part[u] : -1;
+        const int32_t e0 = valid ? A.xadj[u] : 0, e1 = valid ? A.xadj[u + 1] : 0;
         const int s = x == b;
         const bool go = valid && sh.state[s];
-        const int32_t e0 = go ? A.xadj[u] : 0, e1 = go ? A.xadj[u + 1] : 0;
         count_work(sh, W_BFS_ITEMS, (go && gl == 0) ? 1 : 0);
         count_work(sh, W_BFS_ARCS, (go && gl == 0) ? e1 - e0 : 0);
-        for (int32_t a0 = e0; a0 < e1; a0 += GT) {
-          const int32_t e = a0 + gl;
-          bool claim = false;
-          int32_t v = 0;
-          if (e < e1) {
-            v = A.adjncy[e];
-            if (A.part[v] == x && mk[v] < S) claim = atomicMax(&mk[v], S) < S;
+        const int32_t ee = go ? e1 : e0;
+        for (int32_t c0 = e0; c0 < ee; c0 += GTF * KF) {
+          int32_t v[KF], xv[KF], mv[KF], wv[KF];
+#pragma unroll
+          for (int k = 0; k < KF; k++) {
+            const int32_t e = c0 + k * GTF + gl;
+            v[k] = e < ee ? A.adjncy[e] : -1;
           }
-          const int pos = wave_append(ncnt, claim);
-          if (claim) {
-            put_bounded(nxt, pos, V.nv, v, A.ctl);
-            acc2[s] += A.vwgt[v];
-            acc2[2 + s] += 1;
+#pragma unroll
+          for (int k = 0; k < KF; k++) {
+            xv[k] = v[k] >= 0 ? A.part[v[k]] : -1;
+            mv[k] = v[k] >= 0 ? mk[v[k]] : S;
+            wv[k] = v[k] >= 0 ? A.vwgt[v[k]] : 0;
+          }
+#pragma unroll
+          for (int k = 0; k < KF; k++) {
+            bool claim = false;
+            if (v[k] >= 0 && xv[k] == x && mv[k] < S) claim = atomicMax(&mk[v[k]], S) < S;
+            const int pos = wave_append(ncnt, claim);
+            if (claim) {
+              put_bounded(nxt, pos, V.nv, v[k], A.ctl);
+              acc2[s] += wv[k];
+              acc2[2 + s] += 1;
+            }
           }
         }
       });
