@@ -1,7 +1,8 @@
 // Learned area factor: a small MLP that proposes the start factor alpha of
 // each pair's adaptive flow iterations.  It has no counterpart in the paper;
 // the plain adaptive search (Sec. 4.1) keeps running from the proposed
-// factor, so the flow results stay exact and the search remains the judge.
+// factor, so the flow results stay exact; the search from alpha' is the
+// reference for cut quality.
 //
 // Network: 8 features -> 64 -> 64 -> 5 classes (alpha = 1, 2, 4, 8, 16),
 // ReLU hidden layers, softmax cross-entropy.  FP32 throughout, plain FMA

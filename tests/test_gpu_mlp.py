@@ -164,8 +164,9 @@ def test_trained_factor_gain(gpu_lib, ctx):
     """What the trained network gains over the plain adaptive search (start at
     alpha' = 16) on held-out graphs of the training family (one sweep over the
     colour classes): at least 20 % fewer corridor edges, with the total cut at
-    most 1 % above the plain search's.  The plain search stays the judge: both
-    runs are exact flow solves, only the start factor differs."""
+    most 1 % above the plain search's.  The plain search is the reference for
+    cut quality: both runs are exact flow solves, only the start factor
+    differs."""
     import torch
 
     gpu_lib.load_trained_mlp(ctx)
