@@ -301,3 +301,55 @@ def test_random_batches_vs_oracle(gpu_lib, ctx, seed):
         assert trace[i] == o.trace, (seed, (a, b))
         cur = o.part
     assert np.array_equal(dpart.cpu().numpy(), cur)
+
+
+def _pair_grid(width=256, height=128, seed=5):
+    """A weighted grid cut into 2x2-vertex blocks; pairs (2i, 2i+1) are
+    horizontal neighbours: 8192 blocks, 4096 disjoint adjacent pairs."""
+    from tests.helpers import csr_from_edges
+
+    rng = np.random.default_rng(seed)
+    edges, ws = [], []
+    for y in range(height):
+        for x in range(width):
+            v = y * width + x
+            if x + 1 < width:
+                edges.append((v, v + 1))
+                ws.append(int(rng.integers(1, 6)))
+            if y + 1 < height:
+                edges.append((v, v + width))
+                ws.append(int(rng.integers(1, 6)))
+    g = csr_from_edges(width * height, edges, ws)
+    xs, ys = np.arange(g.n) % width, np.arange(g.n) // width
+    part = ((ys // 2) * (width // 2) + xs // 2).astype(np.int32)
+    k = (width // 2) * (height // 2)
+    pairs = [(2 * i, 2 * i + 1) for i in range(k // 2)]
+    for a, b in pairs[::3]:  # move one vertex of every third pair across
+        part[np.where(part == a)[0][0]] = b
+    return g, part, k, pairs
+
+
+def test_batch_at_the_pair_limit(gpu_lib, ctx):
+    """4096 pairs in one call (the per-round maximum) against the oracle;
+    one more pair is rejected without touching the partition."""
+    import torch
+
+    g, part, k, pairs = _pair_grid()
+    p = dict(area_mode=0, depth=0, alpha=4, alpha_max=8, adaptive=1, max_iters=4,
+             eps_ppm=300000)
+    dg = gpu_lib.DeviceGraph.from_host(g)
+    dpart = torch.as_tensor(part.copy()).cuda()
+    res, trace = gpu_lib.flow_refine_batch(ctx, dg, dpart, k, pairs, gpu_lib.params(**p))
+    rc, ores, otr, opart = oracle.refine_batch(g, part, k, pairs, p)
+    assert rc == 0 and len(res) == 4096
+    for i in range(len(pairs)):
+        for key in RESULT_KEYS:
+            assert res[i][key] == ores[i][key], (i, key)
+        assert trace[i] == otr[i]
+    assert np.array_equal(dpart.cpu().numpy(), opart)
+    too_many = pairs + [(k - 1, k - 2)]
+    dpart2 = torch.as_tensor(part.copy()).cuda()
+    with pytest.raises(gpu_lib.FlowRefineError) as e:
+        gpu_lib.flow_refine_batch(ctx, dg, dpart2, k, too_many, gpu_lib.params(**p))
+    assert e.value.code == -8
+    assert np.array_equal(dpart2.cpu().numpy(), part)
