@@ -55,7 +55,7 @@ extern "C" {
 #define FR_E_INVALID_PAIR (-3)       /* block id outside [0, k), or a == b */
 #define FR_E_PAIRS_NOT_DISJOINT (-4) /* two pairs of one batch share a block */
 #define FR_E_OVERFLOW (-5)           /* capacities of one corridor reach 2^31, or an edge weight >= 2^30 */
-#define FR_E_DEVICE (-6)             /* HIP runtime error or an aborted device barrier */
+#define FR_E_DEVICE (-6)             /* HIP runtime error, or a failed internal consistency check */
 #define FR_E_OOM (-7)                /* device or host allocation failed */
 #define FR_E_INVALID_ARG (-8)        /* NULL pointer, bad parameter value */
 #define FR_E_SOLVER_LIMIT (-9)       /* push-relabel exceeded its sweep safety cap */
@@ -133,17 +133,21 @@ typedef struct {
 
 /* Kernel launch parameters; any valid setting gives identical results. */
 typedef struct {
-  int32_t block_threads;   /* threads per workgroup: 64..1024, multiple of 64 */
-  int32_t blocks_per_cu;   /* persistent workgroups per compute unit: 1..4 */
-  int32_t tpv;             /* lanes per vertex in push/relabel sweeps: 1,2,4,8,16 */
-  int32_t relabel_period;  /* push/relabel sweeps between global relabels, >= 1 */
+  int32_t block_threads;   /* threads per workgroup of the per-pair kernels: 256, 512 or 1024 */
+  int32_t blocks_per_cu;   /* persistent per-pair workgroups per compute unit: 1..8 */
+  int32_t tpv;             /* lanes per vertex in push/relabel sweeps: 1, 2, 4, 8 or 16
+                              (1 runs as 2, 16 as 8) */
+  int32_t relabel_period;  /* push/relabel sweeps between global relabels, 1..10^6 */
 } fr_tuning;
 
 typedef struct fr_context fr_context;
 
-/* Create a context on HIP device `device`, issuing work on `hip_stream` (a
- * hipStream_t; NULL = the null stream).  Device scratch is allocated lazily and
- * grows with the largest graph seen. */
+/* Create a context on HIP device `device`.  Calls wait for work already
+ * queued on `hip_stream` (a hipStream_t; NULL = the null stream) and run on
+ * the context's own stream.  Device scratch is allocated lazily and grows
+ * with the largest graph seen: per-pair arenas and corridor marks take
+ * (speculative factors per pair) x (n vertices, 2m arcs) slots, at most
+ * 2^28 vertex and 2^29 arc slots. */
 int32_t fr_create(int32_t device, void *hip_stream, fr_context **ctx);
 int32_t fr_destroy(fr_context *ctx);
 const char *fr_strerror(int32_t code);
@@ -176,10 +180,10 @@ int32_t fr_quotient_matchings(fr_context *ctx, const fr_graph *g, const int32_t 
                               int32_t *edges, int32_t *colour, int32_t max_edges,
                               int32_t *nedges);
 
-/* Repeated rounds: build and colour the quotient graph, run one batched solve
- * per colour class in colour order (all rounds of a sweep recorded into one
- * hipGraph and launched once), until a sweep changes nothing or max_sweeps
- * sweeps ran.  stats (optional, host int64 [4]): sweeps, flow
+/* Repeated rounds (Sec. 4.3): build and colour the quotient graph, run one
+ * batched solve per colour class in colour order (all rounds of a sweep
+ * recorded into one hipGraph and launched once), until a sweep changes
+ * nothing or max_sweeps sweeps ran.  stats (optional, host int64 [4]): sweeps, flow
  * solves, pairs with an applied change, region edges.  total_cut_out: the cut
  * sum_{i<j} omega(E_ij) after the sweep. */
 int32_t flow_refine_sweep(fr_context *ctx, const fr_graph *g, int32_t *part, int32_t k,
@@ -197,10 +201,10 @@ int32_t fr_get_tuning(fr_context *ctx, fr_tuning *t);
  * the finished solves in order: the recorded solves, the trace, the result
  * and the partition are those of the sequential loop; solves past the walk
  * are discarded (counted in the work counters, not in region_vertices /
- * region_edges).  Used for pair and batch calls with adaptive iterations (the
- * chain starts at the learned factor when use_mlp is set), as far as every
- * factor of every pair gets a workgroup slot; fr_last_stats counters[7]
- * reports the factors per pair. */
+ * region_edges).  Used for pair, batch and sweep calls with adaptive
+ * iterations (the chain starts at the learned factor when use_mlp is set), as
+ * far as every factor of every pair gets a workgroup slot; fr_last_stats
+ * counters[7] reports the factors per pair of the last pair / batch call. */
 int32_t fr_set_speculation(fr_context *ctx, int32_t on);
 
 /* Input checks of every call (CSR shape, ranges, symmetry: O(sum deg^2)) on
