@@ -713,15 +713,33 @@ template <int TPB>
 __device__ int32_t global_relabel(const KArgs &A, const PairView &V, int32_t nr, int32_t NL,
                                   SolveShared<TPB> &sh, Rot &R, int64_t &levels, bool lds) {
   uint32_t *vis = sh.u.f.bm[0];
-  BLOCK_WAVE_LOOP(i, nr) {
-    if (i < nr) {
-      const uint32_t f = V.fl[i];
-      V.lab[i] = LF_SNK(f) ? 0 : (LF_SRC(f) ? NL + 1 : NL);
+  // start labels (sink border 0, source border NL + 1, the rest NL) and, with
+  // the LDS bitmaps, visited = border and a cleared second bitmap: one pass,
+  // four vertices per lane with their flags loaded together
+  for (int64_t b0 = (int64_t)(threadIdx.x & ~63u) * 4; b0 < nr; b0 += 4 * (int64_t)blockDim.x) {
+    uint32_t f[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int64_t i = b0 + 64 * j + lane64();
+      f[j] = i < nr ? V.fl[i] : 0u;
     }
-  }
-  if (lds) {
-    bm_fill(vis, nr, [&](int32_t i) { return (V.fl[i] & LF_BORDER) != 0; });
-    bm_fill(sh.u.f.bm[1], nr, [&](int32_t) { return false; });
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int64_t i = b0 + 64 * j + lane64();
+      if (i < nr) V.lab[i] = LF_SNK(f[j]) ? 0 : (LF_SRC(f[j]) ? NL + 1 : NL);
+      if (lds) {
+        const unsigned long long m = __ballot(i < nr && (f[j] & LF_BORDER));
+        const int64_t w0 = (b0 + 64 * j) >> 5;  // 64-aligned: two bitmap words
+        if (lane64() == 0) {
+          vis[w0] = (uint32_t)m;
+          sh.u.f.bm[1][w0] = 0u;
+        }
+        if (lane64() == 32) {
+          vis[w0 + 1] = (uint32_t)(m >> 32);
+          sh.u.f.bm[1][w0 + 1] = 0u;
+        }
+      }
+    }
   }
   if (threadIdx.x == 0) sh.cnt[(R.c + 1) % 3] = 0;
   __syncthreads();
@@ -782,11 +800,24 @@ __device__ int32_t global_relabel(const KArgs &A, const PairView &V, int32_t nr,
   {
     const ListRef act_list = flist(V, sh, 0, lds);
     int32_t *ncnt = &sh.cnt[(R.c + 1) % 3];
-    BLOCK_WAVE_LOOP(i, nr) {
-      bool act = false;
-      if (i < nr) act = !(V.fl[i] & LF_BORDER) && V.ex[i] > 0 && V.lab[i] < NL;
-      const int pos = wave_append(ncnt, act);
-      if (act) lput(act_list, pos, V.nv, (int32_t)i, A.ctl);
+    // active vertices, four per lane with their loads issued together
+    for (int64_t b0 = (int64_t)(threadIdx.x & ~63u) * 4; b0 < nr; b0 += 4 * (int64_t)blockDim.x) {
+      uint32_t f[4];
+      int32_t e[4], l[4];
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int64_t i = b0 + 64 * j + lane64();
+        const bool in = i < nr;
+        f[j] = in ? V.fl[i] : LF_BORDER;
+        e[j] = in ? V.ex[i] : 0;
+        l[j] = in ? V.lab[i] : NL;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const bool act = !(f[j] & LF_BORDER) && e[j] > 0 && l[j] < NL;
+        const int pos = wave_append(ncnt, act);
+        if (act) lput(act_list, pos, V.nv, (int32_t)(b0 + 64 * j + lane64()), A.ctl);
+      }
     }
     if (threadIdx.x == 0) sh.cnt[(R.c + 2) % 3] = 0;
     __syncthreads();
