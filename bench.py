@@ -130,6 +130,26 @@ def run_cpu_baseline(w):
     return o, dt
 
 
+def run_cpu_parallel(w, pairs, threads):
+    """The oracle on the pairs of one round (independent: disjoint blocks),
+    spread over a thread pool on the host; region edges/s of the sample."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(ab):
+        return oracle.refine_pair(w.graph, w.part, w.k, ab[0], ab[1], w.params,
+                                  want_side=False).result["region_edges"]
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        edges = sum(pool.map(one, pairs))
+    dt = time.perf_counter() - t0
+    return {"value": edges / dt, "unit": "region edges/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(pairs)} pairs of the same round, each the sequential oracle, "
+                      f"spread over {threads} host threads",
+            "seconds": dt}
+
+
 def run_batched(args, fr, torch, gen, cid="C3"):
     """The largest matching round of a workload (C3: 3D RGG n=2^20, mean
     degree 12, k=16 RCB + 2 % noise; C5: 2D RGG n=2^24, k=256): all pairs in
@@ -180,6 +200,9 @@ def run_batched(args, fr, torch, gen, cid="C3"):
     ctx.close()
     e_b = sum(r["region_edges"] for r in res_b)
     e_p = sum(r["region_edges"] for r in res_p)
+    cpu = None
+    if cid == "C5" and not args.no_cpu_baseline:
+        cpu = run_cpu_parallel(w, pairs[:32], 16)
     same = bool(np.array_equal(part_b, part_p)) and all(
         rb["cut_after"] == rp["cut_after"] for rb, rp in zip(res_b, res_p))
     desc = {"C3": "C3: 3D RGG n=2^20 mean degree 12 unit weights, k=16 RCB + 2% noise",
@@ -195,6 +218,7 @@ def run_batched(args, fr, torch, gen, cid="C3"):
         "speedup": t_p / t_b,
         "equal_result": same,
         "tuning": tuning,
+        "cpu_parallel": cpu,
         "region_edges": e_b,
     }
 
@@ -366,8 +390,9 @@ def main():
         line["bit_exact_vs_oracle"] = bool(exact)
     if not args.no_batched:
         line["batched"] = run_batched(args, fr, torch, gen)
-        line["batched_c5_round"] = run_batched(argparse.Namespace(batch_reps=1), fr, torch, gen,
-                                               "C5")
+        line["batched_c5_round"] = run_batched(
+            argparse.Namespace(batch_reps=1, no_cpu_baseline=args.no_cpu_baseline), fr, torch,
+            gen, "C5")
     if not args.no_learned:
         line["learned_factor"] = run_learned(args, fr, torch, gen)
     if not args.no_sweep:
