@@ -5,7 +5,10 @@ max-flow min-cut pair refinement (Section 4.1 of the paper: bounded BFS
 corridor, s-t network with infinite border arcs, max flow, smallest source set
 from the residual graph, balance check, adaptive flow iterations), plus the
 quotient-graph colouring sweep and the per-pair features of the learned area
-factor.  Only ``tests/``, the smoke check and the benchmark's CPU-baseline leg
+factor.  With ``mb_reps > 0`` a solve takes the most balanced minimum cut of
+Section 4.1.1 (residual strongly connected components, removal of the s and t
+closures, sweeps along random topological orders) instead of the smallest
+source set.  Only ``tests/``, the smoke check and the benchmark's CPU-baseline leg
 use it.  It shares no code with the GPU library and never calls it.
 
 ``mlp_*`` below is the float64 reference of the small area-factor network
@@ -43,7 +46,8 @@ class OrGraph(ctypes.Structure):
 
 class OrParams(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int32) for f in
-                ("area_mode", "depth", "alpha", "alpha_max", "adaptive", "max_iters", "eps_ppm")]
+                ("area_mode", "depth", "alpha", "alpha_max", "adaptive", "max_iters", "eps_ppm",
+                 "mb_reps", "mb_seed")]
 
 
 class OrSolve(ctypes.Structure):
@@ -84,6 +88,13 @@ def _load():
     lib.or_sweep.argtypes = [G, vp, i32, P, i32, ctypes.POINTER(i64), vp]
     lib.or_pair_features.restype = i32
     lib.or_pair_features.argtypes = [G, vp, i32, i32, i32, i32, vp]
+    lib.or_splitmix64.restype = ctypes.c_uint64
+    lib.or_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+    lib.or_scc.restype = i32
+    lib.or_scc.argtypes = [i32, i64, vp, vp, vp]
+    lib.or_mbcut.restype = i32
+    lib.or_mbcut.argtypes = [i32, i64, vp, vp, vp, i32, i32, vp, vp, i64, i64, i32,
+                             ctypes.c_uint32, ctypes.POINTER(i64), vp, vp, vp, vp, vp]
     _lib = lib
     return lib
 
@@ -106,8 +117,11 @@ class _Bound:
 
 
 def _params(p: dict) -> OrParams:
+    seed = int(p.get("mb_seed", 0)) & 0xFFFFFFFF
+    if seed >= 1 << 31:
+        seed -= 1 << 32
     return OrParams(p.get("area_mode", 0), p.get("depth", 0), p["alpha"], p["alpha_max"],
-                    p["adaptive"], p["max_iters"], p["eps_ppm"])
+                    p["adaptive"], p["max_iters"], p["eps_ppm"], p.get("mb_reps", 0), seed)
 
 
 def _struct_dict(s) -> dict:
@@ -132,6 +146,59 @@ def maxflow(nn: int, tails, heads, caps, s: int, t: int):
     if rc != 0:
         raise ValueError("or_maxflow: bad input")
     return int(val.value), reach.astype(bool)
+
+
+def splitmix64(seed: int, n: int) -> int:
+    """Output number n >= 1 of SplitMix64 started at `seed`."""
+    return int(_load().or_splitmix64(seed & (2**64 - 1), n & (2**64 - 1)))
+
+
+def scc(nn: int, tails, heads) -> np.ndarray:
+    """Strongly connected components (Tarjan) of a directed graph: comp[v]."""
+    tails = np.ascontiguousarray(tails, dtype=np.int32)
+    heads = np.ascontiguousarray(heads, dtype=np.int32)
+    comp = np.zeros(nn, dtype=np.int32)
+    nc = _load().or_scc(nn, tails.shape[0], _ptr(tails), _ptr(heads), _ptr(comp))
+    if nc < 0:
+        raise ValueError("or_scc: bad input")
+    return comp
+
+
+@dataclass
+class MBCut:
+    flow: int
+    src: np.ndarray    # chosen source side (bool [nn])
+    smin: np.ndarray   # smallest source set
+    cls: np.ndarray    # 0 with s, 1 remaining, 2 with t
+    comp: np.ndarray   # residual strongly connected component
+    info: dict
+
+
+def mbcut(nn: int, tails, heads, caps, s: int, t: int, w, gid, base_s: int, base_t: int,
+          reps: int, seed: int) -> MBCut:
+    """Max flow, then the most balanced minimum cut (Sec. 4.1.1) of a directed
+    network; the balance of a source side C is max(base_s + w(C),
+    base_t + w(V minus C))."""
+    tails = np.ascontiguousarray(tails, dtype=np.int32)
+    heads = np.ascontiguousarray(heads, dtype=np.int32)
+    caps = np.ascontiguousarray(caps, dtype=np.int64)
+    w = np.ascontiguousarray(w, dtype=np.int64)
+    gid = np.ascontiguousarray(gid, dtype=np.int32)
+    src = np.zeros(nn, dtype=np.uint8)
+    smin = np.zeros(nn, dtype=np.uint8)
+    cls = np.zeros(nn, dtype=np.int8)
+    comp = np.zeros(nn, dtype=np.int32)
+    info = np.zeros(7, dtype=np.int64)
+    val = ctypes.c_int64(0)
+    rc = _load().or_mbcut(nn, tails.shape[0], _ptr(tails), _ptr(heads), _ptr(caps), s, t,
+                          _ptr(w), _ptr(gid), base_s, base_t, reps, seed & 0xFFFFFFFF,
+                          ctypes.byref(val), _ptr(src), _ptr(smin), _ptr(cls), _ptr(comp),
+                          _ptr(info))
+    if rc != 0:
+        raise ValueError("or_mbcut: bad input")
+    keys = ("ncomp", "reduced", "reduced_arcs", "limited", "best_rep", "best_pos", "best_bal")
+    return MBCut(int(val.value), src.astype(bool), smin.astype(bool), cls, comp,
+                 dict(zip(keys, info.tolist())))
 
 
 @dataclass

@@ -18,6 +18,10 @@
  *     max-flow algorithm gives the same value and residual closure)
  *   - smallest source set = vertices reachable from s in the residual graph
  *     (Sec. 4.1.1, Ford-Fulkerson labelling)
+ *   - optionally, the most balanced minimum cut instead (Sec. 4.1.1): strongly
+ *     connected components of the residual graph, removal of the sink's
+ *     component with its predecessors and of the source's with its
+ *     successors, then sweeps along random topological orders of what is left
  *   - balance check and adaptive flow iterations  (Sec. 4.1, improvements)
  *   - balance constraint L_max and cut objective  (Sec. 2.1)
  *
@@ -33,6 +37,12 @@
  *       improving => stop; at most max_iters solves
  *   R8  the first block of the pair is the source side
  *   R9  DEPTH mode includes BFS distance <= depth from the boundary
+ *   R11 most balanced cut: balance of a cut = the heavier of the two new block
+ *       weights; a random topological order takes, among the components whose
+ *       predecessors are all placed, the one with the smallest key, keys from
+ *       SplitMix64; first best wins (earlier sweep, then earlier position);
+ *       more than OR_MB_MAX_COMP remaining components keep the smallest
+ *       source set
  */
 #include <math.h>
 #include <stdint.h>
@@ -55,6 +65,8 @@ typedef struct {
   int32_t adaptive;
   int32_t max_iters;
   int32_t eps_ppm;
+  int32_t mb_reps;  /* 0: smallest source set; > 0: most balanced minimum cut, this many sweeps */
+  int32_t mb_seed;  /* seed of the sweeps' random keys (its 32 bits, zero-extended) */
 } or_params;
 
 /* one flow solve */
@@ -280,6 +292,323 @@ int32_t or_maxflow(int32_t nn, int64_t narcs, const int32_t *tails, const int32_
 }
 
 /* ------------------------------------------------------------------------ */
+/* most balanced minimum cut (Sec. 4.1.1)                                    */
+
+#define OR_MB_MAX_COMP 2048
+
+/* SplitMix64 (Steele, Lea & Flood, "Fast splittable pseudorandom number
+ * generators", OOPSLA 2014): the generator started at `seed` adds the golden
+ * gamma to its state per call and returns the state through a 64-bit finaliser
+ * (xor-shift 30, multiply, xor-shift 27, multiply, xor-shift 31).  Output
+ * number n >= 1 is therefore a function of seed + n * gamma alone. */
+static uint64_t splitmix64_out(uint64_t seed, uint64_t n) {
+  uint64_t z = seed + n * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+uint64_t or_splitmix64(uint64_t seed, uint64_t n) { return splitmix64_out(seed, n); }
+
+/* key of a component with identifier id (its smallest global vertex id) in
+ * sweep r: output number r * 2^32 + id + 1 of the generator */
+static uint64_t mb_key(uint64_t seed, int32_t r, int32_t id) {
+  return splitmix64_out(seed, (((uint64_t)(uint32_t)r << 32) | (uint32_t)id) + 1);
+}
+
+/* Strongly connected components of the directed graph formed by the arcs with
+ * positive residual capacity (Tarjan 1972): depth-first search keeping the
+ * visit index and the lowest index reachable through the search tree and the
+ * vertices still on the component stack; a vertex whose lowest index is its
+ * own closes a component.  Recursion replaced by an explicit stack of (vertex,
+ * next arc).  comp[v] in [0, nc), components numbered in closing order.
+ * Returns nc, or -1 when out of memory. */
+static int32_t net_scc(const or_net *N, int32_t *comp) {
+  int32_t nn = N->nn;
+  int32_t *idx = (int32_t *)malloc(sizeof(int32_t) * (size_t)nn);
+  int32_t *low = (int32_t *)malloc(sizeof(int32_t) * (size_t)nn);
+  int32_t *stk = (int32_t *)malloc(sizeof(int32_t) * (size_t)nn);
+  int32_t *cv = (int32_t *)malloc(sizeof(int32_t) * (size_t)nn);
+  int64_t *cp = (int64_t *)malloc(sizeof(int64_t) * (size_t)nn);
+  uint8_t *on = (uint8_t *)calloc((size_t)nn, 1);
+  int32_t nc = 0;
+  if (!idx || !low || !stk || !cv || !cp || !on) { nc = -1; goto done; }
+  for (int32_t v = 0; v < nn; v++) idx[v] = -1;
+  int32_t next = 0, ns = 0;
+  for (int32_t root = 0; root < nn; root++) {
+    if (idx[root] >= 0) continue;
+    int32_t depth = 0;
+    cv[0] = root;
+    cp[0] = N->off[root];
+    idx[root] = low[root] = next++;
+    stk[ns++] = root;
+    on[root] = 1;
+    while (depth >= 0) {
+      int32_t v = cv[depth];
+      if (cp[depth] < N->off[v + 1]) {
+        int64_t a = N->byt[cp[depth]++];
+        if (N->res[a] <= 0) continue;
+        int32_t w = N->head[a];
+        if (idx[w] < 0) {  /* tree arc: descend */
+          idx[w] = low[w] = next++;
+          stk[ns++] = w;
+          on[w] = 1;
+          depth++;
+          cv[depth] = w;
+          cp[depth] = N->off[w];
+        } else if (on[w] && idx[w] < low[v]) {
+          low[v] = idx[w];
+        }
+        continue;
+      }
+      /* all arcs of v done */
+      if (low[v] == idx[v]) {
+        int32_t x;
+        do {
+          x = stk[--ns];
+          on[x] = 0;
+          comp[x] = nc;
+        } while (x != v);
+        nc++;
+      }
+      depth--;
+      if (depth >= 0 && low[v] < low[cv[depth]]) low[cv[depth]] = low[v];
+    }
+  }
+done:
+  free(idx); free(low); free(stk); free(cv); free(cp); free(on);
+  return nc;
+}
+
+typedef struct {
+  int32_t ncomp;      /* components of the residual graph */
+  int32_t reduced;    /* components left after removing the s and t closures */
+  int32_t reduced_arcs;
+  int32_t limited;    /* more than OR_MB_MAX_COMP components left: smallest source set kept */
+  int32_t best_rep;   /* sweep and position of the chosen cut (-1: none) */
+  int32_t best_pos;
+  int64_t best_bal;   /* max(source side weight, sink side weight) of the chosen cut */
+} or_mbinfo;
+
+/* Most balanced minimum cut on a network that holds a maximum s-t flow.
+ * Node weights w (s and t included), key identifiers gid, fixed weights base_s
+ * and base_t of the two sides outside the network; the balance of a source
+ * side C is max(base_s + w(C), base_t + w(V \ C)), smaller is better.
+ * Writes src[v] = 1 for the source side of the chosen cut and, if not NULL,
+ * cls[v] = 0 (with s), 1 (remaining), 2 (with t) and comp[v].  Returns 0, or
+ * -1 when out of memory. */
+static int32_t net_mb_cut(const or_net *N, int32_t s, int32_t t, const int64_t *w,
+                          const int32_t *gid, int64_t base_s, int64_t base_t, int32_t reps,
+                          uint64_t seed, uint8_t *src, int8_t *cls_out, int32_t *comp_out,
+                          or_mbinfo *info) {
+  int32_t nn = N->nn;
+  memset(info, 0, sizeof(*info));
+  info->best_rep = info->best_pos = -1;
+  int32_t *comp = (int32_t *)malloc(sizeof(int32_t) * (size_t)nn);
+  if (!comp) return -1;
+  int32_t nc = net_scc(N, comp);
+  if (nc < 0) { free(comp); return -1; }
+  info->ncomp = nc;
+  /* the contracted graph: one arc per residual arc between two components,
+   * as forward and backward adjacency lists */
+  int64_t na = 0;
+  for (int64_t a = 0; a < N->na; a++)
+    if (N->res[a] > 0 && comp[N->tail[a]] != comp[N->head[a]]) na++;
+  int64_t *fo = (int64_t *)calloc((size_t)nc + 1, sizeof(int64_t));
+  int64_t *bo = (int64_t *)calloc((size_t)nc + 1, sizeof(int64_t));
+  int32_t *fa = (int32_t *)malloc(sizeof(int32_t) * (size_t)(na ? na : 1));
+  int32_t *ba = (int32_t *)malloc(sizeof(int32_t) * (size_t)(na ? na : 1));
+  int8_t *cl = (int8_t *)malloc((size_t)nc);
+  int32_t *q = (int32_t *)malloc(sizeof(int32_t) * (size_t)nc);
+  int64_t *wc = (int64_t *)calloc((size_t)nc, sizeof(int64_t));
+  int32_t *kid = (int32_t *)malloc(sizeof(int32_t) * (size_t)nc);
+  int32_t *indeg = (int32_t *)malloc(sizeof(int32_t) * (size_t)nc);
+  uint8_t *placed = (uint8_t *)malloc((size_t)nc);
+  int rc = 0;
+  if (!fo || !bo || !fa || !ba || !cl || !q || !wc || !kid || !indeg || !placed) { rc = -1; goto done; }
+  for (int64_t a = 0; a < N->na; a++) {
+    int32_t x = comp[N->tail[a]], y = comp[N->head[a]];
+    if (N->res[a] > 0 && x != y) { fo[x + 1]++; bo[y + 1]++; }
+  }
+  for (int32_t c = 0; c < nc; c++) { fo[c + 1] += fo[c]; bo[c + 1] += bo[c]; }
+  {
+    int64_t *fp = (int64_t *)malloc(sizeof(int64_t) * (size_t)nc);
+    int64_t *bp = (int64_t *)malloc(sizeof(int64_t) * (size_t)nc);
+    if (!fp || !bp) { free(fp); free(bp); rc = -1; goto done; }
+    memcpy(fp, fo, sizeof(int64_t) * (size_t)nc);
+    memcpy(bp, bo, sizeof(int64_t) * (size_t)nc);
+    for (int64_t a = 0; a < N->na; a++) {
+      int32_t x = comp[N->tail[a]], y = comp[N->head[a]];
+      if (N->res[a] > 0 && x != y) { fa[fp[x]++] = y; ba[bp[y]++] = x; }
+    }
+    free(fp); free(bp);
+  }
+  /* remove the sink's component with all its predecessors (class 2) and the
+   * source's component with all its successors (class 0), by BFS */
+  for (int32_t c = 0; c < nc; c++) cl[c] = 1;
+  {
+    int32_t qh = 0, qt = 0;
+    cl[comp[t]] = 2;
+    q[qt++] = comp[t];
+    while (qh < qt) {
+      int32_t c = q[qh++];
+      for (int64_t j = bo[c]; j < bo[c + 1]; j++)
+        if (cl[ba[j]] != 2) { cl[ba[j]] = 2; q[qt++] = ba[j]; }
+    }
+    qh = qt = 0;
+    if (cl[comp[s]] == 2) { rc = -1; goto done; } /* s reaches t: the flow is not maximal */
+    cl[comp[s]] = 0;
+    q[qt++] = comp[s];
+    while (qh < qt) {
+      int32_t c = q[qh++];
+      for (int64_t j = fo[c]; j < fo[c + 1]; j++) {
+        if (cl[fa[j]] == 2) { rc = -1; goto done; }
+        if (cl[fa[j]] != 0) { cl[fa[j]] = 0; q[qt++] = fa[j]; }
+      }
+    }
+  }
+  /* weights and key identifiers of the remaining components; the two fixed sides */
+  int64_t w_src = base_s, w_snk = base_t;
+  for (int32_t c = 0; c < nc; c++) kid[c] = INT32_MAX;
+  for (int32_t v = 0; v < nn; v++) {
+    int32_t c = comp[v];
+    if (cl[c] == 2) w_snk += w[v];
+    else w_src += w[v];  /* the sweeps start with every remaining component on the source side */
+    if (cl[c] == 1) {
+      wc[c] += w[v];
+      if (gid[v] < kid[c]) kid[c] = gid[v];
+    }
+  }
+  int32_t nrem = 0;
+  for (int32_t c = 0; c < nc; c++) nrem += cl[c] == 1;
+  info->reduced = nrem;
+  for (int32_t c = 0; c < nc; c++)
+    if (cl[c] == 1)
+      for (int64_t j = fo[c]; j < fo[c + 1]; j++) info->reduced_arcs += cl[fa[j]] == 1;
+  int32_t best_r = -1, best_j = 0;
+  int64_t best = 0;
+  if (nrem > OR_MB_MAX_COMP) info->limited = 1;
+  if (nrem > 0 && reps > 0 && !info->limited) {
+    /* sweeps: a random topological order of the remaining components moves
+     * them one by one to the sink side; the first most balanced cut wins */
+    for (int32_t r = 0; r < reps; r++) {
+      for (int32_t c = 0; c < nc; c++) {
+        indeg[c] = 0;
+        placed[c] = 0;
+      }
+      for (int32_t c = 0; c < nc; c++)
+        if (cl[c] == 1)
+          for (int64_t j = fo[c]; j < fo[c + 1]; j++)
+            if (cl[fa[j]] == 1) indeg[fa[j]]++;
+      int64_t ws = w_src, wt = w_snk;
+      for (int32_t j = 0; j <= nrem; j++) {
+        if (j > 0) {
+          int32_t pick = -1;
+          uint64_t kp = 0;
+          for (int32_t c = 0; c < nc; c++) {
+            if (cl[c] != 1 || placed[c] || indeg[c] != 0) continue;
+            uint64_t kc = mb_key(seed, r, kid[c]);
+            if (pick < 0 || kc < kp) { pick = c; kp = kc; }
+          }
+          if (pick < 0) { rc = -1; goto done; } /* a cycle: cannot happen after contraction */
+          placed[pick] = 1;
+          ws -= wc[pick];
+          wt += wc[pick];
+          for (int64_t e = fo[pick]; e < fo[pick + 1]; e++)
+            if (cl[fa[e]] == 1) indeg[fa[e]]--;
+        }
+        int64_t bal = ws > wt ? ws : wt;
+        if (best_r < 0 || bal < best) { best = bal; best_r = r; best_j = j; }
+      }
+    }
+    /* the chosen cut: the first best_j components of sweep best_r's order */
+    for (int32_t c = 0; c < nc; c++) { indeg[c] = 0; placed[c] = 0; }
+    for (int32_t c = 0; c < nc; c++)
+      if (cl[c] == 1)
+        for (int64_t j = fo[c]; j < fo[c + 1]; j++)
+          if (cl[fa[j]] == 1) indeg[fa[j]]++;
+    for (int32_t j = 0; j < best_j; j++) {
+      int32_t pick = -1;
+      uint64_t kp = 0;
+      for (int32_t c = 0; c < nc; c++) {
+        if (cl[c] != 1 || placed[c] || indeg[c] != 0) continue;
+        uint64_t kc = mb_key(seed, best_r, kid[c]);
+        if (pick < 0 || kc < kp) { pick = c; kp = kc; }
+      }
+      placed[pick] = 1;
+      for (int64_t e = fo[pick]; e < fo[pick + 1]; e++)
+        if (cl[fa[e]] == 1) indeg[fa[e]]--;
+    }
+    info->best_rep = best_r;
+    info->best_pos = best_j;
+    info->best_bal = best;
+    for (int32_t v = 0; v < nn; v++) {
+      int32_t c = comp[v];
+      src[v] = (uint8_t)(cl[c] == 0 || (cl[c] == 1 && !placed[c]));
+    }
+  } else {
+    for (int32_t v = 0; v < nn; v++) src[v] = (uint8_t)(cl[comp[v]] == 0);
+  }
+  if (cls_out) for (int32_t v = 0; v < nn; v++) cls_out[v] = cl[comp[v]];
+  if (comp_out) memcpy(comp_out, comp, sizeof(int32_t) * (size_t)nn);
+done:
+  free(comp); free(fo); free(bo); free(fa); free(ba); free(cl); free(q); free(wc); free(kid);
+  free(indeg); free(placed);
+  return rc;
+}
+
+/* Strongly connected components of a plain directed graph (tails -> heads).
+ * comp: [nn].  Returns the number of components, or -1 on bad input. */
+int32_t or_scc(int32_t nn, int64_t narcs, const int32_t *tails, const int32_t *heads,
+               int32_t *comp) {
+  if (nn <= 0) return -1;
+  or_net N;
+  if (net_init(&N, nn, 2 * narcs) != 0) { net_free(&N); return -1; }
+  for (int64_t i = 0; i < narcs; i++) {
+    if (tails[i] < 0 || tails[i] >= nn || heads[i] < 0 || heads[i] >= nn) { net_free(&N); return -1; }
+    net_add(&N, tails[i], heads[i], 1, 0);
+  }
+  if (net_finish(&N) != 0) { net_free(&N); return -1; }
+  int32_t nc = net_scc(&N, comp);
+  net_free(&N);
+  return nc;
+}
+
+/* Max flow, then the most balanced minimum cut, on an explicit network (arcs
+ * with zero-capacity reverses).  w, gid: [nn] node weights and key ids.
+ * Outputs (each [nn]): src (chosen source side), smin (smallest source set),
+ * cls, comp; info[7] = ncomp, reduced, reduced_arcs, limited, best_rep,
+ * best_pos, best_bal.  Returns 0, or -1 on bad input. */
+int32_t or_mbcut(int32_t nn, int64_t narcs, const int32_t *tails, const int32_t *heads,
+                 const int64_t *caps, int32_t s, int32_t t, const int64_t *w, const int32_t *gid,
+                 int64_t base_s, int64_t base_t, int32_t reps, uint32_t seed, int64_t *flow_out,
+                 uint8_t *src, uint8_t *smin, int8_t *cls, int32_t *comp, int64_t *info) {
+  if (nn <= 0 || s < 0 || s >= nn || t < 0 || t >= nn || s == t || reps < 0) return -1;
+  or_net N;
+  if (net_init(&N, nn, 2 * narcs) != 0) { net_free(&N); return -1; }
+  for (int64_t i = 0; i < narcs; i++) {
+    if (tails[i] < 0 || tails[i] >= nn || heads[i] < 0 || heads[i] >= nn || caps[i] < 0) {
+      net_free(&N);
+      return -1;
+    }
+    net_add(&N, tails[i], heads[i], caps[i], 0);
+  }
+  if (net_finish(&N) != 0) { net_free(&N); return -1; }
+  *flow_out = net_dinic(&N, s, t);
+  int32_t *qq = (int32_t *)malloc(sizeof(int32_t) * (size_t)nn);
+  if (!qq) { net_free(&N); return -1; }
+  net_reach(&N, s, smin, qq);
+  free(qq);
+  or_mbinfo mi;
+  int32_t rc = net_mb_cut(&N, s, t, w, gid, base_s, base_t, reps, (uint64_t)seed, src, cls,
+                          comp, &mi);
+  info[0] = mi.ncomp; info[1] = mi.reduced; info[2] = mi.reduced_arcs; info[3] = mi.limited;
+  info[4] = mi.best_rep; info[5] = mi.best_pos; info[6] = mi.best_bal;
+  net_free(&N);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* pair refinement                                                           */
 
 static int cmp_i32(const void *x, const void *y) {
@@ -436,8 +765,30 @@ static int32_t solve_once(const or_graph *g, int32_t *part, int32_t k, int32_t a
   int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * ((size_t)nb + 2));
   if (!reach || !queue) { free(reach); free(queue); net_free(&N); goto oom; }
   net_reach(&N, S, reach, queue);
+  if (p->mb_reps > 0) {
+    /* Sec. 4.1.1: the most balanced minimum cut replaces the smallest source
+     * set; the blocks keep their vertices outside the corridor */
+    int64_t *w = (int64_t *)calloc((size_t)nb + 2, sizeof(int64_t));
+    int32_t *gid = (int32_t *)malloc(sizeof(int32_t) * ((size_t)nb + 2));
+    if (!w || !gid) { free(w); free(gid); free(reach); free(queue); net_free(&N); goto oom; }
+    int64_t base_s = cA, base_t = cB;
+    for (int32_t u = 0; u < n; u++) {
+      if (!inB[u]) continue;
+      w[loc[u]] = g->vwgt[u];
+      gid[loc[u]] = u;
+      if (inB[u] == 1) base_s -= g->vwgt[u];
+      else base_t -= g->vwgt[u];
+    }
+    gid[S] = gid[T] = INT32_MAX;
+    or_mbinfo mi;
+    int32_t mrc = net_mb_cut(&N, S, T, w, gid, base_s, base_t, p->mb_reps,
+                             (uint64_t)(uint32_t)p->mb_seed, reach, NULL, NULL, &mi);
+    free(w);
+    free(gid);
+    if (mrc != 0) { free(reach); free(queue); net_free(&N); goto oom; }
+  }
 
-  /* candidate: corridor vertex -> a iff in the smallest source set */
+  /* candidate: corridor vertex -> a iff on the source side of the cut */
   int64_t wa = cA, wb = cB, src = 0;
   for (int32_t u = 0; u < n; u++) {
     if (!inB[u]) continue;
@@ -478,7 +829,7 @@ int32_t or_refine_pair(const or_graph *g, int32_t *part, int32_t k, int32_t a, i
   memset(res, 0, sizeof(*res));
   if (a < 0 || b < 0 || a >= k || b >= k || a == b) return -3;
   if (p->alpha < 1 || p->alpha_max < 1 || p->max_iters < 1 || p->eps_ppm < 0 ||
-      (p->area_mode != 0 && p->area_mode != 1) || p->depth < 0)
+      (p->area_mode != 0 && p->area_mode != 1) || p->depth < 0 || p->mb_reps < 0)
     return -8;
   int64_t w_a = 0, w_b = 0;
   for (int32_t u = 0; u < g->n; u++) {
