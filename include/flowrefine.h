@@ -14,7 +14,8 @@
  *   4. a maximum s-t flow (push-relabel with global relabelling);
  *   5. the minimum cut with the smallest source set, i.e. the vertices
  *      reachable from s in the residual graph (Sec. 4.1.1, Ford-Fulkerson
- *      labelling);
+ *      labelling), or on request the most balanced minimum cut found by the
+ *      heuristic of Sec. 4.1.1 (see fr_params.mb_reps);
  *   6. the balance check c(V_i) <= L_max = (1+eps) c(V)/k + max_v c(v)
  *      (Sec. 2.1) and the adaptive flow iterations on alpha (Sec. 4.1).
  * All arithmetic is integer.  Every output (flow value, smallest source set,
@@ -31,7 +32,13 @@
  *     min(2 alpha, alpha_max) and repeat; infeasible => alpha = max(alpha/2,1),
  *     stop if it already was 1; feasible but not smaller => stop; at most
  *     max_iters flow solves;
- *   - the first block of a pair is the source side.
+ *   - the first block of a pair is the source side;
+ *   - most balanced minimum cut: a cut's balance is the heavier of the two
+ *     new block weights; a random topological order of the remaining residual
+ *     components takes, among those whose predecessors are all placed, the
+ *     one with the smallest key (SplitMix64, see mb_seed); the first most
+ *     balanced cut wins (earlier sweep, then earlier position); more than
+ *     FR_MB_MAX_COMP remaining components keep the smallest source set.
  *
  * Conventions: every entry point returns FR_OK (0) or a negative FR_E_* code,
  * and never throws.  On error the partition is left unchanged.  All buffers
@@ -102,7 +109,25 @@ typedef struct {
   int32_t max_iters; /* flow solves per pair, in [1, 64] */
   int32_t eps_ppm;   /* imbalance eps in parts per million (3 % = 30000), >= 0 */
   int32_t use_mlp;   /* start each pair at the learned factor (needs loaded weights) */
+  /* Most balanced minimum cut (Sec. 4.1.1; "balanced adaptive flow
+   * iterations" when adaptive = 1).  0: the candidate is the smallest source
+   * set.  r > 0: after each max flow, the strongly connected components of
+   * the residual graph that lie neither with s (its component and successors)
+   * nor with t (its component and predecessors) are swept r times: sweep j
+   * moves them to the sink side one by one in a random topological order,
+   * starting from the largest minimum source side; the candidate is the
+   * minimum cut with the smallest max(c'(a), c'(b)) seen.  Flow value and
+   * candidate cut are those of any minimum cut; only the balance changes.
+   * At most FR_MB_MAX_REPS. */
+  int32_t mb_reps;
+  /* Keys of the sweeps: component x (identified by its smallest vertex id
+   * g) in sweep j gets output number j * 2^32 + g + 1 of SplitMix64 started
+   * at mb_seed (the 32 bits, zero-extended to 64). */
+  int32_t mb_seed;
 } fr_params;
+
+#define FR_MB_MAX_REPS 256
+#define FR_MB_MAX_COMP 2048
 
 /* Outcome of one pair. */
 typedef struct {
@@ -125,7 +150,7 @@ typedef struct {
   int64_t flow;            /* max-flow value */
   int64_t region_vertices; /* |B| */
   int64_t region_edges;    /* edges of G[B] */
-  int64_t source_side;     /* corridor vertices in the smallest source set */
+  int64_t source_side;     /* corridor vertices on the source side of the candidate cut */
   int64_t cut_before;      /* pair cut before the solve */
   int64_t cut_candidate;   /* pair cut of the candidate partition */
   int64_t wa, wb;          /* block weights of the candidate */
@@ -138,6 +163,8 @@ typedef struct {
   int32_t tpv;             /* lanes per vertex in push/relabel sweeps: 1, 2, 4, 8 or 16
                               (1 runs as 2, 16 as 8) */
   int32_t relabel_period;  /* push/relabel sweeps between global relabels, 1..10^6 */
+  int32_t mb_lds;          /* most balanced cut: 1 = component graph in LDS when it fits,
+                              0 = always in device memory */
 } fr_tuning;
 
 typedef struct fr_context fr_context;

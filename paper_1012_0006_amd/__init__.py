@@ -36,7 +36,7 @@ class FrGraph(ctypes.Structure):
 
 class FrParams(ctypes.Structure):
     _fields_ = [(f, i32) for f in ("area_mode", "depth", "alpha", "alpha_max", "adaptive",
-                                   "max_iters", "eps_ppm", "use_mlp")]
+                                   "max_iters", "eps_ppm", "use_mlp", "mb_reps", "mb_seed")]
 
 
 class FrResult(ctypes.Structure):
@@ -53,7 +53,8 @@ class FrSolve(ctypes.Structure):
 
 
 class FrTuning(ctypes.Structure):
-    _fields_ = [(f, i32) for f in ("block_threads", "blocks_per_cu", "tpv", "relabel_period")]
+    _fields_ = [(f, i32) for f in ("block_threads", "blocks_per_cu", "tpv", "relabel_period",
+                                   "mb_lds")]
 
 
 EXPORTS = ("fr_create", "fr_destroy", "fr_strerror", "flow_refine_pair", "flow_refine_batch",
@@ -137,9 +138,13 @@ def _struct_dict(s) -> dict:
 
 
 def params(**kw) -> FrParams:
+    """fr_params with the defaults below; mb_seed takes any int (its low 32
+    bits are used)."""
     d = dict(area_mode=0, depth=0, alpha=16, alpha_max=16, adaptive=1, max_iters=16,
-             eps_ppm=30000, use_mlp=0)
+             eps_ppm=30000, use_mlp=0, mb_reps=0, mb_seed=0)
     d.update(kw)
+    seed = int(d["mb_seed"]) & 0xFFFFFFFF
+    d["mb_seed"] = seed - (1 << 32) if seed >= 1 << 31 else seed
     return FrParams(**{k: int(d[k]) for k, _ in FrParams._fields_})
 
 
@@ -204,8 +209,9 @@ class Context:
             pass
 
     # -- tuning ---------------------------------------------------------
-    def set_tuning(self, block_threads=1024, blocks_per_cu=2, tpv=4, relabel_period=200):
-        t = FrTuning(block_threads, blocks_per_cu, tpv, relabel_period)
+    def set_tuning(self, block_threads=1024, blocks_per_cu=2, tpv=4, relabel_period=200,
+                   mb_lds=1):
+        t = FrTuning(block_threads, blocks_per_cu, tpv, relabel_period, mb_lds)
         _check(self.lib.fr_set_tuning(self.handle, ctypes.byref(t)), "fr_set_tuning")
 
     def get_tuning(self) -> dict:
@@ -236,7 +242,8 @@ def stats_dict(ctx) -> dict:
     d = dict(setup_ms=ms[0], round_ms=ms[1], corridor_ms=ms[2], build_ms=ms[3],
              call_ms=ms[4], relabel_ms=ms[5], push_ms=ms[6], flow_kernel_ms=ms[7],
              sweeps=cnt[0], relabels=cnt[1], bfs_levels=cnt[2], gr_levels=cnt[3],
-             cl_levels=cnt[4], workgroups=cnt[5], diag=cnt[6], slots=cnt[7])
+             cl_levels=cnt[4], workgroups=cnt[5], diag=cnt[6], slots=cnt[7],
+             mb_kernel_ms=cnt[8] / 1e6, mb_free=cnt[9], mb_comp=cnt[10], mb_limited=cnt[11])
     d.update({k: cnt[16 + i] for i, k in enumerate(WORK_KEYS)})
     return d
 
@@ -405,7 +412,7 @@ def fr_autotune(ctx: Context, graph: DeviceGraph, part, k: int, pairs, prm: FrPa
     kept in the context.  Returns (best index, per-candidate ms)."""
     gs = graph.struct()
     pr = _i32(pairs).reshape(-1)
-    cand = (FrTuning * len(candidates))(*[FrTuning(**c) for c in candidates])
+    cand = (FrTuning * len(candidates))(*[FrTuning(**{"mb_lds": 1, **c}) for c in candidates])
     ms = (ctypes.c_double * len(candidates))()
     best = i32(-1)
     _check(ctx.lib.fr_autotune(ctx.handle, ctypes.byref(gs), _part_arg(part, True), k,

@@ -12,6 +12,7 @@
 
 #include "fr_internal.h"
 #include "fr_kernels.h"
+#include "fr_mb.h"
 #include "fr_mlp.h"
 
 #define HIPCHK(x)                        \
@@ -38,6 +39,8 @@ struct DevBufs {
           *SNK = nullptr, *partw = nullptr, *parts = nullptr, *gx = nullptr, *gv = nullptr;
   uint8_t *lflag = nullptr;
   int8_t *side = nullptr;
+  int32_t *mbq = nullptr;  // most balanced cut: quotient arcs, one per arc slot (lazy)
+  int64_t mbqcap = 0;
   // per arc
   int32_t *ga = nullptr, *gw = nullptr;
   Arc *arc = nullptr;  // corridor arcs
@@ -65,7 +68,7 @@ struct fr_context {
   hipStream_t user_stream = nullptr;
   hipStream_t cs = nullptr;  // the library's own stream (graph capture needs a non-null one)
   int num_cus = 0;
-  fr_tuning tune{1024, 2, 4, 200};
+  fr_tuning tune{1024, 2, 4, 200, 1};
   int validate = 1;
   int mlp_loaded = 0;
   DevBufs d;
@@ -73,7 +76,7 @@ struct fr_context {
   int32_t stamp = 2;
   double wall_khz = 100000.0;  // device constant-rate clock
   int64_t graph_launches = 0;
-  hipEvent_t itev[4 * FR_MAX_ITERS] = {};
+  hipEvent_t itev[5 * FR_MAX_ITERS] = {};
   int32_t timed_iters = 0;
   int speculate = 1;
   // stats of the last call
@@ -110,6 +113,9 @@ static void free_vertex_arc(DevBufs &d) {
   }
   dfree(d.arc);
   d.arc = nullptr;
+  dfree(d.mbq);
+  d.mbq = nullptr;
+  d.mbqcap = 0;
   dfree(d.lflag);
   d.lflag = nullptr;
   dfree(d.side);
@@ -237,7 +243,7 @@ extern "C" int32_t fr_create(int32_t device, void *hip_stream, fr_context **out)
 #undef A_
   if (e == hipSuccess) e = hipHostMalloc((void **)&c->h_ctl, sizeof(Ctl), hipHostMallocDefault);
   for (int i = 0; i < 4 && e == hipSuccess; i++) e = hipEventCreate(&c->ev[i]);
-  for (int i = 0; i < 4 * FR_MAX_ITERS && e == hipSuccess; i++) e = hipEventCreate(&c->itev[i]);
+  for (int i = 0; i < 5 * FR_MAX_ITERS && e == hipSuccess; i++) e = hipEventCreate(&c->itev[i]);
   if (e != hipSuccess) {
     fr_destroy(c);
     return FR_E_OOM;
@@ -265,7 +271,7 @@ extern "C" int32_t fr_destroy(fr_context *c) {
   if (c->h_ctl) (void)hipHostFree(c->h_ctl);
   for (int i = 0; i < 4; i++)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
-  for (int i = 0; i < 4 * FR_MAX_ITERS; i++)
+  for (int i = 0; i < 5 * FR_MAX_ITERS; i++)
     if (c->itev[i]) (void)hipEventDestroy(c->itev[i]);
   if (c->cs) (void)hipStreamDestroy(c->cs);
   delete c;
@@ -280,6 +286,7 @@ extern "C" int32_t fr_set_tuning(fr_context *c, const fr_tuning *t) {
   if (!(t->tpv == 1 || t->tpv == 2 || t->tpv == 4 || t->tpv == 8 || t->tpv == 16))
     return FR_E_INVALID_ARG;
   if (t->relabel_period < 1 || t->relabel_period > 1000000) return FR_E_INVALID_ARG;
+  if (t->mb_lds != 0 && t->mb_lds != 1) return FR_E_INVALID_ARG;
   c->tune = *t;
   return FR_OK;
 }
@@ -319,7 +326,8 @@ static int32_t check_params(const fr_params *p) {
   if (!p) return FR_E_INVALID_ARG;
   if (p->area_mode != FR_AREA_FACTOR && p->area_mode != FR_AREA_DEPTH) return FR_E_INVALID_ARG;
   if (p->depth < 0 || p->alpha < 1 || p->alpha_max < 1 || p->alpha_max > FR_MAX_ALPHA ||
-      p->max_iters < 1 || p->max_iters > FR_MAX_ITERS || p->eps_ppm < 0 || p->eps_ppm > 100000000)
+      p->max_iters < 1 || p->max_iters > FR_MAX_ITERS || p->eps_ppm < 0 || p->eps_ppm > 100000000 ||
+      p->mb_reps < 0 || p->mb_reps > FR_MB_MAX_REPS)
     return FR_E_INVALID_ARG;
   return FR_OK;
 }
@@ -389,7 +397,11 @@ static KArgs call_args(fr_context *c, const fr_graph *g, int32_t *dpart, int32_t
     A.adaptive = p->adaptive;
     A.max_iters = p->max_iters;
     A.eps_ppm = p->eps_ppm;
+    A.mb_reps = p->mb_reps;
+    A.mb_seed = p->mb_seed;
   }
+  A.mb_lds = c->tune.mb_lds;
+  A.mbq = d.mbq;
   A.mark = d.mark;
   A.vmap = d.vmap;
   A.voff = d.voff;
@@ -492,7 +504,7 @@ static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t s
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(A.P, slots));
   const iter_fn corr = corr_kernel(tpb), flow = flow_kernel(tpb);
   for (int32_t it = 0; it < A.max_iters; it++) {
-    hipEvent_t *ev = c->itev + 4 * it;
+    hipEvent_t *ev = c->itev + 5 * it;
     if (timed) HIPCHK(hipEventRecord(ev[0], st));
     hipLaunchKernelGGL(k_iter_begin, dim3(1), dim3(1024), 0, st, A, it);
     hipLaunchKernelGGL(k_bnd, dim3(sblocks), dim3(256), 0, st, A, it);
@@ -506,6 +518,8 @@ static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t s
     if (timed) HIPCHK(hipEventRecord(ev[2], st));
     hipLaunchKernelGGL(flow, dim3(blocks), dim3(tpb), 0, st, A, it);
     if (timed) HIPCHK(hipEventRecord(ev[3], st));
+    if (A.mb_reps > 0) hipLaunchKernelGGL(k_mb, dim3(A.P), dim3(MB_TPB), 0, st, A, it);
+    if (timed) HIPCHK(hipEventRecord(ev[4], st));
     hipLaunchKernelGGL(k_select, dim3(A.P / A.W), dim3(1024), 0, st, A, it);
   }
   HIPCHK(hipGetLastError());
@@ -514,13 +528,14 @@ static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t s
   return FR_OK;
 }
 
-// per-phase event times of the last timed round: corridor, build, flow kernel
-static void iteration_times(fr_context *c, double out[3]) {
-  out[0] = out[1] = out[2] = 0.0;
+// per-phase event times of the last timed round: corridor, build, flow
+// kernel, most balanced cut kernel
+static void iteration_times(fr_context *c, double out[4]) {
+  out[0] = out[1] = out[2] = out[3] = 0.0;
   for (int it = 0; it < c->timed_iters; it++) {
     float t = 0.f;
-    hipEvent_t *ev = c->itev + 4 * it;
-    for (int j = 0; j < 3; j++)
+    hipEvent_t *ev = c->itev + 5 * it;
+    for (int j = 0; j < 4; j++)
       if (hipEventElapsedTime(&t, ev[j], ev[j + 1]) == hipSuccess) out[j] += t;
   }
 }
@@ -546,7 +561,7 @@ static void fill_result(const PairState &s, fr_result &r) {
 }
 
 static void collect_stats(fr_context *c, const std::vector<PairState> &ps) {
-  int64_t sw = 0, rl = 0, bl = 0, gl = 0, cl = 0, wk[W_COUNT] = {0};
+  int64_t sw = 0, rl = 0, bl = 0, gl = 0, cl = 0, wk[W_COUNT] = {0}, mb[3] = {0, 0, 0};
   double ph[5] = {0, 0, 0, 0, 0};
   for (const PairState &s : ps) {
     sw += s.sweeps;
@@ -555,6 +570,9 @@ static void collect_stats(fr_context *c, const std::vector<PairState> &ps) {
     gl += s.gr_levels;
     cl += s.cl_levels;
     for (int j = 0; j < W_COUNT; j++) wk[j] += s.work[j];
+    mb[0] += s.mb_free;
+    mb[1] += s.mb_comp;
+    mb[2] += s.mb_limited;
     ph[0] += s.t_corridor;
     ph[1] += s.t_build;
     ph[2] += s.t_relabel;
@@ -568,8 +586,12 @@ static void collect_stats(fr_context *c, const std::vector<PairState> &ps) {
   c->counters[4] = cl;
   c->counters[6] = 0;
   for (int j = 0; j < W_COUNT; j++) c->counters[16 + j] = wk[j];
-  double ev[3];
+  double ev[4];
   iteration_times(c, ev);
+  c->counters[8] = (int64_t)(ev[3] * 1e6);
+  c->counters[9] = mb[0];
+  c->counters[10] = mb[1];
+  c->counters[11] = mb[2];
   c->ms[2] = ev[0];
   c->ms[3] = ev[1];
   c->ms[5] = ph[2] / c->wall_khz;
@@ -622,6 +644,19 @@ static int32_t stage(fr_context *c, const fr_graph *g, int32_t *part, int32_t k,
     s->g.on_device = 1;
     s->dpart = d.parts;
   }
+  return FR_OK;
+}
+
+// Quotient-arc slots of the most balanced cut: one per arena arc slot,
+// allocated on first use.
+static int32_t ensure_mb(fr_context *c, const fr_params *p) {
+  DevBufs &d = c->d;
+  if (p->mb_reps <= 0 || d.mbqcap >= d.sacap) return FR_OK;
+  dfree(d.mbq);
+  d.mbq = nullptr;
+  d.mbqcap = 0;
+  if (dalloc(&d.mbq, d.sacap) != hipSuccess) return FR_E_OOM;
+  d.mbqcap = d.sacap;
   return FR_OK;
 }
 
@@ -683,6 +718,7 @@ static int32_t refine(fr_context *c, const fr_graph *g, int32_t *part, int32_t k
   if ((rc = ensure_pairs(c, (int64_t)npairs * W))) return rc;
   Staged s;
   if ((rc = stage(c, g, part, k, &s, W))) return rc;
+  if ((rc = ensure_mb(c, p))) return rc;
   DevBufs &d = c->d;
   hipStream_t st = c->cs;
   const int64_t n = g->n;
@@ -836,6 +872,7 @@ extern "C" int32_t flow_refine_sweep(fr_context *c, const fr_graph *g, int32_t *
   const int32_t Wmax = speculation_slots(c, p, 1, g->n, narcs0);
   Staged s;
   if ((rc = stage(c, g, part, k, &s, Wmax))) return rc;
+  if ((rc = ensure_mb(c, p))) return rc;
   DevBufs &d = c->d;
   hipStream_t st = c->cs;
   // the caller's partition changes only on success: work on a copy

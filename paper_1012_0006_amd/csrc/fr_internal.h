@@ -36,6 +36,10 @@ struct PairState {
   int64_t sweeps, relabels, bfs_levels, gr_levels, cl_levels;
   int64_t t_corridor, t_build, t_relabel, t_push, t_closure, t_finish;  // wall-clock ticks
   int64_t work[12];     // vertices / arcs touched per phase (W_*), summed over solves
+  // most balanced cut, summed over solves: free vertices, residual components
+  // among them, solves that kept the smallest source set for having more than
+  // FR_MB_MAX_COMP components, wall-clock ticks
+  int64_t mb_free, mb_comp, mb_limited, t_mb;
 };
 
 // work counters: the data each phase of a solve touches
@@ -80,7 +84,7 @@ struct Ctl {
 };
 
 enum { DIAG_NONE = 0, DIAG_LIST = 1, DIAG_CLOSURE = 2, DIAG_REV = 3, DIAG_SWEEPS = 4,
-       DIAG_OVERFLOW = 5 };
+       DIAG_OVERFLOW = 5, DIAG_MB = 6 };
 
 struct KArgs {
   // graph (device)
@@ -117,6 +121,10 @@ struct KArgs {
   // parameters
   int32_t area_mode, depth, alpha_max, adaptive, max_iters, eps_ppm;
   int32_t stamp0;           // corridor mark of the first solve (even)
+  // most balanced minimum cut: sweeps (0 = smallest source set), key seed,
+  // component graph in LDS when it fits, quotient arcs (one slot per arc slot)
+  int32_t mb_reps, mb_seed, mb_lds;
+  int32_t *mbq;
   // per vertex [n]
   int32_t *mark, *vmap;
   // per-pair arenas: vertex slots [voff[p], voff[p+1]), arc slots [aoff[p], aoff[p+1])

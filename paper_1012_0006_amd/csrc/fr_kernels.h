@@ -352,6 +352,7 @@ struct SolveShared {
   fr_solve rec;                   // record of the current solve
   unsigned long long work[W_COUNT];
   int32_t cnt[3];                 // rotating list counters
+  int32_t nfree;                  // free vertices listed for the most balanced cut
   int32_t nr;                     // corridor size
   int32_t nsnk;                   // sink-border vertices
   int32_t pair;                   // queue slot
@@ -1547,10 +1548,19 @@ __global__ void __launch_bounds__(TPB) k_flow(KArgs A, int32_t it) {
     t1 = wall_clock64();
     const int64_t t_cl = t1 - t0;
     t0 = t1;
-    // ---- candidate partition and its balance check (Sec. 2.1)
+    // ---- candidate partition and its balance check (Sec. 2.1); for the most
+    //      balanced cut, also the free vertices (neither in the smallest
+    //      source set nor able to reach the sink: exact label NL), listed in
+    //      LB with LA[i] = i for them and -1 for every other corridor vertex
     int64_t acc[4] = {0, 0, 0, 0};  // flow, moved a->b, moved b->a, source side
+    const bool mb = A.mb_reps > 0 && !overflow;
+    if (mb) {
+      if (threadIdx.x == 0) sh.nfree = 0;
+      __syncthreads();
+    }
     if (!overflow) {
       BLOCK_WAVE_LOOP(i, nr) {
+        bool fv = false;
         if (i < nr) {
           const uint32_t f = V.fl[i];
           const int32_t w = A.vwgt[V.lg[i]];
@@ -1563,6 +1573,14 @@ __global__ void __launch_bounds__(TPB) k_flow(KArgs A, int32_t it) {
           if (!(f & LF_SIDE_B) && !in) acc[1] += w;
           if ((f & LF_SIDE_B) && in) acc[2] += w;
           acc[3] += in ? 1 : 0;
+          if (mb) {
+            fv = !in && !(f & LF_BORDER) && V.lab[i] == NL;
+            V.LA[i] = fv ? (int32_t)i : -1;
+          }
+        }
+        if (mb) {
+          const int pos = wave_append(&sh.nfree, fv);
+          if (fv) V.LB[pos] = (int32_t)i;
         }
       }
     }
@@ -1607,7 +1625,7 @@ __global__ void __launch_bounds__(TPB) k_flow(KArgs A, int32_t it) {
       A.srec[p] = rec;
       st.t_finish += wall_clock64() - t0;
       for (int j = 0; j < PA_N; j++) pa[j] = 0;
-      A.pcnt[p] = 0;
+      A.pcnt[p] = mb ? sh.nfree : 0;  // the most balanced cut kernel reads and clears it
       A.pcnt[A.P + p] = 0;
       A.ps[p] = st;
     }
