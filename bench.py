@@ -295,6 +295,70 @@ def run_sweep(args, fr, torch, gen):
     }
 
 
+def run_balanced(args, fr, torch, gen):
+    """Most balanced minimum cuts (Sec. 4.1.1, balanced adaptive flow
+    iterations) on C5 (2D RGG n=2^24, mean degree 6, unit weights, k=256 RCB +
+    1 % noise): the largest matching round batched with the smallest source
+    set and with 16 sweeps, then whole refinement sweeps until no pair
+    improves, both ways, for the cut they reach."""
+    import oracle  # cut accounting only
+
+    w = gen.config("C5")
+    ctx = fr.Context()
+    ctx.set_validation(False)
+    dg = fr.DeviceGraph.from_host(w.graph)
+    part0 = torch.as_tensor(w.part).cuda()
+    edges_q, colour = fr.fr_quotient_matchings(ctx, dg, part0, w.k)
+    c = int(np.argmax(np.bincount(colour)))
+    pairs = [tuple(e) for e, cc in zip(edges_q.tolist(), colour.tolist()) if cc == c]
+    base = {k: w.params[k] for k in ("area_mode", "depth", "alpha", "alpha_max", "adaptive",
+                                     "max_iters", "eps_ppm")}
+    out = {"workload": f"C5: 2D RGG n=2^24 mean degree 6 unit weights, k=256 RCB + 1% noise, "
+                       f"largest matching round ({len(pairs)} pairs) batched, then sweeps "
+                       f"until no pair improves; eps 3%, alpha 16 adaptive",
+           "pairs": len(pairs)}
+    for name, extra in (("smallest_source_set", {}), ("most_balanced", {"mb_reps": 16,
+                                                                        "mb_seed": 1})):
+        prm = fr.params(**base, **extra)
+        dpart = part0.clone()
+        fr.flow_refine_batch(ctx, dg, dpart, w.k, pairs, prm)  # warm-up
+        reps = max(1, args.batch_reps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            dpart.copy_(part0)
+            res, _ = fr.flow_refine_batch(ctx, dg, dpart, w.k, pairs, prm)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        st = fr.stats_dict(ctx)
+        edges = sum(r["region_edges"] for r in res)
+        rnd = {"round_ms": dt * 1e3, "region_edges_per_s": edges / dt,
+               "flow_solves": sum(r["iters"] for r in res),
+               "applied_pairs": sum(1 for r in res if r["applied"]),
+               "pair_cut_after": sum(r["cut_after"] for r in res),
+               "pair_cut_before": sum(r["cut_before"] for r in res),
+               "flow_kernel_ms": st["flow_kernel_ms"], "mb_kernel_ms": st["mb_kernel_ms"],
+               "mb_free_vertices": st["mb_free"], "mb_components": st["mb_comp"],
+               "mb_limited_solves": st["mb_limited"]}
+        dpart = part0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cut, stats = fr.flow_refine_sweep(ctx, dg, dpart, w.k, prm, args.max_sweeps)
+        torch.cuda.synchronize()
+        ds = time.perf_counter() - t0
+        newp = dpart.cpu().numpy()
+        bw = np.bincount(newp, weights=w.graph.vwgt, minlength=w.k)
+        rnd["sweep"] = {"seconds": ds, "sweeps": int(stats[0]), "flow_solves": int(stats[1]),
+                        "region_edges_per_s": float(stats[3]) / ds, "cut_after": int(cut),
+                        "max_block_weight": int(bw.max())}
+        out[name] = rnd
+    ctx.close()
+    out["cut_before"] = int(oracle.total_cut(w.graph, w.part))
+    out["sweep_cut_ratio"] = (out["most_balanced"]["sweep"]["cut_after"] /
+                              out["smallest_source_set"]["sweep"]["cut_after"])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,6 +369,7 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-balanced", action="store_true")
     ap.add_argument("--max-sweeps", type=int, default=64)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one device copy of 512 MiB (calibrates HBM byte counters)")
@@ -397,6 +462,8 @@ def main():
         line["learned_factor"] = run_learned(args, fr, torch, gen)
     if not args.no_sweep:
         line["sweep"] = run_sweep(args, fr, torch, gen)
+    if not args.no_balanced:
+        line["balanced"] = run_balanced(args, fr, torch, gen)
     print(json.dumps(line), flush=True)
 
 

@@ -55,7 +55,7 @@ struct DevBufs {
   fr_solve *trace = nullptr, *srec = nullptr;
   int32_t *ucnt = nullptr, *qctr = nullptr, *pcnt = nullptr, *act = nullptr, *nact = nullptr;
   int64_t *voff = nullptr, *aoff = nullptr, *fstat = nullptr, *pacc = nullptr, *vpre = nullptr,
-          *cpre = nullptr;
+          *cpre = nullptr, *mpre = nullptr;
   float *feats = nullptr, *probs = nullptr;
   int64_t *base = nullptr, *scal = nullptr;
   Ctl *ctl = nullptr;
@@ -235,6 +235,7 @@ extern "C" int32_t fr_create(int32_t device, void *hip_stream, fr_context **out)
   A_(trace, (int64_t)FR_MAX_PAIRS * FR_MAX_ITERS); A_(ucnt, FR_MAX_PAIRS);
   A_(qctr, 2 * FR_MAX_ITERS); A_(pcnt, 2 * FR_MAX_PAIRS); A_(pacc, (int64_t)PA_N * FR_MAX_PAIRS);
   A_(act, FR_MAX_PAIRS); A_(nact, 1); A_(vpre, FR_MAX_PAIRS + 1); A_(cpre, FR_MAX_PAIRS + 1);
+  A_(mpre, FR_MAX_PAIRS + 1);
   A_(srec, FR_MAX_PAIRS);
   A_(voff, FR_MAX_PAIRS + 1); A_(aoff, FR_MAX_PAIRS + 1); A_(fstat, 4 * FR_MAX_PAIRS);
   A_(feats, MLP_IN * FR_MAX_PAIRS); A_(probs, MLP_OUT * FR_MAX_PAIRS);
@@ -265,7 +266,7 @@ extern "C" int32_t fr_destroy(fr_context *c) {
   void *ptrs[] = {d.blk2pair, d.bstat, d.qadj, d.ps,    d.pairs, d.alpha0, d.order,
                   d.trace,    d.ucnt,  d.voff, d.aoff,  d.fstat, d.feats,  d.probs,
                   d.base,     d.scal,  d.ctl,  d.mlp,   d.mlp_m, d.mlp_v,  d.mlp_g,
-                  d.qctr,     d.pcnt,  d.pacc, d.act,   d.nact,  d.vpre,   d.cpre,
+                  d.qctr,     d.pcnt,  d.pacc, d.act,   d.nact,  d.vpre,   d.cpre, d.mpre,
                   d.srec};
   for (void *q : ptrs) dfree(q);
   if (c->h_ctl) (void)hipHostFree(c->h_ctl);
@@ -389,6 +390,7 @@ static KArgs call_args(fr_context *c, const fr_graph *g, int32_t *dpart, int32_t
   A.nact = d.nact;
   A.vpre = d.vpre;
   A.cpre = d.cpre;
+  A.mpre = d.mpre;
   A.base = d.base;
   if (p) {
     A.area_mode = p->area_mode;
@@ -518,7 +520,11 @@ static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t s
     if (timed) HIPCHK(hipEventRecord(ev[2], st));
     hipLaunchKernelGGL(flow, dim3(blocks), dim3(tpb), 0, st, A, it);
     if (timed) HIPCHK(hipEventRecord(ev[3], st));
-    if (A.mb_reps > 0) hipLaunchKernelGGL(k_mb, dim3(A.P), dim3(MB_TPB), 0, st, A, it);
+    if (A.mb_reps > 0) {
+      hipLaunchKernelGGL(k_mb_scan, dim3(1), dim3(1024), 0, st, A, it);
+      hipLaunchKernelGGL(k_mb_union, dim3(sblocks), dim3(256), 0, st, A, it);
+      hipLaunchKernelGGL(k_mb, dim3(A.P), dim3(MB_TPB), 0, st, A, it);
+    }
     if (timed) HIPCHK(hipEventRecord(ev[4], st));
     hipLaunchKernelGGL(k_select, dim3(A.P / A.W), dim3(1024), 0, st, A, it);
   }

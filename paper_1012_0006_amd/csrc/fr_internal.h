@@ -125,6 +125,7 @@ struct KArgs {
   // component graph in LDS when it fits, quotient arcs (one slot per arc slot)
   int32_t mb_reps, mb_seed, mb_lds;
   int32_t *mbq;
+  int64_t *mpre;            // [P + 1] prefix sums of the entries' free-vertex counts
   // per vertex [n]
   int32_t *mark, *vmap;
   // per-pair arenas: vertex slots [voff[p], voff[p+1]), arc slots [aoff[p], aoff[p+1])

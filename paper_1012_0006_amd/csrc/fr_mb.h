@@ -8,12 +8,14 @@
 // kernel.  Their residual strongly connected components form a DAG whose
 // closed sets are exactly the remaining choices:
 //   1. union-find over residual arcs usable in both directions (such
-//      vertices share a component): the "bidirectional classes";
-//   2. the quotient graph Q of the classes over the one-way residual arcs,
-//      and Tarjan's SCC algorithm on Q in one lane (LDS when Q is small);
+//      vertices share a component): the "bidirectional classes", grid-wide
+//      over the free vertices of all entries (k_mb_scan, k_mb_union); the
+//      same pass lists the one-way residual arcs inside M (saturated edges);
+//   2. the quotient graph Q of the classes over those one-way arcs, and
+//      Tarjan's SCC algorithm on Q in one lane (LDS when Q is small);
 //   3. the component DAG (weights, key ids, in-degrees, arcs);
-//   4. sweeps, one lane each: Kahn's algorithm taking the ready component
-//      with the smallest SplitMix64 key moves components to the sink side
+//   4. sweeps, one per wave: Kahn's algorithm taking the ready component
+//      with the smallest SplitMix64 key (a wave-wide minimum) moves them to the sink side
 //      one by one, starting from the largest minimum source side; the first
 //      most balanced cut is kept;
 //   5. the chosen components join the source side; the solve's record gets
@@ -24,34 +26,41 @@
 #pragma once
 #include "fr_kernels.h"
 
-#define MB_TPB 256
+#define MB_TPB 1024
 #define MB_LQ 1024        // quotient nodes handled in LDS
-#define MB_LQA 1024       // quotient arcs handled in LDS
+#define MB_LQA 4096       // quotient arcs handled in LDS
 #define MB_LDAG 4096      // component arcs held in LDS
-#define MB_RS_BYTES 20480 // per-lane sweep state (in-degrees and heaps)
+#define MB_RS_BYTES 24576 // sweep state of the concurrent sweeps (in-degrees, states)
+#define MBK 8             // arc records in flight per lane
 
 struct MBShared {
-  int64_t cw[FR_MB_MAX_COMP];      // component weights
-  int32_t ckey[FR_MB_MAX_COMP];    // component key id: smallest global vertex id
-  int32_t cend[FR_MB_MAX_COMP];    // component arcs: counts, then end offsets
-  int32_t cin[FR_MB_MAX_COMP];     // in-degrees among the components
-  int32_t qidx[MB_LQ];             // Tarjan index / component of each quotient node
-  int16_t adj[MB_LDAG];            // component arcs (when they fit)
-  uint8_t sink[FR_MB_MAX_COMP];    // chosen cut: component on the sink side
   union {
-    struct {
-      int32_t qoff[MB_LQ];         // quotient arcs: counts, then start offsets
-      int32_t qarc[MB_LQA];
+    struct {                         // Tarjan's scratch (LDS path)
       int32_t low[MB_LQ], stk[MB_LQ], cnode[MB_LQ], cpos[MB_LQ];
     } t;
-    uint32_t rs[MB_RS_BYTES / 4];
-  } u;
+    struct {                         // the component DAG, built after Tarjan
+      int64_t cw[FR_MB_MAX_COMP];    // component weights
+      int32_t ckey[FR_MB_MAX_COMP];  // component key id: smallest global vertex id
+      int32_t cend[FR_MB_MAX_COMP];  // component arcs: counts, then end offsets
+      int32_t cin[FR_MB_MAX_COMP];   // in-degrees among the components
+      int16_t adj[MB_LDAG];          // component arcs (when they fit)
+      uint8_t sink[FR_MB_MAX_COMP];  // chosen cut: component on the sink side
+    } c;
+  } u1;
+  union {
+    struct {                         // the quotient graph (LDS path), until the DAG is built
+      int32_t qidx[MB_LQ];           // Tarjan index / component of each quotient node
+      int32_t qoff[MB_LQ];           // quotient arcs: counts, then start offsets
+      int32_t qarc[MB_LQA];
+    } q;
+    uint32_t rs[MB_RS_BYTES / 4];    // sweep state (in-degrees and states)
+  } u2;
   int64_t red[64];
-  int64_t lane_bal[WAVE];
-  int32_t lane_pos[WAVE];
+  int64_t lane_bal[MB_TPB / WAVE];
+  int32_t lane_pos[MB_TPB / WAVE];
   int64_t best_bal;
   int32_t best_rep, best_pos;
-  int32_t nq, eq, nc, ne, skip;
+  int32_t nq, eq, nc, ne, n1w, skip;
 };
 static_assert(sizeof(MBShared) <= 80 * 1024, "two workgroups per CU");
 
@@ -67,6 +76,21 @@ __device__ __forceinline__ uint64_t mb_splitmix(uint64_t seed, uint64_t n) {
 // key of the component with key id g in sweep r
 __device__ __forceinline__ uint64_t mb_key(uint64_t seed, int32_t r, int32_t g) {
   return mb_splitmix(seed, ((((uint64_t)(uint32_t)r) << 32) | (uint32_t)g) + 1ull);
+}
+
+// minimum of v over the lanes with the same key, one atomic per distinct key
+// of the wave (keys < 0 take no part).  Converged wave only.
+__device__ __forceinline__ void wave_min_by_key(int32_t *base, int key, int32_t v) {
+  unsigned long long todo = __ballot(key >= 0);
+  while (todo) {
+    const int leader = __ffsll(todo) - 1;
+    const int k0 = __shfl(key, leader);
+    const bool mine = key == k0;
+    int32_t x = mine ? v : 0x7fffffff;
+    for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o));
+    if (lane64() == leader) atomicMin(base + k0, x);
+    todo &= ~__ballot(mine);
+  }
 }
 
 __device__ __forceinline__ int32_t aload(const int32_t *p) {
@@ -113,91 +137,95 @@ __device__ int32_t mb_exscan(int32_t *a, int32_t N, int64_t *red) {
   return (int32_t)carry;
 }
 
-// Binary min-heap of component ids ordered by their sweep keys.
-struct MBHeap {
-  int16_t *h;
-  int32_t n;
-  const int32_t *ckey;
-  uint64_t seed;
-  int32_t rep;
-  __device__ __forceinline__ uint64_t key(int32_t c) const { return mb_key(seed, rep, ckey[c]); }
-  __device__ void push(int32_t c) {
-    int32_t i = n++;
-    const uint64_t kc = key(c);
-    while (i > 0) {
-      const int32_t pa = (i - 1) >> 1;
-      const int32_t cp = h[pa];
-      if (key(cp) <= kc) break;
-      h[i] = (int16_t)cp;
-      i = pa;
-    }
-    h[i] = (int16_t)c;
-  }
-  __device__ int32_t pop() {
-    const int32_t top = h[0];
-    const int32_t last = h[--n];
-    const uint64_t kl = key(last);
-    int32_t i = 0;
-    for (;;) {
-      int32_t ch = 2 * i + 1;
-      if (ch >= n) break;
-      uint64_t kc = key(h[ch]);
-      if (ch + 1 < n) {
-        const uint64_t k2 = key(h[ch + 1]);
-        if (k2 < kc) {
-          ch++;
-          kc = k2;
-        }
-      }
-      if (kl <= kc) break;
-      h[i] = h[ch];
-      i = ch;
-    }
-    if (n > 0) h[i] = (int16_t)last;
-    return top;
-  }
-};
-
-// One sweep in one lane: Kahn's algorithm over the C components with the
-// smallest key first; component j of the order moves to the sink side.
-// wa/wb: block weights with every free component on the source side.
-// Returns the first position with the smallest max(wa, wb) (0 = none moved)
-// and its balance; with mark set, stops there and flags the moved components.
+// One sweep, run by one wave: Kahn's algorithm over the C components that
+// takes, among the ready ones (all predecessors placed), the one with the
+// smallest key -- the lanes hold C/64 components each and a wave-wide minimum
+// picks it; the placed component moves to the sink side and its arcs release
+// their targets.  wa/wb: block weights with every free component on the
+// source side.  Returns, in every lane, the first position with the smallest
+// max(wa, wb) (0 = none moved) and its balance; with mark set, flags the
+// components moved up to position stop.
+template <typename ADJ>
 struct MBSweep {
   int32_t C;
-  const int32_t *cin, *cend, *gadj;
-  const int16_t *ladj;
+  const int32_t *cin, *cend;
+  const ADJ *adj;  // component arcs: int16 in LDS or int32 in device memory
   const int64_t *cw;
   const int32_t *ckey;
   uint64_t seed;
-  __device__ __forceinline__ int32_t arc(int32_t e) const { return ladj ? ladj[e] : gadj[e]; }
-  __device__ int32_t run(int32_t rep, int32_t *ind, int16_t *heap, int64_t wa, int64_t wb,
+  __device__ int32_t run(int32_t rep, int32_t *ind, uint8_t *state, int64_t wa, int64_t wb,
                          int32_t stop, uint8_t *mark, int64_t *best_out, Ctl *ctl) const {
-    MBHeap H{heap, 0, ckey, seed, rep};
-    for (int32_t c = 0; c < C; c++) {
-      ind[c] = cin[c];
-      if (ind[c] == 0) H.push(c);
+    const int lane = lane64();
+    for (int32_t c = lane; c < C; c += WAVE) {  // state: 0 waiting, 1 ready, 2 placed
+      const int32_t d = cin[c];
+      ind[c] = d;
+      state[c] = d == 0 ? 1 : 0;
     }
     int64_t best = wa > wb ? wa : wb;
     int32_t bj = 0;
     for (int32_t j = 1; j <= stop; j++) {
-      if (H.n == 0) {  // a cycle among the components: cannot happen
-        ctl->err = FR_E_DEVICE;
-        ctl->diag = DIAG_MB;
+      uint64_t bk = 0;
+      int32_t bc = -1;
+      for (int32_t c = lane; c < C; c += WAVE)
+        if (state[c] == 1) {
+          const uint64_t k = mb_key(seed, rep, ckey[c]);
+          if (bc < 0 || k < bk) {
+            bk = k;
+            bc = c;
+          }
+        }
+      // the wave's minimum (keys of distinct components differ): lane by lane
+      // in scalar registers when few lanes hold a candidate, else a butterfly
+      unsigned long long cand = __ballot(bc >= 0);
+      if (__popcll(cand) <= 8) {
+        uint64_t wk = 0;
+        int32_t wc = -1;
+        while (cand) {
+          const int l = __ffsll(cand) - 1;
+          cand &= cand - 1;
+          const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)bk, l);
+          const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(bk >> 32), l);
+          const uint64_t k = ((uint64_t)hi << 32) | lo;
+          if (wc < 0 || k < wk) {
+            wk = k;
+            wc = __builtin_amdgcn_readlane(bc, l);
+          }
+        }
+        bk = wk;
+        bc = wc;
+      } else {
+        for (int o = WAVE / 2; o > 0; o >>= 1) {
+          const uint32_t lo = __shfl_xor((uint32_t)bk, o), hi = __shfl_xor((uint32_t)(bk >> 32), o);
+          const uint64_t ok = ((uint64_t)hi << 32) | lo;
+          const int32_t oc = __shfl_xor(bc, o);
+          if (oc >= 0 && (bc < 0 || ok < bk)) {
+            bk = ok;
+            bc = oc;
+          }
+        }
+      }
+      if (bc < 0) {  // nothing ready: a cycle among the components, cannot happen
+        if (lane == 0) {
+          ctl->err = FR_E_DEVICE;
+          ctl->diag = DIAG_MB;
+        }
         break;
       }
-      const int32_t c = H.pop();
-      if (mark) mark[c] = 1;
-      wa -= cw[c];
-      wb += cw[c];
+      if (lane == 0) {
+        state[bc] = 2;
+        if (mark) mark[bc] = 1;
+      }
+      wa -= cw[bc];
+      wb += cw[bc];
       const int64_t bal = wa > wb ? wa : wb;
       if (bal < best) {
         best = bal;
         bj = j;
       }
-      for (int32_t e = c ? cend[c - 1] : 0; e < cend[c]; e++) {
-        const int32_t d = arc(e);
-        if (--ind[d] == 0) H.push(d);
+      const int32_t e1 = cend[bc];
+      for (int32_t e = (bc ? cend[bc - 1] : 0) + lane; e < e1; e += WAVE) {
+        const int32_t d = adj[e];
+        if (atomicSub(ind + d, 1) == 1) state[d] = 1;
       }
     }
     *best_out = best;
@@ -208,37 +236,41 @@ struct MBSweep {
 // Quotient-graph SCC (Tarjan 1972) in one lane: idx[q] = -1 unvisited,
 // >= 0 visit index while on the component stack, -2 - c once in component c.
 // Returns the number of components.
-__device__ int32_t mb_tarjan(int32_t nq, int32_t eq, const int32_t *qoff, const int32_t *qarc,
-                             int32_t *idx, int32_t *low, int32_t *stk, int32_t *cnode,
-                             int32_t *cpos) {
+__device__ __forceinline__ int32_t mb_tarjan(int32_t nq, int32_t eq, const int32_t *qoff,
+                                             const int32_t *qarc, int32_t *idx, int32_t *low,
+                                             int32_t *stk, int32_t *cnode, int32_t *cpos) {
   int32_t next = 0, ns = 0, nc = 0;
   for (int32_t root = 0; root < nq; root++) {
     if (idx[root] != -1) continue;
+    // the node being searched lives in registers (v, its next arc e, its arc
+    // end, its lowest reachable index lv); the call stack keeps the parents'
+    // (node, next arc) in cnode/cpos and their lowest index in low
     int32_t depth = 0;
-    cnode[0] = root;
-    cpos[0] = qoff[root];
-    idx[root] = low[root] = next++;
+    int32_t v = root, e = qoff[root], end = root + 1 < nq ? qoff[root + 1] : eq;
+    int32_t lv = next;
+    idx[root] = next++;
     stk[ns++] = root;
-    while (depth >= 0) {
-      const int32_t v = cnode[depth];
-      const int32_t e = cpos[depth];
-      const int32_t end = v + 1 < nq ? qoff[v + 1] : eq;
+    for (;;) {
       if (e < end) {
-        cpos[depth] = e + 1;
-        const int32_t w = qarc[e];
+        const int32_t w = qarc[e++];
         const int32_t iw = idx[w];
-        if (iw == -1) {
-          idx[w] = low[w] = next++;
-          stk[ns++] = w;
+        if (iw == -1) {  // tree arc: descend
+          cnode[depth] = v;
+          cpos[depth] = e;
+          low[v] = lv;
           depth++;
-          cnode[depth] = w;
-          cpos[depth] = qoff[w];
-        } else if (iw >= 0 && iw < low[v]) {
-          low[v] = iw;
+          v = w;
+          e = qoff[w];
+          end = w + 1 < nq ? qoff[w + 1] : eq;
+          lv = next;
+          idx[w] = next++;
+          stk[ns++] = w;
+        } else if (iw >= 0 && iw < lv) {  // on the component stack
+          lv = iw;
         }
         continue;
       }
-      if (low[v] == idx[v]) {
+      if (lv == idx[v]) {  // v closes a component
         int32_t x;
         do {
           x = stk[--ns];
@@ -246,14 +278,125 @@ __device__ int32_t mb_tarjan(int32_t nq, int32_t eq, const int32_t *qoff, const 
         } while (x != v);
         nc++;
       }
+      if (depth == 0) break;
       depth--;
-      if (depth >= 0) {
-        const int32_t u = cnode[depth];
-        if (low[v] < low[u]) low[u] = low[v];
-      }
+      const int32_t u = cnode[depth];
+      const int32_t lu = low[u];
+      lv = lv < lu ? lv : lu;
+      v = u;
+      e = cpos[depth];
+      end = u + 1 < nq ? qoff[u + 1] : eq;
     }
   }
   return nc;
+}
+
+// Entries that take part in the most balanced cut this launch and their
+// free-vertex counts, as prefix sums over the entries (one block).
+__device__ __forceinline__ int32_t mb_free_count(const KArgs &A, int32_t p) {
+  const PairState &ps = A.ps[p];
+  if (ps.done || A.srec[p].decision == FR_DEC_NOT_ADJACENT) return 0;
+  return min(A.pcnt[p], ps.nr);
+}
+
+__global__ void __launch_bounds__(1024) k_mb_scan(KArgs A, int32_t it) {
+  __shared__ int64_t red[17];
+  (void)it;
+  int64_t carry = 0;
+  for (int32_t b0 = 0; b0 < A.P; b0 += blockDim.x) {
+    const int32_t p = b0 + (int32_t)threadIdx.x;
+    const int64_t v = (p < A.P && A.ctl->err == 0) ? mb_free_count(A, p) : 0;
+    int64_t tot;
+    const int64_t ex = block_exscan64(v, &tot, red);
+    if (p < A.P) A.mpre[p] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) A.mpre[A.P] = carry;
+}
+
+// Step 1 over the free vertices of every entry, one lane per vertex with its
+// arc records loaded MBK at a time: union of the ends of every residual arc
+// usable both ways (agent-scope atomics, so the workgroups of one entry may
+// sit on any XCD), and the entry's one-way arcs inside M appended to its
+// list (count in pcnt[P + p]).
+__global__ void __launch_bounds__(256) k_mb_union(KArgs A, int32_t it) {
+  (void)it;
+  const int64_t total = A.mpre[A.P];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t p = pair_of(A.mpre, A.P, i);
+    const int64_t vb = A.voff[p], ab = A.aoff[p];
+    int32_t *par = A.LA + vb;
+    const int32_t *lo = A.lo + vb + p;
+    const Arc *arc = A.arc + ab;
+    int32_t *w1 = A.mbq + ab;
+    const int32_t u = A.LB[vb + (i - A.mpre[p])];
+    const int32_t e1 = lo[u + 1];
+    for (int32_t c0 = lo[u]; c0 < e1; c0 += MBK) {
+      Arc x[MBK];
+#pragma unroll
+      for (int k = 0; k < MBK; k++) x[k] = c0 + k < e1 ? arc[c0 + k] : Arc{0, 0, 0ull};
+      int32_t pv[MBK];
+#pragma unroll
+      for (int k = 0; k < MBK; k++) pv[k] = res_own(x[k].rc) > 0 ? par[x[k].lh] : -1;
+#pragma unroll
+      for (int k = 0; k < MBK; k++) {
+        if (pv[k] < 0) continue;
+        if (res_rev(x[k].rc) > 0) {
+          if (x[k].lh > u) uf_union(par, u, x[k].lh);
+        } else {
+          w1[atomicAdd(A.pcnt + A.P + p, 1)] = c0 + k;
+        }
+      }
+    }
+  }
+}
+
+// The mb_reps sweeps, one per wave in batches that fit the LDS state (an
+// int32 in-degree and a state byte per component and sweep), then a replay
+// of the winning sweep by the first wave that flags its sink components.
+template <typename ADJ>
+__device__ __forceinline__ void mb_sweeps(const KArgs &A, MBShared &sh, const MBSweep<ADJ> &S,
+                                          int64_t wa0, int64_t wb0) {
+  const int32_t C = S.C;
+  const int32_t per = max(1, min(MB_TPB / WAVE, (int32_t)(MB_RS_BYTES / (5 * C))));
+  if (threadIdx.x == 0) {
+    sh.best_rep = -1;
+    sh.best_pos = 0;
+    sh.best_bal = 0;
+  }
+  int32_t *rs = reinterpret_cast<int32_t *>(sh.u2.rs);
+  for (int32_t r0 = 0; r0 < A.mb_reps; r0 += per) {
+    const int32_t nl = min(per, A.mb_reps - r0);
+    const int l = threadIdx.x / WAVE;
+    if (l < nl) {
+      int64_t bal;
+      const int32_t j = S.run(r0 + l, rs + (int64_t)l * C,
+                              reinterpret_cast<uint8_t *>(rs + (int64_t)nl * C) + (int64_t)l * C,
+                              wa0, wb0, C, nullptr, &bal, A.ctl);
+      if (lane64() == 0) {
+        sh.lane_bal[l] = bal;
+        sh.lane_pos[l] = j;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int k = 0; k < nl; k++)
+        if (sh.best_rep < 0 || sh.lane_bal[k] < sh.best_bal) {
+          sh.best_bal = sh.lane_bal[k];
+          sh.best_rep = r0 + k;
+          sh.best_pos = sh.lane_pos[k];
+        }
+    }
+    __syncthreads();
+  }
+  // the chosen cut: replay the winning sweep up to its position
+  if (threadIdx.x < WAVE && sh.best_pos > 0) {
+    int64_t bal;
+    S.run(sh.best_rep, rs, reinterpret_cast<uint8_t *>(rs + C), wa0, wb0, sh.best_pos,
+          sh.u1.c.sink, &bal, A.ctl);
+  }
+  __syncthreads();
 }
 
 __global__ void __launch_bounds__(MB_TPB) k_mb(KArgs A, int32_t it) {
@@ -263,13 +406,17 @@ __global__ void __launch_bounds__(MB_TPB) k_mb(KArgs A, int32_t it) {
   // the free-vertex count the flow kernel left in pcnt[p]; cleared for the
   // next iteration's boundary kernel
   const int32_t nm0 = A.pcnt[p];
+  const int32_t n1w0 = A.pcnt[A.P + p];
   if (threadIdx.x == 0) {
     const fr_solve &rec = A.srec[p];
     sh.skip = (A.ps[p].done || A.ctl->err != 0 || rec.decision == FR_DEC_NOT_ADJACENT) ? 1 : 0;
     sh.nq = 0;
   }
   __syncthreads();
-  if (threadIdx.x == 0) A.pcnt[p] = 0;
+  if (threadIdx.x == 0) {
+    A.pcnt[p] = 0;
+    A.pcnt[A.P + p] = 0;
+  }
   if (sh.skip) return;
   const int64_t t0 = wall_clock64();
   const PairView V = make_view(A, p);
@@ -291,88 +438,72 @@ __global__ void __launch_bounds__(MB_TPB) k_mb(KArgs A, int32_t it) {
   }
   int32_t *par = V.LA;        // [nr]: -1 outside M; class parent, later the component
   const int32_t *ml = V.LB;   // the free vertices M
+  int32_t *w1 = A.mbq + A.aoff[p];  // one-way arcs inside M, then (device path) quotient arcs
 
-  // ---- 1. bidirectional classes
-  for_groups<8>(nm, [&](int item, bool valid, int gl) {
-    if (!valid) return;
-    const int32_t u = ml[item];
-    const int32_t e1 = V.lo[u + 1];
-    for (int32_t e = V.lo[u] + gl; e < e1; e += 8) {
-      const Arc x = V.arc[e];
-      const int32_t v = x.lh;
-      if (v > u && res_own(x.rc) > 0 && res_rev(x.rc) > 0 && par[v] >= 0) uf_union(par, u, v);
-    }
-  });
-  __syncthreads();
-  BLOCK_WAVE_LOOP(j, nm) {
-    if (j < nm) {
-      const int32_t u = ml[j];
-      int32_t r = u;
-      for (int32_t y = aload(par + r); y != r; y = aload(par + r)) r = y;
-      par[u] = r;
-    }
-  }
-  __syncthreads();
-  // ---- 2. quotient graph: class roots numbered, one-way arcs between classes
+  // ---- 1. (k_mb_union did the union-find and listed the one-way arcs)
+  // compression (every free vertex points at its class root, the class's
+  // smallest vertex) and the roots numbered as quotient nodes
   int32_t *qid = V.lab;  // [root] -> quotient node
   BLOCK_WAVE_LOOP(j, nm) {
-    const bool root = j < nm && par[ml[j]] == ml[j];
+    bool root = false;
+    int32_t u = 0;
+    if (j < nm) {
+      u = ml[j];
+      int32_t r = u;
+      for (int32_t y = par[r]; y != r; y = par[r]) r = y;
+      par[u] = r;
+      root = r == u;
+    }
     const int pos = wave_append(&sh.nq, root);
-    if (root) qid[ml[j]] = pos;
+    if (root) qid[u] = pos;
   }
   __syncthreads();
-  const int32_t nq = uni(sh.nq);
+  // ---- 2. quotient graph over the one-way arcs between classes
+  const int32_t nq = uni(sh.nq), n1w = uni(n1w0);
   const bool lq = A.mb_lds && nq <= MB_LQ;
-  int32_t *qoff = lq ? sh.u.t.qoff : V.ex;
+  int32_t *qoff = lq ? sh.u2.q.qoff : V.ex;
   for (int32_t q = threadIdx.x; q < nq; q += blockDim.x) qoff[q] = 0;
   __syncthreads();
-  auto one_way = [&](int32_t u, bool valid, int gl, auto &&f) {
-    if (!valid) return;
-    const int32_t ru = par[u];
-    const int32_t e1 = V.lo[u + 1];
-    for (int32_t e = V.lo[u] + gl; e < e1; e += 8) {
-      const Arc x = V.arc[e];
-      const int32_t v = x.lh;
-      if (res_own(x.rc) > 0 && res_rev(x.rc) == 0) {
-        const int32_t rv = par[v];
-        if (rv >= 0 && rv != ru) f(qid[ru], qid[rv]);
-      }
-    }
+  auto one_way = [&](int32_t j, auto &&f) {
+    const Arc x = V.arc[w1[j]];
+    const int32_t ru = par[V.arc[x.lr].lh], rv = par[x.lh];
+    if (ru != rv) f(qid[ru], qid[rv]);
   };
-  for_groups<8>(nm, [&](int item, bool valid, int gl) {
-    one_way(valid ? ml[item] : 0, valid, gl, [&](int32_t a, int32_t) { atomicAdd(qoff + a, 1); });
-  });
+  for (int32_t j = threadIdx.x; j < n1w; j += blockDim.x)
+    one_way(j, [&](int32_t a, int32_t) { atomicAdd(qoff + a, 1); });
   __syncthreads();
   const int32_t eq = mb_exscan(qoff, nq, sh.red);
   if (threadIdx.x == 0) sh.eq = eq;
-  const bool lqa = lq && eq <= MB_LQA;
-  int32_t *qarc = lqa ? sh.u.t.qarc : A.mbq + A.aoff[p];
-  int32_t *cur = lq ? sh.u.t.cpos : V.SNK;
+  // all of Q and Tarjan's scratch in LDS, or all in device memory
+  const bool lt = lq && eq <= MB_LQA;
+  if (lq && !lt) {
+    for (int32_t q = threadIdx.x; q < nq; q += blockDim.x) V.ex[q] = qoff[q];
+    __syncthreads();
+    qoff = V.ex;
+  }
+  int32_t *qarc = lt ? sh.u2.q.qarc : w1 + n1w;  // eq <= n1w <= arc slots / 2
+  int32_t *cur = lt ? sh.u1.t.cpos : V.SNK;
   for (int32_t q = threadIdx.x; q < nq; q += blockDim.x) cur[q] = qoff[q];
   __syncthreads();
-  for_groups<8>(nm, [&](int item, bool valid, int gl) {
-    one_way(valid ? ml[item] : 0, valid, gl, [&](int32_t a, int32_t b) {
-      qarc[atomicAdd(cur + a, 1)] = b;
-    });
-  });
+  for (int32_t j = threadIdx.x; j < n1w; j += blockDim.x)
+    one_way(j, [&](int32_t a, int32_t b) { qarc[atomicAdd(cur + a, 1)] = b; });
   __syncthreads();  // the arc records are dead from here on
-  // ---- Tarjan on the quotient graph (its scratch: LDS, or the arc arena,
-  //      whose records are no longer read)
+  // ---- Tarjan on the quotient graph (its scratch: LDS, or the arc arena)
   int32_t *W = reinterpret_cast<int32_t *>(V.arc);
-  int32_t *idx = lq ? sh.qidx : W;
+  int32_t *idx = lt ? sh.u2.q.qidx : W;
   for (int32_t q = threadIdx.x; q < nq; q += blockDim.x) idx[q] = -1;
   __syncthreads();
   if (threadIdx.x == 0) {
-    if (!lq && nq > V.na) {  // cannot happen: nq <= corridor vertices <= arc slots
+    if (lt) {
+      sh.nc = mb_tarjan(nq, eq, sh.u2.q.qoff, sh.u2.q.qarc, sh.u2.q.qidx, sh.u1.t.low, sh.u1.t.stk,
+                        sh.u1.t.cnode, sh.u1.t.cpos);
+    } else if (nq > V.na) {  // cannot happen: nq <= corridor vertices <= arc slots
       A.ctl->err = FR_E_DEVICE;
       A.ctl->diag = DIAG_MB;
       sh.nc = FR_MB_MAX_COMP + 1;
     } else {
-      int32_t *low = lq ? sh.u.t.low : W + nq;
-      int32_t *stk = lq ? sh.u.t.stk : W + 2 * (int64_t)nq;
-      int32_t *cnode = lq ? sh.u.t.cnode : W + 3 * (int64_t)nq;
-      int32_t *cpos = lq ? sh.u.t.cpos : V.SNK;
-      sh.nc = mb_tarjan(nq, eq, qoff, qarc, idx, low, stk, cnode, cpos);
+      sh.nc = mb_tarjan(nq, eq, V.ex, w1 + n1w, W, W + nq, W + 2 * (int64_t)nq,
+                        W + 3 * (int64_t)nq, V.SNK);
     }
   }
   __syncthreads();
@@ -383,35 +514,58 @@ __global__ void __launch_bounds__(MB_TPB) k_mb(KArgs A, int32_t it) {
   }
   // ---- 3. the component DAG
   for (int32_t c = threadIdx.x; c < C; c += blockDim.x) {
-    sh.cw[c] = 0;
-    sh.ckey[c] = 0x7fffffff;
-    sh.cend[c] = 0;
-    sh.cin[c] = 0;
-    sh.sink[c] = 0;
+    sh.u1.c.cw[c] = 0;
+    sh.u1.c.ckey[c] = 0x7fffffff;
+    sh.u1.c.cend[c] = 0;
+    sh.u1.c.cin[c] = 0;
+    sh.u1.c.sink[c] = 0;
   }
   __syncthreads();
+  // every free vertex: its component (into par), the components' weights and
+  // key ids; four vertices per lane with their loads issued together
   int64_t wfree = 0;
-  BLOCK_WAVE_LOOP(j, nm) {
-    if (j < nm) {
-      const int32_t u = ml[j];
-      const int32_t c = -2 - idx[qid[par[u]]];
-      const int32_t g = V.lg[u];
-      const int64_t w = A.vwgt[g];
-      par[u] = c;
-      wfree += w;
-      atomicAdd((unsigned long long *)&sh.cw[c], (unsigned long long)w);
-      atomicMin(&sh.ckey[c], g);
+  for (int64_t b0 = (int64_t)(threadIdx.x & ~63u) * 4; b0 < nm; b0 += 4 * (int64_t)blockDim.x) {
+    int32_t u[4], r[4], g[4], c[4];
+    int64_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int64_t j = b0 + 64 * k + lane64();
+      u[k] = j < nm ? ml[j] : -1;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      r[k] = u[k] >= 0 ? par[u[k]] : 0;
+      g[k] = u[k] >= 0 ? V.lg[u[k]] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      c[k] = u[k] >= 0 ? -2 - idx[qid[r[k]]] : -1;
+      w[k] = u[k] >= 0 ? A.vwgt[g[k]] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      if (u[k] >= 0) par[u[k]] = c[k];
+      wfree += w[k];
+      wave_add_by_key(reinterpret_cast<unsigned long long *>(sh.u1.c.cw), 1, 0, c[k], w[k]);
+      wave_min_by_key(sh.u1.c.ckey, c[k], g[k]);
     }
   }
-  for (int32_t q = threadIdx.x; q < nq; q += blockDim.x) {
-    const int32_t c = -2 - idx[q];
-    const int32_t end = q + 1 < nq ? qoff[q + 1] : eq;
-    for (int32_t e = qoff[q]; e < end; e++) {
-      const int32_t d = -2 - idx[qarc[e]];
-      if (d != c) {
-        atomicAdd(&sh.cend[c], 1);
-        atomicAdd(&sh.cin[d], 1);
-      }
+  // component arcs, one lane per quotient arc (a hub class can own most of
+  // them): its source node by binary search over the offsets
+  auto qsrc = [&](int32_t e) {
+    int32_t lo = 0, hi = nq;
+    while (hi - lo > 1) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (qoff[mid] <= e) lo = mid;
+      else hi = mid;
+    }
+    return lo;
+  };
+  for (int32_t e = threadIdx.x; e < eq; e += blockDim.x) {
+    const int32_t c = -2 - idx[qsrc(e)], d = -2 - idx[qarc[e]];
+    if (d != c) {
+      atomicAdd(&sh.u1.c.cend[c], 1);
+      atomicAdd(&sh.u1.c.cin[d], 1);
     }
   }
   {
@@ -419,71 +573,33 @@ __global__ void __launch_bounds__(MB_TPB) k_mb(KArgs A, int32_t it) {
     block_sums<1>(s1, sh.red);
     wfree = s1[0];
   }
-  const int32_t ne = mb_exscan(sh.cend, C, sh.red);
+  const int32_t ne = mb_exscan(sh.u1.c.cend, C, sh.red);
   const bool ladj = A.mb_lds && ne <= MB_LDAG;
-  int32_t *gadj = W + (lq ? 0 : nq);
+  int32_t *gadj = W + (lt ? 0 : nq);
   // fill: cend[c] counts up from c's start to its end
-  for (int32_t q = threadIdx.x; q < nq; q += blockDim.x) {
-    const int32_t c = -2 - idx[q];
-    const int32_t end = q + 1 < nq ? qoff[q + 1] : eq;
-    for (int32_t e = qoff[q]; e < end; e++) {
-      const int32_t d = -2 - idx[qarc[e]];
-      if (d != c) {
-        const int32_t pos = atomicAdd(&sh.cend[c], 1);
-        if (ladj) sh.adj[pos] = (int16_t)d;
-        else gadj[pos] = d;
-      }
+  for (int32_t e = threadIdx.x; e < eq; e += blockDim.x) {
+    const int32_t c = -2 - idx[qsrc(e)], d = -2 - idx[qarc[e]];
+    if (d != c) {
+      const int32_t pos = atomicAdd(&sh.u1.c.cend[c], 1);
+      if (ladj) sh.u1.c.adj[pos] = (int16_t)d;
+      else gadj[pos] = d;
     }
   }
   __syncthreads();
-  // ---- 4. sweeps, one lane each, in batches that fit the LDS state
+  // ---- 4. sweeps, one per wave, in batches that fit the LDS state
   const fr_solve rec0 = A.srec[p];
   const int64_t wa0 = rec0.wa + wfree, wb0 = rec0.wb - wfree;  // all free components with s
   const uint64_t seed = (uint64_t)(uint32_t)A.mb_seed;
-  const MBSweep S{C, sh.cin, sh.cend, gadj, ladj ? sh.adj : nullptr, sh.cw, sh.ckey, seed};
-  const int32_t per = max(1, min(WAVE, (int32_t)(MB_RS_BYTES / (6 * C))));
-  if (threadIdx.x == 0) {
-    sh.best_rep = -1;
-    sh.best_pos = 0;
-    sh.best_bal = 0;
-  }
-  for (int32_t r0 = 0; r0 < A.mb_reps; r0 += per) {
-    const int32_t nl = min(per, A.mb_reps - r0);
-    if (threadIdx.x < (unsigned)nl) {
-      const int l = threadIdx.x;
-      int32_t *ind = reinterpret_cast<int32_t *>(sh.u.rs) + (int64_t)l * C;
-      int16_t *heap = reinterpret_cast<int16_t *>(reinterpret_cast<int32_t *>(sh.u.rs) +
-                                                  (int64_t)nl * C) + (int64_t)l * C;
-      int64_t bal;
-      const int32_t j = S.run(r0 + l, ind, heap, wa0, wb0, C, nullptr, &bal, A.ctl);
-      sh.lane_bal[l] = bal;
-      sh.lane_pos[l] = j;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int l = 0; l < nl; l++)
-        if (sh.best_rep < 0 || sh.lane_bal[l] < sh.best_bal) {
-          sh.best_bal = sh.lane_bal[l];
-          sh.best_rep = r0 + l;
-          sh.best_pos = sh.lane_pos[l];
-        }
-    }
-    __syncthreads();
-  }
-  // the chosen cut: replay the winning sweep up to its position
-  if (threadIdx.x == 0 && sh.best_pos > 0) {
-    int64_t bal;
-    S.run(sh.best_rep, reinterpret_cast<int32_t *>(sh.u.rs),
-          reinterpret_cast<int16_t *>(reinterpret_cast<int32_t *>(sh.u.rs) + C), wa0, wb0,
-          sh.best_pos, sh.sink, &bal, A.ctl);
-  }
-  __syncthreads();
+  if (ladj)
+    mb_sweeps(A, sh, MBSweep<int16_t>{C, sh.u1.c.cin, sh.u1.c.cend, sh.u1.c.adj, sh.u1.c.cw, sh.u1.c.ckey, seed}, wa0, wb0);
+  else
+    mb_sweeps(A, sh, MBSweep<int32_t>{C, sh.u1.c.cin, sh.u1.c.cend, gadj, sh.u1.c.cw, sh.u1.c.ckey, seed}, wa0, wb0);
   // ---- 5. components left on the source side join S_min
   int64_t acc[2] = {0, 0};  // weight, vertices
   BLOCK_WAVE_LOOP(j, nm) {
     if (j < nm) {
       const int32_t u = ml[j];
-      if (!sh.sink[par[u]]) {
+      if (!sh.u1.c.sink[par[u]]) {
         V.ins[u] = 1;
         acc[0] += A.vwgt[V.lg[u]];
         acc[1] += 1;

@@ -26,7 +26,7 @@ def ctx(gpu_lib):
     c.close()
 
 
-def _round_vs_oracle(gpu_lib, ctx, w, sample, use_mlp=0):
+def _round_vs_oracle(gpu_lib, ctx, w, sample, use_mlp=0, extra=None):
     import torch
 
     dg = gpu_lib.DeviceGraph.from_host(w.graph)
@@ -37,6 +37,7 @@ def _round_vs_oracle(gpu_lib, ctx, w, sample, use_mlp=0):
     dpart = part0.clone()
     p = {k: w.params[k] for k in ("area_mode", "depth", "alpha", "alpha_max", "adaptive",
                                   "max_iters", "eps_ppm")}
+    p.update(extra or {})
     res, trace = gpu_lib.flow_refine_batch(ctx, dg, dpart, w.k, pairs,
                                            gpu_lib.params(**p, use_mlp=use_mlp))
     out = dpart.cpu().numpy()
@@ -69,6 +70,15 @@ def test_c4_round_with_learned_factor_sampled(gpu_lib, ctx):
     gpu_lib.load_trained_mlp(ctx)
     print("C4 largest round, learned start factor", flush=True)
     _round_vs_oracle(gpu_lib, ctx, w, sample=3, use_mlp=1)
+
+
+@pytest.mark.parametrize("cid", ["C3", "C5"])
+def test_round_most_balanced_sampled(gpu_lib, ctx, cid):
+    """The largest round of C3 / C5 with balanced adaptive flow iterations
+    (16 sweeps), as the benchmark runs it."""
+    w = gen.config(cid)
+    print(f"{cid} largest round, most balanced cuts", flush=True)
+    _round_vs_oracle(gpu_lib, ctx, w, sample=3, extra=dict(mb_reps=16, mb_seed=1))
 
 
 def test_c5_sweep_properties(gpu_lib, ctx):
