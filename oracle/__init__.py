@@ -47,7 +47,7 @@ class OrGraph(ctypes.Structure):
 class OrParams(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int32) for f in
                 ("area_mode", "depth", "alpha", "alpha_max", "adaptive", "max_iters", "eps_ppm",
-                 "mb_reps", "mb_seed")]
+                 "mb_reps", "mb_seed", "fm_limit", "fm_seed")]
 
 
 class OrSolve(ctypes.Structure):
@@ -88,6 +88,8 @@ def _load():
     lib.or_sweep.argtypes = [G, vp, i32, P, i32, ctypes.POINTER(i64), vp]
     lib.or_pair_features.restype = i32
     lib.or_pair_features.argtypes = [G, vp, i32, i32, i32, i32, vp]
+    lib.or_pair_fm.restype = i32
+    lib.or_pair_fm.argtypes = [G, vp, i32, i32, i32, i32, i32, ctypes.c_uint32, vp, vp]
     lib.or_splitmix64.restype = ctypes.c_uint64
     lib.or_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
     lib.or_scc.restype = i32
@@ -116,12 +118,15 @@ class _Bound:
                          _ptr(self.vwgt), _ptr(self.adjwgt))
 
 
+def _i32(x: int) -> int:
+    x = int(x) & 0xFFFFFFFF
+    return x - (1 << 32) if x >= 1 << 31 else x
+
+
 def _params(p: dict) -> OrParams:
-    seed = int(p.get("mb_seed", 0)) & 0xFFFFFFFF
-    if seed >= 1 << 31:
-        seed -= 1 << 32
     return OrParams(p.get("area_mode", 0), p.get("depth", 0), p["alpha"], p["alpha_max"],
-                    p["adaptive"], p["max_iters"], p["eps_ppm"], p.get("mb_reps", 0), seed)
+                    p["adaptive"], p["max_iters"], p["eps_ppm"], p.get("mb_reps", 0),
+                    _i32(p.get("mb_seed", 0)), p.get("fm_limit", 0), _i32(p.get("fm_seed", 0)))
 
 
 def _struct_dict(s) -> dict:
@@ -146,6 +151,23 @@ def maxflow(nn: int, tails, heads, caps, s: int, t: int):
     if rc != 0:
         raise ValueError("or_maxflow: bad input")
     return int(val.value), reach.astype(bool)
+
+
+def pair_fm(graph, part: np.ndarray, k: int, a: int, b: int, eps_ppm: int, limit: int,
+            seed: int):
+    """One 2-way FM pass with TopGain on blocks a, b (Sec. 2.2); returns
+    (new partition, info dict, move log)."""
+    bnd = _Bound(graph)
+    out = np.ascontiguousarray(part, dtype=np.int32).copy()
+    info = np.zeros(6, dtype=np.int64)
+    log = np.zeros(max(1, bnd.s.n), dtype=np.int32)
+    rc = _load().or_pair_fm(ctypes.byref(bnd.s), _ptr(out), k, a, b, eps_ppm, limit,
+                            seed & 0xFFFFFFFF, _ptr(info), _ptr(log))
+    if rc != 0:
+        raise ValueError(f"or_pair_fm: {rc}")
+    keys = ("cut_before", "cut_after", "steps", "kept", "weight_a", "weight_b")
+    d = dict(zip(keys, info.tolist()))
+    return out, d, log[: d["steps"]].copy()
 
 
 def splitmix64(seed: int, n: int) -> int:

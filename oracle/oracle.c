@@ -37,6 +37,16 @@
  *       improving => stop; at most max_iters solves
  *   R8  the first block of the pair is the source side
  *   R9  DEPTH mode includes BFS distance <= depth from the boundary
+ *   R12 2-way FM before the flow (Sec. 2.2, KaPPa's local search with TopGain):
+ *       one queue per block of the pair, ordered by gain, equal gains by a
+ *       per-vertex SplitMix64 key (larger first); boundary vertices start in
+ *       the queues, a vertex joins its queue when a neighbour moves, and moves
+ *       at most once; TopGain picks the block with the larger top gain (a
+ *       random bit on ties), the heavier block while one is overloaded;
+ *       stop after fm_limit moves without a better state or when both queues
+ *       are empty; roll back to the best state: feasible before infeasible,
+ *       then the smaller cut (feasible) or the lighter heavier block
+ *       (infeasible), the earliest on ties
  *   R11 most balanced cut: balance of a cut = the heavier of the two new block
  *       weights; a random topological order takes, among the components whose
  *       predecessors are all placed, the one with the smallest key, keys from
@@ -67,6 +77,9 @@ typedef struct {
   int32_t eps_ppm;
   int32_t mb_reps;  /* 0: smallest source set; > 0: most balanced minimum cut, this many sweeps */
   int32_t mb_seed;  /* seed of the sweeps' random keys (its 32 bits, zero-extended) */
+  int32_t fm_limit; /* 0: no FM; > 0: 2-way FM before the flow, stop after this many moves
+                       without improvement */
+  int32_t fm_seed;  /* seed of the FM keys and tie bits (its 32 bits, zero-extended) */
 } or_params;
 
 /* one flow solve */
@@ -822,6 +835,146 @@ oom:
   return -1;
 }
 
+/* ------------------------------------------------------------------------ */
+/* 2-way FM local search with TopGain (Sec. 2.2)                             */
+
+/* FM key of vertex v: output number v + 1 of SplitMix64 started at the seed;
+ * the tie bit of move step t: bit 0 of output number 2^32 + t + 1 */
+static uint64_t fm_key(uint64_t seed, int32_t v) { return splitmix64_out(seed, (uint64_t)(uint32_t)v + 1); }
+static int fm_bit(uint64_t seed, int64_t t) {
+  return (int)(splitmix64_out(seed, (1ull << 32) + (uint64_t)t + 1) & 1ull);
+}
+
+typedef struct {
+  int64_t cut0, cut;   /* pair cut before and after */
+  int64_t steps;       /* moves made */
+  int64_t kept;        /* moves kept after the rollback */
+  int64_t wa, wb;      /* block weights after */
+} or_fminfo;
+
+/* one pass of 2-way FM on blocks a, b of part (in place).  lmax: the balance
+ * bound.  Returns 0 or -1 (out of memory).  move_log (optional, n): the
+ * vertices in move order, info->steps of them. */
+static int32_t pair_fm(const or_graph *g, int32_t *part, int32_t a, int32_t b, int64_t lmax,
+                       int32_t limit, uint64_t seed, or_fminfo *info, int32_t *move_log) {
+  int32_t n = g->n;
+  int64_t *gain = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+  int8_t *st = (int8_t *)calloc((size_t)n, 1); /* 0 out, 1 queued, 2 moved */
+  int32_t *log = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+  int32_t *qa = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+  if (!gain || !st || !log || !qa) { free(gain); free(st); free(log); free(qa); return -1; }
+  memset(info, 0, sizeof(*info));
+  int64_t wa = 0, wb = 0, cut = 0;
+  /* gains: weight to the other block of the pair minus weight to the own */
+  for (int32_t v = 0; v < n; v++) {
+    if (part[v] != a && part[v] != b) continue;
+    int32_t other = part[v] == a ? b : a;
+    int64_t ext = 0, in = 0;
+    for (int32_t e = g->xadj[v]; e < g->xadj[v + 1]; e++) {
+      int32_t u = g->adjncy[e];
+      if (part[u] == other) ext += g->adjwgt[e];
+      else if (part[u] == part[v]) in += g->adjwgt[e];
+    }
+    gain[v] = ext - in;
+    if (ext > 0) st[v] = 1; /* boundary vertex: queued */
+    if (part[v] == a) { wa += g->vwgt[v]; cut += ext; }
+    else wb += g->vwgt[v];
+  }
+  int32_t nq = 0; /* the queued vertices, scanned for the top of each block */
+  for (int32_t v = 0; v < n; v++) if (st[v] == 1) qa[nq++] = v;
+  info->cut0 = cut;
+  /* quality of a state: (infeasible, feasible ? cut : max(wa, wb)) */
+  int best_inf = !(wa <= lmax && wb <= lmax);
+  int64_t best_val = best_inf ? (wa > wb ? wa : wb) : cut;
+  int64_t best_step = 0, steps = 0, since = 0;
+  for (;;) {
+    if (since >= limit) break;
+    /* tops of the two queues: largest gain, then largest key */
+    int32_t top[2] = {-1, -1};
+    uint64_t tk[2] = {0, 0};
+    for (int32_t i = 0; i < nq; i++) {
+      int32_t v = qa[i];
+      if (st[v] != 1) continue;
+      int side = part[v] == a ? 0 : 1;
+      uint64_t kv = fm_key(seed, v);
+      int32_t t = top[side];
+      if (t < 0 || gain[v] > gain[t] || (gain[v] == gain[t] && kv > tk[side])) {
+        top[side] = v;
+        tk[side] = kv;
+      }
+    }
+    if (top[0] < 0 && top[1] < 0) break;
+    int side;
+    if ((wa > lmax || wb > lmax) && wa != wb) side = wa > wb ? 0 : 1;  /* move out of the heavier */
+    else if (top[0] < 0 || top[1] < 0) side = top[0] < 0 ? 1 : 0;
+    else if (gain[top[0]] != gain[top[1]]) side = gain[top[0]] > gain[top[1]] ? 0 : 1;
+    else side = fm_bit(seed, steps);
+    if (top[side] < 0) side = 1 - side;
+    int32_t v = top[side];
+    int32_t from = part[v], to = from == a ? b : a;
+    /* move */
+    part[v] = to;
+    st[v] = 2;
+    cut -= gain[v];
+    if (from == a) { wa -= g->vwgt[v]; wb += g->vwgt[v]; }
+    else { wb -= g->vwgt[v]; wa += g->vwgt[v]; }
+    log[steps++] = v;
+    for (int32_t e = g->xadj[v]; e < g->xadj[v + 1]; e++) {
+      int32_t u = g->adjncy[e];
+      if ((part[u] != a && part[u] != b) || st[u] == 2) continue;
+      /* the edge turns from internal to cut for u in `from`, and back for u in `to` */
+      gain[u] += part[u] == from ? 2 * (int64_t)g->adjwgt[e] : -2 * (int64_t)g->adjwgt[e];
+      if (st[u] == 0) { st[u] = 1; qa[nq++] = u; }
+    }
+    int inf = !(wa <= lmax && wb <= lmax);
+    int64_t val = inf ? (wa > wb ? wa : wb) : cut;
+    if (inf < best_inf || (inf == best_inf && val < best_val)) {
+      best_inf = inf;
+      best_val = val;
+      best_step = steps;
+      since = 0;
+    } else {
+      since++;
+    }
+  }
+  /* roll back the moves after the best state */
+  for (int64_t i = steps - 1; i >= best_step; i--) {
+    int32_t v = log[i];
+    int32_t to = part[v], from = to == a ? b : a;
+    part[v] = from;
+    if (from == a) { wa += g->vwgt[v]; wb -= g->vwgt[v]; }
+    else { wb += g->vwgt[v]; wa -= g->vwgt[v]; }
+  }
+  info->steps = steps;
+  info->kept = best_step;
+  info->wa = wa;
+  info->wb = wb;
+  info->cut = pair_cut(g, part, a, b);
+  if (move_log) memcpy(move_log, log, sizeof(int32_t) * (size_t)steps);
+  free(gain); free(st); free(log); free(qa);
+  return 0;
+}
+
+/* 2-way FM on one pair alone (for tests).  info[6] = cut before, cut after,
+ * moves made, moves kept, weight a, weight b; move_log (optional, n). */
+int32_t or_pair_fm(const or_graph *g, int32_t *part, int32_t k, int32_t a, int32_t b,
+                   int32_t eps_ppm, int32_t limit, uint32_t seed, int64_t *info,
+                   int32_t *move_log) {
+  if (a < 0 || b < 0 || a >= k || b >= k || a == b || limit < 0) return -3;
+  int64_t cV = 0, maxc = 0;
+  for (int32_t u = 0; u < g->n; u++) {
+    cV += g->vwgt[u];
+    if (g->vwgt[u] > maxc) maxc = g->vwgt[u];
+  }
+  int64_t lmax = (int64_t)(((__int128)(1000000 + (int64_t)eps_ppm) * cV) /
+                           ((__int128)1000000 * k)) + maxc;
+  or_fminfo fi;
+  if (pair_fm(g, part, a, b, lmax, limit, (uint64_t)seed, &fi, move_log) != 0) return -7;
+  info[0] = fi.cut0; info[1] = fi.cut; info[2] = fi.steps; info[3] = fi.kept;
+  info[4] = fi.wa; info[5] = fi.wb;
+  return 0;
+}
+
 /* Adaptive flow iterations (Sec. 4.1) on one pair.  trace (optional) gets
  * one record per solve, at most p->max_iters.  side_out: of the last solve. */
 int32_t or_refine_pair(const or_graph *g, int32_t *part, int32_t k, int32_t a, int32_t b,
@@ -829,7 +982,8 @@ int32_t or_refine_pair(const or_graph *g, int32_t *part, int32_t k, int32_t a, i
   memset(res, 0, sizeof(*res));
   if (a < 0 || b < 0 || a >= k || b >= k || a == b) return -3;
   if (p->alpha < 1 || p->alpha_max < 1 || p->max_iters < 1 || p->eps_ppm < 0 ||
-      (p->area_mode != 0 && p->area_mode != 1) || p->depth < 0 || p->mb_reps < 0)
+      (p->area_mode != 0 && p->area_mode != 1) || p->depth < 0 || p->mb_reps < 0 ||
+      p->fm_limit < 0)
     return -8;
   int64_t w_a = 0, w_b = 0;
   for (int32_t u = 0; u < g->n; u++) {
@@ -837,6 +991,22 @@ int32_t or_refine_pair(const or_graph *g, int32_t *part, int32_t k, int32_t a, i
     if (part[u] == b) w_b += g->vwgt[u];
   }
   res->cut_before = pair_cut(g, part, a, b);
+  int64_t fm_kept = 0;
+  if (p->fm_limit > 0) {
+    /* Sec. 2.2 / appendix: the pairwise improvement starts with 2-way FM,
+     * followed by the flow-based improvement */
+    int64_t cV = 0, maxc = 0;
+    for (int32_t u = 0; u < g->n; u++) {
+      cV += g->vwgt[u];
+      if (g->vwgt[u] > maxc) maxc = g->vwgt[u];
+    }
+    int64_t lmax = (int64_t)(((__int128)(1000000 + (int64_t)p->eps_ppm) * cV) /
+                             ((__int128)1000000 * k)) + maxc;
+    or_fminfo fi;
+    if (pair_fm(g, part, a, b, lmax, p->fm_limit, (uint64_t)(uint32_t)p->fm_seed, &fi, NULL) != 0)
+      return -7;
+    fm_kept = fi.kept;
+  }
   int32_t alpha = p->alpha < p->alpha_max ? p->alpha : p->alpha_max;
   int32_t last = 0;
   int stopped = 0;
@@ -864,7 +1034,7 @@ int32_t or_refine_pair(const or_graph *g, int32_t *part, int32_t k, int32_t a, i
   }
   res->iter_cap = !stopped;
   if (last == DEC_NOT_ADJ && res->applied == 0) res->status = ST_NOT_ADJACENT;
-  else if (res->applied > 0) res->status = ST_ACCEPTED;
+  else if (res->applied > 0 || fm_kept > 0) res->status = ST_ACCEPTED;
   else if (last == DEC_INFEASIBLE) res->status = ST_REJECTED;
   else res->status = ST_NO_IMPROVEMENT;
   res->cut_after = pair_cut(g, part, a, b);
