@@ -124,6 +124,22 @@ typedef struct {
    * g) in sweep j gets output number j * 2^32 + g + 1 of SplitMix64 started
    * at mb_seed (the 32 bits, zero-extended to 64). */
   int32_t mb_seed;
+  /* Pairwise 2-way FM local search with TopGain before the flow (Sec. 2.2 and
+   * the pairwise improvement of active block scheduling: FM, then max-flow
+   * min-cut).  0: off.  f > 0: one FM pass on each pair before its adaptive
+   * flow iterations, stopped after f moves without a better state (or when
+   * no vertex is left to move), rolled back to the best state.  Queues: one
+   * per block, ordered by gain, equal gains by the key SplitMix64(fm_seed)
+   * output number v + 1 of vertex v (larger first); boundary vertices start
+   * queued, a vertex joins when a neighbour moves, each moves at most once.
+   * TopGain: the block with the larger top gain moves, the heavier block
+   * while one is overloaded (c > L_max), ties by bit 0 of output number
+   * 2^32 + t + 1 for move t (1: block b).  Best state: feasible before
+   * infeasible, then the smaller pair cut (feasible) or the lighter heavier
+   * block (infeasible), the earliest on ties.  Each vertex's weighted degree
+   * within the pair must stay below 2^31 (else FR_E_OVERFLOW). */
+  int32_t fm_limit;
+  int32_t fm_seed;
 } fr_params;
 
 #define FR_MB_MAX_REPS 256
@@ -248,7 +264,10 @@ int32_t fr_set_validation(fr_context *ctx, int32_t on);
  * counters[32]: [0] push/relabel sweeps, [1] global relabels, [2] corridor
  *   BFS levels, [3] relabel BFS levels, [4] closure levels, [5] workgroups
  *   of the per-pair kernels, [6] internal check that failed (0 = none),
- *   [7] speculative factors per pair (1 = none);
+ *   [7] speculative factors per pair (1 = none); [8] most-balanced-cut
+ *   kernels time in ns, [9] free vertices, [10] their residual components,
+ *   [11] solves that kept the smallest source set for having more than
+ *   FR_MB_MAX_COMP components; [12] FM moves made, [13] FM moves kept;
  *   [16..27] vertices and arcs touched: boundary scan, corridor BFS, network
  *   build, push/relabel sweeps, global relabels, residual closure (vertices
  *   then arcs for each); the rest 0. */

@@ -36,7 +36,8 @@ class FrGraph(ctypes.Structure):
 
 class FrParams(ctypes.Structure):
     _fields_ = [(f, i32) for f in ("area_mode", "depth", "alpha", "alpha_max", "adaptive",
-                                   "max_iters", "eps_ppm", "use_mlp", "mb_reps", "mb_seed")]
+                                   "max_iters", "eps_ppm", "use_mlp", "mb_reps", "mb_seed",
+                                   "fm_limit", "fm_seed")]
 
 
 class FrResult(ctypes.Structure):
@@ -141,10 +142,11 @@ def params(**kw) -> FrParams:
     """fr_params with the defaults below; mb_seed takes any int (its low 32
     bits are used)."""
     d = dict(area_mode=0, depth=0, alpha=16, alpha_max=16, adaptive=1, max_iters=16,
-             eps_ppm=30000, use_mlp=0, mb_reps=0, mb_seed=0)
+             eps_ppm=30000, use_mlp=0, mb_reps=0, mb_seed=0, fm_limit=0, fm_seed=0)
     d.update(kw)
-    seed = int(d["mb_seed"]) & 0xFFFFFFFF
-    d["mb_seed"] = seed - (1 << 32) if seed >= 1 << 31 else seed
+    for f in ("mb_seed", "fm_seed"):
+        seed = int(d[f]) & 0xFFFFFFFF
+        d[f] = seed - (1 << 32) if seed >= 1 << 31 else seed
     return FrParams(**{k: int(d[k]) for k, _ in FrParams._fields_})
 
 
@@ -243,7 +245,8 @@ def stats_dict(ctx) -> dict:
              call_ms=ms[4], relabel_ms=ms[5], push_ms=ms[6], flow_kernel_ms=ms[7],
              sweeps=cnt[0], relabels=cnt[1], bfs_levels=cnt[2], gr_levels=cnt[3],
              cl_levels=cnt[4], workgroups=cnt[5], diag=cnt[6], slots=cnt[7],
-             mb_kernel_ms=cnt[8] / 1e6, mb_free=cnt[9], mb_comp=cnt[10], mb_limited=cnt[11])
+             mb_kernel_ms=cnt[8] / 1e6, mb_free=cnt[9], mb_comp=cnt[10], mb_limited=cnt[11],
+             fm_steps=cnt[12], fm_kept=cnt[13])
     d.update({k: cnt[16 + i] for i, k in enumerate(WORK_KEYS)})
     return d
 

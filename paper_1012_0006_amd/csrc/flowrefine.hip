@@ -13,6 +13,7 @@
 #include "fr_internal.h"
 #include "fr_kernels.h"
 #include "fr_mb.h"
+#include "fr_fm.h"
 #include "fr_mlp.h"
 
 #define HIPCHK(x)                        \
@@ -41,6 +42,8 @@ struct DevBufs {
   int8_t *side = nullptr;
   int32_t *mbq = nullptr;  // most balanced cut: quotient arcs, one per arc slot (lazy)
   int64_t mbqcap = 0;
+  int32_t *fmg = nullptr, *fmq = nullptr;  // 2-way FM: per-vertex gains, queue positions (lazy)
+  int64_t fmcap = 0;
   // per arc
   int32_t *ga = nullptr, *gw = nullptr;
   Arc *arc = nullptr;  // corridor arcs
@@ -116,6 +119,10 @@ static void free_vertex_arc(DevBufs &d) {
   dfree(d.mbq);
   d.mbq = nullptr;
   d.mbqcap = 0;
+  dfree(d.fmg);
+  dfree(d.fmq);
+  d.fmg = d.fmq = nullptr;
+  d.fmcap = 0;
   dfree(d.lflag);
   d.lflag = nullptr;
   dfree(d.side);
@@ -328,7 +335,7 @@ static int32_t check_params(const fr_params *p) {
   if (p->area_mode != FR_AREA_FACTOR && p->area_mode != FR_AREA_DEPTH) return FR_E_INVALID_ARG;
   if (p->depth < 0 || p->alpha < 1 || p->alpha_max < 1 || p->alpha_max > FR_MAX_ALPHA ||
       p->max_iters < 1 || p->max_iters > FR_MAX_ITERS || p->eps_ppm < 0 || p->eps_ppm > 100000000 ||
-      p->mb_reps < 0 || p->mb_reps > FR_MB_MAX_REPS)
+      p->mb_reps < 0 || p->mb_reps > FR_MB_MAX_REPS || p->fm_limit < 0)
     return FR_E_INVALID_ARG;
   return FR_OK;
 }
@@ -401,9 +408,13 @@ static KArgs call_args(fr_context *c, const fr_graph *g, int32_t *dpart, int32_t
     A.eps_ppm = p->eps_ppm;
     A.mb_reps = p->mb_reps;
     A.mb_seed = p->mb_seed;
+    A.fm_limit = p->fm_limit;
+    A.fm_seed = p->fm_seed;
   }
   A.mb_lds = c->tune.mb_lds;
   A.mbq = d.mbq;
+  A.fmg = d.fmg;
+  A.fmq = d.fmq;
   A.mark = d.mark;
   A.vmap = d.vmap;
   A.voff = d.voff;
@@ -501,6 +512,8 @@ static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t s
   }
   hipLaunchKernelGGL(k_arena, dim3(1), dim3(1024), 0, st, A);
   hipLaunchKernelGGL(k_union, dim3(sblocks), dim3(256), 0, st, A);
+  // pairwise FM before the flow iterations (one workgroup per pair)
+  if (A.fm_limit > 0) hipLaunchKernelGGL(k_fm, dim3(A.P / A.W), dim3(FM_TPB), 0, st, A);
   const int tpb = c->tune.block_threads;
   const int64_t slots = (int64_t)c->num_cus * c->tune.blocks_per_cu;
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(A.P, slots));
@@ -562,12 +575,14 @@ static void fill_result(const PairState &s, fr_result &r) {
   r.region_edges = s.re_sum;
   if (s.applied > 0) r.status = FR_ACCEPTED;
   else if (s.last_dec == FR_DEC_NOT_ADJACENT) r.status = FR_NOT_ADJACENT;
+  else if (s.fm_kept > 0) r.status = FR_ACCEPTED;  // FM moved vertices, the flow did not
   else if (s.last_dec == FR_DEC_INFEASIBLE) r.status = FR_REJECTED_IMBALANCE;
   else r.status = FR_NO_IMPROVEMENT;
 }
 
 static void collect_stats(fr_context *c, const std::vector<PairState> &ps) {
   int64_t sw = 0, rl = 0, bl = 0, gl = 0, cl = 0, wk[W_COUNT] = {0}, mb[3] = {0, 0, 0};
+  int64_t fm[2] = {0, 0};
   double ph[5] = {0, 0, 0, 0, 0};
   for (const PairState &s : ps) {
     sw += s.sweeps;
@@ -579,6 +594,8 @@ static void collect_stats(fr_context *c, const std::vector<PairState> &ps) {
     mb[0] += s.mb_free;
     mb[1] += s.mb_comp;
     mb[2] += s.mb_limited;
+    fm[0] += s.fm_steps;
+    fm[1] += s.fm_kept;
     ph[0] += s.t_corridor;
     ph[1] += s.t_build;
     ph[2] += s.t_relabel;
@@ -598,6 +615,8 @@ static void collect_stats(fr_context *c, const std::vector<PairState> &ps) {
   c->counters[9] = mb[0];
   c->counters[10] = mb[1];
   c->counters[11] = mb[2];
+  c->counters[12] = fm[0];
+  c->counters[13] = fm[1];
   c->ms[2] = ev[0];
   c->ms[3] = ev[1];
   c->ms[5] = ph[2] / c->wall_khz;
@@ -657,6 +676,15 @@ static int32_t stage(fr_context *c, const fr_graph *g, int32_t *part, int32_t k,
 // allocated on first use.
 static int32_t ensure_mb(fr_context *c, const fr_params *p) {
   DevBufs &d = c->d;
+  if (p->fm_limit > 0 && d.fmcap < d.ncap) {  // FM: gains and queue positions per vertex
+    dfree(d.fmg);
+    dfree(d.fmq);
+    d.fmg = d.fmq = nullptr;
+    d.fmcap = 0;
+    if (dalloc(&d.fmg, d.ncap) != hipSuccess || dalloc(&d.fmq, d.ncap) != hipSuccess)
+      return FR_E_OOM;
+    d.fmcap = d.ncap;
+  }
   if (p->mb_reps <= 0 || d.mbqcap >= d.sacap) return FR_OK;
   dfree(d.mbq);
   d.mbq = nullptr;

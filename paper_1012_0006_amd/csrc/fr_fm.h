@@ -1,0 +1,232 @@
+// 2-way FM local search with TopGain (Sanders & Schulz, Section 2.2; KaPPa's
+// pairwise local search) on the GPU: the pairwise improvement that runs on
+// each pair of a round before its adaptive flow iterations.
+//
+// One workgroup per pair.  The workgroup computes the gains of all vertices
+// of the pair's two blocks at once; the moves themselves are sequential by
+// nature and run in one lane:
+//   - one queue per block: a binary max-heap in the pair's arena ordered by
+//     (gain, key), the key a per-vertex SplitMix64 output, so the order does
+//     not depend on how the heap was built; heap positions (or -1 = not
+//     queued, -2 = moved) and gains live in per-vertex arrays;
+//   - TopGain: the block with the larger top gain moves (a random bit on
+//     ties), the heavier block while one is overloaded;
+//   - after a move, the unmoved neighbours in the pair get their gains
+//     changed by +-2 w and are queued if they were not;
+//   - stop after fm_limit moves without a better state (feasible before
+//     infeasible, then smaller cut, or a lighter heavier block while
+//     infeasible) or when both queues are empty; roll back to the first best
+//     state.
+#pragma once
+#include "fr_kernels.h"
+
+#define FM_TPB 256
+
+__device__ __forceinline__ uint64_t fm_splitmix(uint64_t seed, uint64_t n) {
+  uint64_t z = seed + n * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Addressable binary max-heap of vertex ids over (gain, key).
+struct FMHeap {
+  int32_t *h;        // heap slots
+  int32_t n;
+  int32_t *pos;      // per vertex: slot, -1 not queued, -2 moved
+  const int32_t *gain;
+  uint64_t seed;
+  __device__ __forceinline__ uint64_t key(int32_t v) const {
+    return fm_splitmix(seed, (uint64_t)(uint32_t)v + 1);
+  }
+  // true when u comes before v
+  __device__ __forceinline__ bool above(int32_t u, int32_t v) const {
+    const int32_t gu = gain[u], gv = gain[v];
+    return gu != gv ? gu > gv : key(u) > key(v);
+  }
+  __device__ void up(int32_t i) {
+    const int32_t v = h[i];
+    while (i > 0) {
+      const int32_t pa = (i - 1) >> 1;
+      const int32_t w = h[pa];
+      if (!above(v, w)) break;
+      h[i] = w;
+      pos[w] = i;
+      i = pa;
+    }
+    h[i] = v;
+    pos[v] = i;
+  }
+  __device__ void down(int32_t i) {
+    const int32_t v = h[i];
+    for (;;) {
+      int32_t c = 2 * i + 1;
+      if (c >= n) break;
+      if (c + 1 < n && above(h[c + 1], h[c])) c++;
+      const int32_t w = h[c];
+      if (!above(w, v)) break;
+      h[i] = w;
+      pos[w] = i;
+      i = c;
+    }
+    h[i] = v;
+    pos[v] = i;
+  }
+  __device__ void push(int32_t v) {
+    h[n] = v;
+    pos[v] = n;
+    up(n++);
+  }
+  __device__ int32_t pop() {
+    const int32_t top = h[0];
+    const int32_t last = h[--n];
+    if (n > 0) {
+      h[0] = last;
+      pos[last] = 0;
+      down(0);
+    }
+    return top;
+  }
+  // the key of the vertex in slot i went up (grew) or down
+  __device__ void changed(int32_t i, bool grew) {
+    if (grew) up(i);
+    else down(i);
+  }
+};
+
+__global__ void __launch_bounds__(FM_TPB) k_fm(KArgs A) {
+  __shared__ int32_t s_n[2];
+  __shared__ int64_t s_red[16 * 8];
+  __shared__ int32_t s_bad;
+  const int32_t q = blockIdx.x;  // pair of the round
+  const int32_t v0 = q * A.W;   // its first entry
+  const int32_t a = A.pairs[2 * v0], b = A.pairs[2 * v0 + 1];
+  const int64_t vb = A.voff[v0];
+  const int32_t nv = (int32_t)min<int64_t>(A.ucnt[v0], A.voff[v0 + 1] - vb);
+  const int32_t *uv = A.uvert + vb;
+  int32_t *heapA = A.ex + vb, *heapB = A.LA + vb, *log = A.lab + vb;
+  int32_t *gain = A.fmg, *pos = A.fmq;
+  if (threadIdx.x == 0) {
+    s_n[0] = s_n[1] = 0;
+    s_bad = 0;
+  }
+  __syncthreads();
+  // gains of every vertex of the two blocks; boundary vertices are queued
+  int64_t cut = 0;
+  for (int32_t i = threadIdx.x; i < nv; i += blockDim.x) {
+    const int32_t v = uv[i];
+    const int32_t pv = A.part[v];
+    const int32_t other = pv == a ? b : a;
+    int64_t ext = 0, in = 0;
+    for (int32_t e = A.xadj[v]; e < A.xadj[v + 1]; e++) {
+      const int32_t pu = A.part[A.adjncy[e]];
+      if (pu == other) ext += A.adjwgt[e];
+      else if (pu == pv) in += A.adjwgt[e];
+    }
+    if (ext + in > 0x7fffffffLL) s_bad = 1;  // gains must fit int32
+    gain[v] = (int32_t)(ext - in);
+    pos[v] = -1;
+    if (pv == a) cut += ext;
+    if (ext > 0) {
+      const int side = pv == a ? 0 : 1;
+      const int32_t k = atomicAdd(&s_n[side], 1);
+      (side ? heapB : heapA)[k] = v;
+    }
+  }
+  {
+    int64_t s1[1] = {cut};
+    block_sums<1>(s1, s_red);
+    cut = s1[0];
+  }
+  if (threadIdx.x != 0) return;
+  if (s_bad) {
+    A.ctl->err = FR_E_OVERFLOW;
+    A.ctl->diag = DIAG_FM;
+    return;
+  }
+  const uint64_t seed = (uint64_t)(uint32_t)A.fm_seed;
+  // two named heaps (an array indexed at run time would live in scratch)
+  FMHeap HA{heapA, s_n[0], pos, gain, seed}, HB{heapB, s_n[1], pos, gain, seed};
+  for (int32_t i = 0; i < HA.n; i++) pos[HA.h[i]] = i;
+  for (int32_t i = HA.n / 2 - 1; i >= 0; i--) HA.down(i);
+  for (int32_t i = 0; i < HB.n; i++) pos[HB.h[i]] = i;
+  for (int32_t i = HB.n / 2 - 1; i >= 0; i--) HB.down(i);
+  const int64_t lmax = A.lmax;
+  int64_t wa = A.ps[v0].cA, wb = A.ps[v0].cB;
+  const int64_t cut0 = cut;
+  int best_inf = !(wa <= lmax && wb <= lmax);
+  int64_t best_val = best_inf ? (wa > wb ? wa : wb) : cut;
+  int32_t steps = 0, best_step = 0, since = 0;
+  while (since < A.fm_limit) {
+    const int32_t tA = HA.n > 0 ? HA.h[0] : -1, tB = HB.n > 0 ? HB.h[0] : -1;
+    if (tA < 0 && tB < 0) break;
+    int side;
+    if ((wa > lmax || wb > lmax) && wa != wb) side = wa > wb ? 0 : 1;
+    else if (tA < 0 || tB < 0) side = tA < 0 ? 1 : 0;
+    else if (gain[tA] != gain[tB]) side = gain[tA] > gain[tB] ? 0 : 1;
+    else side = (int)(fm_splitmix(seed, (1ull << 32) + (uint64_t)steps + 1) & 1ull);
+    if ((side ? tB : tA) < 0) side = 1 - side;
+    const int32_t v = side ? HB.pop() : HA.pop();
+    const int32_t from = side ? b : a, to = side ? a : b;
+    A.part[v] = to;
+    pos[v] = -2;
+    cut -= gain[v];
+    const int64_t wv = A.vwgt[v];
+    if (side == 0) {
+      wa -= wv;
+      wb += wv;
+    } else {
+      wb -= wv;
+      wa += wv;
+    }
+    log[steps++] = v;
+    for (int32_t e = A.xadj[v]; e < A.xadj[v + 1]; e++) {
+      const int32_t u = A.adjncy[e];
+      const int32_t pu = A.part[u];
+      if (pu != a && pu != b) continue;
+      const int32_t pq = pos[u];
+      if (pq == -2) continue;
+      const bool grew = pu == from;  // an internal edge of u became a cut edge
+      gain[u] += grew ? 2 * A.adjwgt[e] : -2 * A.adjwgt[e];
+      if (pu == a) {
+        if (pq >= 0) HA.changed(pq, grew);
+        else HA.push(u);
+      } else {
+        if (pq >= 0) HB.changed(pq, grew);
+        else HB.push(u);
+      }
+    }
+    const int inf = !(wa <= lmax && wb <= lmax);
+    const int64_t val = inf ? (wa > wb ? wa : wb) : cut;
+    if (inf < best_inf || (inf == best_inf && val < best_val)) {
+      best_inf = inf;
+      best_val = val;
+      best_step = steps;
+      since = 0;
+    } else {
+      since++;
+    }
+  }
+  // roll back the moves after the best state
+  for (int32_t i = steps - 1; i >= best_step; i--) {
+    const int32_t v = log[i];
+    const int32_t back = A.part[v] == a ? b : a;
+    A.part[v] = back;
+    const int64_t wv = A.vwgt[v];
+    if (back == a) {
+      wa += wv;
+      wb -= wv;
+    } else {
+      wb += wv;
+      wa -= wv;
+    }
+  }
+  for (int32_t s = 0; s < A.W; s++) {
+    PairState &ps = A.ps[v0 + s];
+    ps.cA = wa;
+    ps.cB = wb;
+    ps.cut0 = cut0;
+  }
+  A.ps[v0].fm_steps += steps;
+  A.ps[v0].fm_kept += best_step;
+}

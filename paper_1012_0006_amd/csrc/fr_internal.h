@@ -40,6 +40,8 @@ struct PairState {
   // among them, solves that kept the smallest source set for having more than
   // FR_MB_MAX_COMP components, wall-clock ticks
   int64_t mb_free, mb_comp, mb_limited, t_mb;
+  // 2-way FM before the flow: moves made, moves kept after the rollback
+  int64_t fm_steps, fm_kept;
 };
 
 // work counters: the data each phase of a solve touches
@@ -84,7 +86,7 @@ struct Ctl {
 };
 
 enum { DIAG_NONE = 0, DIAG_LIST = 1, DIAG_CLOSURE = 2, DIAG_REV = 3, DIAG_SWEEPS = 4,
-       DIAG_OVERFLOW = 5, DIAG_MB = 6 };
+       DIAG_OVERFLOW = 5, DIAG_MB = 6, DIAG_FM = 7 };
 
 struct KArgs {
   // graph (device)
@@ -126,6 +128,10 @@ struct KArgs {
   int32_t mb_reps, mb_seed, mb_lds;
   int32_t *mbq;
   int64_t *mpre;            // [P + 1] prefix sums of the entries' free-vertex counts
+  // 2-way FM before the flow: non-improving moves before it stops (0 = off),
+  // key seed, per-vertex gains and queue positions (-1 not queued, -2 moved)
+  int32_t fm_limit, fm_seed;
+  int32_t *fmg, *fmq;
   // per vertex [n]
   int32_t *mark, *vmap;
   // per-pair arenas: vertex slots [voff[p], voff[p+1]), arc slots [aoff[p], aoff[p+1])
