@@ -81,6 +81,16 @@ def test_round_most_balanced_sampled(gpu_lib, ctx, cid):
     _round_vs_oracle(gpu_lib, ctx, w, sample=3, extra=dict(mb_reps=16, mb_seed=1))
 
 
+@pytest.mark.parametrize("cid", ["C3", "C5"])
+def test_round_fm_then_most_balanced_sampled(gpu_lib, ctx, cid):
+    """The largest round of C3 / C5 with 2-way FM before the flow and most
+    balanced cuts, as the benchmark's quality leg runs it."""
+    w = gen.config(cid)
+    print(f"{cid} largest round, FM then most balanced cuts", flush=True)
+    _round_vs_oracle(gpu_lib, ctx, w, sample=3,
+                     extra=dict(fm_limit=100, fm_seed=1, mb_reps=16, mb_seed=1))
+
+
 def test_c5_sweep_properties(gpu_lib, ctx):
     """One full sweep of C5 (every colour class, learned start): the reported
     cut is the cut of the returned partition, it does not grow, and blocks
