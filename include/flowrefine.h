@@ -140,6 +140,12 @@ typedef struct {
    * within the pair must stay below 2^31 (else FR_E_OVERFLOW). */
   int32_t fm_limit;
   int32_t fm_seed;
+  /* Sweeps only (Sec. 4.3, active block scheduling): 1 = every block starts
+   * active, a sweep refines only the pairs with an active block (the colour
+   * classes of the whole quotient graph, filtered) and the blocks of the
+   * pairs it changed (a flow solve applied or FM moves kept) are the active
+   * ones of the next sweep; 0 = every pair every sweep. */
+  int32_t active_blocks;
 } fr_params;
 
 #define FR_MB_MAX_REPS 256
@@ -226,8 +232,10 @@ int32_t fr_quotient_matchings(fr_context *ctx, const fr_graph *g, const int32_t 
 /* Repeated rounds (Sec. 4.3): build and colour the quotient graph, run one
  * batched solve per colour class in colour order (all rounds of a sweep
  * recorded into one hipGraph and launched once), until a sweep changes
- * nothing or max_sweeps sweeps ran.  stats (optional, host int64 [4]): sweeps, flow
- * solves, pairs with an applied change, region edges.  total_cut_out: the cut
+ * nothing or max_sweeps sweeps ran (p->active_blocks: only pairs with a block
+ * changed in the previous sweep).  stats (optional, host int64 [4]): sweeps,
+ * flow solves, changed pairs (a flow solve applied or FM moves kept), region
+ * edges.  total_cut_out: the cut
  * sum_{i<j} omega(E_ij) after the sweep. */
 int32_t flow_refine_sweep(fr_context *ctx, const fr_graph *g, int32_t *part, int32_t k,
                           const fr_params *p, int32_t max_sweeps, int64_t *total_cut_out,

@@ -80,6 +80,7 @@ typedef struct {
   int32_t fm_limit; /* 0: no FM; > 0: 2-way FM before the flow, stop after this many moves
                        without improvement */
   int32_t fm_seed;  /* seed of the FM keys and tie bits (its 32 bits, zero-extended) */
+  int32_t active_blocks; /* sweeps: refine only pairs with a block changed in the previous sweep */
 } or_params;
 
 /* one flow solve */
@@ -1116,9 +1117,14 @@ int64_t or_total_cut(const or_graph *g, const int32_t *part) {
 }
 
 /* Refinement sweep: build and colour the quotient graph, refine the pairs of
- * each colour class in colour order, repeat until a sweep applies nothing or
- * max_sweeps is reached.  Returns 0; stats[0] = sweeps run, stats[1] = flow
- * solves, stats[2] = pairs with an applied change, stats[3] = region edges. */
+ * each colour class in colour order, repeat until a sweep changes nothing or
+ * max_sweeps is reached.  With active_blocks (Sec. 4.3, active block
+ * scheduling): every block starts active; a sweep refines only the pairs with
+ * an active block (the colour classes of the whole quotient graph, filtered),
+ * and the blocks of the pairs it changed are the active ones of the next
+ * sweep.  A pair changed when a flow solve or its FM pass changed the
+ * partition.  Returns 0; stats[0] = sweeps run, stats[1] = flow solves,
+ * stats[2] = changed pairs, stats[3] = region edges. */
 int32_t or_sweep(const or_graph *g, int32_t *part, int32_t k, const or_params *p,
                  int32_t max_sweeps, int64_t *total_cut_out, int64_t *stats) {
   int32_t maxe = k * (k - 1) / 2 + 1;
@@ -1126,7 +1132,12 @@ int32_t or_sweep(const or_graph *g, int32_t *part, int32_t k, const or_params *p
   int32_t *colour = (int32_t *)malloc(sizeof(int32_t) * (size_t)maxe);
   int32_t *pairs = (int32_t *)malloc(sizeof(int32_t) * 2 * (size_t)maxe);
   or_result *res = (or_result *)malloc(sizeof(or_result) * (size_t)maxe);
-  if (!edges || !colour || !pairs || !res) { free(edges); free(colour); free(pairs); free(res); return -7; }
+  uint8_t *act = (uint8_t *)malloc((size_t)k), *nact = (uint8_t *)malloc((size_t)k);
+  if (!edges || !colour || !pairs || !res || !act || !nact) {
+    free(edges); free(colour); free(pairs); free(res); free(act); free(nact);
+    return -7;
+  }
+  memset(act, 1, (size_t)k);
   memset(stats, 0, sizeof(int64_t) * 4);
   int32_t rc = 0;
   for (int32_t s = 0; s < max_sweeps; s++) {
@@ -1135,25 +1146,35 @@ int32_t or_sweep(const or_graph *g, int32_t *part, int32_t k, const or_params *p
     int32_t ncol = 0;
     for (int32_t i = 0; i < ne; i++) if (colour[i] + 1 > ncol) ncol = colour[i] + 1;
     int64_t changed = 0;
+    memset(nact, 0, (size_t)k);
     for (int32_t c = 0; c < ncol; c++) {
       int32_t np = 0;
       for (int32_t i = 0; i < ne; i++)
-        if (colour[i] == c) { pairs[2 * np] = edges[2 * i]; pairs[2 * np + 1] = edges[2 * i + 1]; np++; }
+        if (colour[i] == c && (!p->active_blocks || act[edges[2 * i]] || act[edges[2 * i + 1]])) {
+          pairs[2 * np] = edges[2 * i];
+          pairs[2 * np + 1] = edges[2 * i + 1];
+          np++;
+        }
+      if (np == 0) continue;
       rc = or_refine_batch(g, part, k, pairs, np, p, res, NULL);
       if (rc != 0) break;
       for (int32_t i = 0; i < np; i++) {
         stats[1] += res[i].iters;
         stats[3] += res[i].region_edges;
-        if (res[i].applied) changed++;
+        if (res[i].status == ST_ACCEPTED) {
+          changed++;
+          nact[pairs[2 * i]] = nact[pairs[2 * i + 1]] = 1;
+        }
       }
     }
     if (rc != 0) break;
     stats[0]++;
     stats[2] += changed;
     if (changed == 0) break;
+    memcpy(act, nact, (size_t)k);
   }
   *total_cut_out = or_total_cut(g, part);
-  free(edges); free(colour); free(pairs); free(res);
+  free(edges); free(colour); free(pairs); free(res); free(act); free(nact);
   return rc;
 }
 

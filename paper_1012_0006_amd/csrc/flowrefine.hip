@@ -918,8 +918,20 @@ extern "C" int32_t flow_refine_sweep(fr_context *c, const fr_graph *g, int32_t *
   int64_t acc[4] = {0, 0, 0, 0};
   std::vector<int32_t> e, col, pairs, offs;
   std::vector<PairState> ps;
+  std::vector<uint8_t> active((size_t)k, 1);  // active block scheduling (Sec. 4.3)
   for (int32_t sw = 0; sw < max_sweeps; sw++) {
     if ((rc = quotient_dev(c, &s.g, work, k, e, col))) return rc;
+    if (p->active_blocks) {  // keep the quotient edges with an active block
+      size_t m = 0;
+      for (size_t i = 0; i < col.size(); i++)
+        if (active[(size_t)e[2 * i]] || active[(size_t)e[2 * i + 1]]) {
+          e[2 * m] = e[2 * i];
+          e[2 * m + 1] = e[2 * i + 1];
+          col[m++] = col[i];
+        }
+      e.resize(2 * m);
+      col.resize(m);
+    }
     int32_t ncol = 0;
     for (int32_t x : col) ncol = std::max(ncol, x + 1);
     std::vector<int32_t> per_class((size_t)ncol, 0);
@@ -989,11 +1001,15 @@ extern "C" int32_t flow_refine_sweep(fr_context *c, const fr_graph *g, int32_t *
     HIPCHK(hipMemcpyAsync(ps.data(), d.ps, sizeof(PairState) * total, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     int64_t changed = 0;
+    std::fill(active.begin(), active.end(), 0);
     for (int64_t i = 0; i < total; i += W) {  // the pair's record is its first entry
       const PairState &q = ps[(size_t)i];
       acc[1] += q.iters;
       acc[3] += q.re_sum;
-      if (q.applied) changed++;
+      if (q.applied || q.fm_kept) {  // the partition changed (flow or FM)
+        changed++;
+        active[(size_t)pairs[2 * i]] = active[(size_t)pairs[2 * i + 1]] = 1;
+      }
     }
     acc[0]++;
     acc[2] += changed;

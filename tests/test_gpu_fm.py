@@ -14,7 +14,7 @@ from tests.test_gpu_parity import RESULT_KEYS
 pytestmark = pytest.mark.gpu
 
 PKEYS = ("area_mode", "depth", "alpha", "alpha_max", "adaptive", "max_iters", "eps_ppm",
-         "mb_reps", "mb_seed", "fm_limit", "fm_seed")
+         "mb_reps", "mb_seed", "fm_limit", "fm_seed", "active_blocks")
 
 
 def _prm(fr, d):
@@ -164,3 +164,22 @@ def test_rejects_negative_limit(gpu_lib, ctx):
     part = np.array([0, 0, 1, 1], dtype=np.int32)
     with pytest.raises(gpu_lib.FlowRefineError):
         gpu_lib.flow_refine_pair(ctx, g, part, 2, 0, 1, gpu_lib.params(fm_limit=-1))
+
+
+@pytest.mark.parametrize("fm", [0, 50])
+def test_sweep_active_blocks(gpu_lib, ctx, fm):
+    import torch
+
+    g = gen.rgg(1 << 14, 2, 7.0, 93, 1, 1)
+    part = gen.rcb(g, 16)
+    gen.global_noise(g, part, 0.03, 93)
+    p = dict(area_mode=0, depth=0, alpha=16, alpha_max=16, adaptive=1, max_iters=16,
+             eps_ppm=30000, fm_limit=fm, fm_seed=93, active_blocks=1)
+    rc, tc, stats, opart = oracle.sweep(g, part, 16, p, max_sweeps=8)
+    assert rc == 0
+    dpart = torch.as_tensor(part.copy()).cuda()
+    tc_gpu, st_gpu = gpu_lib.flow_refine_sweep(ctx, gpu_lib.DeviceGraph.from_host(g), dpart, 16,
+                                               _prm(gpu_lib, p), 8)
+    assert tc_gpu == tc
+    assert st_gpu.tolist() == stats.tolist()
+    assert np.array_equal(dpart.cpu().numpy(), opart)

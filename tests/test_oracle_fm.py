@@ -187,3 +187,54 @@ def test_fm_off_and_pair_level():
     fpart, finfo, _ = oracle.pair_fm(g, part, 2, 0, 1, 30000, 50, 2)
     assert fm.trace[0]["cut_before"] == finfo["cut_after"]
     assert fm.result["cut_after"] == oracle.total_cut(g, fm.part)
+
+
+# ------------------------------------------------- active block scheduling --
+
+def _active_sweeps(g, part, k, p, max_sweeps):
+    """Active block scheduling (Sec. 4.3) written out over the oracle's
+    quotient colouring and batch refinement: every block starts active; a
+    sweep refines, class by class, the pairs with an active block; the blocks
+    of the pairs it changed are the next sweep's active ones."""
+    part = part.copy()
+    active = np.ones(k, dtype=bool)
+    solves = changed_pairs = sweeps = 0
+    for _ in range(max_sweeps):
+        edges, colour = oracle.quotient_colouring(g, part, k)
+        nxt = np.zeros(k, dtype=bool)
+        changed = 0
+        for c in sorted(set(colour.tolist())):
+            pairs = [tuple(e) for e, cc in zip(edges.tolist(), colour.tolist())
+                     if cc == c and (active[e[0]] or active[e[1]])]
+            if not pairs:
+                continue
+            rc, res, _, part = oracle.refine_batch(g, part, k, pairs, p)
+            assert rc == 0
+            for (a, b), r in zip(pairs, res):
+                solves += r["iters"]
+                if r["status"] == oracle.ST_ACCEPTED:
+                    changed += 1
+                    nxt[a] = nxt[b] = True
+        sweeps += 1
+        changed_pairs += changed
+        if changed == 0:
+            break
+        active = nxt
+    return part, sweeps, solves, changed_pairs
+
+
+@pytest.mark.parametrize("fm", [0, 30])
+def test_active_block_sweeps(fm):
+    g = gen.rgg(1 << 13, 2, 7.0, 17, 1, 1)
+    part = gen.rcb(g, 16)
+    gen.global_noise(g, part, 0.03, 17)
+    p = dict(area_mode=0, depth=0, alpha=8, alpha_max=8, adaptive=1, max_iters=8,
+             eps_ppm=30000, fm_limit=fm, fm_seed=4, active_blocks=1)
+    want, sweeps, solves, changed = _active_sweeps(g, part, 16, p, 6)
+    rc, tc, stats, got = oracle.sweep(g, part, 16, p, max_sweeps=6)
+    assert rc == 0 and np.array_equal(got, want)
+    assert stats[0] == sweeps and stats[1] == solves and stats[2] == changed
+    # the first sweep refines every pair, as without active blocks
+    rc1, _, s1, p1 = oracle.sweep(g, part, 16, p, max_sweeps=1)
+    rc2, _, s2, p2 = oracle.sweep(g, part, 16, dict(p, active_blocks=0), max_sweeps=1)
+    assert np.array_equal(p1, p2) and s1.tolist() == s2.tolist()
