@@ -300,8 +300,9 @@ def run_balanced(args, fr, torch, gen):
     degree 6, unit weights, k=256 RCB + 1 % noise): most balanced minimum cuts
     (Sec. 4.1.1, 16 sweeps) and 2-way FM with TopGain before the flow
     (Sec. 2.2, stop after 100 moves without improvement), alone and together,
-    against the plain flow: the largest matching round batched, then whole
-    refinement sweeps until no pair improves, for time and the cut reached."""
+    and together with active block scheduling (Sec. 4.3), against the plain
+    flow: the largest matching round batched, then whole refinement sweeps
+    until no pair improves, for time and the cut reached."""
     import oracle  # cut accounting only
 
     w = gen.config("C5")
@@ -322,7 +323,9 @@ def run_balanced(args, fr, torch, gen):
                 ("most_balanced", {"mb_reps": 16, "mb_seed": 1}),
                 ("fm_then_flow", {"fm_limit": 100, "fm_seed": 1}),
                 ("fm_then_most_balanced", {"fm_limit": 100, "fm_seed": 1, "mb_reps": 16,
-                                           "mb_seed": 1}))
+                                           "mb_seed": 1}),
+                ("fm_then_most_balanced_active", {"fm_limit": 100, "fm_seed": 1, "mb_reps": 16,
+                                                  "mb_seed": 1, "active_blocks": 1}))
     for name, extra in variants:
         prm = fr.params(**base, **extra)
         dpart = part0.clone()

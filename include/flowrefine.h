@@ -146,6 +146,13 @@ typedef struct {
    * pairs it changed (a flow solve applied or FM moves kept) are the active
    * ones of the next sweep; 0 = every pair every sweep. */
   int32_t active_blocks;
+  /* Candidate cut without most balanced cuts (mb_reps = 0; with them the
+   * sweeps already include both): 0 = the smallest source set (Sec. 4.1.1);
+   * 1 = the largest minimum source side, every corridor vertex that cannot
+   * reach t in the residual graph; 2 = the smallest, or the largest when the
+   * smallest breaks L_max and the largest does not.  Both have the minimum
+   * cut's value, so only the balance differs. */
+  int32_t cut_side;
 } fr_params;
 
 #define FR_MB_MAX_REPS 256

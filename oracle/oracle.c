@@ -81,6 +81,8 @@ typedef struct {
                        without improvement */
   int32_t fm_seed;  /* seed of the FM keys and tie bits (its 32 bits, zero-extended) */
   int32_t active_blocks; /* sweeps: refine only pairs with a block changed in the previous sweep */
+  int32_t cut_side; /* without mb_reps: 0 smallest source set, 1 largest, 2 the smallest unless
+                       it is infeasible and the largest is feasible */
 } or_params;
 
 /* one flow solve */
@@ -260,6 +262,23 @@ static int64_t net_dinic(or_net *N, int32_t s, int32_t t) {
 done:
   free(level); free(queue); free(it); free(path);
   return flow;
+}
+
+/* T-side closure: reach[v] = 1 iff t is reachable from v over arcs with
+ * positive residual (a BFS from t over the reverses of residual arcs) */
+static void net_reach_to(const or_net *N, int32_t t, uint8_t *reach, int32_t *queue) {
+  memset(reach, 0, (size_t)N->nn);
+  int32_t qh = 0, qt = 0;
+  reach[t] = 1;
+  queue[qt++] = t;
+  while (qh < qt) {
+    int32_t w = queue[qh++];
+    for (int64_t j = N->off[w]; j < N->off[w + 1]; j++) {
+      int64_t a = N->byt[j] ^ 1; /* the arc v -> w */
+      int32_t v = N->tail[a];
+      if (N->res[a] > 0 && !reach[v]) { reach[v] = 1; queue[qt++] = v; }
+    }
+  }
 }
 
 /* reach[v] = 1 iff v is reachable from s over arcs with positive residual */
@@ -800,6 +819,28 @@ static int32_t solve_once(const or_graph *g, int32_t *part, int32_t k, int32_t a
     free(w);
     free(gid);
     if (mrc != 0) { free(reach); free(queue); net_free(&N); goto oom; }
+  } else if (p->cut_side != 0) {
+    /* the largest minimum source side: every node that cannot reach t
+     * (Sec. 4.1.1: the closed sets between the two closures are the minimum
+     * cuts); cut_side 2 takes it only when the smallest source set is
+     * infeasible and it is feasible */
+    uint8_t *tr = (uint8_t *)malloc((size_t)nb + 2);
+    if (!tr) { free(reach); free(queue); net_free(&N); goto oom; }
+    net_reach_to(&N, T, tr, queue);
+    int64_t wa1 = cA, wb1 = cB, wa2 = cA, wb2 = cB;
+    for (int32_t u = 0; u < n; u++) {
+      if (!inB[u]) continue;
+      int in1 = reach[loc[u]], in2 = !tr[loc[u]];
+      if (inB[u] == 1 && !in1) { wa1 -= g->vwgt[u]; wb1 += g->vwgt[u]; }
+      if (inB[u] == 2 && in1) { wb1 -= g->vwgt[u]; wa1 += g->vwgt[u]; }
+      if (inB[u] == 1 && !in2) { wa2 -= g->vwgt[u]; wb2 += g->vwgt[u]; }
+      if (inB[u] == 2 && in2) { wb2 -= g->vwgt[u]; wa2 += g->vwgt[u]; }
+    }
+    int take = p->cut_side == 1 ||
+               (!(wa1 <= lmax && wb1 <= lmax) && (wa2 <= lmax && wb2 <= lmax));
+    if (take)
+      for (int32_t v = 0; v < nb + 2; v++) reach[v] = (uint8_t)!tr[v];
+    free(tr);
   }
 
   /* candidate: corridor vertex -> a iff on the source side of the cut */
@@ -984,7 +1025,7 @@ int32_t or_refine_pair(const or_graph *g, int32_t *part, int32_t k, int32_t a, i
   if (a < 0 || b < 0 || a >= k || b >= k || a == b) return -3;
   if (p->alpha < 1 || p->alpha_max < 1 || p->max_iters < 1 || p->eps_ppm < 0 ||
       (p->area_mode != 0 && p->area_mode != 1) || p->depth < 0 || p->mb_reps < 0 ||
-      p->fm_limit < 0)
+      p->fm_limit < 0 || p->cut_side < 0 || p->cut_side > 2)
     return -8;
   int64_t w_a = 0, w_b = 0;
   for (int32_t u = 0; u < g->n; u++) {

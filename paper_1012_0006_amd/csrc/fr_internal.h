@@ -132,6 +132,9 @@ struct KArgs {
   // key seed, per-vertex gains and queue positions (-1 not queued, -2 moved)
   int32_t fm_limit, fm_seed;
   int32_t *fmg, *fmq;
+  // candidate without the most balanced cut: 0 smallest source set, 1 largest,
+  // 2 the largest only when the smallest is infeasible and it is feasible
+  int32_t cut_side;
   // per vertex [n]
   int32_t *mark, *vmap;
   // per-pair arenas: vertex slots [voff[p], voff[p+1]), arc slots [aoff[p], aoff[p+1])

@@ -353,6 +353,7 @@ struct SolveShared {
   unsigned long long work[W_COUNT];
   int32_t cnt[3];                 // rotating list counters
   int32_t nfree;                  // free vertices listed for the most balanced cut
+  int32_t use_max;                // the candidate is the largest minimum source side
   int32_t nr;                     // corridor size
   int32_t nsnk;                   // sink-border vertices
   int32_t pair;                   // queue slot
@@ -1552,8 +1553,11 @@ __global__ void __launch_bounds__(TPB) k_flow(KArgs A, int32_t it) {
     //      balanced cut, also the free vertices (neither in the smallest
     //      source set nor able to reach the sink: exact label NL), listed in
     //      LB with LA[i] = i for them and -1 for every other corridor vertex
-    int64_t acc[4] = {0, 0, 0, 0};  // flow, moved a->b, moved b->a, source side
+    // flow, moved a->b, moved b->a, source side; the same three for the
+    // largest minimum source side (label >= NL: cannot reach the sink)
+    int64_t acc[7] = {0, 0, 0, 0, 0, 0, 0};
     const bool mb = A.mb_reps > 0 && !overflow;
+    const int side_mode = (A.mb_reps > 0 || overflow) ? 0 : A.cut_side;
     if (mb) {
       if (threadIdx.x == 0) sh.nfree = 0;
       __syncthreads();
@@ -1573,6 +1577,12 @@ __global__ void __launch_bounds__(TPB) k_flow(KArgs A, int32_t it) {
           if (!(f & LF_SIDE_B) && !in) acc[1] += w;
           if ((f & LF_SIDE_B) && in) acc[2] += w;
           acc[3] += in ? 1 : 0;
+          if (side_mode) {
+            const bool inx = V.lab[i] >= NL;
+            if (!(f & LF_SIDE_B) && !inx) acc[4] += w;
+            if ((f & LF_SIDE_B) && inx) acc[5] += w;
+            acc[6] += inx ? 1 : 0;
+          }
           if (mb) {
             fv = !in && !(f & LF_BORDER) && V.lab[i] == NL;
             V.LA[i] = fv ? (int32_t)i : -1;
@@ -1584,7 +1594,7 @@ __global__ void __launch_bounds__(TPB) k_flow(KArgs A, int32_t it) {
         }
       }
     }
-    block_sums<4>(acc, sh.red);
+    block_sums<7>(acc, sh.red);
     // the record of this solve; the adaptive rule and the write-back run in
     // k_select, over all slots of the pair
     if (threadIdx.x == 0) {
@@ -1607,6 +1617,17 @@ __global__ void __launch_bounds__(TPB) k_flow(KArgs A, int32_t it) {
       int64_t cand = cut - pa[PA_RCIN] + acc[0];
       int64_t wa = st.cA - acc[1] + acc[2];
       int64_t wb = st.cB + acc[1] - acc[2];
+      sh.use_max = 0;
+      if (side_mode && cut != 0) {  // the largest minimum source side instead
+        const int64_t wa2 = st.cA - acc[4] + acc[5], wb2 = st.cB + acc[4] - acc[5];
+        const bool f1 = wa <= A.lmax && wb <= A.lmax, f2 = wa2 <= A.lmax && wb2 <= A.lmax;
+        if (side_mode == 1 || (!f1 && f2)) {
+          sh.use_max = 1;
+          wa = wa2;
+          wb = wb2;
+          rec.source_side = acc[6];
+        }
+      }
       int dec;
       if (cut == 0) {
         dec = FR_DEC_NOT_ADJACENT;
@@ -1630,6 +1651,12 @@ __global__ void __launch_bounds__(TPB) k_flow(KArgs A, int32_t it) {
       A.ps[p] = st;
     }
     __syncthreads();
+    if (sh.use_max) {  // the source side becomes every vertex that cannot reach the sink
+      BLOCK_WAVE_LOOP(i, nr) {
+        if (i < nr) V.ins[i] = V.lab[i] >= NL ? 1 : 0;
+      }
+      __syncthreads();
+    }
   }
 }
 

@@ -15,7 +15,7 @@ from tests.test_gpu_parity import RESULT_KEYS
 pytestmark = pytest.mark.gpu
 
 PKEYS = ("area_mode", "depth", "alpha", "alpha_max", "adaptive", "max_iters", "eps_ppm",
-         "mb_reps", "mb_seed")
+         "mb_reps", "mb_seed", "cut_side")
 
 
 def _prm(fr, d):
@@ -211,3 +211,44 @@ def test_rejects_too_many_sweeps(gpu_lib, ctx):
     part = ((np.arange(20) % 10) >= 5).astype(np.int32)
     with pytest.raises(gpu_lib.FlowRefineError):
         gpu_lib.flow_refine_pair(ctx, g, part, 2, 0, 1, gpu_lib.params(mb_reps=257))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_largest_source_side_candidates(gpu_lib, ctx, seed):
+    """cut_side 1 (the largest minimum source side) and 2 (the largest only
+    when the smallest is infeasible and it is feasible) against the oracle."""
+    rng = np.random.default_rng(1500 + seed)
+    if seed < 6:
+        n = int(rng.integers(8, 50))
+        g = random_graph(n, 0.2, 1500 + seed, wmax=3, vwmax=int(rng.choice([1, 4])))
+        part = (rng.random(n) < 0.5).astype(np.int32)
+        part[0], part[1] = 0, 1
+    else:
+        g = gen.rgg(1 << 13, 2, 7.0, 1500 + seed, 1, int(rng.choice([1, 5])))
+        part = gen.rcb(g, 2, force_axis=0)
+        gen.pair_swap_noise(g, part, 0.03, seed)
+    p = dict(area_mode=0, depth=0, alpha=16, alpha_max=16, adaptive=1, max_iters=8,
+             eps_ppm=int(rng.choice([30000, 300000])), cut_side=1 + seed % 2)
+    _compare(gpu_lib, ctx, g, part, 2, 0, 1, p)
+
+
+def test_largest_source_side_batch(gpu_lib, ctx):
+    import torch
+
+    g = gen.rgg(1 << 15, 2, 8.0, seed=64, wlo=1, whi=1)
+    part = gen.rcb(g, 16)
+    gen.global_noise(g, part, 0.02, 64)
+    edges, colour = oracle.quotient_colouring(g, part, 16)
+    pairs = [tuple(e) for e, cc in zip(edges.tolist(), colour) if cc == 0]
+    p = dict(area_mode=0, depth=0, alpha=16, alpha_max=16, adaptive=1, max_iters=16,
+             eps_ppm=30000, cut_side=2)
+    rc, ores, otr, opart = oracle.refine_batch(g, part, 16, pairs, p)
+    assert rc == 0
+    dpart = torch.as_tensor(part.copy()).cuda()
+    res, trace = gpu_lib.flow_refine_batch(ctx, gpu_lib.DeviceGraph.from_host(g), dpart, 16,
+                                           pairs, _prm(gpu_lib, p))
+    for i in range(len(pairs)):
+        for key in RESULT_KEYS:
+            assert res[i][key] == ores[i][key], (i, key)
+        assert trace[i] == otr[i]
+    assert np.array_equal(dpart.cpu().numpy(), opart)

@@ -267,3 +267,48 @@ def test_pair_solve_balance_not_worse_than_smallest_source_set(seed):
     for key in ("flow", "region_vertices", "region_edges", "cut_candidate", "cut_before"):
         assert ta[key] == tb[key], key
     assert max(tb["wa"], tb["wb"]) <= max(ta["wa"], ta["wb"])
+
+
+# ------------------------------------ the largest minimum source side --
+
+@pytest.mark.parametrize("seed", range(20))
+def test_largest_source_side_is_the_union_of_minimum_source_sides(seed):
+    """cut_side = 1: the candidate is every corridor vertex that cannot reach
+    t, which brute force finds as the union of all minimum source sides of
+    the corridor network; cut_side = 2 takes it only when the smallest source
+    set is infeasible and it is feasible."""
+    from tests.helpers import area_bound, corridor_by_sorting, l_max, pair_network, random_graph
+
+    rng = np.random.default_rng(2000 + seed)
+    n = int(rng.integers(8, 18))
+    g = random_graph(n, 0.3, 2000 + seed, wmax=3, vwmax=int(rng.choice([1, 4])))
+    part = (rng.random(n) < 0.5).astype(np.int32)
+    part[0], part[1] = 0, 1
+    eps = int(rng.choice([30000, 300000, 1000000]))
+    p = dict(area_mode=0, depth=0, alpha=4, alpha_max=4, adaptive=0, max_iters=1, eps_ppm=eps)
+    ua = area_bound(g, part, 2, 1, 4, eps)
+    ub = area_bound(g, part, 2, 0, 4, eps)
+    in_a = corridor_by_sorting(g, part, 0, 1, 0, 0, ua)
+    in_b = corridor_by_sorting(g, part, 1, 0, 0, 0, ub)
+    nn, arcs, s, t, verts, border = pair_network(g, part, 0, 1, in_a, in_b)
+    side, cap = _all_cuts(nn, arcs, s, t)
+    mins = side[cap == cap.min()]
+    union, inter = mins.any(axis=0), mins.all(axis=0)
+    lmax = l_max(g, 2, eps)
+
+    def weights(src):
+        new = part.copy()
+        for i, u in enumerate(verts):
+            new[u] = 0 if src[i] else 1
+        return int(g.vwgt[new == 0].sum()), int(g.vwgt[new == 1].sum()), new
+
+    o1 = oracle.refine_pair(g, part.copy(), 2, 0, 1, dict(p, cut_side=1))
+    got = np.array([o1.side[u] in (0, 2) for u in verts], dtype=bool)
+    assert np.array_equal(got, union[: len(verts)])
+    assert (o1.trace[0]["wa"], o1.trace[0]["wb"]) == weights(union)[:2]
+    o2 = oracle.refine_pair(g, part.copy(), 2, 0, 1, dict(p, cut_side=2))
+    w1, w2 = weights(inter)[:2], weights(union)[:2]
+    feas = lambda w: max(w) <= lmax
+    want = union if (not feas(w1) and feas(w2)) else inter
+    got2 = np.array([o2.side[u] in (0, 2) for u in verts], dtype=bool)
+    assert np.array_equal(got2, want[: len(verts)])
