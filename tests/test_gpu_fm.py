@@ -14,10 +14,12 @@ from tests.test_gpu_parity import RESULT_KEYS
 pytestmark = pytest.mark.gpu
 
 PKEYS = ("area_mode", "depth", "alpha", "alpha_max", "adaptive", "max_iters", "eps_ppm",
-         "mb_reps", "mb_seed", "fm_limit", "fm_seed", "active_blocks")
+         "mb_reps", "mb_seed", "fm_limit", "fm_seed", "active_blocks", "cut_side")
 
 
 def _prm(fr, d):
+    unknown = set(d) - set(PKEYS)
+    assert not unknown, unknown  # every oracle parameter must reach the library too
     return fr.params(**{k: d[k] for k in PKEYS if k in d})
 
 
@@ -183,3 +185,57 @@ def test_sweep_active_blocks(gpu_lib, ctx, fm):
     assert tc_gpu == tc
     assert st_gpu.tolist() == stats.tolist()
     assert np.array_equal(dpart.cpu().numpy(), opart)
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_random_rounds_all_options(gpu_lib, seed):
+    """Randomised whole rounds mixing every option: most balanced cuts, FM
+    before the flow, the candidate side, speculation, weights and k; and a
+    short sweep with active blocks on every fourth seed."""
+    import torch
+
+    rng = np.random.default_rng(3100 + seed)
+    dim = int(rng.choice([2, 3]))
+    n = int(rng.choice([1 << 11, 1 << 12, 1 << 13]))
+    whi = int(rng.choice([1, 1, 4, 10]))
+    g = gen.rgg(n, dim, 8.0 if dim == 2 else 11.0, 3100 + seed, 1, whi)
+    k = int(rng.choice([2, 4, 8, 16]))
+    part = gen.rcb(g, k)
+    gen.global_noise(g, part, float(rng.choice([0.01, 0.03, 0.06])), seed)
+    amax = int(rng.choice([1, 3, 8, 16]))
+    mb = int(rng.choice([0, 0, 1, 5, 17]))
+    p = dict(area_mode=0, depth=0, alpha=int(rng.integers(1, amax + 1)), alpha_max=amax,
+             adaptive=int(rng.integers(0, 2)), max_iters=int(rng.integers(1, 12)),
+             eps_ppm=int(rng.choice([0, 30000, 100000])), mb_reps=mb,
+             mb_seed=int(rng.integers(0, 2**32)), fm_limit=int(rng.choice([0, 0, 5, 60, 300])),
+             fm_seed=int(rng.integers(0, 2**32)), cut_side=int(rng.integers(0, 3)))
+    c = gpu_lib.Context()
+    try:
+        c.set_speculation(bool(rng.integers(0, 2)))
+        c.set_validation(bool(rng.integers(0, 2)))
+        dg = gpu_lib.DeviceGraph.from_host(g)
+        if seed % 4 == 3:
+            p["active_blocks"] = 1
+            print(f"sweep seed={seed} n={n} k={k} params={p}", flush=True)
+            rc, tc, stats, opart = oracle.sweep(g, part, k, p, max_sweeps=3)
+            assert rc == 0
+            dpart = torch.as_tensor(part.copy()).cuda()
+            tc_gpu, st_gpu = gpu_lib.flow_refine_sweep(c, dg, dpart, k, _prm(gpu_lib, p), 3)
+            assert tc_gpu == tc and st_gpu.tolist() == stats.tolist()
+            assert np.array_equal(dpart.cpu().numpy(), opart)
+            return
+        edges, colour = oracle.quotient_colouring(g, part, k)
+        cls = int(rng.integers(0, colour.max() + 1))
+        pairs = [tuple(e) for e, cc in zip(edges.tolist(), colour) if cc == cls]
+        print(f"round seed={seed} n={n} k={k} pairs={len(pairs)} params={p}", flush=True)
+        rc, ores, otr, opart = oracle.refine_batch(g, part, k, pairs, p)
+        assert rc == 0
+        dpart = torch.as_tensor(part.copy()).cuda()
+        res, trace = gpu_lib.flow_refine_batch(c, dg, dpart, k, pairs, _prm(gpu_lib, p))
+        for i in range(len(pairs)):
+            for key in RESULT_KEYS:
+                assert res[i][key] == ores[i][key], (i, key)
+            assert trace[i] == otr[i]
+        assert np.array_equal(dpart.cpu().numpy(), opart)
+    finally:
+        c.close()

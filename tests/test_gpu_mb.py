@@ -19,6 +19,8 @@ PKEYS = ("area_mode", "depth", "alpha", "alpha_max", "adaptive", "max_iters", "e
 
 
 def _prm(fr, d):
+    unknown = set(d) - set(PKEYS)
+    assert not unknown, unknown  # every oracle parameter must reach the library too
     return fr.params(**{k: d[k] for k in PKEYS if k in d})
 
 
