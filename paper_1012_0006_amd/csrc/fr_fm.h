@@ -4,7 +4,8 @@
 //
 // One workgroup per pair.  The workgroup computes the gains of all vertices
 // of the pair's two blocks at once; the moves themselves are sequential by
-// nature and run in one lane:
+// nature: lane 0 makes every decision and heap update, the rest of its wave
+// fetches each moved vertex's neighbourhood at once:
 //   - one queue per block: a binary max-heap in the pair's arena ordered by
 //     (gain, key), the key a per-vertex SplitMix64 output, so the order does
 //     not depend on how the heap was built; heap positions (or -1 = not
@@ -29,66 +30,82 @@ __device__ __forceinline__ uint64_t fm_splitmix(uint64_t seed, uint64_t n) {
   return z ^ (z >> 31);
 }
 
-// Addressable binary max-heap of vertex ids over (gain, key).
+// Addressable binary max-heap of vertex ids over (gain, key).  Each slot
+// keeps its vertex's gain beside the id (hv, hg), so a level of a sift is
+// one round of independent loads.
 struct FMHeap {
-  int32_t *h;        // heap slots
+  int32_t *hv;       // heap slots: vertex
+  int32_t *hg;       // heap slots: its gain
   int32_t n;
   int32_t *pos;      // per vertex: slot, -1 not queued, -2 moved
-  const int32_t *gain;
   uint64_t seed;
   __device__ __forceinline__ uint64_t key(int32_t v) const {
     return fm_splitmix(seed, (uint64_t)(uint32_t)v + 1);
   }
-  // true when u comes before v
-  __device__ __forceinline__ bool above(int32_t u, int32_t v) const {
-    const int32_t gu = gain[u], gv = gain[v];
+  // true when (gu, u) comes before (gv, v)
+  __device__ __forceinline__ bool above(int32_t gu, int32_t u, int32_t gv, int32_t v) const {
     return gu != gv ? gu > gv : key(u) > key(v);
   }
   __device__ void up(int32_t i) {
-    const int32_t v = h[i];
+    const int32_t v = hv[i], gv = hg[i];
     while (i > 0) {
       const int32_t pa = (i - 1) >> 1;
-      const int32_t w = h[pa];
-      if (!above(v, w)) break;
-      h[i] = w;
+      const int32_t w = hv[pa], gw = hg[pa];
+      if (!above(gv, v, gw, w)) break;
+      hv[i] = w;
+      hg[i] = gw;
       pos[w] = i;
       i = pa;
     }
-    h[i] = v;
+    hv[i] = v;
+    hg[i] = gv;
     pos[v] = i;
   }
   __device__ void down(int32_t i) {
-    const int32_t v = h[i];
+    const int32_t v = hv[i], gv = hg[i];
     for (;;) {
       int32_t c = 2 * i + 1;
       if (c >= n) break;
-      if (c + 1 < n && above(h[c + 1], h[c])) c++;
-      const int32_t w = h[c];
-      if (!above(w, v)) break;
-      h[i] = w;
+      int32_t w = hv[c], gw = hg[c];
+      if (c + 1 < n) {
+        const int32_t w2 = hv[c + 1], g2 = hg[c + 1];
+        if (above(g2, w2, gw, w)) {
+          c++;
+          w = w2;
+          gw = g2;
+        }
+      }
+      if (!above(gw, w, gv, v)) break;
+      hv[i] = w;
+      hg[i] = gw;
       pos[w] = i;
       i = c;
     }
-    h[i] = v;
+    hv[i] = v;
+    hg[i] = gv;
     pos[v] = i;
   }
-  __device__ void push(int32_t v) {
-    h[n] = v;
+  __device__ void push(int32_t v, int32_t g) {
+    hv[n] = v;
+    hg[n] = g;
     pos[v] = n;
     up(n++);
   }
   __device__ int32_t pop() {
-    const int32_t top = h[0];
-    const int32_t last = h[--n];
+    const int32_t top = hv[0];
+    --n;
     if (n > 0) {
-      h[0] = last;
+      const int32_t last = hv[n];
+      hv[0] = last;
+      hg[0] = hg[n];
       pos[last] = 0;
       down(0);
     }
     return top;
   }
-  // the key of the vertex in slot i went up (grew) or down
-  __device__ void changed(int32_t i, bool grew) {
+  // the vertex in slot i has the new gain g, up (grew) or down
+  __device__ void changed(int32_t i, int32_t g, bool grew) {
+    hg[i] = g;
     if (grew) up(i);
     else down(i);
   }
@@ -104,7 +121,10 @@ __global__ void __launch_bounds__(FM_TPB) k_fm(KArgs A) {
   const int64_t vb = A.voff[v0];
   const int32_t nv = (int32_t)min<int64_t>(A.ucnt[v0], A.voff[v0 + 1] - vb);
   const int32_t *uv = A.uvert + vb;
-  int32_t *heapA = A.ex + vb, *heapB = A.LA + vb, *log = A.lab + vb;
+  // heaps (vertex and gain per slot) and the move log in the first entry's
+  // arena, whose per-iteration arrays are free until the flow iterations
+  int32_t *hvA = A.ex + vb, *hgA = A.lab + vb, *hvB = A.LA + vb, *hgB = A.SNK + vb;
+  int32_t *log = A.LB + vb;
   int32_t *gain = A.fmg, *pos = A.fmq;
   if (threadIdx.x == 0) {
     s_n[0] = s_n[1] = 0;
@@ -130,7 +150,8 @@ __global__ void __launch_bounds__(FM_TPB) k_fm(KArgs A) {
     if (ext > 0) {
       const int side = pv == a ? 0 : 1;
       const int32_t k = atomicAdd(&s_n[side], 1);
-      (side ? heapB : heapA)[k] = v;
+      (side ? hvB : hvA)[k] = v;
+      (side ? hgB : hgA)[k] = (int32_t)(ext - in);
     }
   }
   {
@@ -138,75 +159,113 @@ __global__ void __launch_bounds__(FM_TPB) k_fm(KArgs A) {
     block_sums<1>(s1, s_red);
     cut = s1[0];
   }
-  if (threadIdx.x != 0) return;
+  // the moves: the first wave; lane 0 keeps the state and makes every
+  // decision, the other lanes fetch the moved vertex's neighbourhood
+  if (threadIdx.x >= WAVE) return;
+  const int lane = lane64();
   if (s_bad) {
-    A.ctl->err = FR_E_OVERFLOW;
-    A.ctl->diag = DIAG_FM;
+    if (lane == 0) {
+      A.ctl->err = FR_E_OVERFLOW;
+      A.ctl->diag = DIAG_FM;
+    }
     return;
   }
   const uint64_t seed = (uint64_t)(uint32_t)A.fm_seed;
   // two named heaps (an array indexed at run time would live in scratch)
-  FMHeap HA{heapA, s_n[0], pos, gain, seed}, HB{heapB, s_n[1], pos, gain, seed};
-  for (int32_t i = 0; i < HA.n; i++) pos[HA.h[i]] = i;
-  for (int32_t i = HA.n / 2 - 1; i >= 0; i--) HA.down(i);
-  for (int32_t i = 0; i < HB.n; i++) pos[HB.h[i]] = i;
-  for (int32_t i = HB.n / 2 - 1; i >= 0; i--) HB.down(i);
+  FMHeap HA{hvA, hgA, s_n[0], pos, seed}, HB{hvB, hgB, s_n[1], pos, seed};
+  if (lane == 0) {
+    for (int32_t i = 0; i < HA.n; i++) pos[HA.hv[i]] = i;
+    for (int32_t i = HA.n / 2 - 1; i >= 0; i--) HA.down(i);
+    for (int32_t i = 0; i < HB.n; i++) pos[HB.hv[i]] = i;
+    for (int32_t i = HB.n / 2 - 1; i >= 0; i--) HB.down(i);
+  }
   const int64_t lmax = A.lmax;
   int64_t wa = A.ps[v0].cA, wb = A.ps[v0].cB;
   const int64_t cut0 = cut;
   int best_inf = !(wa <= lmax && wb <= lmax);
   int64_t best_val = best_inf ? (wa > wb ? wa : wb) : cut;
   int32_t steps = 0, best_step = 0, since = 0;
-  while (since < A.fm_limit) {
-    const int32_t tA = HA.n > 0 ? HA.h[0] : -1, tB = HB.n > 0 ? HB.h[0] : -1;
-    if (tA < 0 && tB < 0) break;
-    int side;
-    if ((wa > lmax || wb > lmax) && wa != wb) side = wa > wb ? 0 : 1;
-    else if (tA < 0 || tB < 0) side = tA < 0 ? 1 : 0;
-    else if (gain[tA] != gain[tB]) side = gain[tA] > gain[tB] ? 0 : 1;
-    else side = (int)(fm_splitmix(seed, (1ull << 32) + (uint64_t)steps + 1) & 1ull);
-    if ((side ? tB : tA) < 0) side = 1 - side;
-    const int32_t v = side ? HB.pop() : HA.pop();
-    const int32_t from = side ? b : a, to = side ? a : b;
-    A.part[v] = to;
-    pos[v] = -2;
-    cut -= gain[v];
-    const int64_t wv = A.vwgt[v];
-    if (side == 0) {
-      wa -= wv;
-      wb += wv;
-    } else {
-      wb -= wv;
-      wa += wv;
-    }
-    log[steps++] = v;
-    for (int32_t e = A.xadj[v]; e < A.xadj[v + 1]; e++) {
-      const int32_t u = A.adjncy[e];
-      const int32_t pu = A.part[u];
-      if (pu != a && pu != b) continue;
-      const int32_t pq = pos[u];
-      if (pq == -2) continue;
-      const bool grew = pu == from;  // an internal edge of u became a cut edge
-      gain[u] += grew ? 2 * A.adjwgt[e] : -2 * A.adjwgt[e];
-      if (pu == a) {
-        if (pq >= 0) HA.changed(pq, grew);
-        else HA.push(u);
-      } else {
-        if (pq >= 0) HB.changed(pq, grew);
-        else HB.push(u);
+  for (;;) {
+    int32_t v = -1, side = 0;
+    if (lane == 0 && since < A.fm_limit) {
+      const int32_t tA = HA.n > 0 ? HA.hv[0] : -1, tB = HB.n > 0 ? HB.hv[0] : -1;
+      if (tA >= 0 || tB >= 0) {
+        if ((wa > lmax || wb > lmax) && wa != wb) side = wa > wb ? 0 : 1;
+        else if (tA < 0 || tB < 0) side = tA < 0 ? 1 : 0;
+        else if (HA.hg[0] != HB.hg[0]) side = HA.hg[0] > HB.hg[0] ? 0 : 1;
+        else side = (int)(fm_splitmix(seed, (1ull << 32) + (uint64_t)steps + 1) & 1ull);
+        if ((side ? tB : tA) < 0) side = 1 - side;
+        v = side ? HB.pop() : HA.pop();
+        A.part[v] = side ? a : b;
+        pos[v] = -2;
+        cut -= gain[v];
+        const int64_t wv = A.vwgt[v];
+        if (side == 0) {
+          wa -= wv;
+          wb += wv;
+        } else {
+          wb -= wv;
+          wa += wv;
+        }
+        log[steps++] = v;
       }
     }
-    const int inf = !(wa <= lmax && wb <= lmax);
-    const int64_t val = inf ? (wa > wb ? wa : wb) : cut;
-    if (inf < best_inf || (inf == best_inf && val < best_val)) {
-      best_inf = inf;
-      best_val = val;
-      best_step = steps;
-      since = 0;
-    } else {
-      since++;
+    v = __builtin_amdgcn_readfirstlane(v);
+    side = __builtin_amdgcn_readfirstlane(side);
+    if (v < 0) break;
+    const int32_t from = side ? b : a;
+    // the neighbours, one per lane, then lane 0 updates them in adjacency
+    // order (their heap slots re-read: an earlier update may move them)
+    const int32_t e0 = A.xadj[v], e1 = A.xadj[v + 1];
+    for (int32_t c0 = e0; c0 < e1; c0 += WAVE) {
+      const int32_t e = c0 + lane;
+      int32_t u = 0, w = 0, pu = -1, gu = 0;
+      if (e < e1) {
+        u = A.adjncy[e];
+        w = A.adjwgt[e];
+        pu = A.part[u];
+        gu = gain[u];
+        const int32_t pq = pos[u];  // brings the line close for lane 0
+        asm volatile("" ::"v"(pq));
+      }
+      const int32_t cnt = min(WAVE, e1 - c0);
+      for (int32_t j = 0; j < cnt; j++) {
+        const int32_t uj = __builtin_amdgcn_readlane(u, j);
+        const int32_t pj = __builtin_amdgcn_readlane(pu, j);
+        if (pj != a && pj != b) continue;
+        const int32_t wj = __builtin_amdgcn_readlane(w, j);
+        const int32_t gj = __builtin_amdgcn_readlane(gu, j);
+        if (lane == 0) {
+          const int32_t pq = pos[uj];
+          if (pq != -2) {
+            const bool grew = pj == from;  // an internal edge of u became a cut edge
+            const int32_t g2 = gj + (grew ? 2 * wj : -2 * wj);
+            gain[uj] = g2;
+            if (pj == a) {
+              if (pq >= 0) HA.changed(pq, g2, grew);
+              else HA.push(uj, g2);
+            } else {
+              if (pq >= 0) HB.changed(pq, g2, grew);
+              else HB.push(uj, g2);
+            }
+          }
+        }
+      }
+    }
+    if (lane == 0) {
+      const int inf = !(wa <= lmax && wb <= lmax);
+      const int64_t val = inf ? (wa > wb ? wa : wb) : cut;
+      if (inf < best_inf || (inf == best_inf && val < best_val)) {
+        best_inf = inf;
+        best_val = val;
+        best_step = steps;
+        since = 0;
+      } else {
+        since++;
+      }
     }
   }
+  if (lane != 0) return;
   // roll back the moves after the best state
   for (int32_t i = steps - 1; i >= best_step; i--) {
     const int32_t v = log[i];
