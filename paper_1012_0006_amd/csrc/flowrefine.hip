@@ -514,8 +514,12 @@ static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t s
   }
   hipLaunchKernelGGL(k_arena, dim3(1), dim3(1024), 0, st, A);
   hipLaunchKernelGGL(k_union, dim3(sblocks), dim3(256), 0, st, A);
-  // pairwise FM before the flow iterations (one workgroup per pair)
-  if (A.fm_limit > 0) hipLaunchKernelGGL(k_fm, dim3(A.P / A.W), dim3(FM_TPB), 0, st, A);
+  // pairwise FM before the flow iterations: gains grid-wide, then one
+  // workgroup per pair
+  if (A.fm_limit > 0) {
+    hipLaunchKernelGGL(k_fm_gain, dim3(sblocks), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_fm, dim3(A.P / A.W), dim3(FM_TPB), 0, st, A);
+  }
   const int tpb = c->tune.block_threads;
   const int64_t slots = (int64_t)c->num_cus * c->tune.blocks_per_cu;
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(A.P, slots));

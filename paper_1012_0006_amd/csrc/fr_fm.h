@@ -2,8 +2,9 @@
 // pairwise local search) on the GPU: the pairwise improvement that runs on
 // each pair of a round before its adaptive flow iterations.
 //
-// One workgroup per pair.  The workgroup computes the gains of all vertices
-// of the pair's two blocks at once; the moves themselves are sequential by
+// A grid-wide pass computes the gains of all vertices of the round's pairs
+// and lists each pair's boundary vertices; then one workgroup per pair builds
+// its two queues level by level.  The moves themselves are sequential by
 // nature: lane 0 makes every decision and heap update, the rest of its wave
 // fetches each moved vertex's neighbourhood at once:
 //   - one queue per block: a binary max-heap in the pair's arena ordered by
@@ -111,60 +112,79 @@ struct FMHeap {
   }
 };
 
+// Queues of the pair's two blocks in the first entry's arena (vertex and gain
+// per slot), whose per-iteration arrays are free until the flow iterations;
+// the move log follows them.
+#define FM_QUEUES(A, vb)                                                        \
+  int32_t *hvA = (A).ex + (vb), *hgA = (A).lab + (vb), *hvB = (A).LA + (vb),  \
+          *hgB = (A).SNK + (vb), *log = (A).LB + (vb)
+
+// Gains of every vertex in a block of a pair of the round (weight to the other
+// block minus weight inside its own), queue position -1, the pair's boundary
+// vertices (a neighbour in the other block) listed per side in the queue
+// slots (counts in pcnt[p] and pcnt[P + p]), the pair's cut summed into
+// pacc[p][PA_CUT] and vertices whose weighted degree does not fit int32
+// counted in pacc[p][PA_BW0].  The FM kernel reads and clears these sums.
+__global__ void __launch_bounds__(256) k_fm_gain(KArgs A) {
+  unsigned long long *acc = (unsigned long long *)A.pacc;
+  for (int64_t b0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) & ~(int64_t)63;
+       b0 < A.n; b0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t u = b0 + lane64();
+    int32_t p = -1, side = 0;
+    int64_t ext = 0, in = 0;
+    if (u < A.n) {
+      const int32_t pv = A.part[u];
+      p = A.blk2pair[pv];
+      if (p >= 0) {
+        side = pv == A.pairs[2 * p] ? 0 : 1;
+        const int32_t other = A.pairs[2 * p + 1 - side];
+        for (int32_t e = A.xadj[u]; e < A.xadj[u + 1]; e++) {
+          const int32_t pu = A.part[A.adjncy[e]];
+          if (pu == other) ext += A.adjwgt[e];
+          else if (pu == pv) in += A.adjwgt[e];
+        }
+        A.fmg[u] = (int32_t)(ext - in);
+        A.fmq[u] = -1;
+      }
+    }
+    wave_add_by_key(acc, PA_N, PA_CUT, p >= 0 && side == 0 ? p : -1, ext);
+    wave_add_by_key(acc, PA_N, PA_BW0, p >= 0 && ext + in > 0x7fffffffLL ? p : -1, 1);
+    const int key = p >= 0 && ext > 0 ? (side ? A.P + p : p) : -1;
+    const int slot = wave_append_by_key(A.pcnt, key);
+    if (key >= 0) {
+      const int64_t vb = A.voff[p];
+      if (slot < A.voff[p + 1] - vb) {
+        FM_QUEUES(A, vb);
+        (side ? hvB : hvA)[slot] = (int32_t)u;
+        (side ? hgB : hgA)[slot] = (int32_t)(ext - in);
+      }
+    }
+  }
+}
+
 __global__ void __launch_bounds__(FM_TPB) k_fm(KArgs A) {
   __shared__ int32_t s_n[2];
-  __shared__ int64_t s_red[16 * 8];
+  __shared__ int64_t s_cut;
   __shared__ int32_t s_bad;
   const int32_t q = blockIdx.x;  // pair of the round
   const int32_t v0 = q * A.W;   // its first entry
   const int32_t a = A.pairs[2 * v0], b = A.pairs[2 * v0 + 1];
   const int64_t vb = A.voff[v0];
-  const int32_t nv = (int32_t)min<int64_t>(A.ucnt[v0], A.voff[v0 + 1] - vb);
-  const int32_t *uv = A.uvert + vb;
-  // heaps (vertex and gain per slot) and the move log in the first entry's
-  // arena, whose per-iteration arrays are free until the flow iterations
-  int32_t *hvA = A.ex + vb, *hgA = A.lab + vb, *hvB = A.LA + vb, *hgB = A.SNK + vb;
-  int32_t *log = A.LB + vb;
+  FM_QUEUES(A, vb);
   int32_t *gain = A.fmg, *pos = A.fmq;
-  if (threadIdx.x == 0) {
-    s_n[0] = s_n[1] = 0;
-    s_bad = 0;
+  if (threadIdx.x == 0) {  // the gain pass's sums, cleared for the flow iterations
+    const int64_t cap = A.voff[v0 + 1] - vb;
+    int64_t *pa = A.pacc + (int64_t)v0 * PA_N;
+    s_n[0] = (int32_t)min<int64_t>(A.pcnt[v0], cap);
+    s_n[1] = (int32_t)min<int64_t>(A.pcnt[A.P + v0], cap);
+    s_cut = pa[PA_CUT];
+    s_bad = pa[PA_BW0] != 0;  // gains must fit int32
+    pa[PA_CUT] = pa[PA_BW0] = 0;
+    A.pcnt[v0] = A.pcnt[A.P + v0] = 0;
   }
   __syncthreads();
-  // gains of every vertex of the two blocks; boundary vertices are queued
-  int64_t cut = 0;
-  for (int32_t i = threadIdx.x; i < nv; i += blockDim.x) {
-    const int32_t v = uv[i];
-    const int32_t pv = A.part[v];
-    const int32_t other = pv == a ? b : a;
-    int64_t ext = 0, in = 0;
-    for (int32_t e = A.xadj[v]; e < A.xadj[v + 1]; e++) {
-      const int32_t pu = A.part[A.adjncy[e]];
-      if (pu == other) ext += A.adjwgt[e];
-      else if (pu == pv) in += A.adjwgt[e];
-    }
-    if (ext + in > 0x7fffffffLL) s_bad = 1;  // gains must fit int32
-    gain[v] = (int32_t)(ext - in);
-    pos[v] = -1;
-    if (pv == a) cut += ext;
-    if (ext > 0) {
-      const int side = pv == a ? 0 : 1;
-      const int32_t k = atomicAdd(&s_n[side], 1);
-      (side ? hvB : hvA)[k] = v;
-      (side ? hgB : hgA)[k] = (int32_t)(ext - in);
-    }
-  }
-  {
-    int64_t s1[1] = {cut};
-    block_sums<1>(s1, s_red);
-    cut = s1[0];
-  }
-  // the moves: the first wave; lane 0 keeps the state and makes every
-  // decision, the other lanes fetch the moved vertex's neighbourhood
-  if (threadIdx.x >= WAVE) return;
-  const int lane = lane64();
   if (s_bad) {
-    if (lane == 0) {
+    if (threadIdx.x == 0) {
       A.ctl->err = FR_E_OVERFLOW;
       A.ctl->diag = DIAG_FM;
     }
@@ -173,12 +193,29 @@ __global__ void __launch_bounds__(FM_TPB) k_fm(KArgs A) {
   const uint64_t seed = (uint64_t)(uint32_t)A.fm_seed;
   // two named heaps (an array indexed at run time would live in scratch)
   FMHeap HA{hvA, hgA, s_n[0], pos, seed}, HB{hvB, hgB, s_n[1], pos, seed};
-  if (lane == 0) {
-    for (int32_t i = 0; i < HA.n; i++) pos[HA.hv[i]] = i;
-    for (int32_t i = HA.n / 2 - 1; i >= 0; i--) HA.down(i);
-    for (int32_t i = 0; i < HB.n; i++) pos[HB.hv[i]] = i;
-    for (int32_t i = HB.n / 2 - 1; i >= 0; i--) HB.down(i);
+  // heap build: slots, then sift-downs one tree level at a time from the
+  // deepest internal level up (the subtrees of one level are disjoint)
+  for (int32_t i = threadIdx.x; i < HA.n + HB.n; i += blockDim.x) {
+    if (i < HA.n) pos[HA.hv[i]] = i;
+    else pos[HB.hv[i - HA.n]] = i - HA.n;
   }
+  __syncthreads();
+  const int32_t ia = HA.n / 2, ib = HB.n / 2;  // internal nodes: [0, n / 2)
+  for (int d = 30; d >= 0; d--) {
+    const int32_t lo = (1 << d) - 1;  // level d: [lo, 2 lo + 1)
+    if (lo >= ia && lo >= ib) continue;
+    const int32_t ca = max(0, min(2 * lo + 1, ia) - lo), cb = max(0, min(2 * lo + 1, ib) - lo);
+    for (int32_t j = threadIdx.x; j < ca + cb; j += blockDim.x) {
+      if (j < ca) HA.down(lo + j);
+      else HB.down(lo + j - ca);
+    }
+    __syncthreads();
+  }
+  // the moves: the first wave; lane 0 keeps the state and makes every
+  // decision, the other lanes fetch the moved vertex's neighbourhood
+  if (threadIdx.x >= WAVE) return;
+  const int lane = lane64();
+  int64_t cut = s_cut;
   const int64_t lmax = A.lmax;
   int64_t wa = A.ps[v0].cA, wb = A.ps[v0].cB;
   const int64_t cut0 = cut;

@@ -168,6 +168,18 @@ def test_rejects_negative_limit(gpu_lib, ctx):
         gpu_lib.flow_refine_pair(ctx, g, part, 2, 0, 1, gpu_lib.params(fm_limit=-1))
 
 
+def test_gain_overflow(gpu_lib, ctx):
+    # vertex 0 has three edges of weight 2^30 - 1 into the other block: its
+    # FM gain does not fit int32, so the FM pass reports FR_E_OVERFLOW
+    w = (1 << 30) - 1
+    g = csr_from_edges(5, [(0, 1), (0, 2), (0, 3), (3, 4)], weights=[w, w, w, 1])
+    part = np.array([0, 1, 1, 1, 0], dtype=np.int32)
+    with pytest.raises(gpu_lib.FlowRefineError) as e:
+        gpu_lib.flow_refine_pair(ctx, g, part, 2, 0, 1, gpu_lib.params(fm_limit=10))
+    assert e.value.code == -5
+    assert gpu_lib.stats_dict(ctx)["diag"] == 7  # raised by the FM pass
+
+
 @pytest.mark.parametrize("fm", [0, 50])
 def test_sweep_active_blocks(gpu_lib, ctx, fm):
     import torch
