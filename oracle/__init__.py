@@ -47,7 +47,8 @@ class OrGraph(ctypes.Structure):
 class OrParams(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int32) for f in
                 ("area_mode", "depth", "alpha", "alpha_max", "adaptive", "max_iters", "eps_ppm",
-                 "mb_reps", "mb_seed", "fm_limit", "fm_seed", "active_blocks", "cut_side")]
+                 "mb_reps", "mb_seed", "fm_limit", "fm_seed", "active_blocks", "cut_side",
+                 "terminals")]
 
 
 class OrSolve(ctypes.Structure):
@@ -127,7 +128,7 @@ def _params(p: dict) -> OrParams:
     return OrParams(p.get("area_mode", 0), p.get("depth", 0), p["alpha"], p["alpha_max"],
                     p["adaptive"], p["max_iters"], p["eps_ppm"], p.get("mb_reps", 0),
                     _i32(p.get("mb_seed", 0)), p.get("fm_limit", 0), _i32(p.get("fm_seed", 0)),
-                    p.get("active_blocks", 0), p.get("cut_side", 0))
+                    p.get("active_blocks", 0), p.get("cut_side", 0), p.get("terminals", 0))
 
 
 def _struct_dict(s) -> dict:

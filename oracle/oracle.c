@@ -47,6 +47,14 @@
  *       are empty; roll back to the best state: feasible before infeasible,
  *       then the smaller cut (feasible) or the lighter heavier block
  *       (infeasible), the earliest on ties
+ *   R30 terminals 1: instead of pinning the corridor border to s and t with
+ *       infinite arcs, the parts of blocks a and b outside the corridor are
+ *       contracted into s and t; a corridor vertex gets an arc s -> u with the
+ *       weight of its edges into a outside the corridor and an arc u -> t with
+ *       the weight of its edges into b outside; edges between the two
+ *       outside parts are cut whatever happens (constant); so every corridor
+ *       vertex may change sides and the min cut is the best reassignment of
+ *       the corridor
  *   R11 most balanced cut: balance of a cut = the heavier of the two new block
  *       weights; a random topological order takes, among the components whose
  *       predecessors are all placed, the one with the smallest key, keys from
@@ -83,6 +91,8 @@ typedef struct {
   int32_t active_blocks; /* sweeps: refine only pairs with a block changed in the previous sweep */
   int32_t cut_side; /* without mb_reps: 0 smallest source set, 1 largest, 2 the smallest unless
                        it is infeasible and the largest is feasible */
+  int32_t terminals; /* 0: corridor border pinned to s / t by infinite arcs (Sec. 4.1);
+                        1: the blocks' outside parts contracted into s / t (arcs of weight omega) */
 } or_params;
 
 /* one flow solve */
@@ -177,6 +187,7 @@ static void net_free(or_net *N) {
 /* add arc u->v with capacity c and its reverse v->u with capacity rc */
 static void net_add(or_net *N, int32_t u, int32_t v, int64_t c, int64_t rc) {
   int64_t i = N->na;
+  if (i + 2 > N->cap) abort(); /* sized too small by the caller: a bug, never data */
   N->tail[i] = u; N->head[i] = v; N->res[i] = c; N->cap0[i] = c;
   N->tail[i + 1] = v; N->head[i + 1] = u; N->res[i + 1] = rc; N->cap0[i + 1] = rc;
   N->na += 2;
@@ -708,7 +719,8 @@ static void area_bfs(const or_graph *g, const int32_t *part, int32_t blk, int32_
 /* One flow solve for the pair (a = source side, b = sink side) at factor
  * alpha.  Fills rec; if apply is set and the candidate is accepted, writes it
  * into part.  side_out (optional, length n): -1 outside the corridor, 0/1
- * corridor vertex ending in a / b, 2/3 border vertex pinned to s / t. */
+ * corridor vertex ending in a / b, 2/3 border vertex pinned to s / t (only
+ * with pinned terminals). */
 static int32_t solve_once(const or_graph *g, int32_t *part, int32_t k, int32_t a, int32_t b,
                           const or_params *p, int32_t alpha, or_solve *rec, int8_t *side_out) {
   int32_t n = g->n;
@@ -755,8 +767,14 @@ static int32_t solve_once(const or_graph *g, int32_t *part, int32_t k, int32_t a
   for (int32_t u = 0; u < n; u++) loc[u] = inB[u] ? nb++ : -1;
   int32_t S = nb, T = nb + 1;
   /* R2: border within G[A u B]: a corridor vertex with a neighbour in A u B
-   * outside the corridor */
+   * outside the corridor.  cin: the old a-b edges whose cut state the solve
+   * decides (both ends in the corridor; with contracted terminals also those
+   * with one end outside).  R30: cs / ct = weight from a corridor vertex into
+   * a / b outside the corridor. */
   uint8_t *border = (uint8_t *)calloc((size_t)(nb ? nb : 1), 1);
+  int64_t *cs = (int64_t *)calloc((size_t)(nb ? nb : 1), sizeof(int64_t));
+  int64_t *ct = (int64_t *)calloc((size_t)(nb ? nb : 1), sizeof(int64_t));
+  if (!border || !cs || !ct) { free(cs); free(ct); goto oom; }
   int64_t nedges = 0, sumw = 0, cin = 0;
   for (int32_t u = 0; u < n; u++) {
     if (!inB[u]) continue;
@@ -770,28 +788,37 @@ static int32_t solve_once(const or_graph *g, int32_t *part, int32_t k, int32_t a
         }
       } else if (part[v] == a || part[v] == b) {
         border[loc[u]] = 1;
+        if (part[v] == a) cs[loc[u]] += g->adjwgt[e];
+        else ct[loc[u]] += g->adjwgt[e];
+        if (p->terminals && part[v] != part[u]) cin += g->adjwgt[e];
       }
     }
   }
+  if (p->terminals) memset(border, 0, (size_t)(nb ? nb : 1)); /* nothing is pinned */
   rec->region_vertices = nb;
   rec->region_edges = nedges;
   int64_t INF = 2 * sumw + 1; /* exceeds every finite cut */
   or_net N;
-  int64_t nborder = 0;
-  for (int32_t i = 0; i < nb; i++) nborder += border[i];
-  if (net_init(&N, nb + 2, 2 * nedges + 2 * nborder) != 0) goto oom;
+  /* two arcs per corridor edge, and an s or t arc with its reverse at most twice per vertex */
+  if (net_init(&N, nb + 2, 2 * nedges + 4 * (int64_t)nb) != 0) { free(cs); free(ct); goto oom; }
   for (int32_t u = 0; u < n; u++) {
     if (!inB[u]) continue;
     for (int32_t e = g->xadj[u]; e < g->xadj[u + 1]; e++) {
       int32_t v = g->adjncy[e];
       if (inB[v] && u < v) net_add(&N, loc[u], loc[v], g->adjwgt[e], g->adjwgt[e]);
     }
-    if (border[loc[u]]) {
+    if (p->terminals) {
+      /* R30: arcs from the contracted outside of a, into that of b */
+      if (cs[loc[u]] > 0) net_add(&N, S, loc[u], cs[loc[u]], 0);
+      if (ct[loc[u]] > 0) net_add(&N, loc[u], T, ct[loc[u]], 0);
+    } else if (border[loc[u]]) {
       if (inB[u] == 1) net_add(&N, S, loc[u], INF, 0); /* s -> left border */
       else net_add(&N, loc[u], T, INF, 0);             /* right border -> t */
     }
   }
-  if (net_finish(&N) != 0) goto oom;
+  free(cs);
+  free(ct);
+  if (net_finish(&N) != 0) { net_free(&N); goto oom; }
   int64_t flow = net_dinic(&N, S, T);
   rec->flow = flow;
   uint8_t *reach = (uint8_t *)malloc((size_t)nb + 2);
@@ -856,7 +883,7 @@ static int32_t solve_once(const or_graph *g, int32_t *part, int32_t k, int32_t a
   rec->source_side = src;
   rec->wa = wa;
   rec->wb = wb;
-  /* edges with both ends in the corridor: C_in before, flow after */
+  /* the decided edges: C_in before, flow after */
   int64_t cand = cut - cin + flow;
   rec->cut_candidate = cand;
   int feasible = wa <= lmax && wb <= lmax;
@@ -1025,7 +1052,8 @@ int32_t or_refine_pair(const or_graph *g, int32_t *part, int32_t k, int32_t a, i
   if (a < 0 || b < 0 || a >= k || b >= k || a == b) return -3;
   if (p->alpha < 1 || p->alpha_max < 1 || p->max_iters < 1 || p->eps_ppm < 0 ||
       (p->area_mode != 0 && p->area_mode != 1) || p->depth < 0 || p->mb_reps < 0 ||
-      p->fm_limit < 0 || p->cut_side < 0 || p->cut_side > 2)
+      p->fm_limit < 0 || p->cut_side < 0 || p->cut_side > 2 ||
+      (p->terminals != 0 && p->terminals != 1))
     return -8;
   int64_t w_a = 0, w_b = 0;
   for (int32_t u = 0; u < g->n; u++) {
