@@ -296,13 +296,15 @@ def run_sweep(args, fr, torch, gen):
 
 
 def run_balanced(args, fr, torch, gen):
-    """The two widenings of the pair refinement on C5 (2D RGG n=2^24, mean
-    degree 6, unit weights, k=256 RCB + 1 % noise): most balanced minimum cuts
+    """The widenings of the pair refinement on C5 (2D RGG n=2^24, mean degree
+    6, unit weights, k=256 RCB + 1 % noise): most balanced minimum cuts
     (Sec. 4.1.1, 16 sweeps) and 2-way FM with TopGain before the flow
     (Sec. 2.2, stop after 100 moves without improvement), alone and together,
-    and together with active block scheduling (Sec. 4.3), against the plain
-    flow: the largest matching round batched, then whole refinement sweeps
-    until no pair improves, for time and the cut reached."""
+    and together with active block scheduling (Sec. 4.3); the corridor network
+    with the blocks' outside parts contracted into s and t instead of the
+    pinned border, alone and with all of the above; against the plain flow:
+    the largest matching round batched, then whole refinement sweeps until no
+    pair improves, for time and the cut reached."""
     import oracle  # cut accounting only
 
     w = gen.config("C5")
@@ -325,7 +327,11 @@ def run_balanced(args, fr, torch, gen):
                 ("fm_then_most_balanced", {"fm_limit": 100, "fm_seed": 1, "mb_reps": 16,
                                            "mb_seed": 1}),
                 ("fm_then_most_balanced_active", {"fm_limit": 100, "fm_seed": 1, "mb_reps": 16,
-                                                  "mb_seed": 1, "active_blocks": 1}))
+                                                  "mb_seed": 1, "active_blocks": 1}),
+                ("contracted_terminals", {"terminals": 1}),
+                ("contracted_fm_most_balanced_active", {"terminals": 1, "fm_limit": 100,
+                                                        "fm_seed": 1, "mb_reps": 16, "mb_seed": 1,
+                                                        "active_blocks": 1}))
     for name, extra in variants:
         prm = fr.params(**base, **extra)
         dpart = part0.clone()

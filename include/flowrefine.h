@@ -153,7 +153,20 @@ typedef struct {
    * smallest breaks L_max and the largest does not.  Both have the minimum
    * cut's value, so only the balance differs. */
   int32_t cut_side;
+  /* Terminals of the corridor network.  FR_TERM_PINNED (0, Sec. 4.1): the
+   * corridor border is tied to s / t by infinite arcs, so it never moves.
+   * FR_TERM_CONTRACTED (1): the parts of blocks a and b outside the corridor
+   * are contracted into s and t; a corridor vertex gets an arc s -> u of the
+   * weight of its edges into a outside the corridor and an arc u -> t of the
+   * weight of its edges into b outside.  Every corridor vertex may then
+   * change sides: the minimum cut is the best reassignment of the corridor
+   * (balance aside), never worse than the pinned one.  Those arc capacities
+   * count toward the 2^31 capacity bound. */
+  int32_t terminals;
 } fr_params;
+
+#define FR_TERM_PINNED 0
+#define FR_TERM_CONTRACTED 1
 
 #define FR_MB_MAX_REPS 256
 #define FR_MB_MAX_COMP 2048
@@ -212,7 +225,7 @@ const char *fr_strerror(int32_t code);
  * part: [n] in/out, block ids in [0, k).  res: host, one record.
  * side_out (optional, host int8 [n]): per vertex of the LAST solve, -1 outside
  * the corridor, 0 / 1 corridor vertex ending in a / b, 2 / 3 border vertex
- * pinned to s (block a) / t (block b).
+ * pinned to s (block a) / t (block b; pinned terminals only).
  * trace (optional, host, p->max_iters records): one record per solve. */
 int32_t flow_refine_pair(fr_context *ctx, const fr_graph *g, int32_t *part, int32_t k,
                          int32_t a, int32_t b, const fr_params *p, fr_result *res,

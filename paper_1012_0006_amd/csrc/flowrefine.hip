@@ -336,7 +336,7 @@ static int32_t check_params(const fr_params *p) {
   if (p->depth < 0 || p->alpha < 1 || p->alpha_max < 1 || p->alpha_max > FR_MAX_ALPHA ||
       p->max_iters < 1 || p->max_iters > FR_MAX_ITERS || p->eps_ppm < 0 || p->eps_ppm > 100000000 ||
       p->mb_reps < 0 || p->mb_reps > FR_MB_MAX_REPS || p->fm_limit < 0 || p->cut_side < 0 ||
-      p->cut_side > 2)
+      p->cut_side > 2 || (p->terminals != FR_TERM_PINNED && p->terminals != FR_TERM_CONTRACTED))
     return FR_E_INVALID_ARG;
   return FR_OK;
 }
@@ -412,6 +412,7 @@ static KArgs call_args(fr_context *c, const fr_graph *g, int32_t *dpart, int32_t
     A.fm_limit = p->fm_limit;
     A.fm_seed = p->fm_seed;
     A.cut_side = p->cut_side;
+    A.terminals = p->terminals;
   }
   A.mb_lds = c->tune.mb_lds;
   A.mbq = d.mbq;

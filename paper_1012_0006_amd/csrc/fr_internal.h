@@ -70,7 +70,8 @@ enum {
   PA_BC1,
   PA_RARCS,    // corridor arcs
   PA_RCAP,     // their capacity sum
-  PA_RCIN,     // weight of old a-b edges inside the corridor
+  PA_RCIN,     // weight of the old a-b edges the solve decides
+  PA_CS,       // contracted terminals: capacity out of s (the initial excess)
   PA_N
 };
 
@@ -135,6 +136,10 @@ struct KArgs {
   // candidate without the most balanced cut: 0 smallest source set, 1 largest,
   // 2 the largest only when the smallest is infeasible and it is feasible
   int32_t cut_side;
+  // terminals of the corridor network: 0 border pinned by infinite arcs,
+  // 1 the blocks' outside parts contracted into s / t (per-vertex capacities:
+  // s -> u as the initial excess, u -> t in the sink-list array SNK)
+  int32_t terminals;
   // per vertex [n]
   int32_t *mark, *vmap;
   // per-pair arenas: vertex slots [voff[p], voff[p+1]), arc slots [aoff[p], aoff[p+1])

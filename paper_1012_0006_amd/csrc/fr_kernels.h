@@ -495,20 +495,32 @@ __device__ void pr_sweep(const KArgs &A, const PairView &V, const ListRef &cur, 
     // the group leader reads label and excess once: excess may grow
     // concurrently, and every lane must push against the same value; the
     // arc range is read by all lanes at the same time
-    int32_t d = NL, e = 0;
+    // (contracted terminals: and the residual of u -> t, which only the
+    // vertex's own discharge changes)
+    int32_t d = NL, e = 0, rt = 0;
     if (valid && gl == 0) {
       d = V.lab[u];
       e = V.ex[u];
+      if (A.terminals) rt = V.SNK[u];
     }
     int32_t ab = valid ? V.lo[u] : 0;
     int32_t ae = valid ? V.lo[u + 1] : 0;
     if (T > 1) {
       d = __shfl(d, 0, T);
       e = __shfl(e, 0, T);
+      rt = __shfl(rt, 0, T);
     }
     const bool work = valid && d < NL && e > 0;
     if (!work) ab = ae = 0;
     int64_t erem = e, pushed = 0;
+    // the arc to t first: always admissible (t is at label 0); once it is
+    // saturated it takes no part in the relabel
+    if (work && rt > 0) {
+      const int32_t amt = e < rt ? e : rt;
+      if (gl == 0) V.SNK[u] = rt - amt;
+      erem -= amt;
+      pushed += amt;
+    }
     int32_t minres = 0x7fffffff;
     count_work_wave(wcnt, W_SWEEP_ITEMS, (work && gl == 0) ? 1 : 0);
     count_work_wave(wcnt, W_SWEEP_ARCS, (work && gl == 0) ? ae - ab : 0);
@@ -704,10 +716,12 @@ __device__ __forceinline__ ListRef flist(const PairView &V, SolveShared<TPB> &sh
   return L;
 }
 
-// Exact distance labels: BFS from the sink border backwards over residual
-// arcs (v gets d+1 when the arc v -> w into a labelled w has residual
-// capacity); unreached vertices keep NL and are inactive.  With lds set the
-// visited marks are an LDS bitmap (bm[0]) and bm[1] is cleared for the
+// Exact distance labels: BFS from the sink backwards over residual arcs (v
+// gets d+1 when the arc v -> w into a labelled w has residual capacity);
+// unreached vertices keep NL and are inactive.  Pinned terminals: the BFS
+// starts at the sink border (label 0).  Contracted terminals: it starts at the
+// vertices whose arc to t has residual capacity left (label 1).  With lds set
+// the visited marks are an LDS bitmap (bm[0]) and bm[1] is cleared for the
 // sweeps; otherwise labels are claimed by compare-and-swap.  Leaves the
 // active list (excess > 0, label < NL, not border) in list slot 0 and
 // returns its size.
@@ -715,22 +729,30 @@ template <int TPB>
 __device__ int32_t global_relabel(const KArgs &A, const PairView &V, int32_t nr, int32_t NL,
                                   SolveShared<TPB> &sh, Rot &R, int64_t &levels, bool lds) {
   uint32_t *vis = sh.u.f.bm[0];
-  // start labels (sink border 0, source border NL + 1, the rest NL) and, with
-  // the LDS bitmaps, visited = border and a cleared second bitmap: one pass,
-  // four vertices per lane with their flags loaded together
+  const bool term = A.terminals != 0;
+  const ListRef start = flist(V, sh, 1, lds);  // contracted terminals: the first level
+  int32_t *scnt = &sh.cnt[(R.c + 1) % 3];
+  // start labels (pinned: sink border 0, source border NL + 1, the rest NL;
+  // contracted: 1 with a residual arc to t, else NL) and, with the LDS
+  // bitmaps, visited = those starting below NL and a cleared second bitmap:
+  // one pass, four vertices per lane with their flags loaded together
   for (int64_t b0 = (int64_t)(threadIdx.x & ~63u) * 4; b0 < nr; b0 += 4 * (int64_t)blockDim.x) {
     uint32_t f[4];
+    int32_t rt[4];
 #pragma unroll
     for (int j = 0; j < 4; j++) {
       const int64_t i = b0 + 64 * j + lane64();
       f[j] = i < nr ? V.fl[i] : 0u;
+      rt[j] = term && i < nr ? V.SNK[i] : 0;
     }
 #pragma unroll
     for (int j = 0; j < 4; j++) {
       const int64_t i = b0 + 64 * j + lane64();
-      if (i < nr) V.lab[i] = LF_SNK(f[j]) ? 0 : (LF_SRC(f[j]) ? NL + 1 : NL);
+      const bool first = i < nr && (term ? rt[j] > 0 : (f[j] & LF_BORDER) != 0u);
+      if (i < nr)
+        V.lab[i] = term ? (rt[j] > 0 ? 1 : NL) : (LF_SNK(f[j]) ? 0 : (LF_SRC(f[j]) ? NL + 1 : NL));
       if (lds) {
-        const unsigned long long m = __ballot(i < nr && (f[j] & LF_BORDER));
+        const unsigned long long m = __ballot(first);
         const int64_t w0 = (b0 + 64 * j) >> 5;  // 64-aligned: two bitmap words
         if (lane64() == 0) {
           vis[w0] = (uint32_t)m;
@@ -741,17 +763,33 @@ __device__ int32_t global_relabel(const KArgs &A, const PairView &V, int32_t nr,
           sh.u.f.bm[1][w0 + 1] = 0u;
         }
       }
+      if (term) {
+        const int pos = wave_append(scnt, first);
+        if (first) lput(start, pos, V.nv, (int32_t)i, A.ctl);
+      }
     }
   }
-  if (threadIdx.x == 0) sh.cnt[(R.c + 1) % 3] = 0;
-  __syncthreads();
   ListRef cur;
-  cur.g = V.SNK;
-  cur.s = nullptr;
-  cur.ns = 0;
-  int32_t cnt = uni(min(sh.nsnk, (int32_t)V.nv));
-  int32_t lev = 0;
-  int which = 0;  // next list slot
+  int32_t cnt, lev;
+  int which;  // next list slot
+  if (term) {
+    if (threadIdx.x == 0) sh.cnt[(R.c + 2) % 3] = 0;
+    __syncthreads();
+    R.c = (R.c + 1) % 3;
+    cur = start;
+    cnt = uni(min(sh.cnt[R.c], (int32_t)V.nv));
+    lev = 1;
+    which = 0;
+  } else {
+    if (threadIdx.x == 0) sh.cnt[(R.c + 1) % 3] = 0;
+    __syncthreads();
+    cur.g = V.SNK;
+    cur.s = nullptr;
+    cur.ns = 0;
+    cnt = uni(min(sh.nsnk, (int32_t)V.nv));
+    lev = 0;
+    which = 0;
+  }
   while (cnt > 0) {
     const ListRef next = flist(V, sh, which, lds);
     int32_t *ncnt = &sh.cnt[(R.c + 1) % 3];
@@ -1193,15 +1231,22 @@ __global__ void __launch_bounds__(TPB) k_corr(KArgs A, int32_t it) {
 
 // ---- corridor network G' (Sec. 4.1), pass 1: arcs of each corridor vertex
 //      inside the corridor (edges of G[B], capacity omega both ways), border
-//      flag (a neighbour in A u B outside the corridor: merged into s or t)
+//      flag (a neighbour in A u B outside the corridor: merged into s or t).
+//      With contracted terminals no vertex is pinned: the weight into a
+//      outside the corridor is the capacity of s -> u (written as u's initial
+//      excess), the weight into b outside that of u -> t (written to SNK),
+//      and the old a-b edges with one end outside count as decided too.
 __global__ void __launch_bounds__(256) k_net_count(KArgs A, int32_t it) {
   const int32_t S = A.stamp0 + 2 * it;
+  const bool term = A.terminals != 0;
   unsigned long long *acc = (unsigned long long *)A.pacc;
   unsigned long long *psw = (unsigned long long *)A.ps;
-  // corridor arcs, capacity sum, old a-b weight inside, vertices, arcs scanned
-  KeyedSums<5> sums;
+  // corridor arcs, capacity sum, decided old a-b weight, vertices, arcs
+  // scanned, capacity out of s
+  KeyedSums<6> sums;
   auto out = [&](int j, int key, int64_t v) {
     if (j < 3) wave_add_by_key(acc, PA_N, PA_RARCS + j, key, v);
+    else if (j == 5) wave_add_by_key(acc, PA_N, PA_CS, key, v);
     else wave_add_by_key(psw, PS_WORDS, PS_WORK + (j == 3 ? W_NET_VERTS : W_NET_ARCS), key, v);
   };
   grid_groups<GT>(A.cpre[*A.nact], [&](int64_t i0, bool valid, int gl) {
@@ -1214,7 +1259,7 @@ __global__ void __launch_bounds__(256) k_net_count(KArgs A, int32_t it) {
     const int side = on && A.part[u] == b;
     const int32_t *mk = on ? mark_of(A, p) : A.mark;
     const int32_t e0 = on ? A.xadj[u] : 0, e1 = on ? A.xadj[u + 1] : 0;
-    int64_t cnt = 0, cap = 0, cin = 0;
+    int64_t cnt = 0, cap = 0, cin = 0, cs = 0, ct = 0;
     bool border = false;
     for (int32_t a0 = e0; a0 < e1; a0 += GT) {
       const int32_t e = a0 + gl;
@@ -1228,18 +1273,32 @@ __global__ void __launch_bounds__(256) k_net_count(KArgs A, int32_t it) {
         if (!side && xv == b) cin += A.adjwgt[e];
       } else {
         border = true;
+        if (xv == a) cs += A.adjwgt[e];
+        else ct += A.adjwgt[e];
+        if (term && xv != (side ? b : a)) cin += A.adjwgt[e];
       }
     }
-    border = group_any<GT>(border);
+    border = group_any<GT>(border) && !term;
     cnt = group_sum<GT>(cnt);
     cap = group_sum<GT>(cap);
     cin = group_sum<GT>(cin);
+    if (term) {
+      cs = group_sum<GT>(cs);
+      ct = group_sum<GT>(ct);
+      cap += cs + ct;
+    } else {
+      cs = 0;
+    }
     const bool lead = on && gl == 0;
     if (lead) {
       A.lo[i + p + 1] = (int32_t)cnt;  // the pair's offsets start at voff[p] + p
       A.lflag[i] = (uint8_t)((side ? LF_SIDE_B : 0u) | (border ? LF_BORDER : 0u));
+      if (term) {  // clamped: past 2^31 the pair reports FR_E_OVERFLOW before any use
+        A.ex[i] = (int32_t)min<int64_t>(cs, 0x7fffffffLL);
+        A.SNK[i] = (int32_t)min<int64_t>(ct, 0x7fffffffLL);
+      }
     }
-    const int64_t x[5] = {cnt, cap, cin, 1, e1 - e0};
+    const int64_t x[6] = {cnt, cap, cin, 1, e1 - e0, cs};
     sums.add(lead ? p : -1, x, out);
     (void)item;
   });
@@ -1365,7 +1424,7 @@ __global__ void __launch_bounds__(256) k_net_rev(KArgs A, int32_t it) {
     }
     ex = group_sum<GT>(ex);
     if (on && gl == 0) {
-      A.ex[vb + item] = src ? 0 : (int32_t)ex;
+      if (!A.terminals) A.ex[vb + item] = src ? 0 : (int32_t)ex;  // else: the s -> u capacity
       A.ins[vb + item] = 0;
       if (overflow) {
         A.ctl->err = FR_E_OVERFLOW;
@@ -1556,6 +1615,7 @@ __global__ void __launch_bounds__(TPB) k_flow(KArgs A, int32_t it) {
     // flow, moved a->b, moved b->a, source side; the same three for the
     // largest minimum source side (label >= NL: cannot reach the sink)
     int64_t acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    const bool term = A.terminals != 0;
     const bool mb = A.mb_reps > 0 && !overflow;
     const int side_mode = (A.mb_reps > 0 || overflow) ? 0 : A.cut_side;
     if (mb) {
@@ -1569,11 +1629,15 @@ __global__ void __launch_bounds__(TPB) k_flow(KArgs A, int32_t it) {
           const uint32_t f = V.fl[i];
           const int32_t w = A.vwgt[V.lg[i]];
           const bool in = V.ins[i] != 0;
-          if (in && LF_SNK(f)) {  // the closure reached the sink: the preflow was not maximal
+          // the closure reached the sink: the preflow was not maximal
+          if (in && (term ? V.SNK[i] > 0 : LF_SNK(f))) {
             A.ctl->err = FR_E_DEVICE;
             A.ctl->diag = DIAG_CLOSURE;
           }
-          if (LF_SNK(f)) acc[0] += V.ex[i];
+          // flow: what reached the sink border; contracted terminals: what
+          // left s and stayed nowhere in the corridor
+          if (term) acc[0] -= V.ex[i];
+          else if (LF_SNK(f)) acc[0] += V.ex[i];
           if (!(f & LF_SIDE_B) && !in) acc[1] += w;
           if ((f & LF_SIDE_B) && in) acc[2] += w;
           acc[3] += in ? 1 : 0;
@@ -1609,6 +1673,7 @@ __global__ void __launch_bounds__(TPB) k_flow(KArgs A, int32_t it) {
       fr_solve rec;
       const int64_t cut = st.cut;
       rec.alpha = st.alpha;
+      if (term) acc[0] += pa[PA_CS];
       rec.flow = acc[0];
       rec.region_vertices = nr;
       rec.region_edges = pa[PA_RARCS] / 2;

@@ -14,7 +14,7 @@ from tests.test_gpu_parity import RESULT_KEYS
 pytestmark = pytest.mark.gpu
 
 PKEYS = ("area_mode", "depth", "alpha", "alpha_max", "adaptive", "max_iters", "eps_ppm",
-         "mb_reps", "mb_seed", "fm_limit", "fm_seed", "active_blocks", "cut_side")
+         "mb_reps", "mb_seed", "fm_limit", "fm_seed", "active_blocks", "cut_side", "terminals")
 
 
 def _prm(fr, d):
@@ -202,8 +202,8 @@ def test_sweep_active_blocks(gpu_lib, ctx, fm):
 @pytest.mark.parametrize("seed", range(20))
 def test_random_rounds_all_options(gpu_lib, seed):
     """Randomised whole rounds mixing every option: most balanced cuts, FM
-    before the flow, the candidate side, speculation, weights and k; and a
-    short sweep with active blocks on every fourth seed."""
+    before the flow, the candidate side, the terminals, speculation, weights
+    and k; and a short sweep with active blocks on every fourth seed."""
     import torch
 
     rng = np.random.default_rng(3100 + seed)
@@ -225,6 +225,7 @@ def test_random_rounds_all_options(gpu_lib, seed):
     try:
         c.set_speculation(bool(rng.integers(0, 2)))
         c.set_validation(bool(rng.integers(0, 2)))
+        p["terminals"] = int(rng.integers(0, 2))
         dg = gpu_lib.DeviceGraph.from_host(g)
         if seed % 4 == 3:
             p["active_blocks"] = 1
