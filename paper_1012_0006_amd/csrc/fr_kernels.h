@@ -730,29 +730,23 @@ __device__ int32_t global_relabel(const KArgs &A, const PairView &V, int32_t nr,
                                   SolveShared<TPB> &sh, Rot &R, int64_t &levels, bool lds) {
   uint32_t *vis = sh.u.f.bm[0];
   const bool term = A.terminals != 0;
-  const ListRef start = flist(V, sh, 1, lds);  // contracted terminals: the first level
-  int32_t *scnt = &sh.cnt[(R.c + 1) % 3];
-  // start labels (pinned: sink border 0, source border NL + 1, the rest NL;
-  // contracted: 1 with a residual arc to t, else NL) and, with the LDS
-  // bitmaps, visited = those starting below NL and a cleared second bitmap:
-  // one pass, four vertices per lane with their flags loaded together
+  // start labels (sink border 0, source border NL + 1, the rest NL) and, with
+  // the LDS bitmaps, visited = border and a cleared second bitmap: one pass,
+  // four vertices per lane with their flags loaded together (contracted
+  // terminals set no border flag: every label NL, nothing visited)
   for (int64_t b0 = (int64_t)(threadIdx.x & ~63u) * 4; b0 < nr; b0 += 4 * (int64_t)blockDim.x) {
     uint32_t f[4];
-    int32_t rt[4];
 #pragma unroll
     for (int j = 0; j < 4; j++) {
       const int64_t i = b0 + 64 * j + lane64();
       f[j] = i < nr ? V.fl[i] : 0u;
-      rt[j] = term && i < nr ? V.SNK[i] : 0;
     }
 #pragma unroll
     for (int j = 0; j < 4; j++) {
       const int64_t i = b0 + 64 * j + lane64();
-      const bool first = i < nr && (term ? rt[j] > 0 : (f[j] & LF_BORDER) != 0u);
-      if (i < nr)
-        V.lab[i] = term ? (rt[j] > 0 ? 1 : NL) : (LF_SNK(f[j]) ? 0 : (LF_SRC(f[j]) ? NL + 1 : NL));
+      if (i < nr) V.lab[i] = LF_SNK(f[j]) ? 0 : (LF_SRC(f[j]) ? NL + 1 : NL);
       if (lds) {
-        const unsigned long long m = __ballot(first);
+        const unsigned long long m = __ballot(i < nr && (f[j] & LF_BORDER));
         const int64_t w0 = (b0 + 64 * j) >> 5;  // 64-aligned: two bitmap words
         if (lane64() == 0) {
           vis[w0] = (uint32_t)m;
@@ -763,10 +757,26 @@ __device__ int32_t global_relabel(const KArgs &A, const PairView &V, int32_t nr,
           sh.u.f.bm[1][w0 + 1] = 0u;
         }
       }
-      if (term) {
-        const int pos = wave_append(scnt, first);
-        if (first) lput(start, pos, V.nv, (int32_t)i, A.ctl);
+    }
+  }
+  if (term) {
+    // contracted terminals: the vertices with a residual arc to t start at
+    // label 1, visited, listed in slot 1 as the first level.  This pass
+    // splits the vertices over the waves differently from the one above, so
+    // it waits for that one's label and bitmap stores first.
+    __syncthreads();
+    const ListRef start = flist(V, sh, 1, lds);
+    int32_t *scnt = &sh.cnt[(R.c + 1) % 3];
+    BLOCK_WAVE_LOOP(i, nr) {
+      const bool first = i < nr && V.SNK[i] > 0;
+      if (first) V.lab[i] = 1;
+      if (lds) {
+        const unsigned long long m = __ballot(first);
+        if (lane64() == 0) vis[i >> 5] = (uint32_t)m;
+        if (lane64() == 32) vis[i >> 5] = (uint32_t)(m >> 32);
       }
+      const int pos = wave_append(scnt, first);
+      if (first) lput(start, pos, V.nv, (int32_t)i, A.ctl);
     }
   }
   ListRef cur;
@@ -776,7 +786,7 @@ __device__ int32_t global_relabel(const KArgs &A, const PairView &V, int32_t nr,
     if (threadIdx.x == 0) sh.cnt[(R.c + 2) % 3] = 0;
     __syncthreads();
     R.c = (R.c + 1) % 3;
-    cur = start;
+    cur = flist(V, sh, 1, lds);
     cnt = uni(min(sh.cnt[R.c], (int32_t)V.nv));
     lev = 1;
     which = 0;
@@ -1466,16 +1476,15 @@ __global__ void __launch_bounds__(TPB) k_flow(KArgs A, int32_t it) {
     Rot R;
     int64_t gr_levels = 0, sweeps = 0, relabels = 0, cl_levels = 0;
     if (!overflow) {
-      relabels = 1;
-      int32_t cnt = global_relabel<TPB>(A, V, nr, NL, sh, R, gr_levels, lds);
-      t1 = wall_clock64();
-      t_rel += t1 - t0;
-      t0 = t1;
-      ListRef cur = flist(V, sh, 0, lds), nxt = flist(V, sh, 1, lds);
+      // one relabel call site (the relabel is inlined; one copy keeps the
+      // kernel within its registers): at the start, when the active list
+      // runs dry and every relabel_period passes
+      int32_t cnt = 0;
+      ListRef cur, nxt;
       int since = 0;
+      bool relabel = true;
       for (;;) {
-        if (cnt == 0) {
-          if (since == 0) break;  // an exact relabel found no active vertex
+        if (relabel) {
           t1 = wall_clock64();
           t_push += t1 - t0;
           t0 = t1;
@@ -1487,6 +1496,11 @@ __global__ void __launch_bounds__(TPB) k_flow(KArgs A, int32_t it) {
           cur = flist(V, sh, 0, lds);
           nxt = flist(V, sh, 1, lds);
           since = 0;
+          relabel = false;
+        }
+        if (cnt == 0) {
+          if (since == 0) break;  // an exact relabel found no active vertex
+          relabel = true;
           continue;
         }
         if (sweeps >= A.max_sweeps) {
@@ -1514,19 +1528,7 @@ __global__ void __launch_bounds__(TPB) k_flow(KArgs A, int32_t it) {
         cur = nxt;
         nxt = t;
         sweeps++;
-        if (++since >= A.relabel_period) {
-          t1 = wall_clock64();
-          t_push += t1 - t0;
-          t0 = t1;
-          cnt = global_relabel<TPB>(A, V, nr, NL, sh, R, gr_levels, lds);
-          t1 = wall_clock64();
-          t_rel += t1 - t0;
-          t0 = t1;
-          relabels++;
-          cur = flist(V, sh, 0, lds);
-          nxt = flist(V, sh, 1, lds);
-          since = 0;
-        }
+        if (++since >= A.relabel_period) relabel = true;
       }
       t1 = wall_clock64();
       t_push += t1 - t0;
