@@ -779,17 +779,18 @@ __device__ int32_t global_relabel(const KArgs &A, const PairView &V, int32_t nr,
       if (first) lput(start, pos, V.nv, (int32_t)i, A.ctl);
     }
   }
-  ListRef cur;
+  // the levels alternate between list slots 0 and 1: `nextl` takes the next
+  // level, `spare` is the other slot; swapped each level (a slot chosen by a
+  // run-time index would make the compiler keep both bases in scratch)
+  ListRef cur, nextl = flist(V, sh, 0, lds), spare = flist(V, sh, 1, lds);
   int32_t cnt, lev;
-  int which;  // next list slot
   if (term) {
     if (threadIdx.x == 0) sh.cnt[(R.c + 2) % 3] = 0;
     __syncthreads();
     R.c = (R.c + 1) % 3;
-    cur = flist(V, sh, 1, lds);
+    cur = spare;  // slot 1
     cnt = uni(min(sh.cnt[R.c], (int32_t)V.nv));
     lev = 1;
-    which = 0;
   } else {
     if (threadIdx.x == 0) sh.cnt[(R.c + 1) % 3] = 0;
     __syncthreads();
@@ -798,10 +799,9 @@ __device__ int32_t global_relabel(const KArgs &A, const PairView &V, int32_t nr,
     cur.ns = 0;
     cnt = uni(min(sh.nsnk, (int32_t)V.nv));
     lev = 0;
-    which = 0;
   }
   while (cnt > 0) {
-    const ListRef next = flist(V, sh, which, lds);
+    const ListRef next = nextl;
     int32_t *ncnt = &sh.cnt[(R.c + 1) % 3];
     const int32_t nl = lev + 1;
     for_groups<GTF>(cnt, [&](int item, bool valid, int gl) {
@@ -843,7 +843,8 @@ __device__ int32_t global_relabel(const KArgs &A, const PairView &V, int32_t nr,
     R.c = (R.c + 1) % 3;
     cnt = uni(min(sh.cnt[R.c], (int32_t)V.nv));
     cur = next;
-    which ^= 1;
+    nextl = spare;
+    spare = next;
     lev++;
   }
   levels += lev;
