@@ -49,6 +49,11 @@ CORRIDOR_ARC_BYTES = 36  # reverse-arc search and writes of head / reverse / res
 FLOW_KEYS = ("sweep_items", "sweep_arcs", "gr_items", "gr_arcs", "cl_items", "cl_arcs")
 
 
+def progress(msg: str):
+    """One line on stderr per finished leg (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def algorithmic_bytes(stats: dict, region_edges: int) -> int:
     """Bytes the whole solve path must move (every phase)."""
     b = sum(stats[k] * v for k, v in BYTES.items())
@@ -367,6 +372,8 @@ def run_balanced(args, fr, torch, gen):
                         "region_edges_per_s": float(stats[3]) / ds, "cut_after": int(cut),
                         "max_block_weight": int(bw.max())}
         out[name] = rnd
+        progress(f"quality leg {name}: round {rnd['round_ms']:.0f} ms, sweeps {ds:.1f} s, "
+                 f"cut {int(cut)}")
     ctx.close()
     out["cut_before"] = int(oracle.total_cut(w.graph, w.part))
     ref = out["smallest_source_set"]["sweep"]["cut_after"]
@@ -404,6 +411,7 @@ def main():
     fr.load()  # fails loudly when the HIP library is not built
 
     plain = run_plain(args, fr, torch, gen)
+    progress(f"C2 plain: {plain['wall'] * 1e3 / args.steps:.1f} ms per step")
     if args.copy_probe:
         x = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.int32, device="cuda")
         y = torch.empty_like(x)
@@ -468,15 +476,20 @@ def main():
             "seconds": dt,
         }
         line["bit_exact_vs_oracle"] = bool(exact)
+        progress(f"CPU baseline: {dt:.1f} s, bit-exact {exact}")
     if not args.no_batched:
         line["batched"] = run_batched(args, fr, torch, gen)
+        progress("C3 batched round done")
         line["batched_c5_round"] = run_batched(
             argparse.Namespace(batch_reps=1, no_cpu_baseline=args.no_cpu_baseline), fr, torch,
             gen, "C5")
+        progress("C5 batched round done")
     if not args.no_learned:
         line["learned_factor"] = run_learned(args, fr, torch, gen)
+        progress("C4 learned factor done")
     if not args.no_sweep:
         line["sweep"] = run_sweep(args, fr, torch, gen)
+        progress("C5 sweep done")
     if not args.no_balanced:
         line["balanced"] = run_balanced(args, fr, torch, gen)
     print(json.dumps(line), flush=True)
