@@ -1040,18 +1040,77 @@ static_assert(sizeof(PairState) % 8 == 0, "PairState is summed as 8-byte words")
 
 // ---- pair boundary (Sec. 4.1): vertices of a with a neighbour in b and vice
 //      versa become BFS level 0 (marked with the stamp S); also the pair cut
-//      and the boundary weight and size per side
+//      and the boundary weight and size per side.
+//      Every slot of a pair solves the same partition, so the boundary of a
+//      vertex is the same for all of them.  While the pairs still iterating
+//      cover a large part of the graph, the kernel walks the vertices once in
+//      id order (coalesced; the pair from the block) and hands each result to
+//      every live slot (one lane per vertex); late in a round, with few pairs
+//      left, it walks only their union lists, one item per slot.
 __global__ void __launch_bounds__(256) k_bnd(KArgs A, int32_t it) {
   const int32_t S = A.stamp0 + 2 * it;
   unsigned long long *acc = (unsigned long long *)A.pacc;
   unsigned long long *psw = (unsigned long long *)A.ps;
   // pair cut, boundary weight a / b, boundary count a / b, vertices, arcs
   KeyedSums<7> sums;
+  const int64_t total = A.vpre[*A.nact];  // union items of the live slots
+  if (4 * total >= (int64_t)A.n) {
+    // keyed by the pair's first entry; a flush adds to each live slot
+    auto out = [&](int j, int key, int64_t v) {
+      for (int32_t s = 0; s < A.W; s++) {
+        const int32_t q = key >= 0 && !A.ps[key + s].done ? key + s : -1;
+        if (j < 5) wave_add_by_key(acc, PA_N, PA_CUT + j, q, v);
+        else wave_add_by_key(psw, PS_WORDS, PS_WORK + (j == 5 ? W_BND_VERTS : W_BND_ARCS), q, v);
+      }
+    };
+    // one lane per vertex (64 vertices per wave): the chain of dependent
+    // loads per vertex is short, and many vertices are in flight per lane
+    for (int64_t b0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) & ~(int64_t)63; b0 < A.n;
+         b0 += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t u = b0 + lane64();
+      int32_t p0 = -1, side = 0, deg = 0;
+      bool bnd = false;
+      int64_t cw = 0;
+      if (u < A.n) {
+        const int32_t pv = A.part[u];
+        p0 = A.blk2pair[pv];
+        bool live = false;
+        for (int32_t s = 0; s < A.W && p0 >= 0 && !live; s++) live = !A.ps[p0 + s].done;
+        if (!live) p0 = -1;
+        if (p0 >= 0) {
+          const int32_t a = A.pairs[2 * p0], b = A.pairs[2 * p0 + 1];
+          side = pv == b;
+          const int32_t y = side ? a : b;
+          const int32_t e0 = A.xadj[u], e1 = A.xadj[u + 1];
+          deg = e1 - e0;
+          for (int32_t e = e0; e < e1; e++) {
+            if (A.part[A.adjncy[e]] == y) {
+              bnd = true;
+              if (!side) cw += A.adjwgt[e];
+            }
+          }
+        }
+      }
+      const bool bl = p0 >= 0 && bnd;
+      const int64_t w = bl ? A.vwgt[u] : 0;
+      const int64_t x[7] = {cw, bl && !side ? w : 0, bl && side ? w : 0, bl && !side ? 1 : 0,
+                            bl && side ? 1 : 0, 1, deg};
+      sums.add(p0, x, out);
+      for (int32_t s = 0; s < A.W; s++) {
+        const int32_t p = bl && !A.ps[p0 + s].done ? p0 + s : -1;
+        if (p >= 0) mark_of(A, p)[u] = S;
+        const int pos = wave_append_by_key(A.pcnt, p);
+        if (p >= 0) put_bounded(A.LA + A.voff[p], pos, A.voff[p + 1] - A.voff[p], (int32_t)u, A.ctl);
+      }
+    }
+    sums.flush(out);
+    return;
+  }
   auto out = [&](int j, int key, int64_t v) {
     if (j < 5) wave_add_by_key(acc, PA_N, PA_CUT + j, key, v);
     else wave_add_by_key(psw, PS_WORDS, PS_WORK + (j == 5 ? W_BND_VERTS : W_BND_ARCS), key, v);
   };
-  grid_groups<GT>(A.vpre[*A.nact], [&](int64_t i, bool valid, int gl) {
+  grid_groups<GT>(total, [&](int64_t i, bool valid, int gl) {
     int32_t p;
     const int64_t slot = active_item(A, A.vpre, i, valid, p);
     const bool on = p >= 0;
