@@ -929,30 +929,28 @@ __device__ __forceinline__ int32_t *vmap_of(const KArgs &A, int32_t p) {
   return A.vmap + (int64_t)(p % A.W) * A.mstride;
 }
 
-// Grid-wide version of for_groups: G lanes per item over 0..N-1, the trip
-// count uniform over each wave.
-template <int G, typename F>
-__device__ __forceinline__ void grid_groups(int64_t N, F &&f) {
-  const int gl = lane64() & (G - 1);
-  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t wf = (gt & ~(int64_t)63) / G;
-  const int64_t gid = gt / G;
-  const int64_t step = (int64_t)gridDim.x * blockDim.x / G;
-  for (int64_t base = wf; base < N; base += step) {
-    const int64_t item = base + (gid - wf);
-    f(item, item < N, gl);
+// Items of the compacted range of the live slots (pre = vpre or cpre), one
+// lane each: f(p, item) with p the slot and item the offset inside it (p = -1
+// past the end).  The wave's first item finds its slot by binary search, the
+// other lanes step on from there (a wave's 64 items span few slots).  The
+// trip count is uniform over each wave.
+template <typename F>
+__device__ __forceinline__ void grid_items(const KArgs &A, const int64_t *pre, F &&f) {
+  const int32_t na = *A.nact;
+  const int64_t N = pre[na];
+  for (int64_t b0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) & ~(int64_t)63; b0 < N;
+       b0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = b0 + lane64();
+    int32_t p = -1;
+    int64_t item = 0;
+    if (i < N) {
+      int32_t j = pair_of(pre, na, b0);
+      while (pre[j + 1] <= i) j++;  // ends below na: i < pre[na]
+      p = A.act[j];
+      item = i - pre[j];
+    }
+    f(p, item);
   }
-}
-
-// Item i of the compacted range of the pairs still iterating: the pair p and
-// the item's offset inside that pair (pre = vpre or cpre); p = -1 past the end.
-__device__ __forceinline__ int64_t active_item(const KArgs &A, const int64_t *pre, int64_t i,
-                                               bool valid, int32_t &p) {
-  p = -1;
-  if (!valid) return -1;
-  const int32_t j = pair_of(pre, *A.nact, i);
-  p = A.act[j];
-  return i - pre[j];
 }
 
 // Per-lane running sums of N per-pair quantities, added to their per-pair
@@ -1110,9 +1108,7 @@ __global__ void __launch_bounds__(256) k_bnd(KArgs A, int32_t it) {
     if (j < 5) wave_add_by_key(acc, PA_N, PA_CUT + j, key, v);
     else wave_add_by_key(psw, PS_WORDS, PS_WORK + (j == 5 ? W_BND_VERTS : W_BND_ARCS), key, v);
   };
-  grid_groups<GT>(total, [&](int64_t i, bool valid, int gl) {
-    int32_t p;
-    const int64_t slot = active_item(A, A.vpre, i, valid, p);
+  grid_items(A, A.vpre, [&](int32_t p, int64_t slot) {
     const bool on = p >= 0;
     const int32_t a = on ? A.pairs[2 * p] : 0, b = on ? A.pairs[2 * p + 1] : 0;
     // the union list is held by the pair's first entry
@@ -1122,16 +1118,13 @@ __global__ void __launch_bounds__(256) k_bnd(KArgs A, int32_t it) {
     const int32_t e0 = on ? A.xadj[u] : 0, e1 = on ? A.xadj[u + 1] : 0;
     bool bnd = false;
     int64_t cw = 0;
-    for (int32_t a0 = e0; a0 < e1; a0 += GT) {
-      const int32_t e = a0 + gl;
-      if (e < e1 && A.part[A.adjncy[e]] == y) {
+    for (int32_t e = e0; e < e1; e++) {
+      if (A.part[A.adjncy[e]] == y) {
         bnd = true;
         if (!side) cw += A.adjwgt[e];
       }
     }
-    bnd = group_any<GT>(bnd);
-    cw = group_sum<GT>(cw);
-    const bool lead = on && gl == 0;
+    const bool lead = on;
     const bool bl = lead && bnd;
     const int64_t w = bl ? A.vwgt[u] : 0;
     if (bl) mark_of(A, p)[u] = S;
@@ -1319,9 +1312,7 @@ __global__ void __launch_bounds__(256) k_net_count(KArgs A, int32_t it) {
     else if (j == 5) wave_add_by_key(acc, PA_N, PA_CS, key, v);
     else wave_add_by_key(psw, PS_WORDS, PS_WORK + (j == 3 ? W_NET_VERTS : W_NET_ARCS), key, v);
   };
-  grid_groups<GT>(A.cpre[*A.nact], [&](int64_t i0, bool valid, int gl) {
-    int32_t p;
-    const int64_t item = active_item(A, A.cpre, i0, valid, p);
+  grid_items(A, A.cpre, [&](int32_t p, int64_t item) {
     const int64_t i = p >= 0 ? A.voff[p] + item : 0;  // arena slot
     const bool on = p >= 0;
     const int32_t a = on ? A.pairs[2 * p] : 0, b = on ? A.pairs[2 * p + 1] : 0;
@@ -1331,9 +1322,7 @@ __global__ void __launch_bounds__(256) k_net_count(KArgs A, int32_t it) {
     const int32_t e0 = on ? A.xadj[u] : 0, e1 = on ? A.xadj[u + 1] : 0;
     int64_t cnt = 0, cap = 0, cin = 0, cs = 0, ct = 0;
     bool border = false;
-    for (int32_t a0 = e0; a0 < e1; a0 += GT) {
-      const int32_t e = a0 + gl;
-      if (e >= e1) continue;
+    for (int32_t e = e0; e < e1; e++) {
       const int32_t v = A.adjncy[e];
       const int32_t xv = A.part[v];
       if (xv != a && xv != b) continue;
@@ -1348,18 +1337,10 @@ __global__ void __launch_bounds__(256) k_net_count(KArgs A, int32_t it) {
         if (term && xv != (side ? b : a)) cin += A.adjwgt[e];
       }
     }
-    border = group_any<GT>(border) && !term;
-    cnt = group_sum<GT>(cnt);
-    cap = group_sum<GT>(cap);
-    cin = group_sum<GT>(cin);
-    if (term) {
-      cs = group_sum<GT>(cs);
-      ct = group_sum<GT>(ct);
-      cap += cs + ct;
-    } else {
-      cs = 0;
-    }
-    const bool lead = on && gl == 0;
+    border = border && !term;
+    if (term) cap += cs + ct;
+    else cs = 0;
+    const bool lead = on;
     if (lead) {
       A.lo[i + p + 1] = (int32_t)cnt;  // the pair's offsets start at voff[p] + p
       A.lflag[i] = (uint8_t)((side ? LF_SIDE_B : 0u) | (border ? LF_BORDER : 0u));
@@ -1370,7 +1351,6 @@ __global__ void __launch_bounds__(256) k_net_count(KArgs A, int32_t it) {
     }
     const int64_t x[6] = {cnt, cap, cin, 1, e1 - e0, cs};
     sums.add(lead ? p : -1, x, out);
-    (void)item;
   });
   sums.flush(out);
 }
@@ -1413,38 +1393,44 @@ __global__ void __launch_bounds__(1024) k_net_scan(KArgs A, int32_t it) {
 // pass 3: arcs (local head and capacity) in the order of the global adjacency
 __global__ void __launch_bounds__(256) k_net_fill(KArgs A, int32_t it) {
   const int32_t S = A.stamp0 + 2 * it;
-  grid_groups<GT>(A.cpre[*A.nact], [&](int64_t i0, bool valid, int gl) {
-    int32_t p;
-    const int64_t item = active_item(A, A.cpre, i0, valid, p);
-    const int64_t i = p >= 0 ? A.voff[p] + item : 0;  // arena slot
-    const bool on = p >= 0;
-    const int32_t a = on ? A.pairs[2 * p] : 0, b = on ? A.pairs[2 * p + 1] : 0;
-    const int32_t u = on ? A.lg[i] : 0;
-    const int32_t *mk = on ? mark_of(A, p) : A.mark;
-    const int32_t *vm = on ? vmap_of(A, p) : A.vmap;
-    const int32_t e0 = on ? A.xadj[u] : 0, e1 = on ? A.xadj[u + 1] : 0;
-    const int64_t ab = on ? A.aoff[p] : 0;
-    const int64_t na = on ? A.aoff[p + 1] - ab : 0;
-    int32_t k = on ? A.lo[i + p] : 0;
-    for (int32_t a0 = e0; a0 < e1; a0 += GT) {
-      const int32_t e = a0 + gl;
-      int32_t v = 0;
-      bool in = false;
-      if (e < e1) {
-        v = A.adjncy[e];
-        const int32_t xv = A.part[v];
-        in = (xv == a || xv == b) && mk[v] == S;
+  grid_items(A, A.cpre, [&](int32_t p, int64_t item) {
+    if (p < 0) return;
+    const int64_t i = A.voff[p] + item;  // arena slot
+    const int32_t a = A.pairs[2 * p], b = A.pairs[2 * p + 1];
+    const int32_t u = A.lg[i];
+    const int32_t *mk = mark_of(A, p);
+    const int32_t *vm = vmap_of(A, p);
+    const int32_t e0 = A.xadj[u], e1 = A.xadj[u + 1];
+    const int64_t ab = A.aoff[p];
+    const int64_t na = A.aoff[p + 1] - ab;
+    int32_t k = A.lo[i + p];
+    // four arcs per step, their loads issued together
+    for (int32_t c = e0; c < e1; c += 4) {
+      int32_t v[4], w[4], xv[4], mv[4];
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const bool in = c + q < e1;
+        v[q] = in ? A.adjncy[c + q] : 0;
+        w[q] = in ? A.adjwgt[c + q] : 0;
       }
-      int32_t tot;
-      const int32_t off = group_exscan<GT>(in ? 1 : 0, &tot);
-      if (in && k + off < na) {
-        Arc &x = A.arc[ab + k + off];
-        x.lh = vm[v];
-        x.rc = res_pair(A.adjwgt[e], A.adjwgt[e]);
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const bool in = c + q < e1;
+        xv[q] = in ? A.part[v[q]] : -1;
+        mv[q] = in ? mk[v[q]] : S - 1;
       }
-      k += tot;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        if ((xv[q] == a || xv[q] == b) && mv[q] == S) {
+          if (k < na) {
+            Arc &x = A.arc[ab + k];
+            x.lh = vm[v[q]];
+            x.rc = res_pair(w[q], w[q]);
+          }
+          k++;
+        }
+      }
     }
-    (void)item;
   });
 }
 
@@ -1452,9 +1438,7 @@ __global__ void __launch_bounds__(256) k_net_fill(KArgs A, int32_t it) {
 // border is saturated), cleared closure marks, the sink list
 __global__ void __launch_bounds__(256) k_net_rev(KArgs A, int32_t it) {
   (void)it;
-  grid_groups<GT>(A.cpre[*A.nact], [&](int64_t i0, bool valid, int gl) {
-    int32_t p;
-    const int64_t item64 = active_item(A, A.cpre, i0, valid, p);
+  grid_items(A, A.cpre, [&](int32_t p, int64_t item64) {
     const bool on = p >= 0;
     const int32_t item = (int32_t)item64;
     bool overflow = false;
@@ -1472,12 +1456,18 @@ __global__ void __launch_bounds__(256) k_net_rev(KArgs A, int32_t it) {
     const bool snk = on && LF_SNK(f);
     const int32_t b0 = on ? lo[item] : 0, e0 = on ? lo[item + 1] : 0;
     int64_t ex = 0;
-    for (int32_t a0 = b0; a0 < e0; a0 += GT) {
-      const int32_t ar = a0 + gl;
-      if (ar >= e0) continue;
+    for (int32_t ar = b0; ar < e0; ar++) {
       const int32_t j = arc[ar].lh;
       const int32_t je = lo[j + 1];
       int32_t r = lo[j];
+      // the reverse arc: the head's arc list is short; four heads per step
+      for (; r + 3 < je; r += 4) {
+        const int32_t h0 = arc[r].lh, h1 = arc[r + 1].lh, h2 = arc[r + 2].lh, h3 = arc[r + 3].lh;
+        if (h0 == item) break;
+        if (h1 == item) { r += 1; break; }
+        if (h2 == item) { r += 2; break; }
+        if (h3 == item) { r += 3; break; }
+      }
       while (r < je && arc[r].lh != item) r++;
       if (r == je) {  // asymmetric input slipped past validation
         A.ctl->err = FR_E_INVALID_GRAPH;
@@ -1492,8 +1482,7 @@ __global__ void __launch_bounds__(256) k_net_rev(KArgs A, int32_t it) {
         arc[r].rc = res_pair(0, 2 * c);
       }
     }
-    ex = group_sum<GT>(ex);
-    if (on && gl == 0) {
+    if (on) {
       if (!A.terminals) A.ex[vb + item] = src ? 0 : (int32_t)ex;  // else: the s -> u capacity
       A.ins[vb + item] = 0;
       if (overflow) {
@@ -1501,9 +1490,8 @@ __global__ void __launch_bounds__(256) k_net_rev(KArgs A, int32_t it) {
         A.ctl->diag = DIAG_OVERFLOW;
       }
     }
-    const bool lead = snk && gl == 0;
-    const int pos = wave_append_by_key(A.pcnt + A.P, lead ? p : -1);
-    if (lead) put_bounded(A.SNK + vb, pos, A.voff[p + 1] - vb, item, A.ctl);
+    const int pos = wave_append_by_key(A.pcnt + A.P, snk ? p : -1);
+    if (snk) put_bounded(A.SNK + vb, pos, A.voff[p + 1] - vb, item, A.ctl);
   });
 }
 
