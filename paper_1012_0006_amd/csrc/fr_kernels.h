@@ -641,13 +641,9 @@ struct Rot {
   int c = 0;
 };
 
-// Lanes per list item in the frontier passes (BFS, relabel, closure, build):
-// the arcs of one vertex are read by GT lanes at once instead of one after
-// the other, so a level costs a few dependent memory latencies, not one per
-// arc.
-#define GT 8
-// The same for the searches of the flow phases (relabel, closure): GTF lanes
-// per item, each with KF arcs in flight.
+// Lanes per list item in the searches of the flow phases (relabel, closure):
+// the arcs of one vertex are read by GTF lanes at once, each with KF arcs in
+// flight, so a level costs a few dependent memory latencies, not one per arc.
 #define GTF 4
 #define KF 2
 
@@ -663,32 +659,6 @@ __device__ __forceinline__ void for_groups(int32_t N, F &&f) {
     const int item = base + (gid - wf);
     f(item, item < N, gl);
   }
-}
-
-template <int G>
-__device__ __forceinline__ int64_t group_sum(int64_t v) {
-  for (int o = G >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
-  return v;
-}
-
-template <int G>
-__device__ __forceinline__ bool group_any(bool b) {
-  const unsigned long long m = __ballot(b);
-  const int sh = lane64() & ~(G - 1);
-  return ((m >> sh) & ((G == 64) ? ~0ull : ((1ull << G) - 1ull))) != 0ull;
-}
-
-// exclusive prefix of v inside the group; *total = the group sum
-template <int G>
-__device__ __forceinline__ int32_t group_exscan(int32_t v, int32_t *total) {
-  const int gl = lane64() & (G - 1);
-  int32_t inc = v;
-  for (int o = 1; o < G; o <<= 1) {
-    const int32_t t = __shfl_up(inc, o, G);
-    if (gl >= o) inc += t;
-  }
-  *total = __shfl(inc, G - 1, G);
-  return inc - v;
 }
 
 // Sets the bitmap words of vertices 0..nr-1 to the ballot of pred(i) (one
