@@ -353,3 +353,40 @@ def test_batch_at_the_pair_limit(gpu_lib, ctx):
         gpu_lib.flow_refine_batch(ctx, dg, dpart2, k, too_many, gpu_lib.params(**p))
     assert e.value.code == -8
     assert np.array_equal(dpart2.cpu().numpy(), part)
+
+
+@pytest.mark.parametrize("spec", [False, True])
+def test_boundary_pass_modes(gpu_lib, spec):
+    """The boundary pass walks all vertices once (results handed to every
+    live slot) while the live pairs cover at least a quarter of the graph, and
+    the live pairs' vertex lists otherwise: one pair of a 64-way partition
+    without speculation takes the lists, a whole matching round the vertex
+    walk (and the lists once most pairs stopped); both against the oracle."""
+    import torch
+
+    g = gen.rgg(1 << 14, 2, 8.0, 57, 1, 4)
+    part = gen.rcb(g, 64)
+    gen.global_noise(g, part, 0.02, 57)
+    p = dict(area_mode=0, depth=0, alpha=16, alpha_max=16, adaptive=1, max_iters=16,
+             eps_ppm=30000)
+    edges, colour = oracle.quotient_colouring(g, part, 64)
+    c = gpu_lib.Context()
+    try:
+        c.set_speculation(spec)
+        a, b = (int(x) for x in edges[0])
+        _compare_pair(gpu_lib, c, g, part, 64, a, b, p)
+        cls = int(np.argmax(np.bincount(colour)))
+        pairs = [tuple(e) for e, cc in zip(edges.tolist(), colour) if cc == cls]
+        print(f"round of {len(pairs)} pairs, speculation {spec}", flush=True)
+        rc, ores, otr, opart = oracle.refine_batch(g, part, 64, pairs, p)
+        assert rc == 0
+        dpart = torch.as_tensor(part.copy()).cuda()
+        res, trace = gpu_lib.flow_refine_batch(c, gpu_lib.DeviceGraph.from_host(g), dpart, 64,
+                                               pairs, _prm(gpu_lib, p))
+        for i in range(len(pairs)):
+            for key in RESULT_KEYS:
+                assert res[i][key] == ores[i][key], (i, key)
+            assert trace[i] == otr[i]
+        assert np.array_equal(dpart.cpu().numpy(), opart)
+    finally:
+        c.close()
