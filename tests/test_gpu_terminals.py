@@ -196,3 +196,19 @@ def test_rejects_unknown_mode(gpu_lib, ctx):
     with pytest.raises(gpu_lib.FlowRefineError) as e:
         gpu_lib.flow_refine_pair(ctx, g, part, 2, 0, 1, gpu_lib.params(terminals=2))
     assert e.value.code == -8
+
+
+def test_contracted_capacity_overflow(gpu_lib, ctx):
+    # vertex 1 (block 0, on the boundary) has three edges of weight 2^30 - 1
+    # into block 0 outside the boundary-only corridor: pinned, they are not
+    # capacities at all; contracted, they make the arc s -> 1 exceed 2^31
+    w = (1 << 30) - 1
+    g = csr_from_edges(6, [(1, 0), (1, 2), (1, 3), (1, 4), (4, 5)], weights=[w, w, w, 1, 1])
+    part = np.array([0, 0, 0, 0, 1, 1], dtype=np.int32)
+    p = dict(area_mode=1, depth=0, alpha=1, alpha_max=1, adaptive=0, max_iters=1,
+             eps_ppm=30000)
+    _compare(gpu_lib, ctx, g, part, 2, 0, 1, p)
+    with pytest.raises(gpu_lib.FlowRefineError) as e:
+        gpu_lib.flow_refine_pair(ctx, g, part, 2, 0, 1, _prm(gpu_lib, dict(p, terminals=1)))
+    assert e.value.code == -5
+    assert gpu_lib.stats_dict(ctx)["diag"] == 5  # the capacity bound of the network
