@@ -91,6 +91,15 @@ def test_round_fm_then_most_balanced_sampled(gpu_lib, ctx, cid):
                      extra=dict(fm_limit=100, fm_seed=1, mb_reps=16, mb_seed=1))
 
 
+@pytest.mark.parametrize("cid", ["C3", "C5"])
+def test_round_fm_then_flow_sampled(gpu_lib, ctx, cid):
+    """The largest round of C3 / C5 with 2-way FM before the plain flow, as
+    the benchmark's quality leg runs it."""
+    w = gen.config(cid)
+    print(f"{cid} largest round, FM then flow", flush=True)
+    _round_vs_oracle(gpu_lib, ctx, w, sample=3, extra=dict(fm_limit=100, fm_seed=1))
+
+
 @pytest.mark.parametrize("cid", ["C2", "C3", "C5"])
 def test_round_contracted_terminals_sampled(gpu_lib, ctx, cid):
     """The largest round of C3 / C5 (C2: its one pair) with the blocks'
