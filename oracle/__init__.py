@@ -212,7 +212,7 @@ def mbcut(nn: int, tails, heads, caps, s: int, t: int, w, gid, base_s: int, base
     smin = np.zeros(nn, dtype=np.uint8)
     cls = np.zeros(nn, dtype=np.int8)
     comp = np.zeros(nn, dtype=np.int32)
-    info = np.zeros(7, dtype=np.int64)
+    info = np.zeros(6, dtype=np.int64)
     val = ctypes.c_int64(0)
     rc = _load().or_mbcut(nn, tails.shape[0], _ptr(tails), _ptr(heads), _ptr(caps), s, t,
                           _ptr(w), _ptr(gid), base_s, base_t, reps, seed & 0xFFFFFFFF,
@@ -220,7 +220,7 @@ def mbcut(nn: int, tails, heads, caps, s: int, t: int, w, gid, base_s: int, base
                           _ptr(info))
     if rc != 0:
         raise ValueError("or_mbcut: bad input")
-    keys = ("ncomp", "reduced", "reduced_arcs", "limited", "best_rep", "best_pos", "best_bal")
+    keys = ("ncomp", "reduced", "reduced_arcs", "best_rep", "best_pos", "best_bal")
     return MBCut(int(val.value), src.astype(bool), smin.astype(bool), cls, comp,
                  dict(zip(keys, info.tolist())))
 

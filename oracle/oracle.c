@@ -59,8 +59,7 @@
  *       weights; a random topological order takes, among the components whose
  *       predecessors are all placed, the one with the smallest key, keys from
  *       SplitMix64; first best wins (earlier sweep, then earlier position);
- *       more than OR_MB_MAX_COMP remaining components keep the smallest
- *       source set
+ *       the sweeps run for any number of remaining components
  */
 #include <math.h>
 #include <stdint.h>
@@ -338,8 +337,6 @@ int32_t or_maxflow(int32_t nn, int64_t narcs, const int32_t *tails, const int32_
 /* ------------------------------------------------------------------------ */
 /* most balanced minimum cut (Sec. 4.1.1)                                    */
 
-#define OR_MB_MAX_COMP 2048
-
 /* SplitMix64 (Steele, Lea & Flood, "Fast splittable pseudorandom number
  * generators", OOPSLA 2014): the generator started at `seed` adds the golden
  * gamma to its state per call and returns the state through a 64-bit finaliser
@@ -428,7 +425,6 @@ typedef struct {
   int32_t ncomp;      /* components of the residual graph */
   int32_t reduced;    /* components left after removing the s and t closures */
   int32_t reduced_arcs;
-  int32_t limited;    /* more than OR_MB_MAX_COMP components left: smallest source set kept */
   int32_t best_rep;   /* sweep and position of the chosen cut (-1: none) */
   int32_t best_pos;
   int64_t best_bal;   /* max(source side weight, sink side weight) of the chosen cut */
@@ -531,8 +527,7 @@ static int32_t net_mb_cut(const or_net *N, int32_t s, int32_t t, const int64_t *
       for (int64_t j = fo[c]; j < fo[c + 1]; j++) info->reduced_arcs += cl[fa[j]] == 1;
   int32_t best_r = -1, best_j = 0;
   int64_t best = 0;
-  if (nrem > OR_MB_MAX_COMP) info->limited = 1;
-  if (nrem > 0 && reps > 0 && !info->limited) {
+  if (nrem > 0 && reps > 0) {
     /* sweeps: a random topological order of the remaining components moves
      * them one by one to the sink side; the first most balanced cut wins */
     for (int32_t r = 0; r < reps; r++) {
@@ -621,8 +616,8 @@ int32_t or_scc(int32_t nn, int64_t narcs, const int32_t *tails, const int32_t *h
 /* Max flow, then the most balanced minimum cut, on an explicit network (arcs
  * with zero-capacity reverses).  w, gid: [nn] node weights and key ids.
  * Outputs (each [nn]): src (chosen source side), smin (smallest source set),
- * cls, comp; info[7] = ncomp, reduced, reduced_arcs, limited, best_rep,
- * best_pos, best_bal.  Returns 0, or -1 on bad input. */
+ * cls, comp; info[6] = ncomp, reduced, reduced_arcs, best_rep, best_pos,
+ * best_bal.  Returns 0, or -1 on bad input. */
 int32_t or_mbcut(int32_t nn, int64_t narcs, const int32_t *tails, const int32_t *heads,
                  const int64_t *caps, int32_t s, int32_t t, const int64_t *w, const int32_t *gid,
                  int64_t base_s, int64_t base_t, int32_t reps, uint32_t seed, int64_t *flow_out,
@@ -646,8 +641,8 @@ int32_t or_mbcut(int32_t nn, int64_t narcs, const int32_t *tails, const int32_t 
   or_mbinfo mi;
   int32_t rc = net_mb_cut(&N, s, t, w, gid, base_s, base_t, reps, (uint64_t)seed, src, cls,
                           comp, &mi);
-  info[0] = mi.ncomp; info[1] = mi.reduced; info[2] = mi.reduced_arcs; info[3] = mi.limited;
-  info[4] = mi.best_rep; info[5] = mi.best_pos; info[6] = mi.best_bal;
+  info[0] = mi.ncomp; info[1] = mi.reduced; info[2] = mi.reduced_arcs;
+  info[3] = mi.best_rep; info[4] = mi.best_pos; info[5] = mi.best_bal;
   net_free(&N);
   return rc;
 }

@@ -218,6 +218,60 @@ def test_antichain_sweep_follows_ascending_keys(seed):
     assert np.array_equal(res.src, best[1])
 
 
+@pytest.mark.parametrize("k", [2049, 3001, 5000])
+def test_long_chain_beyond_two_thousand_components(k):
+    """A path s - v1 - ... - vk - t of unit capacities: after the flow every
+    inner node is a component of its own (more than 2,048 of them), the
+    minimum cuts are the k + 1 prefix cuts, and the sweep must still run:
+    the chosen source side {s, v1..vj} minimises max(base_s + j, base_t +
+    k - j), the largest such j on ties (the sweep starts from the largest
+    source side).  Unit weights make that j a closed form."""
+    s, t = k, k + 1
+    nodes = [s] + list(range(k)) + [t]
+    arcs = []
+    for u, v in zip(nodes[:-1], nodes[1:]):
+        arcs += [(u, v, 1), (v, u, 1)]
+    w = np.concatenate([np.ones(k, dtype=np.int64), [0, 0]])
+    base_s, base_t = 7, 3
+    res = _run(k + 2, arcs, s, t, w, base_s, base_t, 2, 11)
+    assert res.flow == 1 and res.info["reduced"] == k
+    bals = [max(base_s + j, base_t + k - j) for j in range(k + 1)]
+    best = min(bals)
+    j = max(i for i, b in enumerate(bals) if b == best)
+    want = np.zeros(k + 2, dtype=bool)
+    want[:j] = True
+    want[s] = True
+    assert np.array_equal(res.src, want)
+
+
+def test_wide_antichain_beyond_two_thousand_components():
+    """2,500 independent components (saturated s -> x_i -> t arcs): one
+    sweep moves them to the sink side in ascending key order; the chosen cut
+    is the first best prefix of that order, computed here from the
+    generator module's SplitMix64."""
+    k, mseed = 2500, 2024
+    rng = np.random.default_rng(4)
+    s, t = k, k + 1
+    arcs = [(s, i, 1) for i in range(k)] + [(i, t, 1) for i in range(k)]
+    w = np.concatenate([rng.integers(0, 5, k), [0, 0]])
+    gid = np.concatenate([rng.permutation(10 * k)[:k], [2**31 - 1, 2**31 - 1]])
+    base_s, base_t = 0, 1000
+    order = sorted(range(k), key=lambda i: _key(mseed, 0, int(gid[i])))
+    ws, wt = base_s + int(w[:k].sum()), base_t
+    best, bj = max(ws, wt), 0
+    for j, i in enumerate(order, 1):
+        ws -= int(w[i])
+        wt += int(w[i])
+        if max(ws, wt) < best:
+            best, bj = max(ws, wt), j
+    want = np.ones(k + 2, dtype=bool)
+    want[t] = False
+    want[order[:bj]] = False
+    res = _run(k + 2, arcs, s, t, w, base_s, base_t, 1, mseed, gid=gid)
+    assert res.info["reduced"] == k
+    assert np.array_equal(res.src, want)
+
+
 # ------------------------------------------------------- pair refinement --
 
 def _ladder(cols):
