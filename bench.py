@@ -1,19 +1,26 @@
 """Benchmark of max-flow min-cut pair refinement on one MI355X.
 
-A step is one adaptive flow refinement of the bisection of a 2D random
-geometric graph (n = 2^18, mean degree 8, edge weights 1..10, median-x split
-with 2 % boundary noise, eps = 3 %, alpha 16 adaptive): boundary, bounded BFS
-corridor, network, max preflow, smallest source set, balance check, adaptive
-factor, write-back -- every solve of the loop.  Inputs are resident in device
-memory before the timed region; each step starts from the same partition.
+A step is one full refinement of C5: a 2D random geometric graph (n = 2^24,
+mean degree 6, unit weights) cut into k = 256 blocks by recursive coordinate
+bisection with 1 % boundary noise, eps = 3 %, swept over the colour classes of
+its quotient graph until no pair improves.  Every pair of a class is refined
+in one batched round (boundary, bounded BFS corridors, networks, max preflow,
+smallest source set, balance check, adaptive factor from the learned start,
+write-back).  Inputs are resident in device memory before the timed region;
+each step starts from the same partition.
 
-Printed: one JSON line with region edges/s (corridor edges summed over the
-solves the adaptive loop records, divided by wall time), the roofline of the
-flow kernel (k_flow: relabels, push/relabel passes, closure), the CPU oracle
-on the same input, and beside it: batched vs plain on the largest matching
-round of C3 (3D RGG n = 2^20, k = 16, autotuned launch) and of C5 (2D RGG
-n = 2^24, k = 256), plain vs learned start factor on one sweep of C4 (2D RGG
-n = 2^22, k = 64), and a C5 sweep to convergence.
+Printed: one JSON line with region edges/s of those steps (corridor edges
+summed over the solves the adaptive loops record, divided by wall time), the
+roofline of the flow kernel over the same steps (k_flow: relabels,
+push/relabel passes, closure; HIP events around each of its launches), the
+CPU oracle on the largest round of the same workload, and beside it: the C2
+plain pair refinement (2D RGG n = 2^18), batched vs plain on the largest
+matching round of C3 (3D RGG n = 2^20, k = 16, autotuned launch) and of C5,
+plain vs learned start factor on one sweep of C4 (2D RGG n = 2^22, k = 64),
+and the quality leg (most balanced cuts, FM, contracted terminals on C5).
+
+``python bench.py --summarize KIND DIR ...`` turns rocprofv3 output copied
+back from the GPU machine into the summaries under profiles/ (see summarize()).
 """
 from __future__ import annotations
 
@@ -67,9 +74,16 @@ def flow_bytes(stats: dict) -> int:
 
 
 def kernel_source_hash() -> str:
+    """Hash of every source compiled into the library (all of csrc/ and the
+    public header), so a counter profile goes stale with any kernel change."""
     h = hashlib.sha256()
-    for f in ("fr_kernels.h", "fr_internal.h", "flowrefine.hip"):
-        with open(os.path.join(ROOT, "paper_1012_0006_amd", "csrc", f), "rb") as fh:
+    csrc = os.path.join(ROOT, "paper_1012_0006_amd", "csrc")
+    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc)
+                   if f.endswith((".h", ".hip")))
+    files.append(os.path.join(ROOT, "include", "flowrefine.h"))
+    for f in files:
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -139,26 +153,6 @@ def run_cpu_baseline(w):
     return o, dt
 
 
-def run_cpu_parallel(w, pairs, threads):
-    """The oracle on the pairs of one round (independent: disjoint blocks),
-    spread over a thread pool on the host; region edges/s of the sample."""
-    import oracle
-    from concurrent.futures import ThreadPoolExecutor
-
-    def one(ab):
-        return oracle.refine_pair(w.graph, w.part, w.k, ab[0], ab[1], w.params,
-                                  want_side=False).result["region_edges"]
-
-    t0 = time.perf_counter()
-    with ThreadPoolExecutor(max_workers=threads) as pool:
-        edges = sum(pool.map(one, pairs))
-    dt = time.perf_counter() - t0
-    return {"value": edges / dt, "unit": "region edges/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(pairs)} pairs of the same round, each the sequential oracle, "
-                      f"spread over {threads} host threads",
-            "seconds": dt}
-
-
 def run_batched(args, fr, torch, gen, cid="C3"):
     """The largest matching round of a workload (C3: 3D RGG n=2^20, mean
     degree 12, k=16 RCB + 2 % noise; C5: 2D RGG n=2^24, k=256): all pairs in
@@ -211,9 +205,6 @@ def run_batched(args, fr, torch, gen, cid="C3"):
     ctx.close()
     e_b = sum(r["region_edges"] for r in res_b)
     e_p = sum(r["region_edges"] for r in res_p)
-    cpu = None
-    if cid == "C5" and not args.no_cpu_baseline:
-        cpu = run_cpu_parallel(w, pairs[:32], 16)
     same = bool(np.array_equal(part_b, part_p)) and all(
         rb["cut_after"] == rp["cut_after"] for rb, rp in zip(res_b, res_p))
     desc = {"C3": "C3: 3D RGG n=2^20 mean degree 12 unit weights, k=16 RCB + 2% noise",
@@ -230,7 +221,6 @@ def run_batched(args, fr, torch, gen, cid="C3"):
         "speedup": t_p / t_b,
         "equal_result": same,
         "tuning": tuning,
-        "cpu_parallel": cpu,
         "region_edges": e_b,
     }
 
@@ -277,33 +267,132 @@ def run_learned(args, fr, torch, gen):
     return out
 
 
-def run_sweep(args, fr, torch, gen):
-    """C5 (2D RGG n=2^24, mean degree 6, unit weights, k=256 RCB + 1 % noise):
-    sweeps over the quotient-graph colour classes until no pair improves, each
-    sweep one hipGraph replay, start factors from the learned network."""
+C5_WORKLOAD = ("C5: 2D RGG n=2^24 mean degree 6 unit weights, k=256 RCB + 1% noise, eps 3%, "
+               "alpha' 16 adaptive with learned start, batched rounds over the quotient-graph "
+               "colour classes, swept until no pair improves")
+
+
+def c5_params(fr, w, use_mlp):
+    return fr.params(**{k: w.params[k] for k in ("area_mode", "depth", "alpha", "alpha_max",
+                                                 "adaptive", "max_iters", "eps_ppm")},
+                     use_mlp=use_mlp)
+
+
+def run_c5_headline(args, fr, torch, gen):
+    """C5 refined to convergence per step (learned start factors, every colour
+    class one batched round), timed over args.steps steps after args.warmup
+    untimed ones; with per-phase timing on, each k_flow launch sits between
+    HIP events on the library's stream."""
     import oracle  # cut of the start partition only
 
     w = gen.config("C5")
     ctx = fr.Context()
+    ctx.set_validation(False)  # inputs are generated valid
+    ctx.set_timing(True)
+    fr.load_trained_mlp(ctx)
+    dg = fr.DeviceGraph.from_host(w.graph)
+    part0 = torch.as_tensor(w.part).cuda()
+    dpart = part0.clone()
+    prm = c5_params(fr, w, 1)
+    for _ in range(args.warmup):
+        dpart.copy_(part0)
+        fr.flow_refine_sweep(ctx, dg, dpart, w.k, prm, args.max_sweeps)
+    torch.cuda.synchronize()
+    tot = dict(edges=0, kern_ms=0.0, bytes=0, launches=0, solves=0, sweeps=0, corridor_ms=0.0,
+               build_ms=0.0, sweeps_pr=0, relabels=0)
+    step_ms, first, cut = [], None, None
+    same = True
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        dpart.copy_(part0)
+        cut, stats = fr.flow_refine_sweep(ctx, dg, dpart, w.k, prm, args.max_sweeps)
+        step_ms.append((time.perf_counter() - ts) * 1e3)  # the call synchronises its stream
+        st = fr.stats_dict(ctx)
+        tot["edges"] += int(stats[3])
+        tot["solves"] += int(stats[1])
+        tot["sweeps"] += int(stats[0])
+        tot["kern_ms"] += st["flow_kernel_ms"]
+        tot["bytes"] += flow_bytes(st)
+        tot["launches"] += st["flow_launches"]
+        tot["corridor_ms"] += st["corridor_ms"]
+        tot["build_ms"] += st["build_ms"]
+        tot["sweeps_pr"] += st["sweeps"]
+        tot["relabels"] += st["relabels"]
+        out = dpart.cpu().numpy()
+        if first is None:
+            first = out
+        else:
+            same = same and bool(np.array_equal(first, out))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.close()
+    return dict(w=w, wall=wall, step_ms=step_ms, cut0=int(oracle.total_cut(w.graph, w.part)),
+                cut=int(cut), repeatable=same, part=first, **tot)
+
+
+def run_c5_cpu_baseline(args, fr, torch, w):
+    """The oracle on the largest matching round of C5 (the first colour class
+    of the start partition), each pair from the start factor the learned
+    network gives it on the GPU: over a thread pool of the host cores this
+    process may use (at most 16), and on one thread for the first pairs.  The
+    GPU's results for the same pairs must be bit-exact."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+
+    ctx = fr.Context()
     ctx.set_validation(False)
     fr.load_trained_mlp(ctx)
     dg = fr.DeviceGraph.from_host(w.graph)
-    dpart = torch.as_tensor(w.part).cuda()
-    prm = fr.params(**{k: w.params[k] for k in ("area_mode", "depth", "alpha", "alpha_max",
-                                                 "adaptive", "max_iters", "eps_ppm")}, use_mlp=1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    cut, stats = fr.flow_refine_sweep(ctx, dg, dpart, w.k, prm, args.max_sweeps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    part0 = torch.as_tensor(w.part).cuda()
+    edges_q, colour = fr.fr_quotient_matchings(ctx, dg, part0, w.k)
+    c = int(np.argmax(np.bincount(colour)))
+    pairs = [tuple(e) for e, cc in zip(edges_q.tolist(), colour.tolist()) if cc == c]
+    dpart = part0.clone()
+    res, trace = fr.flow_refine_batch(ctx, dg, dpart, w.k, pairs, c5_params(fr, w, 1))
+    gpu_part = dpart.cpu().numpy()
     ctx.close()
-    cut0 = oracle.total_cut(w.graph, w.part)
+    base = {k: w.params[k] for k in ("area_mode", "depth", "alpha", "alpha_max", "adaptive",
+                                     "max_iters", "eps_ppm")}
+
+    def one(i):
+        a, b = pairs[i]
+        return oracle.refine_pair(w.graph, w.part, w.k, a, b,
+                                  dict(base, alpha=res[i]["start_alpha"]), want_side=False)
+
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    threads = max(1, min(16, avail))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        outs = list(pool.map(one, range(len(pairs))))
+    dt = time.perf_counter() - t0
+    exact = True
+    new = w.part.copy()
+    for i, o in enumerate(outs):
+        exact = exact and o.rc == 0 and o.trace == trace[i] and all(
+            o.result[key] == res[i][key] for key in ("flow_value", "cut_after", "weight_a",
+                                                     "weight_b", "iters", "region_edges"))
+        mine = (w.part == pairs[i][0]) | (w.part == pairs[i][1])
+        new[mine] = o.part[mine]
+    exact = exact and bool(np.array_equal(new, gpu_part))
+    edges = sum(o.result["region_edges"] for o in outs)
+    n1 = min(len(pairs), args.cpu_one_thread_pairs)
+    t1 = time.perf_counter()
+    e1 = sum(one(i).result["region_edges"] for i in range(n1))
+    d1 = time.perf_counter() - t1
     return {
-        "workload": "C5: 2D RGG n=2^24 mean degree 6 unit weights, k=256 RCB + 1% noise, eps 3%, "
-                    "alpha' 16 adaptive with learned start, sweeps until no pair improves",
-        "seconds": dt, "sweeps": int(stats[0]), "flow_solves": int(stats[1]),
-        "applied_pairs": int(stats[2]), "region_edges": int(stats[3]),
-        "region_edges_per_s": float(stats[3]) / dt, "cut_before": int(cut0), "cut_after": int(cut),
+        "value": edges / dt, "unit": "region edges/s", "cores": threads, "kind": "oracle",
+        "sample": f"the largest matching round of C5 ({len(pairs)} pairs, {edges} region edges), "
+                  "each pair the sequential oracle from its learned start factor, spread over "
+                  f"{threads} host threads ({os.cpu_count()} logical CPUs visible)",
+        "seconds": dt, "host_cpus_visible": os.cpu_count(), "threads": threads,
+        "one_thread": {"value": e1 / d1, "unit": "region edges/s", "cores": 1,
+                       "sample": f"the first {n1} pairs of that round, one after the other",
+                       "seconds": d1},
+        "bit_exact_vs_gpu_round": bool(exact),
     }
 
 
@@ -365,7 +454,7 @@ def run_balanced(args, fr, torch, gen):
                "pair_cut_before": sum(r["cut_before"] for r in res),
                "flow_kernel_ms": st["flow_kernel_ms"], "mb_kernel_ms": st["mb_kernel_ms"],
                "mb_free_vertices": st["mb_free"], "mb_components": st["mb_comp"],
-               "mb_limited_solves": st["mb_limited"], "fm_moves": st["fm_steps"],
+               "mb_device_dag_solves": st["mb_big"], "fm_moves": st["fm_steps"],
                "fm_moves_kept": st["fm_kept"]}
         dpart = part0.clone()
         torch.cuda.synchronize()
@@ -388,23 +477,179 @@ def run_balanced(args, fr, torch, gen):
     return out
 
 
+def roofline(bytes_total: float, kern_ms: float, launches: int, traffic) -> dict:
+    """k_flow against the HBM peak: algorithmic bytes per launch over the
+    average launch time from the events (total bytes / total time)."""
+    avg_s = kern_ms / 1e3 / max(1, launches)
+    per_launch = bytes_total / max(1, launches)
+    achieved = per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
+    return {"bound": "hbm", "kernel": "k_flow", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "algorithmic_bytes_per_launch": per_launch, "avg_launch_ms": avg_s * 1e3,
+            "launches": launches}
+
+
+def c2_leg(args, fr, torch, gen):
+    plain = run_plain(args, fr, torch, gen)
+    progress(f"C2 plain: {plain['wall'] * 1e3 / args.steps:.1f} ms per step")
+    out = {
+        "workload": "C2: 2D RGG n=2^18 mean degree 8, edge weights 1..10, median-x bisection "
+                    "+ 2% boundary noise, eps 3%, alpha 16 adaptive (max 16 solves)",
+        "region_edges_per_s": plain["edges"] / plain["wall"],
+        "ms_per_step": plain["wall"] * 1e3 / args.steps,
+        "ms_per_step_median": float(np.median(plain["step_ms"])),
+        "ms_per_step_min": float(np.min(plain["step_ms"])),
+        "region_edges_per_step": plain["edges"] // args.steps,
+        "solves_per_step": plain["result"]["iters"],
+        "sweeps_per_step": plain["stats"]["sweeps"],
+        "relabels_per_step": plain["stats"]["relabels"],
+        "roofline": roofline(plain["bytes"], plain["kern_ms"], plain["launches"],
+                             load_traffic("C2")),
+        "whole_path_gb_per_s": plain["path_bytes"] / (plain["path_ms"] / 1e3) / 1e9,
+    }
+    if not args.no_cpu_baseline:
+        o, dt = run_cpu_baseline(plain["w"])
+        out["bit_exact_vs_oracle"] = bool(
+            o.result["cut_after"] == plain["result"]["cut_after"]
+            and o.result["flow_value"] == plain["result"]["flow_value"]
+            and o.trace == plain["trace"] and np.array_equal(o.part, plain["part"]))
+        out["cpu_baseline"] = {
+            "value": o.result["region_edges"] / dt, "unit": "region edges/s", "cores": 1,
+            "kind": "oracle", "seconds": dt,
+            "sample": "one full adaptive refinement of the same C2 pair "
+                      f"({o.result['iters']} flow solves, {o.result['region_edges']} region "
+                      "edges), single-threaded sequential Dinic oracle"}
+        progress(f"C2 CPU baseline: {dt:.1f} s, bit-exact {out['bit_exact_vs_oracle']}")
+    return out
+
+
+def _csv_rows(root: str, suffix: str):
+    import csv
+
+    rows = []
+    for dp, _, files in os.walk(root):
+        for f in sorted(files):
+            if f.endswith(suffix):
+                with open(os.path.join(dp, f), newline="") as fh:
+                    rows += list(csv.DictReader(fh))
+    if not rows:
+        raise SystemExit(f"no *{suffix} under {root}")
+    return rows
+
+
+def _col(row: dict, *names):
+    for n in names:
+        for k in row:
+            if k.lower() == n.lower():
+                return row[k]
+    raise KeyError(names)
+
+
+def summarize(argv):
+    """Summaries of rocprofv3 output under profiles/ (runs on the host only):
+      stats WORKLOAD DIR CMD...  -- the --kernel-trace --stats table of DIR
+          -> profiles/k_flow_WORKLOAD_kernel_stats.md
+      pmc WORKLOAD FETCH_DIR WRITE_DIR CMD...  -- two --pmc runs (FETCH_SIZE,
+          then WRITE_SIZE) of a command with --copy-probe: the mean per
+          k_flow dispatch, each scaled by the ratio of the true byte count of
+          the 512 MiB copy to what the same counter read for it
+          -> profiles/k_flow_WORKLOAD_traffic.{md,json}
+    CMD is the command line that produced the output, recorded verbatim."""
+    kind, work = argv[0], argv[1]
+    out_dir = os.path.join(ROOT, "profiles")
+    if kind == "stats":
+        src, cmd = argv[2], " ".join(argv[3:])
+        rows = _csv_rows(src, "kernel_stats.csv")
+        rows.sort(key=lambda r: -float(_col(r, "TotalDurationNs")))
+        lines = [f"# Kernel time, {work}", "",
+                 "Command (from the repository root on the GPU box):", "", "```", cmd, "```", "",
+                 "| kernel | calls | total ms | average us | % |", "|---|---:|---:|---:|---:|"]
+        for r in rows:
+            lines.append(f"| {_col(r, 'Name')} | {_col(r, 'Calls')} | "
+                         f"{float(_col(r, 'TotalDurationNs')) / 1e6:.3f} | "
+                         f"{float(_col(r, 'AverageNs')) / 1e3:.1f} | "
+                         f"{float(_col(r, 'Percentage')):.2f} |")
+        path = os.path.join(out_dir, f"k_flow_{work}_kernel_stats.md")
+        with open(path, "w") as f:
+            f.write("\n".join(lines) + "\n")
+        print(path)
+        return
+    if kind != "pmc":
+        raise SystemExit("summarize: stats or pmc")
+    fdir, wdir, cmd = argv[2], argv[3], " ".join(argv[4:])
+
+    def per_dispatch(root, counter):
+        vals, names = {}, {}
+        for r in _csv_rows(root, "counter_collection.csv"):
+            if _col(r, "Counter_Name") != counter:
+                continue
+            d = _col(r, "Dispatch_Id")
+            vals[d] = vals.get(d, 0.0) + float(_col(r, "Counter_Value"))
+            names[d] = _col(r, "Kernel_Name")
+        return vals, names
+
+    res = {}
+    for counter, root in (("FETCH_SIZE", fdir), ("WRITE_SIZE", wdir)):
+        vals, names = per_dispatch(root, counter)
+        flow = [v for d, v in vals.items() if "k_flow" in names[d]]
+        copies = [v for d, v in vals.items() if "copy" in names[d].lower()]
+        kname = next(names[d] for d in vals if "k_flow" in names[d])
+        res[counter] = (sum(flow) / len(flow), len(flow), max(copies), kname)
+    probe_kib = COPY_PROBE_BYTES / 1024
+    fscale = probe_kib / res["FETCH_SIZE"][2]
+    wscale = probe_kib / res["WRITE_SIZE"][2]
+    fk, nl, _, kname = res["FETCH_SIZE"]
+    wk = res["WRITE_SIZE"][0]
+    hbm = (fk * fscale + wk * wscale) * 1024
+    d = {"kernel": kname, "workload": work, "launches": nl, "fetch_kib_per_launch": fk,
+         "write_kib_per_launch": wk, "copy_probe_bytes": COPY_PROBE_BYTES,
+         "copy_fetch_kib": res["FETCH_SIZE"][2], "copy_write_kib": res["WRITE_SIZE"][2],
+         "fetch_scale": fscale, "write_scale": wscale, "hbm_bytes_per_launch": hbm,
+         "kernel_source_hash": kernel_source_hash(), "command": cmd}
+    with open(os.path.join(out_dir, f"k_flow_{work}_traffic.json"), "w") as f:
+        json.dump(d, f, indent=1)
+    md = [f"# HBM traffic of {kname}, {work}", "",
+          "Two counter passes, FETCH_SIZE then WRITE_SIZE, each its own run of this command "
+          "(from the repository root on the GPU box):", "", "```", cmd, "```", "",
+          "Calibration: one 512 MiB device copy in the same run (`--copy-probe`).", "",
+          "| | FETCH_SIZE KiB | WRITE_SIZE KiB |", "|---|---:|---:|",
+          f"| copy of 512 MiB | {res['FETCH_SIZE'][2]:.1f} | {res['WRITE_SIZE'][2]:.1f} |",
+          f"| scale to true bytes | {fscale:.3f} | {wscale:.3f} |",
+          f"| {kname}, mean per launch ({nl} launches) | {fk:.1f} | {wk:.1f} |", "",
+          f"HBM bytes per launch (scaled): {hbm / 1e6:.2f} MB.", "",
+          f"Kernel sources hash: {d['kernel_source_hash']}."]
+    with open(os.path.join(out_dir, f"k_flow_{work}_traffic.md"), "w") as f:
+        f.write("\n".join(md) + "\n")
+    print(json.dumps(d))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-one-thread-pairs", type=int, default=8)
+    ap.add_argument("--no-c2", action="store_true")
+    ap.add_argument("--c2-steps", type=int, default=10)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-balanced", action="store_true")
     ap.add_argument("--max-sweeps", type=int, default=64)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one device copy of 512 MiB (calibrates HBM byte counters)")
+    ap.add_argument("--summarize", nargs="+", metavar="ARG",
+                    help="stats WORKLOAD DIR CMD... | pmc WORKLOAD FETCH_DIR WRITE_DIR CMD...: "
+                         "write the profiles/ summaries from rocprofv3 output (no GPU)")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args.summarize)
+        return
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only (the pairs of a round "
+                                   "would shard across GPUs, but no multi-GPU path is built); "
+                                   "--gpus must be 1"}))
         sys.exit(2)
 
     import torch
@@ -417,8 +662,9 @@ def main():
         sys.exit(1)
     fr.load()  # fails loudly when the HIP library is not built
 
-    plain = run_plain(args, fr, torch, gen)
-    progress(f"C2 plain: {plain['wall'] * 1e3 / args.steps:.1f} ms per step")
+    h = run_c5_headline(args, fr, torch, gen)
+    progress(f"C5 headline: {h['wall'] * 1e3 / args.steps:.0f} ms per step, "
+             f"cut {h['cut0']} -> {h['cut']}")
     if args.copy_probe:
         x = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.int32, device="cuda")
         y = torch.empty_like(x)
@@ -426,79 +672,55 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         del x, y
-    value = plain["edges"] / plain["wall"]
-    launches = plain["launches"]  # the flow kernel runs once per adaptive iteration slot
-    avg_kern_s = plain["kern_ms"] / 1e3 / launches
-    bytes_per_launch = plain["bytes"] / launches
-    achieved = bytes_per_launch / avg_kern_s / 1e9
-    traffic = load_traffic("C2")
-    tune = None
     line = {
         "metric": METRIC,
-        "value": value,
+        "value": h["edges"] / h["wall"],
         "unit": "region edges/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": plain["wall"] * 1e3 / args.steps,
-        "ms_per_step_median": float(np.median(plain["step_ms"])),
-        "ms_per_step_min": float(np.min(plain["step_ms"])),
+        "ms_per_step": h["wall"] * 1e3 / args.steps,
+        "ms_per_step_median": float(np.median(h["step_ms"])),
+        "ms_per_step_min": float(np.min(h["step_ms"])),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
         "config": {
-            "workload": "C2: 2D RGG n=2^18 mean degree 8, edge weights 1..10, median-x bisection "
-                        "+ 2% boundary noise, eps 3%, alpha 16 adaptive (max 16 solves)",
-            "region_edges_per_step": plain["edges"] // args.steps,
-            "solves_per_step": plain["result"]["iters"],
+            "workload": C5_WORKLOAD,
+            "region_edges_per_step": h["edges"] // args.steps,
+            "flow_solves_per_step": h["solves"] // args.steps,
+            "sweeps_per_step": h["sweeps"] // args.steps,
+            "cut_before": h["cut0"],
+            "cut_after": h["cut"],
+            "same_partition_every_step": h["repeatable"],
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_flow",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "algorithmic_bytes_per_launch": bytes_per_launch,
-            "avg_launch_ms": avg_kern_s * 1e3,
-            "launches_per_step": launches // args.steps,
-            "whole_path_gb_per_s": plain["path_bytes"] / (plain["path_ms"] / 1e3) / 1e9,
-        },
+        "roofline": roofline(h["bytes"], h["kern_ms"], h["launches"], load_traffic("C5")),
+        "phase_ms_per_step": {"corridor": h["corridor_ms"] / args.steps,
+                              "network_build": h["build_ms"] / args.steps,
+                              "flow_kernel": h["kern_ms"] / args.steps},
+        "push_relabel_sweeps_per_step": h["sweeps_pr"] // args.steps,
+        "global_relabels_per_step": h["relabels"] // args.steps,
     }
     if not args.no_cpu_baseline:
-        o, dt = run_cpu_baseline(plain["w"])
-        exact = (o.result["cut_after"] == plain["result"]["cut_after"]
-                 and o.result["flow_value"] == plain["result"]["flow_value"]
-                 and o.trace == plain["trace"]
-                 and bool(np.array_equal(o.part, plain["part"])))
-        line["cpu_baseline"] = {
-            "value": o.result["region_edges"] / dt,
-            "unit": "region edges/s",
-            "cores": 1,
-            "kind": "oracle",
-            "sample": "one full adaptive refinement of the same C2 pair "
-                      f"({o.result['iters']} flow solves, {o.result['region_edges']} region edges), "
-                      "single-threaded sequential Dinic oracle",
-            "seconds": dt,
-        }
-        line["bit_exact_vs_oracle"] = bool(exact)
-        progress(f"CPU baseline: {dt:.1f} s, bit-exact {exact}")
+        line["cpu_baseline"] = run_c5_cpu_baseline(args, fr, torch, h["w"])
+        line["bit_exact_vs_oracle"] = line["cpu_baseline"]["bit_exact_vs_gpu_round"]
+        progress(f"C5 CPU baseline: {line['cpu_baseline']['seconds']:.1f} s on "
+                 f"{line['cpu_baseline']['cores']} threads, bit-exact {line['bit_exact_vs_oracle']}")
+    del h
+    if not args.no_c2:
+        line["c2_plain"] = c2_leg(argparse.Namespace(**dict(vars(args), steps=args.c2_steps,
+                                                             warmup=2)), fr, torch, gen)
     if not args.no_batched:
         line["batched"] = run_batched(args, fr, torch, gen)
         progress("C3 batched round done")
         line["batched_c5_round"] = run_batched(
-            argparse.Namespace(batch_reps=1, no_cpu_baseline=args.no_cpu_baseline), fr, torch,
-            gen, "C5")
+            argparse.Namespace(batch_reps=1, no_cpu_baseline=True), fr, torch, gen, "C5")
         progress("C5 batched round done")
     if not args.no_learned:
         line["learned_factor"] = run_learned(args, fr, torch, gen)
         progress("C4 learned factor done")
-    if not args.no_sweep:
-        line["sweep"] = run_sweep(args, fr, torch, gen)
-        progress("C5 sweep done")
     if not args.no_balanced:
         line["balanced"] = run_balanced(args, fr, torch, gen)
     print(json.dumps(line), flush=True)

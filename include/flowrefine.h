@@ -37,8 +37,8 @@
  *     new block weights; a random topological order of the remaining residual
  *     components takes, among those whose predecessors are all placed, the
  *     one with the smallest key (SplitMix64, see mb_seed); the first most
- *     balanced cut wins (earlier sweep, then earlier position); more than
- *     FR_MB_MAX_COMP remaining components keep the smallest source set.
+ *     balanced cut wins (earlier sweep, then earlier position), for any
+ *     number of remaining components.
  *
  * Conventions: every entry point returns FR_OK (0) or a negative FR_E_* code,
  * and never throws.  On error the partition is left unchanged.  All buffers
@@ -169,7 +169,6 @@ typedef struct {
 #define FR_TERM_CONTRACTED 1
 
 #define FR_MB_MAX_REPS 256
-#define FR_MB_MAX_COMP 2048
 
 /* Outcome of one pair. */
 typedef struct {
@@ -282,7 +281,17 @@ int32_t fr_set_speculation(fr_context *ctx, int32_t on);
  * (1, the default) or off (0; malformed input then gives undefined results). */
 int32_t fr_set_validation(fr_context *ctx, int32_t on);
 
-/* Statistics of the last pair / batch call (host arrays, either may be NULL).
+/* Per-phase timing of sweeps on (1) or off (0, the default).  On: the rounds
+ * of each sweep are launched one by one instead of as one recorded hipGraph,
+ * with HIP events around the phases of every adaptive iteration, so
+ * fr_last_stats reports the corridor, network-build and flow-kernel times
+ * summed over the whole sweep call (results are identical either way).
+ * Pair and batch calls always time their phases. */
+int32_t fr_set_timing(fr_context *ctx, int32_t on);
+
+/* Statistics of the last pair, batch or sweep call (host arrays, either may
+ * be NULL; a sweep sums its rounds, and reports event times only with
+ * fr_set_timing on).
  * ms[8]: [0] setup (validation, weights, arenas), [1] the round (setup
  *   kernels and every flow iteration), [2] corridor kernels (boundary and
  *   BFS), [3] network-build kernels, [4] whole call on the device, [5]
@@ -294,8 +303,9 @@ int32_t fr_set_validation(fr_context *ctx, int32_t on);
  *   of the per-pair kernels, [6] internal check that failed (0 = none),
  *   [7] speculative factors per pair (1 = none); [8] most-balanced-cut
  *   kernels time in ns, [9] free vertices, [10] their residual components,
- *   [11] solves that kept the smallest source set for having more than
- *   FR_MB_MAX_COMP components; [12] FM moves made, [13] FM moves kept;
+ *   [11] solves whose component graph (more than 2,048 components) was kept
+ *   in device memory instead of LDS; [12] FM moves made, [13] FM moves kept;
+ *   [14] flow-kernel launches (one per adaptive iteration of each round);
  *   [16..27] vertices and arcs touched: boundary scan, corridor BFS, network
  *   build, push/relabel sweeps, global relabels, residual closure (vertices
  *   then arcs for each); the rest 0. */

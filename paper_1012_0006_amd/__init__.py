@@ -61,8 +61,8 @@ class FrTuning(ctypes.Structure):
 
 EXPORTS = ("fr_create", "fr_destroy", "fr_strerror", "flow_refine_pair", "flow_refine_batch",
            "flow_refine_sweep", "fr_quotient_matchings", "fr_set_tuning", "fr_get_tuning",
-           "fr_set_validation", "fr_set_speculation", "fr_last_stats", "fr_mlp_num_params", "fr_mlp_init",
-           "fr_mlp_set_weights", "fr_mlp_get_weights", "fr_mlp_forward", "fr_mlp_loss_grad",
+           "fr_set_validation", "fr_set_speculation", "fr_set_timing", "fr_last_stats",
+           "fr_mlp_num_params", "fr_mlp_init", "fr_mlp_set_weights", "fr_mlp_get_weights", "fr_mlp_forward", "fr_mlp_loss_grad",
            "fr_mlp_train", "fr_pair_features", "fr_autotune")
 ALPHAS = (1, 2, 4, 8, 16)
 
@@ -105,6 +105,8 @@ def load(path: str = LIB_PATH):
     lib.fr_set_validation.argtypes = [vp, i32]
     lib.fr_set_speculation.restype = i32
     lib.fr_set_speculation.argtypes = [vp, i32]
+    lib.fr_set_timing.restype = i32
+    lib.fr_set_timing.argtypes = [vp, i32]
     lib.fr_last_stats.restype = i32
     lib.fr_last_stats.argtypes = [vp, vp, vp]
     lib.fr_mlp_num_params.restype = i32
@@ -229,6 +231,9 @@ class Context:
     def set_speculation(self, on: bool = True):
         _check(self.lib.fr_set_speculation(self.handle, 1 if on else 0), "fr_set_speculation")
 
+    def set_timing(self, on: bool = True):
+        _check(self.lib.fr_set_timing(self.handle, 1 if on else 0), "fr_set_timing")
+
     def last_stats(self):
         ms = (ctypes.c_double * 8)()
         cnt = (ctypes.c_int64 * 32)()
@@ -247,8 +252,8 @@ def stats_dict(ctx) -> dict:
              call_ms=ms[4], relabel_ms=ms[5], push_ms=ms[6], flow_kernel_ms=ms[7],
              sweeps=cnt[0], relabels=cnt[1], bfs_levels=cnt[2], gr_levels=cnt[3],
              cl_levels=cnt[4], workgroups=cnt[5], diag=cnt[6], slots=cnt[7],
-             mb_kernel_ms=cnt[8] / 1e6, mb_free=cnt[9], mb_comp=cnt[10], mb_limited=cnt[11],
-             fm_steps=cnt[12], fm_kept=cnt[13])
+             mb_kernel_ms=cnt[8] / 1e6, mb_free=cnt[9], mb_comp=cnt[10], mb_big=cnt[11],
+             fm_steps=cnt[12], fm_kept=cnt[13], flow_launches=cnt[14])
     d.update({k: cnt[16 + i] for i, k in enumerate(WORK_KEYS)})
     return d
 

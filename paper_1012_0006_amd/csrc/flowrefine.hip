@@ -42,6 +42,8 @@ struct DevBufs {
   int8_t *side = nullptr;
   int32_t *mbq = nullptr;  // most balanced cut: quotient arcs, one per arc slot (lazy)
   int64_t mbqcap = 0;
+  int32_t *mbc = nullptr;  // most balanced cut: large component graphs, 4 per vertex slot (lazy)
+  int64_t mbccap = 0;
   int32_t *fmg = nullptr, *fmq = nullptr;  // 2-way FM: per-vertex gains, queue positions (lazy)
   int64_t fmcap = 0;
   // per arc
@@ -82,6 +84,7 @@ struct fr_context {
   hipEvent_t itev[5 * FR_MAX_ITERS] = {};
   int32_t timed_iters = 0;
   int speculate = 1;
+  int timing = 0;  // sweeps: uncaptured rounds with per-phase events
   // stats of the last call
   double ms[8] = {0};
   int64_t counters[32] = {0};
@@ -119,6 +122,9 @@ static void free_vertex_arc(DevBufs &d) {
   dfree(d.mbq);
   d.mbq = nullptr;
   d.mbqcap = 0;
+  dfree(d.mbc);
+  d.mbc = nullptr;
+  d.mbccap = 0;
   dfree(d.fmg);
   dfree(d.fmq);
   d.fmg = d.fmq = nullptr;
@@ -311,6 +317,12 @@ extern "C" int32_t fr_set_speculation(fr_context *c, int32_t on) {
   return FR_OK;
 }
 
+extern "C" int32_t fr_set_timing(fr_context *c, int32_t on) {
+  if (!c) return FR_E_INVALID_ARG;
+  c->timing = on ? 1 : 0;
+  return FR_OK;
+}
+
 extern "C" int32_t fr_set_validation(fr_context *c, int32_t on) {
   if (!c) return FR_E_INVALID_ARG;
   c->validate = on ? 1 : 0;
@@ -416,6 +428,7 @@ static KArgs call_args(fr_context *c, const fr_graph *g, int32_t *dpart, int32_t
   }
   A.mb_lds = c->tune.mb_lds;
   A.mbq = d.mbq;
+  A.mbc = d.mbc;
   A.fmg = d.fmg;
   A.fmq = d.fmq;
   A.mark = d.mark;
@@ -491,6 +504,12 @@ static KArgs round_args(fr_context *c, const KArgs &base, int64_t off, int32_t P
   return A;
 }
 
+// workgroups of the per-pair kernels for a round of P entries
+static int blocks_of(const fr_context *c, int32_t P) {
+  const int64_t slots = (int64_t)c->num_cus * c->tune.blocks_per_cu;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(P, slots));
+}
+
 // All kernels of one matching round; device-only work, so a sequence of
 // rounds can be captured into a graph.
 // One round: setup kernels, then max_iters launches of the per-iteration
@@ -522,8 +541,7 @@ static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t s
     hipLaunchKernelGGL(k_fm, dim3(A.P / A.W), dim3(FM_TPB), 0, st, A);
   }
   const int tpb = c->tune.block_threads;
-  const int64_t slots = (int64_t)c->num_cus * c->tune.blocks_per_cu;
-  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(A.P, slots));
+  const int blocks = blocks_of(c, A.P);
   const iter_fn corr = corr_kernel(tpb), flow = flow_kernel(tpb);
   for (int32_t it = 0; it < A.max_iters; it++) {
     hipEvent_t *ev = c->itev + 5 * it;
@@ -549,7 +567,6 @@ static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t s
     hipLaunchKernelGGL(k_select, dim3(A.P / A.W), dim3(1024), 0, st, A, it);
   }
   HIPCHK(hipGetLastError());
-  c->counters[5] = blocks;
   c->timed_iters = timed ? A.max_iters : 0;
   return FR_OK;
 }
@@ -587,48 +604,47 @@ static void fill_result(const PairState &s, fr_result &r) {
   else r.status = FR_NO_IMPROVEMENT;
 }
 
-static void collect_stats(fr_context *c, const std::vector<PairState> &ps) {
-  int64_t sw = 0, rl = 0, bl = 0, gl = 0, cl = 0, wk[W_COUNT] = {0}, mb[3] = {0, 0, 0};
-  int64_t fm[2] = {0, 0};
-  double ph[5] = {0, 0, 0, 0, 0};
-  for (const PairState &s : ps) {
-    sw += s.sweeps;
-    rl += s.relabels;
-    bl += s.bfs_levels;
-    gl += s.gr_levels;
-    cl += s.cl_levels;
-    for (int j = 0; j < W_COUNT; j++) wk[j] += s.work[j];
-    mb[0] += s.mb_free;
-    mb[1] += s.mb_comp;
-    mb[2] += s.mb_limited;
-    fm[0] += s.fm_steps;
-    fm[1] += s.fm_kept;
-    ph[0] += s.t_corridor;
-    ph[1] += s.t_build;
-    ph[2] += s.t_relabel;
-    ph[3] += s.t_push;
-    ph[4] += s.t_closure + s.t_finish;
+// Statistics of a call (fr_last_stats): cleared at its start, then every
+// round adds its entries' work counters and, when its iterations were timed,
+// the per-phase event times.
+static void reset_stats(fr_context *c) {
+  memset(c->ms, 0, sizeof(c->ms));
+  memset(c->counters, 0, sizeof(c->counters));
+}
+
+static void add_entry_stats(fr_context *c, const PairState *ps, size_t count) {
+  int64_t *C = c->counters;
+  double ph[3] = {0, 0, 0};
+  for (size_t i = 0; i < count; i++) {
+    const PairState &s = ps[i];
+    C[0] += s.sweeps;
+    C[1] += s.relabels;
+    C[2] += s.bfs_levels;
+    C[3] += s.gr_levels;
+    C[4] += s.cl_levels;
+    for (int j = 0; j < W_COUNT; j++) C[16 + j] += s.work[j];
+    C[9] += s.mb_free;
+    C[10] += s.mb_comp;
+    C[11] += s.mb_big;
+    C[12] += s.fm_steps;
+    C[13] += s.fm_kept;
+    ph[0] += s.t_relabel;
+    ph[1] += s.t_push;
   }
-  c->counters[0] = sw;
-  c->counters[1] = rl;
-  c->counters[2] = bl;
-  c->counters[3] = gl;
-  c->counters[4] = cl;
-  c->counters[6] = 0;
-  for (int j = 0; j < W_COUNT; j++) c->counters[16 + j] = wk[j];
+  c->ms[5] += ph[0] / c->wall_khz;
+  c->ms[6] += ph[1] / c->wall_khz;
+}
+
+// the timed iterations of the round just enqueued (after the stream
+// synchronised): corridor, build, flow kernel, most balanced cut kernels
+static void add_round_times(fr_context *c) {
   double ev[4];
   iteration_times(c, ev);
-  c->counters[8] = (int64_t)(ev[3] * 1e6);
-  c->counters[9] = mb[0];
-  c->counters[10] = mb[1];
-  c->counters[11] = mb[2];
-  c->counters[12] = fm[0];
-  c->counters[13] = fm[1];
-  c->ms[2] = ev[0];
-  c->ms[3] = ev[1];
-  c->ms[5] = ph[2] / c->wall_khz;
-  c->ms[6] = ph[3] / c->wall_khz;
-  c->ms[7] = ev[2];
+  c->ms[2] += ev[0];
+  c->ms[3] += ev[1];
+  c->ms[7] += ev[2];
+  c->counters[8] += (int64_t)(ev[3] * 1e6);
+  c->counters[14] += c->timed_iters;
 }
 
 static int32_t device_error(fr_context *c) {
@@ -679,7 +695,8 @@ static int32_t stage(fr_context *c, const fr_graph *g, int32_t *part, int32_t k,
   return FR_OK;
 }
 
-// Quotient-arc slots of the most balanced cut: one per arena arc slot,
+// Quotient-arc slots of the most balanced cut (one per arena arc slot) and
+// the component graphs too large for LDS (four words per arena vertex slot),
 // allocated on first use.
 static int32_t ensure_mb(fr_context *c, const fr_params *p) {
   DevBufs &d = c->d;
@@ -692,12 +709,21 @@ static int32_t ensure_mb(fr_context *c, const fr_params *p) {
       return FR_E_OOM;
     d.fmcap = d.ncap;
   }
-  if (p->mb_reps <= 0 || d.mbqcap >= d.sacap) return FR_OK;
-  dfree(d.mbq);
-  d.mbq = nullptr;
-  d.mbqcap = 0;
-  if (dalloc(&d.mbq, d.sacap) != hipSuccess) return FR_E_OOM;
-  d.mbqcap = d.sacap;
+  if (p->mb_reps <= 0) return FR_OK;
+  if (d.mbqcap < d.sacap) {
+    dfree(d.mbq);
+    d.mbq = nullptr;
+    d.mbqcap = 0;
+    if (dalloc(&d.mbq, d.sacap) != hipSuccess) return FR_E_OOM;
+    d.mbqcap = d.sacap;
+  }
+  if (d.mbccap < d.sncap) {
+    dfree(d.mbc);
+    d.mbc = nullptr;
+    d.mbccap = 0;
+    if (dalloc(&d.mbc, 4 * d.sncap) != hipSuccess) return FR_E_OOM;
+    d.mbccap = d.sncap;
+  }
   return FR_OK;
 }
 
@@ -806,11 +832,14 @@ static int32_t refine(fr_context *c, const fr_graph *g, int32_t *part, int32_t k
   (void)hipEventElapsedTime(&t01, c->ev[0], c->ev[1]);
   (void)hipEventElapsedTime(&t12, c->ev[1], c->ev[2]);
   (void)hipEventElapsedTime(&t03, c->ev[0], c->ev[3]);
+  reset_stats(c);
+  add_entry_stats(c, ps.data(), ps.size());
+  add_round_times(c);
+  c->counters[5] = blocks_of(c, V);
+  c->counters[7] = W;
   c->ms[0] = t01;  // validation, graph constants
   c->ms[1] = t12;  // the round: setup kernels and every flow iteration
   c->ms[4] = t03;  // whole call on the device
-  collect_stats(c, ps);
-  c->counters[7] = W;
   for (int i = 0; i < npairs; i++) {
     fill_result(ps[(size_t)i * W], res[i]);
     if (trace)
@@ -919,6 +948,8 @@ extern "C" int32_t flow_refine_sweep(fr_context *c, const fr_graph *g, int32_t *
   // the caller's partition changes only on success: work on a copy
   int32_t *work = d.partw;
   HIPCHK(hipMemcpyAsync(work, s.dpart, sizeof(int32_t) * g->n, hipMemcpyDeviceToDevice, st));
+  reset_stats(c);
+  (void)hipEventRecord(c->ev[0], st);
   KArgs A = call_args(c, &s.g, work, k, p);
   A.mstride = g->n;
   if ((rc = call_constants(c, A, s.narcs, p))) return rc;
@@ -979,34 +1010,49 @@ extern "C" int32_t flow_refine_sweep(fr_context *c, const fr_graph *g, int32_t *
     int32_t stamp0 = 0;
     if ((rc = reserve_stamps(c, (int64_t)nrounds * (p->max_iters + 1), &stamp0))) return rc;
     HIPCHK(hipStreamSynchronize(st));
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    int32_t cap_rc = FR_OK;
-    for (int32_t r = 0; r < nrounds && cap_rc == FR_OK; r++) {
-      const KArgs R = round_args(c, A, offs[r], offs[r + 1] - offs[r],
-                                 stamp0 + r * (2 * p->max_iters + 2), false);
-      cap_rc = enqueue_round(c, R, p->use_mlp != 0, st, false);
+    if (c->timing) {
+      // rounds launched one by one, each iteration's phases between events,
+      // read back after every round (the events are reused)
+      for (int32_t r = 0; r < nrounds; r++) {
+        const KArgs R = round_args(c, A, offs[r], offs[r + 1] - offs[r],
+                                   stamp0 + r * (2 * p->max_iters + 2), false);
+        if ((rc = enqueue_round(c, R, p->use_mlp != 0, st, true))) return rc;
+        HIPCHK(hipStreamSynchronize(st));
+        add_round_times(c);
+      }
+    } else {
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      int32_t cap_rc = FR_OK;
+      for (int32_t r = 0; r < nrounds && cap_rc == FR_OK; r++) {
+        const KArgs R = round_args(c, A, offs[r], offs[r + 1] - offs[r],
+                                   stamp0 + r * (2 * p->max_iters + 2), false);
+        cap_rc = enqueue_round(c, R, p->use_mlp != 0, st, false);
+      }
+      hipError_t ce = hipStreamEndCapture(st, &graph);
+      if (cap_rc != FR_OK || ce != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return cap_rc != FR_OK ? cap_rc : FR_E_DEVICE;
+      }
+      ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (ce == hipSuccess) ce = hipGraphLaunch(exec, st);
+      if (ce == hipSuccess) ce = hipStreamSynchronize(st);
+      if (exec) (void)hipGraphExecDestroy(exec);
+      (void)hipGraphDestroy(graph);
+      if (ce != hipSuccess) {
+        last_hip_error = ce;
+        return FR_E_DEVICE;
+      }
+      c->graph_launches++;
+      c->counters[14] += (int64_t)nrounds * p->max_iters;
     }
-    hipError_t ce = hipStreamEndCapture(st, &graph);
-    if (cap_rc != FR_OK || ce != hipSuccess) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return cap_rc != FR_OK ? cap_rc : FR_E_DEVICE;
-    }
-    ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (ce == hipSuccess) ce = hipGraphLaunch(exec, st);
-    if (ce == hipSuccess) ce = hipStreamSynchronize(st);
-    if (exec) (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
-    if (ce != hipSuccess) {
-      last_hip_error = ce;
-      return FR_E_DEVICE;
-    }
-    c->graph_launches++;
     if ((rc = device_error(c))) return rc;
     ps.resize((size_t)total);
     HIPCHK(hipMemcpyAsync(ps.data(), d.ps, sizeof(PairState) * total, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    add_entry_stats(c, ps.data(), ps.size());
+    c->counters[7] = std::max<int64_t>(c->counters[7], W);
     int64_t changed = 0;
     std::fill(active.begin(), active.end(), 0);
     for (int64_t i = 0; i < total; i += W) {  // the pair's record is its first entry
@@ -1030,7 +1076,11 @@ extern "C" int32_t flow_refine_sweep(fr_context *c, const fr_graph *g, int32_t *
   HIPCHK(hipMemcpyAsync(&tc, d.scal, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(part, work, sizeof(int32_t) * g->n,
                         g->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+  (void)hipEventRecord(c->ev[3], st);
   HIPCHK(hipStreamSynchronize(st));
+  float t03 = 0.f;
+  (void)hipEventElapsedTime(&t03, c->ev[0], c->ev[3]);
+  c->ms[4] = t03;
   if (total_cut_out) *total_cut_out = tc;
   if (stats) memcpy(stats, acc, sizeof(acc));
   return FR_OK;

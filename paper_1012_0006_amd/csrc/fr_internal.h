@@ -37,9 +37,9 @@ struct PairState {
   int64_t t_corridor, t_build, t_relabel, t_push, t_closure, t_finish;  // wall-clock ticks
   int64_t work[12];     // vertices / arcs touched per phase (W_*), summed over solves
   // most balanced cut, summed over solves: free vertices, residual components
-  // among them, solves that kept the smallest source set for having more than
-  // FR_MB_MAX_COMP components, wall-clock ticks
-  int64_t mb_free, mb_comp, mb_limited, t_mb;
+  // among them, solves whose component graph was too large for LDS (kept in
+  // device memory), wall-clock ticks
+  int64_t mb_free, mb_comp, mb_big, t_mb;
   // 2-way FM before the flow: moves made, moves kept after the rollback
   int64_t fm_steps, fm_kept;
 };
@@ -128,6 +128,7 @@ struct KArgs {
   // component graph in LDS when it fits, quotient arcs (one slot per arc slot)
   int32_t mb_reps, mb_seed, mb_lds;
   int32_t *mbq;
+  int32_t *mbc;             // large component graphs: 4 words per arena vertex slot
   int64_t *mpre;            // [P + 1] prefix sums of the entries' free-vertex counts
   // 2-way FM before the flow: non-improving moves before it stops (0 = off),
   // key seed, per-vertex gains and queue positions (-1 not queued, -2 moved)

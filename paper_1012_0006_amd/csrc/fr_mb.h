@@ -27,6 +27,7 @@
 #include "fr_kernels.h"
 
 #define MB_TPB 1024
+#define MB_LCOMP 2048     // components whose DAG is held in LDS; more: device memory
 #define MB_LQ 1024        // quotient nodes handled in LDS
 #define MB_LQA 4096       // quotient arcs handled in LDS
 #define MB_LDAG 4096      // component arcs held in LDS
@@ -39,12 +40,12 @@ struct MBShared {
       int32_t low[MB_LQ], stk[MB_LQ], cnode[MB_LQ], cpos[MB_LQ];
     } t;
     struct {                         // the component DAG, built after Tarjan
-      int64_t cw[FR_MB_MAX_COMP];    // component weights
-      int32_t ckey[FR_MB_MAX_COMP];  // component key id: smallest global vertex id
-      int32_t cend[FR_MB_MAX_COMP];  // component arcs: counts, then end offsets
-      int32_t cin[FR_MB_MAX_COMP];   // in-degrees among the components
+      int64_t cw[MB_LCOMP];          // component weights
+      int32_t ckey[MB_LCOMP];        // component key id: smallest global vertex id
+      int32_t cend[MB_LCOMP];        // component arcs: counts, then end offsets
+      int32_t cin[MB_LCOMP];         // in-degrees among the components
       int16_t adj[MB_LDAG];          // component arcs (when they fit)
-      uint8_t sink[FR_MB_MAX_COMP];  // chosen cut: component on the sink side
+      uint8_t sink[MB_LCOMP];        // chosen cut: component on the sink side
     } c;
   } u1;
   union {
@@ -352,28 +353,27 @@ __global__ void __launch_bounds__(256) k_mb_union(KArgs A, int32_t it) {
   }
 }
 
-// The mb_reps sweeps, one per wave in batches that fit the LDS state (an
-// int32 in-degree and a state byte per component and sweep), then a replay
-// of the winning sweep by the first wave that flags its sink components.
+// The mb_reps sweeps, one per wave, `per` at a time: sweep l of a batch
+// keeps its in-degrees at ind + l * C and its state bytes at st + l * C (LDS,
+// or device memory for large component graphs); then a replay of the winning
+// sweep by the first wave flags its sink components in `sink`.
 template <typename ADJ>
 __device__ __forceinline__ void mb_sweeps(const KArgs &A, MBShared &sh, const MBSweep<ADJ> &S,
-                                          int64_t wa0, int64_t wb0) {
+                                          int64_t wa0, int64_t wb0, int32_t *ind, uint8_t *st,
+                                          int32_t per, uint8_t *sink) {
   const int32_t C = S.C;
-  const int32_t per = max(1, min(MB_TPB / WAVE, (int32_t)(MB_RS_BYTES / (5 * C))));
   if (threadIdx.x == 0) {
     sh.best_rep = -1;
     sh.best_pos = 0;
     sh.best_bal = 0;
   }
-  int32_t *rs = reinterpret_cast<int32_t *>(sh.u2.rs);
   for (int32_t r0 = 0; r0 < A.mb_reps; r0 += per) {
     const int32_t nl = min(per, A.mb_reps - r0);
     const int l = threadIdx.x / WAVE;
     if (l < nl) {
       int64_t bal;
-      const int32_t j = S.run(r0 + l, rs + (int64_t)l * C,
-                              reinterpret_cast<uint8_t *>(rs + (int64_t)nl * C) + (int64_t)l * C,
-                              wa0, wb0, C, nullptr, &bal, A.ctl);
+      const int32_t j = S.run(r0 + l, ind + (int64_t)l * C, st + (int64_t)l * C, wa0, wb0, C,
+                              nullptr, &bal, A.ctl);
       if (lane64() == 0) {
         sh.lane_bal[l] = bal;
         sh.lane_pos[l] = j;
@@ -393,8 +393,7 @@ __device__ __forceinline__ void mb_sweeps(const KArgs &A, MBShared &sh, const MB
   // the chosen cut: replay the winning sweep up to its position
   if (threadIdx.x < WAVE && sh.best_pos > 0) {
     int64_t bal;
-    S.run(sh.best_rep, rs, reinterpret_cast<uint8_t *>(rs + C), wa0, wb0, sh.best_pos,
-          sh.u1.c.sink, &bal, A.ctl);
+    S.run(sh.best_rep, ind, st, wa0, wb0, sh.best_pos, sink, &bal, A.ctl);
   }
   __syncthreads();
 }
@@ -423,12 +422,12 @@ __global__ void __launch_bounds__(MB_TPB) k_mb(KArgs A, int32_t it) {
   const int32_t nr = uni(A.ps[p].nr);
   const int32_t nm = uni(min(nm0, nr));
   // per-entry statistics, by thread 0 at every exit
-  auto done = [&](int64_t comps, int64_t limited) {
+  auto done = [&](int64_t comps, int64_t big) {
     if (threadIdx.x == 0) {
       PairState &ps = A.ps[p];
       ps.mb_free += nm;
       ps.mb_comp += comps;
-      ps.mb_limited += limited;
+      ps.mb_big += big;
       ps.t_mb += wall_clock64() - t0;
     }
   };
@@ -500,7 +499,7 @@ __global__ void __launch_bounds__(MB_TPB) k_mb(KArgs A, int32_t it) {
     } else if (nq > V.na) {  // cannot happen: nq <= corridor vertices <= arc slots
       A.ctl->err = FR_E_DEVICE;
       A.ctl->diag = DIAG_MB;
-      sh.nc = FR_MB_MAX_COMP + 1;
+      sh.nc = -1;
     } else {
       sh.nc = mb_tarjan(nq, eq, V.ex, w1 + n1w, W, W + nq, W + 2 * (int64_t)nq,
                         W + 3 * (int64_t)nq, V.SNK);
@@ -508,17 +507,33 @@ __global__ void __launch_bounds__(MB_TPB) k_mb(KArgs A, int32_t it) {
   }
   __syncthreads();
   const int32_t C = uni(sh.nc);
-  if (C > FR_MB_MAX_COMP) {  // too many components: the smallest source set stays
-    done(C, 1);
+  if (C < 0) {
+    done(0, 0);
     return;
   }
-  // ---- 3. the component DAG
+  // ---- 3. the component DAG: in LDS up to MB_LCOMP components, else in
+  // device memory (then Tarjan ran there too, so nq > MB_LQ): weights, key
+  // ids and arc ends in the entry's slice of mbc (4 words per vertex slot,
+  // C <= nq <= corridor vertices), in-degrees in the label array once the
+  // quotient-node ids it holds are dead, sink flags in the sink-list array
+  const bool big = C > MB_LCOMP;
+  int64_t *cw = sh.u1.c.cw;
+  int32_t *ckey = sh.u1.c.ckey, *cend = sh.u1.c.cend, *cin = sh.u1.c.cin;
+  uint8_t *sink = sh.u1.c.sink;
+  if (big) {
+    int32_t *X = A.mbc + 4 * A.voff[p];
+    cw = reinterpret_cast<int64_t *>(X);
+    ckey = X + 2 * (int64_t)C;
+    cend = X + 3 * (int64_t)C;
+    cin = V.lab;
+    sink = reinterpret_cast<uint8_t *>(V.SNK);
+  }
   for (int32_t c = threadIdx.x; c < C; c += blockDim.x) {
-    sh.u1.c.cw[c] = 0;
-    sh.u1.c.ckey[c] = 0x7fffffff;
-    sh.u1.c.cend[c] = 0;
-    sh.u1.c.cin[c] = 0;
-    sh.u1.c.sink[c] = 0;
+    cw[c] = 0;
+    ckey[c] = 0x7fffffff;
+    cend[c] = 0;
+    if (!big) cin[c] = 0;
+    sink[c] = 0;
   }
   __syncthreads();
   // every free vertex: its component (into par), the components' weights and
@@ -546,9 +561,14 @@ __global__ void __launch_bounds__(MB_TPB) k_mb(KArgs A, int32_t it) {
     for (int k = 0; k < 4; k++) {
       if (u[k] >= 0) par[u[k]] = c[k];
       wfree += w[k];
-      wave_add_by_key(reinterpret_cast<unsigned long long *>(sh.u1.c.cw), 1, 0, c[k], w[k]);
-      wave_min_by_key(sh.u1.c.ckey, c[k], g[k]);
+      wave_add_by_key(reinterpret_cast<unsigned long long *>(cw), 1, 0, c[k], w[k]);
+      wave_min_by_key(ckey, c[k], g[k]);
     }
+  }
+  if (big) {  // the quotient-node ids are dead: the label array takes the in-degrees
+    __syncthreads();
+    for (int32_t c = threadIdx.x; c < C; c += blockDim.x) cin[c] = 0;
+    __syncthreads();
   }
   // component arcs, one lane per quotient arc (a hub class can own most of
   // them): its source node by binary search over the offsets
@@ -564,8 +584,8 @@ __global__ void __launch_bounds__(MB_TPB) k_mb(KArgs A, int32_t it) {
   for (int32_t e = threadIdx.x; e < eq; e += blockDim.x) {
     const int32_t c = -2 - idx[qsrc(e)], d = -2 - idx[qarc[e]];
     if (d != c) {
-      atomicAdd(&sh.u1.c.cend[c], 1);
-      atomicAdd(&sh.u1.c.cin[d], 1);
+      atomicAdd(&cend[c], 1);
+      atomicAdd(&cin[d], 1);
     }
   }
   {
@@ -573,33 +593,52 @@ __global__ void __launch_bounds__(MB_TPB) k_mb(KArgs A, int32_t it) {
     block_sums<1>(s1, sh.red);
     wfree = s1[0];
   }
-  const int32_t ne = mb_exscan(sh.u1.c.cend, C, sh.red);
-  const bool ladj = A.mb_lds && ne <= MB_LDAG;
+  const int32_t ne = mb_exscan(cend, C, sh.red);
+  // int16 component ids in LDS only for the small DAG
+  const bool ladj = !big && A.mb_lds && ne <= MB_LDAG;
   int32_t *gadj = W + (lt ? 0 : nq);
   // fill: cend[c] counts up from c's start to its end
   for (int32_t e = threadIdx.x; e < eq; e += blockDim.x) {
     const int32_t c = -2 - idx[qsrc(e)], d = -2 - idx[qarc[e]];
     if (d != c) {
-      const int32_t pos = atomicAdd(&sh.u1.c.cend[c], 1);
+      const int32_t pos = atomicAdd(&cend[c], 1);
       if (ladj) sh.u1.c.adj[pos] = (int16_t)d;
       else gadj[pos] = d;
     }
   }
   __syncthreads();
-  // ---- 4. sweeps, one per wave, in batches that fit the LDS state
+  // ---- 4. sweeps, one per wave, in batches whose state fits: LDS for the
+  // small DAG; for the large one the in-degrees go to the excess array
+  // (quotient offsets, dead; nr >= C words per sweep) and the state bytes to
+  // the Tarjan index array (dead; 4 nq >= 4 C bytes), which ends below the
+  // component arcs at W + nq
   const fr_solve rec0 = A.srec[p];
   const int64_t wa0 = rec0.wa + wfree, wb0 = rec0.wb - wfree;  // all free components with s
   const uint64_t seed = (uint64_t)(uint32_t)A.mb_seed;
+  int32_t *ind;
+  uint8_t *stb;
+  int32_t per;
+  if (big) {
+    per = max(1, min(MB_TPB / WAVE, min(nr / C, (int32_t)((4 * (int64_t)nq) / C))));
+    ind = V.ex;
+    stb = reinterpret_cast<uint8_t *>(W);
+  } else {
+    per = max(1, min(MB_TPB / WAVE, (int32_t)(MB_RS_BYTES / (5 * C))));
+    ind = reinterpret_cast<int32_t *>(sh.u2.rs);
+    stb = reinterpret_cast<uint8_t *>(ind + (int64_t)per * C);
+  }
   if (ladj)
-    mb_sweeps(A, sh, MBSweep<int16_t>{C, sh.u1.c.cin, sh.u1.c.cend, sh.u1.c.adj, sh.u1.c.cw, sh.u1.c.ckey, seed}, wa0, wb0);
+    mb_sweeps(A, sh, MBSweep<int16_t>{C, cin, cend, sh.u1.c.adj, cw, ckey, seed}, wa0, wb0, ind,
+              stb, per, sink);
   else
-    mb_sweeps(A, sh, MBSweep<int32_t>{C, sh.u1.c.cin, sh.u1.c.cend, gadj, sh.u1.c.cw, sh.u1.c.ckey, seed}, wa0, wb0);
+    mb_sweeps(A, sh, MBSweep<int32_t>{C, cin, cend, gadj, cw, ckey, seed}, wa0, wb0, ind, stb,
+              per, sink);
   // ---- 5. components left on the source side join S_min
   int64_t acc[2] = {0, 0};  // weight, vertices
   BLOCK_WAVE_LOOP(j, nm) {
     if (j < nm) {
       const int32_t u = ml[j];
-      if (!sh.u1.c.sink[par[u]]) {
+      if (!sink[par[u]]) {
         V.ins[u] = 1;
         acc[0] += A.vwgt[V.lg[u]];
         acc[1] += 1;
@@ -617,5 +656,5 @@ __global__ void __launch_bounds__(MB_TPB) k_mb(KArgs A, int32_t it) {
                          : (rec.cut_candidate < rec.cut_before ? FR_DEC_APPLY : FR_DEC_EQUAL);
     A.srec[p] = rec;
   }
-  done(C, 0);
+  done(C, big ? 1 : 0);
 }
