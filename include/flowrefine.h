@@ -66,6 +66,7 @@ extern "C" {
 #define FR_E_OOM (-7)                /* device or host allocation failed */
 #define FR_E_INVALID_ARG (-8)        /* NULL pointer, bad parameter value */
 #define FR_E_SOLVER_LIMIT (-9)       /* push-relabel exceeded its sweep safety cap */
+#define FR_E_SCRATCH_LIMIT (-10)     /* flow_refine_pair_static: graph beyond its static scratch */
 
 /* ---- per-pair status (fr_result.status) --------------------------------- */
 #define FR_ACCEPTED 1           /* at least one flow solve was applied */
@@ -229,6 +230,28 @@ const char *fr_strerror(int32_t code);
 int32_t flow_refine_pair(fr_context *ctx, const fr_graph *g, int32_t *part, int32_t k,
                          int32_t a, int32_t b, const fr_params *p, fr_result *res,
                          int8_t *side_out, fr_solve *trace);
+
+/* flow_refine_pair for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same computation and results, with every vertex-, arc-
+ * and block-sized buffer taken from a static device array of 64 MiB that
+ * the library holds on each GPU it runs on until the process ends (its
+ * address is resolved by fr_create); no hipMalloc, hipFree or other
+ * allocating call is made.  Limits: the graph and part must be device
+ * pointers (g->on_device = 1); mb_reps, fm_limit and use_mlp must be 0;
+ * no side output; the adaptive iterations run one solve at a time (no
+ * speculative factors).  The buffers need about 49 bytes per vertex plus
+ * 16 per arc (each undirected edge twice) plus 28 per block, each piece
+ * rounded to 256 bytes: a graph beyond 64 MiB of that returns
+ * FR_E_SCRATCH_LIMIT before any device work, with part unchanged (2D RGG
+ * n = 2^18, mean degree 8, takes 47 MB).  Calls on one GPU share the array
+ * and keep no state in it between calls (it is cleared where needed), so
+ * calls that overlap on one GPU -- from several contexts or threads -- race
+ * and must be serialised by the caller.  res / trace as for
+ * flow_refine_pair. */
+int32_t flow_refine_pair_static(fr_context *ctx, const fr_graph *g, int32_t *part, int32_t k,
+                                int32_t a, int32_t b, const fr_params *p, fr_result *res,
+                                fr_solve *trace);
 
 /* All pairs of one quotient-graph matching in one batched solve.  pairs: host
  * int32 [2*npairs] (a_i, b_i), blocks pairwise disjoint.  res: host

@@ -21,7 +21,7 @@ _lib = None
 FR_OK = 0
 FR_ERRORS = {-1: "INVALID_GRAPH", -2: "INVALID_PART", -3: "INVALID_PAIR",
              -4: "PAIRS_NOT_DISJOINT", -5: "OVERFLOW", -6: "DEVICE", -7: "OOM",
-             -8: "INVALID_ARG", -9: "SOLVER_LIMIT"}
+             -8: "INVALID_ARG", -9: "SOLVER_LIMIT", -10: "SCRATCH_LIMIT"}
 FR_ACCEPTED, FR_REJECTED_IMBALANCE, FR_NO_IMPROVEMENT, FR_NOT_ADJACENT = 1, 2, 3, 4
 FR_DEC_APPLY, FR_DEC_INFEASIBLE, FR_DEC_EQUAL, FR_DEC_NOT_ADJACENT = 1, 2, 3, 4
 FR_AREA_FACTOR, FR_AREA_DEPTH = 0, 1
@@ -59,7 +59,8 @@ class FrTuning(ctypes.Structure):
                                    "mb_lds")]
 
 
-EXPORTS = ("fr_create", "fr_destroy", "fr_strerror", "flow_refine_pair", "flow_refine_batch",
+EXPORTS = ("fr_create", "fr_destroy", "fr_strerror", "flow_refine_pair",
+           "flow_refine_pair_static", "flow_refine_batch",
            "flow_refine_sweep", "fr_quotient_matchings", "fr_set_tuning", "fr_get_tuning",
            "fr_set_validation", "fr_set_speculation", "fr_set_timing", "fr_last_stats",
            "fr_mlp_num_params", "fr_mlp_init", "fr_mlp_set_weights", "fr_mlp_get_weights", "fr_mlp_forward", "fr_mlp_loss_grad",
@@ -91,6 +92,9 @@ def load(path: str = LIB_PATH):
     lib.fr_strerror.argtypes = [i32]
     lib.flow_refine_pair.restype = i32
     lib.flow_refine_pair.argtypes = [vp, P(FrGraph), vp, i32, i32, i32, P(FrParams), vp, vp, vp]
+    lib.flow_refine_pair_static.restype = i32
+    lib.flow_refine_pair_static.argtypes = [vp, P(FrGraph), vp, i32, i32, i32, P(FrParams), vp,
+                                            vp]
     lib.flow_refine_batch.restype = i32
     lib.flow_refine_batch.argtypes = [vp, P(FrGraph), vp, i32, vp, i32, P(FrParams), vp, vp]
     lib.flow_refine_sweep.restype = i32
@@ -290,6 +294,21 @@ def flow_refine_pair(ctx: Context, graph, part, k: int, a: int, b: int, prm: FrP
     _check(rc, "flow_refine_pair")
     r = _struct_dict(res)
     return r, [_struct_dict(trace[i]) for i in range(r["iters"])], side
+
+
+def flow_refine_pair_static(ctx: Context, graph, part, k: int, a: int, b: int, prm: FrParams):
+    """flow_refine_pair without device allocation (the library's static
+    scratch; graph and part on the device).  Returns (result, trace)."""
+    gs, keep = _graph_arg(graph)
+    res = FrResult()
+    trace = (FrSolve * max(1, prm.max_iters))()
+    rc = ctx.lib.flow_refine_pair_static(ctx.handle, ctypes.byref(gs),
+                                         _part_arg(part, gs.on_device), k, a, b,
+                                         ctypes.byref(prm), ctypes.addressof(res),
+                                         ctypes.addressof(trace))
+    _check(rc, "flow_refine_pair_static")
+    r = _struct_dict(res)
+    return r, [_struct_dict(trace[i]) for i in range(r["iters"])]
 
 
 def flow_refine_batch(ctx: Context, graph, part, k: int, pairs, prm: FrParams):

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <numeric>
 #include <random>
 #include <vector>
@@ -206,6 +207,31 @@ static int32_t reserve_stamps(fr_context *c, int64_t count, int32_t *first) {
   return FR_OK;
 }
 
+// ---- device scratch of flow_refine_pair_static (callers that cannot
+// allocate): one array per GPU, resolved once per device by fr_create.  In
+// host code the array's name is only a stand-in; kernels get the address
+// from scratch_ptr.
+#define FR_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+#define FR_MAX_DEVICES 64
+static __device__ __align__(256) unsigned char scratch[FR_STATIC_SCRATCH_BYTES];
+static void *scratch_ptr[FR_MAX_DEVICES];
+static std::mutex scratch_mu;
+
+// With `device` current: its copy of the scratch array.
+static int32_t scratch_address(int device) {
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (device < 0 || device >= FR_MAX_DEVICES) return FR_E_DEVICE;
+  if (scratch_ptr[device]) return FR_OK;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    last_hip_error = e;
+    return FR_E_DEVICE;
+  }
+  scratch_ptr[device] = ptr;
+  return FR_OK;
+}
+
 extern "C" const char *fr_strerror(int32_t code) {
   switch (code) {
     case FR_OK: return "ok";
@@ -218,6 +244,7 @@ extern "C" const char *fr_strerror(int32_t code) {
     case FR_E_OOM: return "out of memory";
     case FR_E_INVALID_ARG: return "invalid argument";
     case FR_E_SOLVER_LIMIT: return "push/relabel sweep limit reached";
+    case FR_E_SCRATCH_LIMIT: return "graph too large for the static scratch of flow_refine_pair_static";
     default: return "unknown error";
   }
 }
@@ -228,6 +255,7 @@ extern "C" int32_t fr_create(int32_t device, void *hip_stream, fr_context **out)
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FR_E_DEVICE;
   if (hipSetDevice(device) != hipSuccess) return FR_E_DEVICE;
+  if (scratch_address(device) != FR_OK) return FR_E_DEVICE;
   fr_context *c = new (std::nothrow) fr_context();
   if (!c) return FR_E_OOM;
   c->device = device;
@@ -386,9 +414,8 @@ static int32_t graph_narcs(fr_context *c, const fr_graph *g, int64_t *narcs) {
 
 // Kernel arguments common to every round of a call: graph, partition,
 // parameters, scratch.  Per-round fields are set by round_args.
-static KArgs call_args(fr_context *c, const fr_graph *g, int32_t *dpart, int32_t k,
-                       const fr_params *p) {
-  DevBufs &d = c->d;
+static KArgs call_args(fr_context *c, const DevBufs &d, const fr_graph *g, int32_t *dpart,
+                       int32_t k, const fr_params *p) {
   KArgs A;
   memset(&A, 0, sizeof(A));
   A.n = g->n;
@@ -479,12 +506,12 @@ static int32_t call_constants(fr_context *c, KArgs &A, int64_t narcs, const fr_p
   // L_max = (1 + eps) c(V) / k + max c(v)  (Sec. 2.1)
   A.lmax = floor_div_u128((unsigned __int128)(1000000 + (int64_t)p->eps_ppm) * (uint64_t)cV, den) +
            maxc;
-  std::vector<int64_t> base((size_t)std::max(p->alpha_max, 1) + 1, 0);
-  for (size_t al = 0; al < base.size(); al++)
+  int64_t base[FR_MAX_ALPHA + 1];
+  const int nb = std::max(p->alpha_max, 1) + 1;
+  for (int al = 0; al < nb; al++)
     base[al] = floor_div_u128(
         (unsigned __int128)(1000000 + (int64_t)al * p->eps_ppm) * (uint64_t)cV, den);
-  HIPCHK(hipMemcpyAsync(d.base, base.data(), sizeof(int64_t) * base.size(), hipMemcpyHostToDevice,
-                        st));
+  HIPCHK(hipMemcpyAsync(d.base, base, sizeof(int64_t) * nb, hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
   return FR_OK;
 }
@@ -744,7 +771,8 @@ static int32_t check_batch_args(const fr_context *c, const fr_graph *g, const in
     return FR_E_INVALID_ARG;
   int32_t rc = check_params(p);
   if (rc) return rc;
-  std::vector<uint8_t> used((size_t)k, 0);
+  uint8_t used[FR_MAX_K];
+  memset(used, 0, (size_t)k);
   for (int i = 0; i < npairs; i++) {
     const int32_t a = pairs[2 * i], b = pairs[2 * i + 1];
     if (a < 0 || b < 0 || a >= k || b >= k || a == b) return FR_E_INVALID_PAIR;
@@ -771,9 +799,44 @@ static int32_t speculation_slots(const fr_context *c, const fr_params *p, int32_
   return W;
 }
 
+// Host-side scratch of a call: inline storage up to N elements, the heap
+// beyond (the entry point without device allocation stays within N).
+template <typename T, size_t N>
+struct HostBuf {
+  T inl[N];
+  std::vector<T> heap;
+  T *p = inl;
+  size_t n = 0;
+  void resize(size_t m) {
+    n = m;
+    if (m > N) {
+      heap.resize(m);
+      p = heap.data();
+    } else {
+      p = inl;
+    }
+  }
+  T *data() { return p; }
+  size_t size() const { return n; }
+  T &operator[](size_t i) { return p[i]; }
+};
+
+// Clears n int32 words on the stream (a kernel, not a memset node, so the
+// work stays correct inside captured graphs).
+__global__ void __launch_bounds__(256) k_fill32(int32_t *x, int64_t n, int32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+// One batched round of disjoint pairs.  carve = nullptr: the context's
+// buffers, grown on demand.  Otherwise the graph must be on the device, the
+// call runs one entry per pair (no speculative slots) and every vertex-,
+// arc- and block-sized buffer comes from *carve, which the caller sized for
+// the graph; nothing is allocated.
 static int32_t refine(fr_context *c, const fr_graph *g, int32_t *part, int32_t k,
                       const int32_t *pairs, int32_t npairs, const fr_params *p, fr_result *res,
-                      int8_t *side_out, fr_solve *trace) {
+                      int8_t *side_out, fr_solve *trace, const DevBufs *carve = nullptr) {
   int32_t rc = check_batch_args(c, g, part, k, pairs, npairs, p);
   if (rc) return rc;
   if (!res) return FR_E_INVALID_ARG;
@@ -781,31 +844,49 @@ static int32_t refine(fr_context *c, const fr_graph *g, int32_t *part, int32_t k
   if ((rc = enter(c))) return rc;
   int64_t narcs0 = 0;
   if ((rc = graph_narcs(c, g, &narcs0))) return rc;
-  const int32_t W = speculation_slots(c, p, npairs, g->n, narcs0);
-  if ((rc = ensure_pairs(c, (int64_t)npairs * W))) return rc;
+  const int32_t W = carve ? 1 : speculation_slots(c, p, npairs, g->n, narcs0);
   Staged s;
-  if ((rc = stage(c, g, part, k, &s, W))) return rc;
-  if ((rc = ensure_mb(c, p))) return rc;
-  DevBufs &d = c->d;
+  if (carve) {
+    if (!g->on_device || (int64_t)npairs > c->d.pcap || side_out) return FR_E_INVALID_ARG;
+    s.g = *g;
+    s.dpart = part;
+    s.narcs = narcs0;
+  } else {
+    if ((rc = ensure_pairs(c, (int64_t)npairs * W))) return rc;
+    if ((rc = stage(c, g, part, k, &s, W))) return rc;
+    if ((rc = ensure_mb(c, p))) return rc;
+  }
+  const DevBufs &d = carve ? *carve : c->d;
   hipStream_t st = c->cs;
   const int64_t n = g->n;
   const int32_t V = npairs * W;
   (void)hipEventRecord(c->ev[0], st);
   HIPCHK(hipMemcpyAsync(d.partw, s.dpart, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
-  KArgs A = call_args(c, &s.g, d.partw, k, p);
+  KArgs A = call_args(c, d, &s.g, d.partw, k, p);
   A.W = W;
   A.mstride = W > 1 ? n : 0;
   if ((rc = call_constants(c, A, s.narcs, p))) return rc;
-  std::vector<int32_t> a0((size_t)V, p->alpha), vp((size_t)2 * V);
+  HostBuf<int32_t, 8> a0, vp;
+  a0.resize((size_t)V);
+  vp.resize((size_t)2 * V);
   for (int32_t i = 0; i < V; i++) {
+    a0[i] = p->alpha;
     vp[2 * i] = pairs[2 * (i / W)];
     vp[2 * i + 1] = pairs[2 * (i / W) + 1];
   }
   HIPCHK(hipMemcpyAsync(d.pairs, vp.data(), sizeof(int32_t) * 2 * V, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(d.alpha0, a0.data(), sizeof(int32_t) * V, hipMemcpyHostToDevice, st));
   int32_t stamp0 = 0;
-  if ((rc = reserve_stamps(c, p->max_iters, &stamp0))) return rc;
-  const KArgs R = round_args(c, A, 0, V, stamp0, true);
+  if (carve) {
+    // the carved marks keep the previous call's stamps: clear them
+    hipLaunchKernelGGL(k_fill32, dim3(std::min<int64_t>((n + 255) / 256, 4 * c->num_cus)),
+                       dim3(256), 0, st, d.mark, n, 0);
+    HIPCHK(hipGetLastError());
+    stamp0 = 2;
+  } else if ((rc = reserve_stamps(c, p->max_iters, &stamp0))) {
+    return rc;
+  }
+  KArgs R = round_args(c, A, 0, V, stamp0, true);
   (void)hipEventRecord(c->ev[1], st);
   if ((rc = enqueue_round(c, R, p->use_mlp != 0, st, true))) return rc;
   (void)hipEventRecord(c->ev[2], st);
@@ -817,9 +898,10 @@ static int32_t refine(fr_context *c, const fr_graph *g, int32_t *part, int32_t k
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(side_out, d.side, n, hipMemcpyDeviceToHost, st));
   }
-  std::vector<PairState> ps((size_t)V);
+  HostBuf<PairState, 4> ps;
+  ps.resize((size_t)V);
   HIPCHK(hipMemcpyAsync(ps.data(), d.ps, sizeof(PairState) * V, hipMemcpyDeviceToHost, st));
-  std::vector<fr_solve> tr;
+  HostBuf<fr_solve, FR_MAX_ITERS> tr;
   if (trace) {
     tr.resize((size_t)npairs * p->max_iters);
     HIPCHK(hipMemcpyAsync(tr.data(), d.trace, sizeof(fr_solve) * tr.size(), hipMemcpyDeviceToHost, st));
@@ -854,6 +936,59 @@ extern "C" int32_t flow_refine_pair(fr_context *c, const fr_graph *g, int32_t *p
                                     int8_t *side_out, fr_solve *trace) {
   const int32_t pr[2] = {a, b};
   return refine(c, g, part, k, pr, 1, p, res, side_out, trace);
+}
+
+// flow_refine_pair without device allocation: the vertex-, arc- and
+// block-sized buffers are carved from the device's static scratch array
+// (256-byte aligned pieces); the context's fixed per-call buffers were
+// allocated by fr_create.
+extern "C" int32_t flow_refine_pair_static(fr_context *c, const fr_graph *g, int32_t *part,
+                                           int32_t k, int32_t a, int32_t b, const fr_params *p,
+                                           fr_result *res, fr_solve *trace) {
+  if (!c || !g || !part || !p || !res || g->n < 1 || k < 2 || k > FR_MAX_K) return FR_E_INVALID_ARG;
+  if (!g->on_device || p->mb_reps != 0 || p->fm_limit != 0 || p->use_mlp) return FR_E_INVALID_ARG;
+  int32_t rc = check_params(p);
+  if (rc) return rc;
+  if (c->device < 0 || c->device >= FR_MAX_DEVICES || !scratch_ptr[c->device]) return FR_E_DEVICE;
+  HIPCHK(hipSetDevice(c->device));
+  int64_t narcs = 0;
+  if ((rc = graph_narcs(c, g, &narcs))) return rc;
+  const int64_t n = g->n;
+  DevBufs v = c->d;  // the fixed buffers stay; the sized ones are replaced
+  unsigned char *const base = (unsigned char *)scratch_ptr[c->device];
+  size_t off = 0;
+  bool fits = true;
+  auto take = [&](auto **ptr, size_t bytes) {
+    off = (off + 255) & ~(size_t)255;
+    fits = fits && off + bytes <= FR_STATIC_SCRATCH_BYTES;
+    *ptr = fits ? reinterpret_cast<std::remove_reference_t<decltype(**ptr)> *>(base + off)
+                : nullptr;
+    off += bytes;
+  };
+  const size_t vn = sizeof(int32_t) * (size_t)n;
+  take(&v.mark, vn);
+  take(&v.vmap, vn);
+  take(&v.uvert, vn);
+  take(&v.lg, vn);
+  take(&v.lo, sizeof(int32_t) * ((size_t)n + 2));
+  take(&v.ex, vn);
+  take(&v.lab, vn);
+  take(&v.ins, vn);
+  take(&v.LA, vn);
+  take(&v.LB, vn);
+  take(&v.SNK, vn);
+  take(&v.partw, vn);
+  take(&v.lflag, (size_t)n);
+  take(&v.arc, sizeof(Arc) * (size_t)narcs);
+  take(&v.blk2pair, sizeof(int32_t) * (size_t)k);
+  take(&v.bstat, sizeof(int64_t) * 3 * (size_t)k);
+  if (!fits) return FR_E_SCRATCH_LIMIT;
+  v.side = nullptr;
+  v.mbq = v.mbc = v.fmg = v.fmq = nullptr;
+  v.gx = v.gv = v.ga = v.gw = v.parts = nullptr;
+  v.qadj = nullptr;
+  const int32_t pr[2] = {a, b};
+  return refine(c, g, part, k, pr, 1, p, res, nullptr, trace, &v);
 }
 
 extern "C" int32_t flow_refine_batch(fr_context *c, const fr_graph *g, int32_t *part, int32_t k,
@@ -950,7 +1085,7 @@ extern "C" int32_t flow_refine_sweep(fr_context *c, const fr_graph *g, int32_t *
   HIPCHK(hipMemcpyAsync(work, s.dpart, sizeof(int32_t) * g->n, hipMemcpyDeviceToDevice, st));
   reset_stats(c);
   (void)hipEventRecord(c->ev[0], st);
-  KArgs A = call_args(c, &s.g, work, k, p);
+  KArgs A = call_args(c, d, &s.g, work, k, p);
   A.mstride = g->n;
   if ((rc = call_constants(c, A, s.narcs, p))) return rc;
   int64_t acc[4] = {0, 0, 0, 0};
@@ -1255,7 +1390,7 @@ extern "C" int32_t fr_pair_features(fr_context *c, const fr_graph *g, const int3
   if ((rc = stage(c, g, const_cast<int32_t *>(part), k, &s))) return rc;
   DevBufs &d = c->d;
   hipStream_t st = c->cs;
-  KArgs A = call_args(c, &s.g, s.dpart, k, &p);
+  KArgs A = call_args(c, d, &s.g, s.dpart, k, &p);
   if ((rc = call_constants(c, A, s.narcs, &p))) return rc;
   HIPCHK(hipMemcpyAsync(d.pairs, pairs, sizeof(int32_t) * 2 * npairs, hipMemcpyHostToDevice, st));
   KArgs R = round_args(c, A, 0, npairs, 0, false);
