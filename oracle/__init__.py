@@ -8,7 +8,9 @@ quotient-graph colouring sweep and the per-pair features of the learned area
 factor.  With ``mb_reps > 0`` a solve takes the most balanced minimum cut of
 Section 4.1.1 (residual strongly connected components, removal of the s and t
 closures, sweeps along random topological orders) instead of the smallest
-source set.  Only ``tests/``, the smoke check and the benchmark's CPU-baseline leg
+source set.  With ``mt_alpha > 0`` a batch ends with the multi-try FM phase of
+Section 4.2 (rounds of localized k-way searches, one round per pair in pair
+order).  Only ``tests/``, the smoke check and the benchmark's CPU-baseline leg
 use it.  It shares no code with the GPU library and never calls it.
 
 ``mlp_*`` below is the float64 reference of the small area-factor network
@@ -48,7 +50,7 @@ class OrParams(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int32) for f in
                 ("area_mode", "depth", "alpha", "alpha_max", "adaptive", "max_iters", "eps_ppm",
                  "mb_reps", "mb_seed", "fm_limit", "fm_seed", "active_blocks", "cut_side",
-                 "terminals")]
+                 "terminals", "mt_alpha", "mt_seed")]
 
 
 class OrSolve(ctypes.Structure):
@@ -61,7 +63,7 @@ class OrResult(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int32) for f in
                 ("status", "iters", "final_alpha", "applied", "iter_cap", "pad")] + [
         (f, ctypes.c_int64) for f in ("flow_value", "cut_before", "cut_after", "weight_a",
-                                      "weight_b", "region_vertices", "region_edges")]
+                                      "weight_b", "region_vertices", "region_edges", "mt_kept")]
 
 
 def _load():
@@ -91,6 +93,9 @@ def _load():
     lib.or_pair_features.argtypes = [G, vp, i32, i32, i32, i32, vp]
     lib.or_pair_fm.restype = i32
     lib.or_pair_fm.argtypes = [G, vp, i32, i32, i32, i32, i32, ctypes.c_uint32, vp, vp]
+    lib.or_multitry.restype = i32
+    lib.or_multitry.argtypes = [G, vp, i32, vp, i32, i32, i32, ctypes.c_uint32, vp, vp, vp, vp,
+                                i64, ctypes.POINTER(i64)]
     lib.or_splitmix64.restype = ctypes.c_uint64
     lib.or_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
     lib.or_scc.restype = i32
@@ -128,7 +133,8 @@ def _params(p: dict) -> OrParams:
     return OrParams(p.get("area_mode", 0), p.get("depth", 0), p["alpha"], p["alpha_max"],
                     p["adaptive"], p["max_iters"], p["eps_ppm"], p.get("mb_reps", 0),
                     _i32(p.get("mb_seed", 0)), p.get("fm_limit", 0), _i32(p.get("fm_seed", 0)),
-                    p.get("active_blocks", 0), p.get("cut_side", 0), p.get("terminals", 0))
+                    p.get("active_blocks", 0), p.get("cut_side", 0), p.get("terminals", 0),
+                    p.get("mt_alpha", 0), _i32(p.get("mt_seed", 0)))
 
 
 def _struct_dict(s) -> dict:
@@ -170,6 +176,41 @@ def pair_fm(graph, part: np.ndarray, k: int, a: int, b: int, eps_ppm: int, limit
     keys = ("cut_before", "cut_after", "steps", "kept", "weight_a", "weight_b")
     d = dict(zip(keys, info.tolist()))
     return out, d, log[: d["steps"]].copy()
+
+
+@dataclass
+class MultiTry:
+    part: np.ndarray      # the partition after the phase
+    stats: dict           # searches, moves, kept
+    kept: list            # moves kept per pair
+    changed: np.ndarray   # [k] bool: blocks a kept move left or entered
+    events: list          # (1, round, start, start set size, 0) / (2, v, from, to, gain) /
+                          # (3, moves, kept, 0, 0)
+
+
+def multitry(graph, part: np.ndarray, k: int, pairs, eps_ppm: int, alpha: int, seed: int,
+             max_events: int = 1 << 20) -> MultiTry:
+    """The multi-try FM phase (Sec. 4.2) alone: one round per pair of the
+    block-disjoint `pairs`, in their order; part is copied, not modified."""
+    bnd = _Bound(graph)
+    part = np.array(part, dtype=np.int32, copy=True)
+    pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1))
+    npairs = pr.shape[0] // 2
+    stats = np.zeros(3, dtype=np.int64)
+    kept = np.zeros(max(1, npairs), dtype=np.int64)
+    chg = np.zeros(k, dtype=np.uint8)
+    ev = np.zeros(5 * max_events, dtype=np.int64)
+    nev = ctypes.c_int64(0)
+    rc = _load().or_multitry(ctypes.byref(bnd.s), _ptr(part), k, _ptr(pr) if npairs else None,
+                             npairs, eps_ppm, alpha, seed & 0xFFFFFFFF, _ptr(stats), _ptr(kept),
+                             _ptr(chg), _ptr(ev), ev.shape[0], ctypes.byref(nev))
+    if rc != 0:
+        raise ValueError(f"or_multitry: {rc}")
+    if nev.value > ev.shape[0]:
+        raise ValueError("or_multitry: event log too small")
+    events = [tuple(int(x) for x in r) for r in ev[:nev.value].reshape(-1, 5)]
+    return MultiTry(part, dict(zip(("searches", "moves", "kept"), stats.tolist())),
+                    kept[:npairs].tolist(), chg.astype(bool), events)
 
 
 def splitmix64(seed: int, n: int) -> int:

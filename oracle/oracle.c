@@ -92,6 +92,9 @@ typedef struct {
                        it is infeasible and the largest is feasible */
   int32_t terminals; /* 0: corridor border pinned to s / t by infinite arcs (Sec. 4.1);
                         1: the blocks' outside parts contracted into s / t (arcs of weight omega) */
+  int32_t mt_alpha; /* 0: no multi-try FM; > 0: after the pairwise improvements of a batch, one
+                       multi-try round per pair (Sec. 4.2), stopping rule parameter alpha */
+  int32_t mt_seed;  /* seed of the multi-try keys (its 32 bits, zero-extended) */
 } or_params;
 
 /* one flow solve */
@@ -118,6 +121,7 @@ typedef struct {
   int64_t cut_before, cut_after;
   int64_t weight_a, weight_b;
   int64_t region_vertices, region_edges;
+  int64_t mt_kept; /* multi-try moves kept (after the pairwise improvement) */
 } or_result;
 
 enum { DEC_APPLY = 1, DEC_INFEASIBLE = 2, DEC_EQUAL = 3, DEC_NOT_ADJ = 4 };
@@ -1039,16 +1043,299 @@ int32_t or_pair_fm(const or_graph *g, int32_t *part, int32_t k, int32_t a, int32
   return 0;
 }
 
-/* Adaptive flow iterations (Sec. 4.1) on one pair.  trace (optional) gets
- * one record per solve, at most p->max_iters.  side_out: of the last solve. */
-int32_t or_refine_pair(const or_graph *g, int32_t *part, int32_t k, int32_t a, int32_t b,
-                       const or_params *p, or_result *res, int8_t *side_out, or_solve *trace) {
+/* ------------------------------------------------------------------------ */
+/* multi-try FM (Sec. 4.2): rounds of localized k-way searches               */
+
+/* Keys of the multi-try searches, SplitMix64 outputs from the seed:
+ *   todo order of vertex v       output number 2^40 + v + 1
+ *   queue order of vertex v      output number 2^41 + v + 1
+ *   tie key of target block P    output number 2^42 + v * k + P + 1        */
+static uint64_t mt_key(uint64_t seed, int which, uint64_t x) {
+  return splitmix64_out(seed, (1ull << (40 + which)) + x + 1);
+}
+
+static int cmp_u64(const void *x, const void *y) {
+  uint64_t a = *(const uint64_t *)x, b = *(const uint64_t *)y;
+  return (a > b) - (a < b);
+}
+
+/* The k-way gain of v (Sec. 2.2, k-way local search): over the blocks P other
+ * than v's own that hold a neighbour of v, the largest omega(v, P) minus
+ * omega(v, own block); the block reaching it is the target, equal gains going
+ * to the smaller tie key.  Returns the target, or -1 when every neighbour is
+ * in v's block (v is not a boundary vertex).  wsum: [k], zero on entry and
+ * on return. */
+static int32_t mt_gain(const or_graph *g, const int32_t *part, int32_t k, uint64_t seed,
+                       int32_t v, int64_t *wsum, int64_t *gain_out) {
+  int32_t own = part[v];
+  for (int32_t e = g->xadj[v]; e < g->xadj[v + 1]; e++) wsum[part[g->adjncy[e]]] += g->adjwgt[e];
+  int32_t best = -1;
+  int64_t bg = 0;
+  uint64_t bk = 0;
+  for (int32_t e = g->xadj[v]; e < g->xadj[v + 1]; e++) {
+    int32_t P = part[g->adjncy[e]];
+    if (P == own) continue;
+    int64_t gP = wsum[P] - wsum[own];
+    uint64_t kP = mt_key(seed, 2, (uint64_t)v * (uint64_t)k + (uint64_t)P);
+    if (best < 0 || gP > bg || (gP == bg && kP < bk)) { best = P; bg = gP; bk = kP; }
+  }
+  for (int32_t e = g->xadj[v]; e < g->xadj[v + 1]; e++) wsum[part[g->adjncy[e]]] = 0;
+  *gain_out = bg;
+  return best;
+}
+
+/* KaSPar's stopping rule (Sec. 2.2): with p moves since the last best state
+ * and S1, S2 the sum and the sum of squares of their gains, mean mu = S1/p and
+ * variance sigma^2 = S2/p - mu^2; stop when p mu^2 > alpha sigma^2 + beta,
+ * beta = ln n.  Multiplied by p^2 and with beta as the fixed-point
+ * beta_fx = floor(ln n * 2^16):  2^16 (p S1^2 - alpha (p S2 - S1^2)) > beta_fx p^2. */
+static int mt_stop(int64_t p, __int128 S1, __int128 S2, int32_t alpha, int64_t beta_fx) {
+  __int128 lhs = ((__int128)p * S1 * S1 - (__int128)alpha * ((__int128)p * S2 - S1 * S1)) * 65536;
+  return lhs > (__int128)beta_fx * p * p;
+}
+
+typedef struct {
+  const or_graph *g;
+  int32_t *part;
+  int32_t k;
+  uint64_t seed;
+  int64_t lmax, beta_fx, over; /* over: blocks heavier than lmax */
+  int32_t alpha;
+  int64_t *bw;                 /* [k] block weights */
+  int64_t *wsum;               /* [k] scratch of mt_gain */
+  int32_t *touched;            /* [n] number of the round that last touched the vertex */
+  uint8_t *inq;                /* [n] queued in the current search */
+  int64_t *gain;               /* [n] gain and target of queued vertices */
+  int32_t *tgt;
+  int32_t *q;                  /* [n] queued vertices (with popped ones) */
+  int32_t *mv, *mfrom;         /* [n] moves of the current search */
+  int64_t *ev;                 /* optional event log */
+  int64_t nev, evcap;
+} mt_ctx;
+
+static void mt_event(mt_ctx *C, int64_t a, int64_t b, int64_t c, int64_t d, int64_t e) {
+  if (C->ev && C->nev + 5 <= C->evcap) {
+    int64_t *x = C->ev + C->nev;
+    x[0] = a; x[1] = b; x[2] = c; x[3] = d; x[4] = e;
+  }
+  C->nev += 5;
+}
+
+/* Queues y when it is a boundary vertex; a queued vertex counts as touched by
+ * this round from then on. */
+static int32_t mt_insert(mt_ctx *C, int32_t y, int32_t round, int32_t *nq) {
+  int32_t t = mt_gain(C->g, C->part, C->k, C->seed, y, C->wsum, &C->gain[y]);
+  if (t < 0) return 0;
+  C->touched[y] = round;
+  C->tgt[y] = t;
+  C->inq[y] = 1;
+  C->q[(*nq)++] = y;
+  return 1;
+}
+
+/* One multi-try round (Sec. 4.2) over a todo list in its order: each entry
+ * that is still a boundary vertex and was not touched by an earlier search of
+ * this round starts a k-way search from itself and its untouched boundary
+ * neighbours.  A search repeatedly takes the queued vertex with the largest
+ * gain (equal gains: the larger queue key), moves it to its target block
+ * unless that block would exceed lmax, and queues the untouched boundary
+ * neighbours of a moved vertex (recomputing the gains of queued ones; a queued
+ * vertex left without a target leaves the queue); it ends when the queue is
+ * empty or the stopping rule fires, and rolls back to its best state: fewest
+ * blocks above lmax, then lowest cut, earliest on ties.  Vertices touched by a
+ * search (queued or moved) are not queued again in this round.  chg (optional,
+ * [k]): the blocks a kept move left or entered get 1. */
+static void mt_round(mt_ctx *C, const int32_t *todo, int32_t ntodo, int32_t round,
+                     int64_t *searches, int64_t *moves, int64_t *kept, uint8_t *chg) {
+  const or_graph *g = C->g;
+  int32_t *part = C->part;
+  for (int32_t i = 0; i < ntodo; i++) {
+    int32_t v = todo[i];
+    if (C->touched[v] == round) continue;
+    int64_t gv;
+    if (mt_gain(g, part, C->k, C->seed, v, C->wsum, &gv) < 0) continue; /* no longer boundary */
+    /* the search's start set: v and its untouched boundary neighbours */
+    int32_t nq = 0;
+    mt_insert(C, v, round, &nq);
+    for (int32_t e = g->xadj[v]; e < g->xadj[v + 1]; e++) {
+      int32_t y = g->adjncy[e];
+      if (C->touched[y] != round) mt_insert(C, y, round, &nq);
+    }
+    (*searches)++;
+    mt_event(C, 1, round, v, nq, 0);
+    int64_t delta = 0, best = 0, best_over = C->over;
+    int64_t nmv = 0, best_n = 0, pcount = 0;
+    __int128 S1 = 0, S2 = 0;
+    for (;;) {
+      int32_t x = -1;
+      uint64_t kx = 0;
+      for (int32_t j = 0; j < nq; j++) {
+        int32_t y = C->q[j];
+        if (!C->inq[y]) continue;
+        uint64_t ky = mt_key(C->seed, 1, (uint64_t)y);
+        if (x < 0 || C->gain[y] > C->gain[x] || (C->gain[y] == C->gain[x] && ky > kx)) { x = y; kx = ky; }
+      }
+      if (x < 0) break;
+      C->inq[x] = 0;
+      int32_t to = C->tgt[x], from = part[x];
+      int64_t gx = C->gain[x], cx = g->vwgt[x];
+      if (C->bw[to] + cx > C->lmax) continue; /* the move would overload its target */
+      if (C->bw[from] > C->lmax && C->bw[from] - cx <= C->lmax) C->over--;
+      C->bw[from] -= cx;
+      C->bw[to] += cx;
+      part[x] = to;
+      delta -= gx;
+      C->mv[nmv] = x;
+      C->mfrom[nmv] = from;
+      nmv++;
+      mt_event(C, 2, x, from, to, gx);
+      if (C->over < best_over || (C->over == best_over && delta < best)) {
+        best = delta;
+        best_over = C->over;
+        best_n = nmv;
+        pcount = 0;
+        S1 = S2 = 0;
+      } else {
+        pcount++;
+        S1 += gx;
+        S2 += (__int128)gx * gx;
+        if (mt_stop(pcount, S1, S2, C->alpha, C->beta_fx)) break;
+      }
+      for (int32_t e = g->xadj[x]; e < g->xadj[x + 1]; e++) {
+        int32_t y = g->adjncy[e];
+        if (C->inq[y]) {
+          int32_t t = mt_gain(g, part, C->k, C->seed, y, C->wsum, &C->gain[y]);
+          if (t < 0) C->inq[y] = 0;
+          else C->tgt[y] = t;
+        } else if (C->touched[y] != round) {
+          mt_insert(C, y, round, &nq);
+        }
+      }
+    }
+    for (int32_t j = 0; j < nq; j++) C->inq[C->q[j]] = 0;
+    /* roll back the moves after the best state */
+    for (int64_t j = nmv - 1; j >= best_n; j--) {
+      int32_t x = C->mv[j], from = C->mfrom[j], to = part[x];
+      int64_t cx = g->vwgt[x];
+      C->bw[to] -= cx;
+      if (C->bw[from] <= C->lmax && C->bw[from] + cx > C->lmax) C->over++;
+      C->bw[from] += cx;
+      part[x] = from;
+    }
+    if (chg)
+      for (int64_t j = 0; j < best_n; j++) {
+        chg[C->mfrom[j]] = 1;
+        chg[part[C->mv[j]]] = 1;
+      }
+    mt_event(C, 3, nmv, best_n, 0, 0);
+    *moves += nmv;
+    *kept += best_n;
+  }
+}
+
+/* The multi-try phase of a batch (after its pairwise improvements): the todo
+ * list of each pair, formed from the partition at the start of the phase, is
+ * every vertex of its two blocks with a neighbour in another block, ordered
+ * by the upper 32 bits of its todo key, then by id; then one round per pair in
+ * pair order.  kept: [npairs] moves kept per pair; chg (optional, [k]).
+ * ev (optional): events of 5 int64: (1, round, start vertex, start set size,
+ * 0) per search, (2, vertex, from, to, gain) per move, (3, moves, kept, 0, 0)
+ * at the end of a search; *nev gets their count * 5 (even past evcap). */
+static int32_t mt_phase(const or_graph *g, int32_t *part, int32_t k, const int32_t *pairs,
+                        int32_t npairs, const or_params *p, int64_t *kept, int64_t *stats3,
+                        uint8_t *chg, int64_t *ev, int64_t evcap, int64_t *nev) {
+  int32_t n = g->n;
+  mt_ctx C;
+  memset(&C, 0, sizeof(C));
+  C.g = g;
+  C.part = part;
+  C.k = k;
+  C.seed = (uint64_t)(uint32_t)p->mt_seed;
+  C.alpha = p->mt_alpha;
+  C.beta_fx = (int64_t)floor(log((double)n) * 65536.0);
+  C.bw = (int64_t *)calloc((size_t)k, sizeof(int64_t));
+  C.wsum = (int64_t *)calloc((size_t)k, sizeof(int64_t));
+  C.touched = (int32_t *)calloc((size_t)n, sizeof(int32_t));
+  C.inq = (uint8_t *)calloc((size_t)n, 1);
+  C.gain = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+  C.tgt = (int32_t *)calloc((size_t)n, sizeof(int32_t));
+  C.q = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  C.mv = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  C.mfrom = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  uint64_t *tk = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+  int64_t *toff = (int64_t *)calloc((size_t)npairs + 1, sizeof(int64_t));
+  int32_t *todo = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t rc = 0;
+  if (!C.bw || !C.wsum || !C.touched || !C.inq || !C.gain || !C.tgt || !C.q || !C.mv || !C.mfrom ||
+      !tk || !toff || !todo) { rc = -7; goto done; }
+  C.ev = ev;
+  C.evcap = evcap;
+  int64_t cV = 0, maxc = 0;
+  for (int32_t u = 0; u < n; u++) {
+    cV += g->vwgt[u];
+    if (g->vwgt[u] > maxc) maxc = g->vwgt[u];
+    C.bw[part[u]] += g->vwgt[u];
+  }
+  C.lmax = (int64_t)(((__int128)(1000000 + (int64_t)p->eps_ppm) * cV) / ((__int128)1000000 * k)) +
+           maxc;
+  for (int32_t b = 0; b < k; b++) C.over += C.bw[b] > C.lmax;
+  /* the todo lists, all formed before the first round */
+  for (int32_t i = 0; i < npairs; i++) {
+    int32_t a = pairs[2 * i], b = pairs[2 * i + 1];
+    int64_t nt = 0;
+    for (int32_t u = 0; u < n; u++) {
+      if (part[u] != a && part[u] != b) continue;
+      int boundary = 0;
+      for (int32_t e = g->xadj[u]; e < g->xadj[u + 1] && !boundary; e++)
+        boundary = part[g->adjncy[e]] != part[u];
+      if (boundary) tk[nt++] = ((mt_key(C.seed, 0, (uint64_t)u) >> 32) << 32) | (uint32_t)u;
+    }
+    qsort(tk, (size_t)nt, sizeof(uint64_t), cmp_u64);
+    for (int64_t j = 0; j < nt; j++) todo[toff[i] + j] = (int32_t)(uint32_t)tk[j];
+    toff[i + 1] = toff[i] + nt;
+  }
+  for (int32_t i = 0; i < npairs; i++) {
+    int64_t s = 0, m = 0, kk = 0;
+    mt_round(&C, todo + toff[i], (int32_t)(toff[i + 1] - toff[i]), i + 1, &s, &m, &kk, chg);
+    kept[i] = kk;
+    if (stats3) { stats3[0] += s; stats3[1] += m; stats3[2] += kk; }
+  }
+  if (nev) *nev = C.nev;
+done:
+  free(C.bw); free(C.wsum); free(C.touched); free(C.inq); free(C.gain); free(C.tgt); free(C.q);
+  free(C.mv); free(C.mfrom); free(tk); free(toff); free(todo);
+  return rc;
+}
+
+/* The multi-try phase alone on a partition (for tests): pairs [2*npairs]
+ * (block-disjoint), stats[3] = searches, moves made, moves kept; kept
+ * [npairs]; chg (optional, [k]); events as for mt_phase. */
+int32_t or_multitry(const or_graph *g, int32_t *part, int32_t k, const int32_t *pairs,
+                    int32_t npairs, int32_t eps_ppm, int32_t alpha, uint32_t seed,
+                    int64_t *stats, int64_t *kept, uint8_t *chg, int64_t *ev, int64_t evcap,
+                    int64_t *nev) {
+  if (alpha < 1 || eps_ppm < 0 || npairs < 0) return -8;
+  or_params p;
+  memset(&p, 0, sizeof(p));
+  p.eps_ppm = eps_ppm;
+  p.mt_alpha = alpha;
+  p.mt_seed = (int32_t)seed;
+  memset(stats, 0, sizeof(int64_t) * 3);
+  return mt_phase(g, part, k, pairs, npairs, &p, kept, stats, chg, ev, evcap, nev);
+}
+
+/* Adaptive flow iterations (Sec. 4.1) on one pair, after its 2-way FM when
+ * fm_limit > 0: the pairwise improvement.  trace (optional) gets one record
+ * per solve, at most p->max_iters.  side_out: of the last solve. */
+static int32_t refine_pair_core(const or_graph *g, int32_t *part, int32_t k, int32_t a, int32_t b,
+                                const or_params *p, or_result *res, int8_t *side_out,
+                                or_solve *trace) {
   memset(res, 0, sizeof(*res));
   if (a < 0 || b < 0 || a >= k || b >= k || a == b) return -3;
   if (p->alpha < 1 || p->alpha_max < 1 || p->max_iters < 1 || p->eps_ppm < 0 ||
       (p->area_mode != 0 && p->area_mode != 1) || p->depth < 0 || p->mb_reps < 0 ||
       p->fm_limit < 0 || p->cut_side < 0 || p->cut_side > 2 ||
-      (p->terminals != 0 && p->terminals != 1))
+      (p->terminals != 0 && p->terminals != 1) || p->mt_alpha < 0)
     return -8;
   int64_t w_a = 0, w_b = 0;
   for (int32_t u = 0; u < g->n; u++) {
@@ -1113,10 +1400,13 @@ int32_t or_refine_pair(const or_graph *g, int32_t *part, int32_t k, int32_t a, i
   return 0;
 }
 
-/* Pairs of one quotient-graph matching, one after the other.  The pairs must
- * be block-disjoint, so the order does not change the outcome. */
-int32_t or_refine_batch(const or_graph *g, int32_t *part, int32_t k, const int32_t *pairs,
-                        int32_t npairs, const or_params *p, or_result *res, or_solve *trace) {
+/* Pairs of one quotient-graph matching: the pairwise improvements one after
+ * the other (the pairs must be block-disjoint, so their order does not change
+ * the outcome), then with mt_alpha > 0 the multi-try phase over the pairs in
+ * their order.  chg (optional, [k]): blocks changed by the multi-try phase. */
+static int32_t refine_batch(const or_graph *g, int32_t *part, int32_t k, const int32_t *pairs,
+                            int32_t npairs, const or_params *p, or_result *res, or_solve *trace,
+                            int8_t *side_out, uint8_t *chg) {
   uint8_t *used = (uint8_t *)calloc((size_t)(k > 0 ? k : 1), 1);
   if (!used) return -7;
   for (int32_t i = 0; i < npairs; i++) {
@@ -1127,11 +1417,30 @@ int32_t or_refine_batch(const or_graph *g, int32_t *part, int32_t k, const int32
   }
   free(used);
   for (int32_t i = 0; i < npairs; i++) {
-    int32_t rc = or_refine_pair(g, part, k, pairs[2 * i], pairs[2 * i + 1], p, &res[i], NULL,
-                                trace ? trace + (size_t)i * p->max_iters : NULL);
+    int32_t rc = refine_pair_core(g, part, k, pairs[2 * i], pairs[2 * i + 1], p, &res[i], side_out,
+                                  trace ? trace + (size_t)i * p->max_iters : NULL);
+    if (rc != 0) return rc;
+  }
+  if (p->mt_alpha > 0 && npairs > 0) {
+    int64_t *kept = (int64_t *)calloc((size_t)npairs, sizeof(int64_t));
+    if (!kept) return -7;
+    int32_t rc = mt_phase(g, part, k, pairs, npairs, p, kept, NULL, chg, NULL, 0, NULL);
+    for (int32_t i = 0; i < npairs && rc == 0; i++) res[i].mt_kept = kept[i];
+    free(kept);
     if (rc != 0) return rc;
   }
   return 0;
+}
+
+int32_t or_refine_pair(const or_graph *g, int32_t *part, int32_t k, int32_t a, int32_t b,
+                       const or_params *p, or_result *res, int8_t *side_out, or_solve *trace) {
+  const int32_t pr[2] = {a, b};
+  return refine_batch(g, part, k, pr, 1, p, res, trace, side_out, NULL);
+}
+
+int32_t or_refine_batch(const or_graph *g, int32_t *part, int32_t k, const int32_t *pairs,
+                        int32_t npairs, const or_params *p, or_result *res, or_solve *trace) {
+  return refine_batch(g, part, k, pairs, npairs, p, res, trace, NULL, NULL);
 }
 
 /* Quotient graph (Sec. 2.1): one edge {a,b}, a < b, per pair of blocks that
@@ -1187,7 +1496,8 @@ int64_t or_total_cut(const or_graph *g, const int32_t *part) {
  * an active block (the colour classes of the whole quotient graph, filtered),
  * and the blocks of the pairs it changed are the active ones of the next
  * sweep.  A pair changed when a flow solve or its FM pass changed the
- * partition.  Returns 0; stats[0] = sweeps run, stats[1] = flow solves,
+ * partition, or its multi-try round kept a move; the blocks a kept multi-try
+ * move left or entered are active in the next sweep too.  Returns 0; stats[0] = sweeps run, stats[1] = flow solves,
  * stats[2] = changed pairs, stats[3] = region edges. */
 int32_t or_sweep(const or_graph *g, int32_t *part, int32_t k, const or_params *p,
                  int32_t max_sweeps, int64_t *total_cut_out, int64_t *stats) {
@@ -1220,15 +1530,13 @@ int32_t or_sweep(const or_graph *g, int32_t *part, int32_t k, const or_params *p
           np++;
         }
       if (np == 0) continue;
-      rc = or_refine_batch(g, part, k, pairs, np, p, res, NULL);
+      rc = refine_batch(g, part, k, pairs, np, p, res, NULL, NULL, nact);
       if (rc != 0) break;
       for (int32_t i = 0; i < np; i++) {
         stats[1] += res[i].iters;
         stats[3] += res[i].region_edges;
-        if (res[i].status == ST_ACCEPTED) {
-          changed++;
-          nact[pairs[2 * i]] = nact[pairs[2 * i + 1]] = 1;
-        }
+        if (res[i].status == ST_ACCEPTED) nact[pairs[2 * i]] = nact[pairs[2 * i + 1]] = 1;
+        if (res[i].status == ST_ACCEPTED || res[i].mt_kept > 0) changed++;
       }
     }
     if (rc != 0) break;
