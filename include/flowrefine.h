@@ -164,6 +164,30 @@ typedef struct {
    * (balance aside), never worse than the pinned one.  Those arc capacities
    * count toward the 2^31 capacity bound. */
   int32_t terminals;
+  /* Multi-try FM (Sec. 4.2; "localized k-way searches"), after the pairwise
+   * improvements of a batch or of each round of a sweep.  0: off.  a > 0:
+   * one multi-try round per pair, in pair order (the searches of a round
+   * may move vertices into any block, so they run one after the other): the
+   * round's todo list is every vertex of the pair's two blocks with a
+   * neighbour in another block, taken when the phase starts, in the order of
+   * key SplitMix64(mt_seed) output number 2^40 + v + 1 (its upper 32 bits,
+   * then v); an entry that is still a boundary vertex and was not touched by
+   * an earlier search of the round starts a k-way search from itself and
+   * its untouched boundary neighbours.  The search keeps one queue ordered by
+   * the k-way gain (the largest weight to another adjacent block minus the
+   * weight to the own block; target ties by the smaller key of output
+   * 2^42 + v*k + P + 1), equal gains by the larger key of output 2^41 + v +
+   * 1; a popped vertex moves unless its target would exceed L_max; a moved
+   * vertex's untouched boundary neighbours join, queued ones are updated (and
+   * leave without a target); it stops when the queue is empty or when
+   * p mu^2 > a sigma^2 + ln n over the p moves since the last best state
+   * (KaSPar's rule, evaluated exactly with ln n as floor(ln n * 2^16) /
+   * 2^16), then rolls back to the first state with the fewest blocks above
+   * L_max, then the lowest cut.  Vertices a search queued are not queued
+   * again in the round.  Each vertex's weighted degree must stay below 2^31
+   * (else FR_E_OVERFLOW).  The paper uses a = 10. */
+  int32_t mt_alpha;
+  int32_t mt_seed;
 } fr_params;
 
 #define FR_TERM_PINNED 0
@@ -183,6 +207,8 @@ typedef struct {
   int64_t cut_before, cut_after;         /* pair cut omega(E_ab) before / after the call */
   int64_t weight_a, weight_b;            /* c(V_a), c(V_b) after the call */
   int64_t region_vertices, region_edges; /* corridor vertices / edges summed over the solves */
+  int64_t mt_kept;     /* multi-try moves kept after this pair's improvement (status,
+                          cut_after and weights are those of the pairwise improvement) */
 } fr_result;
 
 /* One flow solve (trace record). */
@@ -275,8 +301,9 @@ int32_t fr_quotient_matchings(fr_context *ctx, const fr_graph *g, const int32_t 
  * batched solve per colour class in colour order (all rounds of a sweep
  * recorded into one hipGraph and launched once), until a sweep changes
  * nothing or max_sweeps sweeps ran (p->active_blocks: only pairs with a block
- * changed in the previous sweep).  stats (optional, host int64 [4]): sweeps,
- * flow solves, changed pairs (a flow solve applied or FM moves kept), region
+ * changed in the previous sweep, or entered or left by a kept multi-try
+ * move).  stats (optional, host int64 [4]): sweeps, flow solves, changed
+ * pairs (a flow solve applied, or FM or multi-try moves kept), region
  * edges.  total_cut_out: the cut
  * sum_{i<j} omega(E_ij) after the sweep. */
 int32_t flow_refine_sweep(fr_context *ctx, const fr_graph *g, int32_t *part, int32_t k,
@@ -329,6 +356,7 @@ int32_t fr_set_timing(fr_context *ctx, int32_t on);
  *   [11] solves whose component graph (more than 2,048 components) was kept
  *   in device memory instead of LDS; [12] FM moves made, [13] FM moves kept;
  *   [14] flow-kernel launches (one per adaptive iteration of each round);
+ *   [28] multi-try searches, [29] multi-try moves made, [30] kept;
  *   [16..27] vertices and arcs touched: boundary scan, corridor BFS, network
  *   build, push/relabel sweeps, global relabels, residual closure (vertices
  *   then arcs for each); the rest 0. */

@@ -189,9 +189,10 @@ class MultiTry:
 
 
 def multitry(graph, part: np.ndarray, k: int, pairs, eps_ppm: int, alpha: int, seed: int,
-             max_events: int = 1 << 20) -> MultiTry:
+             max_events: int | None = 1 << 20) -> MultiTry:
     """The multi-try FM phase (Sec. 4.2) alone: one round per pair of the
-    block-disjoint `pairs`, in their order; part is copied, not modified."""
+    block-disjoint `pairs`, in their order; part is copied, not modified.
+    max_events=None keeps no event log."""
     bnd = _Bound(graph)
     part = np.array(part, dtype=np.int32, copy=True)
     pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1))
@@ -199,15 +200,18 @@ def multitry(graph, part: np.ndarray, k: int, pairs, eps_ppm: int, alpha: int, s
     stats = np.zeros(3, dtype=np.int64)
     kept = np.zeros(max(1, npairs), dtype=np.int64)
     chg = np.zeros(k, dtype=np.uint8)
-    ev = np.zeros(5 * max_events, dtype=np.int64)
+    ev = np.zeros(5 * max_events if max_events else 1, dtype=np.int64)
     nev = ctypes.c_int64(0)
     rc = _load().or_multitry(ctypes.byref(bnd.s), _ptr(part), k, _ptr(pr) if npairs else None,
                              npairs, eps_ppm, alpha, seed & 0xFFFFFFFF, _ptr(stats), _ptr(kept),
-                             _ptr(chg), _ptr(ev), ev.shape[0], ctypes.byref(nev))
+                             _ptr(chg), _ptr(ev) if max_events else None,
+                             ev.shape[0] if max_events else 0, ctypes.byref(nev))
     if rc != 0:
         raise ValueError(f"or_multitry: {rc}")
-    if nev.value > ev.shape[0]:
+    if max_events and nev.value > ev.shape[0]:
         raise ValueError("or_multitry: event log too small")
+    if not max_events:
+        nev.value = 0
     events = [tuple(int(x) for x in r) for r in ev[:nev.value].reshape(-1, 5)]
     return MultiTry(part, dict(zip(("searches", "moves", "kept"), stats.tolist())),
                     kept[:npairs].tolist(), chg.astype(bool), events)

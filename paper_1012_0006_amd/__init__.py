@@ -38,14 +38,14 @@ class FrParams(ctypes.Structure):
     _fields_ = [(f, i32) for f in ("area_mode", "depth", "alpha", "alpha_max", "adaptive",
                                    "max_iters", "eps_ppm", "use_mlp", "mb_reps", "mb_seed",
                                    "fm_limit", "fm_seed", "active_blocks", "cut_side",
-                                   "terminals")]
+                                   "terminals", "mt_alpha", "mt_seed")]
 
 
 class FrResult(ctypes.Structure):
     _fields_ = [(f, i32) for f in ("status", "iters", "final_alpha", "applied", "iter_cap",
                                    "start_alpha")] + [
         (f, i64) for f in ("flow_value", "cut_before", "cut_after", "weight_a", "weight_b",
-                           "region_vertices", "region_edges")]
+                           "region_vertices", "region_edges", "mt_kept")]
 
 
 class FrSolve(ctypes.Structure):
@@ -150,9 +150,9 @@ def params(**kw) -> FrParams:
     bits are used)."""
     d = dict(area_mode=0, depth=0, alpha=16, alpha_max=16, adaptive=1, max_iters=16,
              eps_ppm=30000, use_mlp=0, mb_reps=0, mb_seed=0, fm_limit=0, fm_seed=0,
-             active_blocks=0, cut_side=0, terminals=0)
+             active_blocks=0, cut_side=0, terminals=0, mt_alpha=0, mt_seed=0)
     d.update(kw)
-    for f in ("mb_seed", "fm_seed"):
+    for f in ("mb_seed", "fm_seed", "mt_seed"):
         seed = int(d[f]) & 0xFFFFFFFF
         d[f] = seed - (1 << 32) if seed >= 1 << 31 else seed
     return FrParams(**{k: int(d[k]) for k, _ in FrParams._fields_})
@@ -257,7 +257,8 @@ def stats_dict(ctx) -> dict:
              sweeps=cnt[0], relabels=cnt[1], bfs_levels=cnt[2], gr_levels=cnt[3],
              cl_levels=cnt[4], workgroups=cnt[5], diag=cnt[6], slots=cnt[7],
              mb_kernel_ms=cnt[8] / 1e6, mb_free=cnt[9], mb_comp=cnt[10], mb_big=cnt[11],
-             fm_steps=cnt[12], fm_kept=cnt[13], flow_launches=cnt[14])
+             fm_steps=cnt[12], fm_kept=cnt[13], flow_launches=cnt[14], mt_searches=cnt[28],
+             mt_moves=cnt[29], mt_kept=cnt[30])
     d.update({k: cnt[16 + i] for i, k in enumerate(WORK_KEYS)})
     return d
 

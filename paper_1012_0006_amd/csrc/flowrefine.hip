@@ -16,6 +16,7 @@
 #include "fr_mb.h"
 #include "fr_fm.h"
 #include "fr_mlp.h"
+#include "fr_mt.h"
 
 #define HIPCHK(x)                        \
   do {                                   \
@@ -47,6 +48,15 @@ struct DevBufs {
   int64_t mbccap = 0;
   int32_t *fmg = nullptr, *fmq = nullptr;  // 2-way FM: per-vertex gains, queue positions (lazy)
   int64_t fmcap = 0;
+  // multi-try FM (lazy): per vertex touched stamps, targets, heap slots, heap
+  // overflow [2n], move log [n] x 2; todo keys per arena slot x 2; per block
+  // weights and changed flags
+  int32_t *mtt = nullptr, *mtb = nullptr, *mtq = nullptr, *mth = nullptr, *mtv = nullptr,
+          *mtf = nullptr;
+  unsigned long long *mtk = nullptr, *mtk2 = nullptr;
+  int64_t *mtw = nullptr;
+  uint8_t *mtchg = nullptr;
+  int64_t mtncap = 0, mtscap = 0, mtkcap = 0;
   // per arc
   int32_t *ga = nullptr, *gw = nullptr;
   Arc *arc = nullptr;  // corridor arcs
@@ -86,6 +96,7 @@ struct fr_context {
   int32_t timed_iters = 0;
   int speculate = 1;
   int timing = 0;  // sweeps: uncaptured rounds with per-phase events
+  int32_t mt_stamp = 0;  // multi-try: touched stamps used so far
   // stats of the last call
   double ms[8] = {0};
   int64_t counters[32] = {0};
@@ -130,6 +141,14 @@ static void free_vertex_arc(DevBufs &d) {
   dfree(d.fmq);
   d.fmg = d.fmq = nullptr;
   d.fmcap = 0;
+  for (int32_t **pp : {&d.mtt, &d.mtb, &d.mtq, &d.mth, &d.mtv, &d.mtf}) {
+    dfree(*pp);
+    *pp = nullptr;
+  }
+  dfree(d.mtk);
+  dfree(d.mtk2);
+  d.mtk = d.mtk2 = nullptr;
+  d.mtncap = d.mtscap = 0;
   dfree(d.lflag);
   d.lflag = nullptr;
   dfree(d.side);
@@ -169,10 +188,13 @@ static int32_t ensure_capacity(fr_context *c, int64_t n, int64_t narcs, int64_t 
     c->stamp = 2;
   }
   if (k > d.kcap) {
-    dfree(d.blk2pair); dfree(d.bstat); dfree(d.qadj);
+    dfree(d.blk2pair); dfree(d.bstat); dfree(d.qadj); dfree(d.mtw); dfree(d.mtchg);
     d.blk2pair = nullptr;
     d.bstat = nullptr;
     d.qadj = nullptr;
+    d.mtw = nullptr;
+    d.mtchg = nullptr;
+    d.mtkcap = 0;
     if (dalloc(&d.blk2pair, k) != hipSuccess || dalloc(&d.bstat, 3 * k) != hipSuccess ||
         dalloc(&d.qadj, k * k) != hipSuccess)
       return FR_E_OOM;
@@ -229,6 +251,18 @@ static int32_t scratch_address(int device) {
     return FR_E_DEVICE;
   }
   scratch_ptr[device] = ptr;
+  return FR_OK;
+}
+
+// Multi-try touched stamps: count rounds of pairs need count + 1 stamps;
+// the stamp array is cleared well before int32 wraps.
+static int32_t reserve_mt(fr_context *c, int64_t count, int32_t *first) {
+  if ((int64_t)c->mt_stamp + count + 2 > (1 << 30)) {
+    HIPCHK(hipMemsetAsync(c->d.mtt, 0, sizeof(int32_t) * (size_t)c->d.mtncap, c->cs));
+    c->mt_stamp = 0;
+  }
+  *first = c->mt_stamp;
+  c->mt_stamp += (int32_t)(count + 1);
   return FR_OK;
 }
 
@@ -304,7 +338,8 @@ extern "C" int32_t fr_destroy(fr_context *c) {
   if (c->cs) (void)hipStreamSynchronize(c->cs);
   free_vertex_arc(c->d);
   DevBufs &d = c->d;
-  void *ptrs[] = {d.blk2pair, d.bstat, d.qadj, d.ps,    d.pairs, d.alpha0, d.order,
+  void *ptrs[] = {d.mtw,      d.mtchg,
+                  d.blk2pair, d.bstat, d.qadj, d.ps,    d.pairs, d.alpha0, d.order,
                   d.trace,    d.ucnt,  d.voff, d.aoff,  d.fstat, d.feats,  d.probs,
                   d.base,     d.scal,  d.ctl,  d.mlp,   d.mlp_m, d.mlp_v,  d.mlp_g,
                   d.qctr,     d.pcnt,  d.pacc, d.act,   d.nact,  d.vpre,   d.cpre, d.mpre,
@@ -376,7 +411,8 @@ static int32_t check_params(const fr_params *p) {
   if (p->depth < 0 || p->alpha < 1 || p->alpha_max < 1 || p->alpha_max > FR_MAX_ALPHA ||
       p->max_iters < 1 || p->max_iters > FR_MAX_ITERS || p->eps_ppm < 0 || p->eps_ppm > 100000000 ||
       p->mb_reps < 0 || p->mb_reps > FR_MB_MAX_REPS || p->fm_limit < 0 || p->cut_side < 0 ||
-      p->cut_side > 2 || (p->terminals != FR_TERM_PINNED && p->terminals != FR_TERM_CONTRACTED))
+      p->cut_side > 2 || (p->terminals != FR_TERM_PINNED && p->terminals != FR_TERM_CONTRACTED) ||
+      p->mt_alpha < 0)
     return FR_E_INVALID_ARG;
   return FR_OK;
 }
@@ -454,6 +490,21 @@ static KArgs call_args(fr_context *c, const DevBufs &d, const fr_graph *g, int32
     A.terminals = p->terminals;
   }
   A.mb_lds = c->tune.mb_lds;
+  if (p && p->mt_alpha > 0) {
+    A.mt_alpha = p->mt_alpha;
+    A.mt_seed = p->mt_seed;
+    A.mt_beta = (int64_t)std::floor(std::log((double)g->n) * 65536.0);
+    A.mtw = d.mtw;
+    A.mtk = d.mtk;
+    A.mtk2 = d.mtk2;
+    A.mtt = d.mtt;
+    A.mtb = d.mtb;
+    A.mtq = d.mtq;
+    A.mth = d.mth;
+    A.mtv = d.mtv;
+    A.mtf = d.mtf;
+    A.mtchg = d.mtchg;
+  }
   A.mbq = d.mbq;
   A.mbc = d.mbc;
   A.fmg = d.fmg;
@@ -593,6 +644,14 @@ static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t s
     if (timed) HIPCHK(hipEventRecord(ev[4], st));
     hipLaunchKernelGGL(k_select, dim3(A.P / A.W), dim3(1024), 0, st, A, it);
   }
+  // multi-try FM (Sec. 4.2) after the pairwise improvements of the round
+  if (A.mt_alpha > 0) {
+    hipLaunchKernelGGL(k_mt_clear, dim3(1), dim3(1024), 0, st, A);
+    hipLaunchKernelGGL(k_mt_weights, dim3(sblocks), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_mt_todo, dim3(sblocks), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_mt_sort, dim3(A.P / A.W), dim3(MT_SORT_TPB), 0, st, A);
+    hipLaunchKernelGGL(k_mt, dim3(1), dim3(WAVE), 0, st, A);
+  }
   HIPCHK(hipGetLastError());
   c->timed_iters = timed ? A.max_iters : 0;
   return FR_OK;
@@ -624,6 +683,7 @@ static void fill_result(const PairState &s, fr_result &r) {
   r.weight_b = s.cB;
   r.region_vertices = s.rv_sum;
   r.region_edges = s.re_sum;
+  r.mt_kept = s.mt_kept;
   if (s.applied > 0) r.status = FR_ACCEPTED;
   else if (s.last_dec == FR_DEC_NOT_ADJACENT) r.status = FR_NOT_ADJACENT;
   else if (s.fm_kept > 0) r.status = FR_ACCEPTED;  // FM moved vertices, the flow did not
@@ -655,6 +715,9 @@ static void add_entry_stats(fr_context *c, const PairState *ps, size_t count) {
     C[11] += s.mb_big;
     C[12] += s.fm_steps;
     C[13] += s.fm_kept;
+    C[28] += s.mt_searches;
+    C[29] += s.mt_moves;
+    C[30] += s.mt_kept;
     ph[0] += s.t_relabel;
     ph[1] += s.t_push;
   }
@@ -735,6 +798,42 @@ static int32_t ensure_mb(fr_context *c, const fr_params *p) {
     if (dalloc(&d.fmg, d.ncap) != hipSuccess || dalloc(&d.fmq, d.ncap) != hipSuccess)
       return FR_E_OOM;
     d.fmcap = d.ncap;
+  }
+  if (p->mt_alpha > 0) {  // multi-try FM
+    if (d.mtncap < d.ncap) {
+      for (int32_t **pp : {&d.mtt, &d.mtb, &d.mtq, &d.mth, &d.mtv, &d.mtf}) {
+        dfree(*pp);
+        *pp = nullptr;
+      }
+      d.mtncap = 0;
+      if (dalloc(&d.mtt, d.ncap) != hipSuccess || dalloc(&d.mtb, d.ncap) != hipSuccess ||
+          dalloc(&d.mtq, d.ncap) != hipSuccess || dalloc(&d.mth, 2 * d.ncap) != hipSuccess ||
+          dalloc(&d.mtv, d.ncap) != hipSuccess || dalloc(&d.mtf, d.ncap) != hipSuccess)
+        return FR_E_OOM;
+      // touched stamps start below every stamp in use, heap slots at -1
+      HIPCHK(hipMemset(d.mtt, 0, sizeof(int32_t) * (size_t)d.ncap));
+      HIPCHK(hipMemset(d.mtq, 0xff, sizeof(int32_t) * (size_t)d.ncap));
+      d.mtncap = d.ncap;
+      c->mt_stamp = 0;
+    }
+    if (d.mtscap < d.sncap) {
+      dfree(d.mtk);
+      dfree(d.mtk2);
+      d.mtk = d.mtk2 = nullptr;
+      d.mtscap = 0;
+      if (dalloc(&d.mtk, d.sncap) != hipSuccess || dalloc(&d.mtk2, d.sncap) != hipSuccess)
+        return FR_E_OOM;
+      d.mtscap = d.sncap;
+    }
+    if (d.mtkcap < d.kcap) {
+      dfree(d.mtw);
+      dfree(d.mtchg);
+      d.mtw = nullptr;
+      d.mtchg = nullptr;
+      if (dalloc(&d.mtw, d.kcap) != hipSuccess || dalloc(&d.mtchg, d.kcap) != hipSuccess)
+        return FR_E_OOM;
+      d.mtkcap = d.kcap;
+    }
   }
   if (p->mb_reps <= 0) return FR_OK;
   if (d.mbqcap < d.sacap) {
@@ -876,6 +975,11 @@ static int32_t refine(fr_context *c, const fr_graph *g, int32_t *part, int32_t k
   }
   HIPCHK(hipMemcpyAsync(d.pairs, vp.data(), sizeof(int32_t) * 2 * V, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(d.alpha0, a0.data(), sizeof(int32_t) * V, hipMemcpyHostToDevice, st));
+  int32_t mts = 0;
+  if (p->mt_alpha > 0) {
+    if ((rc = reserve_mt(c, npairs, &mts))) return rc;
+    HIPCHK(hipMemsetAsync(d.mtchg, 0, (size_t)k, st));
+  }
   int32_t stamp0 = 0;
   if (carve) {
     // the carved marks keep the previous call's stamps: clear them
@@ -887,6 +991,7 @@ static int32_t refine(fr_context *c, const fr_graph *g, int32_t *part, int32_t k
     return rc;
   }
   KArgs R = round_args(c, A, 0, V, stamp0, true);
+  R.mt_stamp0 = mts;
   (void)hipEventRecord(c->ev[1], st);
   if ((rc = enqueue_round(c, R, p->use_mlp != 0, st, true))) return rc;
   (void)hipEventRecord(c->ev[2], st);
@@ -946,7 +1051,8 @@ extern "C" int32_t flow_refine_pair_static(fr_context *c, const fr_graph *g, int
                                            int32_t k, int32_t a, int32_t b, const fr_params *p,
                                            fr_result *res, fr_solve *trace) {
   if (!c || !g || !part || !p || !res || g->n < 1 || k < 2 || k > FR_MAX_K) return FR_E_INVALID_ARG;
-  if (!g->on_device || p->mb_reps != 0 || p->fm_limit != 0 || p->use_mlp) return FR_E_INVALID_ARG;
+  if (!g->on_device || p->mb_reps != 0 || p->fm_limit != 0 || p->use_mlp || p->mt_alpha != 0)
+    return FR_E_INVALID_ARG;
   int32_t rc = check_params(p);
   if (rc) return rc;
   if (c->device < 0 || c->device >= FR_MAX_DEVICES || !scratch_ptr[c->device]) return FR_E_DEVICE;
@@ -1144,13 +1250,25 @@ extern "C" int32_t flow_refine_sweep(fr_context *c, const fr_graph *g, int32_t *
     const int32_t nrounds = (int32_t)offs.size() - 1;
     int32_t stamp0 = 0;
     if ((rc = reserve_stamps(c, (int64_t)nrounds * (p->max_iters + 1), &stamp0))) return rc;
+    // multi-try: consecutive touched stamps per round, changed blocks cleared
+    std::vector<int32_t> mts((size_t)nrounds, 0);
+    if (p->mt_alpha > 0) {
+      int32_t m0 = 0;
+      if ((rc = reserve_mt(c, total / W + nrounds, &m0))) return rc;
+      for (int32_t r = 0; r < nrounds; r++) {
+        mts[(size_t)r] = m0;
+        m0 += (offs[r + 1] - offs[r]) / W + 1;
+      }
+      HIPCHK(hipMemsetAsync(d.mtchg, 0, (size_t)k, st));
+    }
     HIPCHK(hipStreamSynchronize(st));
     if (c->timing) {
       // rounds launched one by one, each iteration's phases between events,
       // read back after every round (the events are reused)
       for (int32_t r = 0; r < nrounds; r++) {
-        const KArgs R = round_args(c, A, offs[r], offs[r + 1] - offs[r],
-                                   stamp0 + r * (2 * p->max_iters + 2), false);
+        KArgs R = round_args(c, A, offs[r], offs[r + 1] - offs[r],
+                             stamp0 + r * (2 * p->max_iters + 2), false);
+        R.mt_stamp0 = mts[(size_t)r];
         if ((rc = enqueue_round(c, R, p->use_mlp != 0, st, true))) return rc;
         HIPCHK(hipStreamSynchronize(st));
         add_round_times(c);
@@ -1161,8 +1279,9 @@ extern "C" int32_t flow_refine_sweep(fr_context *c, const fr_graph *g, int32_t *
       HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
       int32_t cap_rc = FR_OK;
       for (int32_t r = 0; r < nrounds && cap_rc == FR_OK; r++) {
-        const KArgs R = round_args(c, A, offs[r], offs[r + 1] - offs[r],
-                                   stamp0 + r * (2 * p->max_iters + 2), false);
+        KArgs R = round_args(c, A, offs[r], offs[r + 1] - offs[r],
+                             stamp0 + r * (2 * p->max_iters + 2), false);
+        R.mt_stamp0 = mts[(size_t)r];
         cap_rc = enqueue_round(c, R, p->use_mlp != 0, st, false);
       }
       hipError_t ce = hipStreamEndCapture(st, &graph);
@@ -1190,14 +1309,17 @@ extern "C" int32_t flow_refine_sweep(fr_context *c, const fr_graph *g, int32_t *
     c->counters[7] = std::max<int64_t>(c->counters[7], W);
     int64_t changed = 0;
     std::fill(active.begin(), active.end(), 0);
+    if (p->mt_alpha > 0) {  // blocks a kept multi-try move left or entered
+      HIPCHK(hipMemcpyAsync(active.data(), d.mtchg, (size_t)k, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
     for (int64_t i = 0; i < total; i += W) {  // the pair's record is its first entry
       const PairState &q = ps[(size_t)i];
       acc[1] += q.iters;
       acc[3] += q.re_sum;
-      if (q.applied || q.fm_kept) {  // the partition changed (flow or FM)
-        changed++;
+      if (q.applied || q.fm_kept)  // the pairwise improvement changed the partition
         active[(size_t)pairs[2 * i]] = active[(size_t)pairs[2 * i + 1]] = 1;
-      }
+      if (q.applied || q.fm_kept || q.mt_kept) changed++;
     }
     acc[0]++;
     acc[2] += changed;

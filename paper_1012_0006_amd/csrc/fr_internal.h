@@ -42,6 +42,10 @@ struct PairState {
   int64_t mb_free, mb_comp, mb_big, t_mb;
   // 2-way FM before the flow: moves made, moves kept after the rollback
   int64_t fm_steps, fm_kept;
+  // multi-try FM after the round (kept on the pair's first entry): searches
+  // started, moves made, moves kept after the rollbacks
+  int64_t mt_searches, mt_moves, mt_kept;
+  int64_t spare2;
 };
 
 // work counters: the data each phase of a solve touches
@@ -87,7 +91,7 @@ struct Ctl {
 };
 
 enum { DIAG_NONE = 0, DIAG_LIST = 1, DIAG_CLOSURE = 2, DIAG_REV = 3, DIAG_SWEEPS = 4,
-       DIAG_OVERFLOW = 5, DIAG_MB = 6, DIAG_FM = 7 };
+       DIAG_OVERFLOW = 5, DIAG_MB = 6, DIAG_FM = 7, DIAG_MT = 8 };
 
 struct KArgs {
   // graph (device)
@@ -137,6 +141,18 @@ struct KArgs {
   // candidate without the most balanced cut: 0 smallest source set, 1 largest,
   // 2 the largest only when the smallest is infeasible and it is feasible
   int32_t cut_side;
+  // multi-try FM after the round (0 = off): stopping-rule alpha, key seed,
+  // beta = floor(ln n 2^16), touched stamp of the round's first pair minus 1;
+  // block weights [k], todo keys and their sort buffer (arena slots),
+  // per-vertex touched stamps, targets and heap slots (-1 none), heap slots
+  // beyond LDS [2n], move log of a search [n] x 2, changed blocks [k]
+  int32_t mt_alpha, mt_seed;
+  int64_t mt_beta;
+  int32_t mt_stamp0;
+  int64_t *mtw;
+  unsigned long long *mtk, *mtk2;
+  int32_t *mtt, *mtb, *mtq, *mth, *mtv, *mtf;
+  uint8_t *mtchg;
   // terminals of the corridor network: 0 border pinned by infinite arcs,
   // 1 the blocks' outside parts contracted into s / t (per-vertex capacities:
   // s -> u as the initial excess, u -> t in the sink-list array SNK)
