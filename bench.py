@@ -477,6 +477,50 @@ def run_balanced(args, fr, torch, gen):
     return out
 
 
+def run_multitry(args, fr, torch, gen):
+    """Multi-try FM (Sec. 4.2, alpha 10) after the pairwise improvements of the
+    largest matching round of C3 and of C5: one batched call with and one
+    without it, from the same partition: time, the phase's work and the cut
+    reached."""
+    import oracle  # cut accounting only
+
+    out = {}
+    for cid in args.mt_configs.split(","):
+        w = gen.config(cid)
+        ctx = fr.Context()
+        ctx.set_validation(False)
+        dg = fr.DeviceGraph.from_host(w.graph)
+        part0 = torch.as_tensor(w.part).cuda()
+        edges_q, colour = fr.fr_quotient_matchings(ctx, dg, part0, w.k)
+        c = int(np.argmax(np.bincount(colour)))
+        pairs = [tuple(e) for e, cc in zip(edges_q.tolist(), colour.tolist()) if cc == c]
+        base = {k: w.params[k] for k in ("area_mode", "depth", "alpha", "alpha_max", "adaptive",
+                                         "max_iters", "eps_ppm")}
+        leg = {"pairs": len(pairs)}
+        for name, extra in (("pairwise", {}), ("pairwise_then_multitry",
+                                                {"mt_alpha": 10, "mt_seed": 1})):
+            dpart = part0.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res, _ = fr.flow_refine_batch(ctx, dg, dpart, w.k, pairs, fr.params(**base, **extra))
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            st = fr.stats_dict(ctx)
+            leg[name] = {"seconds": dt, "total_cut": int(oracle.total_cut(w.graph,
+                                                                          dpart.cpu().numpy())),
+                         "mt_searches": st["mt_searches"], "mt_moves": st["mt_moves"],
+                         "mt_kept": st["mt_kept"]}
+        leg["cut_before"] = int(oracle.total_cut(w.graph, w.part))
+        leg["multitry_seconds"] = (leg["pairwise_then_multitry"]["seconds"]
+                                   - leg["pairwise"]["seconds"])
+        out[cid] = leg
+        ctx.close()
+        progress(f"multi-try {cid}: {leg['multitry_seconds']:.2f} s, "
+                 f"cut {leg['pairwise']['total_cut']} -> "
+                 f"{leg['pairwise_then_multitry']['total_cut']}")
+    return out
+
+
 def roofline(bytes_total: float, kern_ms: float, launches: int, traffic) -> dict:
     """k_flow against the HBM peak: algorithmic bytes per launch over the
     average launch time from the events (total bytes / total time)."""
@@ -636,6 +680,8 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-balanced", action="store_true")
+    ap.add_argument("--no-multitry", action="store_true")
+    ap.add_argument("--mt-configs", default="C3")
     ap.add_argument("--max-sweeps", type=int, default=64)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one device copy of 512 MiB (calibrates HBM byte counters)")
@@ -723,6 +769,8 @@ def main():
         progress("C4 learned factor done")
     if not args.no_balanced:
         line["balanced"] = run_balanced(args, fr, torch, gen)
+    if not args.no_multitry:
+        line["multitry"] = run_multitry(args, fr, torch, gen)
     print(json.dumps(line), flush=True)
 
 
