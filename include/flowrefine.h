@@ -247,7 +247,17 @@ int32_t fr_create(int32_t device, void *hip_stream, fr_context **ctx);
 int32_t fr_destroy(fr_context *ctx);
 const char *fr_strerror(int32_t code);
 
-/* Adaptive flow refinement of one pair (a = source side, b = sink side).
+/* The imbalance eps as a fraction (0.03 = 3 %) in parts per million, rounded
+ * to the nearest, for fr_params.eps_ppm; FR_E_INVALID_ARG outside [0, 100] or
+ * for NaN.  No GPU work. */
+int32_t fr_eps_to_ppm(double eps, int32_t *ppm);
+
+/* Adaptive flow refinement of one pair (a = source side, b = sink side):
+ * Sec. 4.1 (boundary, corridor by bounded BFS, network with the border tied
+ * to s and t, maximum flow, minimum cut, adaptive flow iterations) and Sec.
+ * 4.1.1 (the smallest source set, or the most balanced minimum cut), preceded
+ * by 2-way FM (Sec. 2.2) with fm_limit and followed by a multi-try round
+ * (Sec. 4.2) with mt_alpha.
  * part: [n] in/out, block ids in [0, k).  res: host, one record.
  * side_out (optional, host int8 [n]): per vertex of the LAST solve, -1 outside
  * the corridor, 0 / 1 corridor vertex ending in a / b, 2 / 3 border vertex
@@ -279,7 +289,10 @@ int32_t flow_refine_pair_static(fr_context *ctx, const fr_graph *g, int32_t *par
                                 int32_t a, int32_t b, const fr_params *p, fr_result *res,
                                 fr_solve *trace);
 
-/* All pairs of one quotient-graph matching in one batched solve.  pairs: host
+/* All pairs of one quotient-graph matching in one batched solve (Sec. 4.3:
+ * the pairs of a matching touch disjoint blocks, so their pairwise
+ * improvements are independent; with mt_alpha the multi-try rounds of the
+ * pairs follow in pair order).  pairs: host
  * int32 [2*npairs] (a_i, b_i), blocks pairwise disjoint.  res: host
  * [npairs]; trace (optional): host [npairs * p->max_iters], record j of pair i
  * at i*max_iters + j.  With p->use_mlp = 1 each pair starts at the factor the
@@ -380,6 +393,10 @@ int32_t fr_mlp_forward(fr_context *ctx, const float *x, int32_t n, float *probs)
  * (either output may be NULL). */
 int32_t fr_mlp_loss_grad(fr_context *ctx, const float *x, const int32_t *labels, int32_t n,
                          float *loss, float *grad);
+/* Start factors alpha[n] in {1, 2, 4, 8, 16} for features x[n*8]: 2^c for the
+ * most probable class c (the first on ties), as batch and sweep calls with
+ * use_mlp take them. */
+int32_t fr_mlp_predict(fr_context *ctx, const float *x, int32_t n, int32_t *alpha);
 /* Minibatch Adam (beta 0.9 / 0.999) on the device; epoch_loss[epochs]
  * (optional) = mean cross-entropy over all n samples after each epoch. */
 int32_t fr_mlp_train(fr_context *ctx, const float *x, const int32_t *labels, int32_t n,

@@ -64,7 +64,7 @@ EXPORTS = ("fr_create", "fr_destroy", "fr_strerror", "flow_refine_pair",
            "flow_refine_sweep", "fr_quotient_matchings", "fr_set_tuning", "fr_get_tuning",
            "fr_set_validation", "fr_set_speculation", "fr_set_timing", "fr_last_stats",
            "fr_mlp_num_params", "fr_mlp_init", "fr_mlp_set_weights", "fr_mlp_get_weights", "fr_mlp_forward", "fr_mlp_loss_grad",
-           "fr_mlp_train", "fr_pair_features", "fr_autotune")
+           "fr_mlp_train", "fr_pair_features", "fr_autotune", "fr_mlp_predict", "fr_eps_to_ppm")
 ALPHAS = (1, 2, 4, 8, 16)
 
 
@@ -121,6 +121,10 @@ def load(path: str = LIB_PATH):
     lib.fr_mlp_set_weights.argtypes = [vp, vp, i32]
     lib.fr_mlp_get_weights.restype = i32
     lib.fr_mlp_get_weights.argtypes = [vp, vp, i32]
+    lib.fr_mlp_predict.restype = i32
+    lib.fr_mlp_predict.argtypes = [vp, vp, i32, vp]
+    lib.fr_eps_to_ppm.restype = i32
+    lib.fr_eps_to_ppm.argtypes = [ctypes.c_double, ctypes.POINTER(i32)]
     lib.fr_mlp_forward.restype = i32
     lib.fr_mlp_forward.argtypes = [vp, vp, i32, vp]
     lib.fr_mlp_loss_grad.restype = i32
@@ -368,6 +372,22 @@ def _i32(a) -> np.ndarray:
 
 def fr_mlp_num_params() -> int:
     return int(load().fr_mlp_num_params())
+
+
+def fr_mlp_predict(ctx: Context, x) -> np.ndarray:
+    """Start factor per sample from the loaded network (features [n, 8])."""
+    xs = _f32(x).reshape(-1, 8)
+    a = np.zeros(xs.shape[0], dtype=np.int32)
+    _check(ctx.lib.fr_mlp_predict(ctx.handle, xs.ctypes.data, xs.shape[0], a.ctypes.data),
+           "fr_mlp_predict")
+    return a
+
+
+def eps_to_ppm(eps: float) -> int:
+    """fr_eps_to_ppm: eps as a fraction -> parts per million."""
+    out = i32(0)
+    _check(load().fr_eps_to_ppm(float(eps), ctypes.byref(out)), "fr_eps_to_ppm")
+    return int(out.value)
 
 
 def mlp_unpack(w: np.ndarray) -> dict:

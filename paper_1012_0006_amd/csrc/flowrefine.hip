@@ -1433,6 +1433,29 @@ extern "C" int32_t fr_mlp_forward(fr_context *c, const float *x, int32_t n, floa
   return FR_OK;
 }
 
+extern "C" int32_t fr_mlp_predict(fr_context *c, const float *x, int32_t n, int32_t *alpha) {
+  if (!c || !x || !alpha || n < 1 || !c->mlp_loaded) return FR_E_INVALID_ARG;
+  HIPCHK(hipSetDevice(c->device));
+  MlpScratch s;
+  int32_t rc = mlp_alloc(s, n, 1);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(s.x, x, sizeof(float) * MLP_IN * n, hipMemcpyHostToDevice, c->cs));
+  if ((rc = mlp_fwd_bwd(c, s.x, nullptr, n, s, false))) return rc;
+  // the start factor of each sample, as the batch and sweep calls take it
+  hipLaunchKernelGGL(k_alpha_from_probs, dim3((n + 255) / 256), dim3(256), 0, c->cs,
+                     (const float *)s.probs, n, s.labels);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(alpha, s.labels, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->cs));
+  HIPCHK(hipStreamSynchronize(c->cs));
+  return FR_OK;
+}
+
+extern "C" int32_t fr_eps_to_ppm(double eps, int32_t *ppm) {
+  if (!ppm || !(eps >= 0.0) || !(eps <= 100.0)) return FR_E_INVALID_ARG;  // NaN fails both
+  *ppm = (int32_t)std::llround(eps * 1e6);
+  return FR_OK;
+}
+
 extern "C" int32_t fr_mlp_loss_grad(fr_context *c, const float *x, const int32_t *labels, int32_t n,
                                     float *loss, float *grad) {
   if (!c || !x || !labels || n < 1 || !c->mlp_loaded) return FR_E_INVALID_ARG;

@@ -99,3 +99,18 @@ def test_tuning_cache_roundtrip(tmp_path, monkeypatch):
     fr.autotune_cached(ctx, type("H", (), {"n": 1 << 20, "narcs": 12 << 20})(), None, 16,
                        [(0, 1)] * 8, None, cache_path=path, arch="gfx950")
     assert len(calls) == 2
+
+
+def test_eps_to_ppm():
+    """The double helper of fr_params.eps_ppm (no GPU work): rounding to the
+    nearest part per million, and rejection outside [0, 100] and of NaN."""
+    if not os.path.exists(fr.LIB_PATH):
+        pytest.skip("library not built")
+    assert fr.eps_to_ppm(0.03) == 30000
+    assert fr.eps_to_ppm(0.0) == 0
+    assert fr.eps_to_ppm(0.0300004) == 30000 and fr.eps_to_ppm(0.0300006) == 30001
+    assert fr.eps_to_ppm(1.0) == 1_000_000
+    for bad in (-1e-9, float("nan"), 100.5):
+        with pytest.raises(fr.FlowRefineError) as e:
+            fr.eps_to_ppm(bad)
+        assert e.value.code == -8

@@ -61,6 +61,21 @@ def test_forward_and_gradient_match_oracle(gpu_lib, ctx):
     assert np.allclose(grad, g_ref_flat, rtol=1e-3, atol=1e-5 * scale)
 
 
+def test_predict_is_the_most_probable_factor(gpu_lib, ctx):
+    """fr_mlp_predict: 2^c for the most probable class c of the forward pass
+    (first on ties), where the fp64 reference is clear of a near-tie."""
+    gpu_lib.fr_mlp_init(ctx, 321)
+    w = gpu_lib.fr_mlp_get_weights(ctx)
+    x = np.random.default_rng(9).normal(0, 2.0, (517, 8)).astype(np.float32)
+    p_ref, _ = oracle.mlp_forward(_oracle_params(gpu_lib, w), x.astype(np.float64))
+    top2 = np.sort(p_ref, axis=1)[:, -2:]
+    clear = (top2[:, 1] - top2[:, 0]) > 1e-4
+    a = gpu_lib.fr_mlp_predict(ctx, x)
+    assert set(np.unique(a)) <= {1, 2, 4, 8, 16}
+    assert np.array_equal(a[clear], (1 << np.argmax(p_ref, axis=1))[clear])
+    assert clear.sum() > 400
+
+
 def test_gradient_finite_differences(gpu_lib, ctx):
     gpu_lib.fr_mlp_init(ctx, 7)
     w = gpu_lib.fr_mlp_get_weights(ctx).astype(np.float64)
