@@ -223,7 +223,7 @@ class Context:
             pass
 
     # -- tuning ---------------------------------------------------------
-    def set_tuning(self, block_threads=1024, blocks_per_cu=2, tpv=4, relabel_period=200,
+    def set_tuning(self, block_threads=1024, blocks_per_cu=2, tpv=8, relabel_period=100,
                    mb_lds=1):
         t = FrTuning(block_threads, blocks_per_cu, tpv, relabel_period, mb_lds)
         _check(self.lib.fr_set_tuning(self.handle, ctypes.byref(t)), "fr_set_tuning")
@@ -472,9 +472,9 @@ def fr_autotune(ctx: Context, graph: DeviceGraph, part, k: int, pairs, prm: FrPa
 
 
 DEFAULT_CANDIDATES = (
-    dict(block_threads=1024, blocks_per_cu=2, tpv=4, relabel_period=200),
-    dict(block_threads=1024, blocks_per_cu=2, tpv=4, relabel_period=100),
     dict(block_threads=1024, blocks_per_cu=2, tpv=8, relabel_period=100),
+    dict(block_threads=1024, blocks_per_cu=2, tpv=8, relabel_period=70),
+    dict(block_threads=1024, blocks_per_cu=2, tpv=4, relabel_period=200),
     dict(block_threads=1024, blocks_per_cu=2, tpv=2, relabel_period=200),
     dict(block_threads=512, blocks_per_cu=4, tpv=4, relabel_period=200),
     dict(block_threads=256, blocks_per_cu=8, tpv=4, relabel_period=200),

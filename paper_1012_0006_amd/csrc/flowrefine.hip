@@ -84,7 +84,7 @@ struct fr_context {
   hipStream_t user_stream = nullptr;
   hipStream_t cs = nullptr;  // the library's own stream (graph capture needs a non-null one)
   int num_cus = 0;
-  fr_tuning tune{1024, 2, 4, 200, 1};
+  fr_tuning tune{1024, 2, 8, 100, 1};
   int validate = 1;
   int mlp_loaded = 0;
   DevBufs d;
