@@ -340,6 +340,20 @@ int32_t fr_get_tuning(fr_context *ctx, fr_tuning *t);
  * counters[7] reports the factors per pair of the last pair / batch call. */
 int32_t fr_set_speculation(fr_context *ctx, int32_t on);
 
+/* Rounds as one launch (1) or as one launch chain per adaptive iteration (0,
+ * the default).  With 1, each workgroup takes a pair of the round and runs
+ * its whole adaptive loop (Sec. 4.1: boundary, corridor, network, flow, the
+ * factor rule) in one persistent kernel, so a pair never waits for the
+ * round's other pairs between its iterations; every solve is then one factor
+ * (no speculative factors, fr_set_speculation has no effect).  With 0, every
+ * iteration of the round is a chain of launches over all pairs, and a pair's
+ * next iteration waits for the slowest pair's current one.  Calls with the
+ * most balanced cut (mb_reps > 0) always run the launch chains.  Results are
+ * identical either way.  The launch chains are the faster choice wherever
+ * measured: they keep the speculative factors, and their boundary and
+ * network passes spread over the whole chip instead of one workgroup. */
+int32_t fr_set_fused(fr_context *ctx, int32_t on);
+
 /* Input checks of every call (CSR shape, ranges, symmetry: O(sum deg^2)) on
  * (1, the default) or off (0; malformed input then gives undefined results). */
 int32_t fr_set_validation(fr_context *ctx, int32_t on);
@@ -360,7 +374,8 @@ int32_t fr_set_timing(fr_context *ctx, int32_t on);
  *   BFS), [3] network-build kernels, [4] whole call on the device, [5]
  *   global relabels and [6] push/relabel sweeps (device clock time summed
  *   over the pairs' workgroups), [7] flow kernel (relabels, sweeps,
- *   closure, decision); [1..3], [7] are HIP event times.
+ *   closure, decision), or with fused rounds the round kernel (every phase;
+ *   [2] and [3] are then 0); [1..3], [7] are HIP event times.
  * counters[32]: [0] push/relabel sweeps, [1] global relabels, [2] corridor
  *   BFS levels, [3] relabel BFS levels, [4] closure levels, [5] workgroups
  *   of the per-pair kernels, [6] internal check that failed (0 = none),
@@ -368,7 +383,8 @@ int32_t fr_set_timing(fr_context *ctx, int32_t on);
  *   kernels time in ns, [9] free vertices, [10] their residual components,
  *   [11] solves whose component graph (more than 2,048 components) was kept
  *   in device memory instead of LDS; [12] FM moves made, [13] FM moves kept;
- *   [14] flow-kernel launches (one per adaptive iteration of each round);
+ *   [14] flow-kernel launches (one per adaptive iteration of each round),
+ *   or round-kernel launches (one per round) with fused rounds;
  *   [28] multi-try searches, [29] multi-try moves made, [30] kept;
  *   [16..27] vertices and arcs touched: boundary scan, corridor BFS, network
  *   build, push/relabel sweeps, global relabels, residual closure (vertices

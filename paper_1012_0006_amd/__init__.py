@@ -62,7 +62,8 @@ class FrTuning(ctypes.Structure):
 EXPORTS = ("fr_create", "fr_destroy", "fr_strerror", "flow_refine_pair",
            "flow_refine_pair_static", "flow_refine_batch",
            "flow_refine_sweep", "fr_quotient_matchings", "fr_set_tuning", "fr_get_tuning",
-           "fr_set_validation", "fr_set_speculation", "fr_set_timing", "fr_last_stats",
+           "fr_set_validation", "fr_set_speculation", "fr_set_fused", "fr_set_timing",
+           "fr_last_stats",
            "fr_mlp_num_params", "fr_mlp_init", "fr_mlp_set_weights", "fr_mlp_get_weights", "fr_mlp_forward", "fr_mlp_loss_grad",
            "fr_mlp_train", "fr_pair_features", "fr_autotune", "fr_mlp_predict", "fr_eps_to_ppm")
 ALPHAS = (1, 2, 4, 8, 16)
@@ -109,6 +110,8 @@ def load(path: str = LIB_PATH):
     lib.fr_set_validation.argtypes = [vp, i32]
     lib.fr_set_speculation.restype = i32
     lib.fr_set_speculation.argtypes = [vp, i32]
+    lib.fr_set_fused.restype = i32
+    lib.fr_set_fused.argtypes = [vp, i32]
     lib.fr_set_timing.restype = i32
     lib.fr_set_timing.argtypes = [vp, i32]
     lib.fr_last_stats.restype = i32
@@ -238,6 +241,11 @@ class Context:
 
     def set_speculation(self, on: bool = True):
         _check(self.lib.fr_set_speculation(self.handle, 1 if on else 0), "fr_set_speculation")
+
+    def set_fused(self, on: bool = True):
+        """Rounds as one persistent launch, or one launch chain per adaptive
+        iteration (the default); results are identical."""
+        _check(self.lib.fr_set_fused(self.handle, 1 if on else 0), "fr_set_fused")
 
     def set_timing(self, on: bool = True):
         _check(self.lib.fr_set_timing(self.handle, 1 if on else 0), "fr_set_timing")

@@ -95,6 +95,7 @@ struct fr_context {
   hipEvent_t itev[5 * FR_MAX_ITERS] = {};
   int32_t timed_iters = 0;
   int speculate = 1;
+  int fused = 0;  // rounds as one persistent launch (k_round) where possible
   int timing = 0;  // sweeps: uncaptured rounds with per-phase events
   int32_t mt_stamp = 0;  // multi-try: touched stamps used so far
   // stats of the last call
@@ -380,6 +381,12 @@ extern "C" int32_t fr_set_speculation(fr_context *c, int32_t on) {
   return FR_OK;
 }
 
+extern "C" int32_t fr_set_fused(fr_context *c, int32_t on) {
+  if (!c) return FR_E_INVALID_ARG;
+  c->fused = on ? 1 : 0;
+  return FR_OK;
+}
+
 extern "C" int32_t fr_set_timing(fr_context *c, int32_t on) {
   if (!c) return FR_E_INVALID_ARG;
   c->timing = on ? 1 : 0;
@@ -433,6 +440,23 @@ static iter_fn flow_kernel(int tpb) {
     case 512: return k_flow<512>;
     default: return k_flow<1024>;
   }
+}
+
+typedef void (*round_fn)(KArgs);
+
+static round_fn round_kernel(int tpb) {
+  switch (tpb) {
+    case 256: return k_round<256>;
+    case 512: return k_round<512>;
+    default: return k_round<1024>;
+  }
+}
+
+// Rounds of these parameters run as one launch (k_round): one entry per
+// pair, and no most balanced cut (its kernels run between the flow and the
+// adaptive rule of every iteration).
+static bool fused_rounds(const fr_context *c, const fr_params *p) {
+  return c->fused && p->mb_reps == 0;
 }
 
 static int32_t graph_narcs(fr_context *c, const fr_graph *g, int64_t *narcs) {
@@ -621,7 +645,18 @@ static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t s
   const int tpb = c->tune.block_threads;
   const int blocks = blocks_of(c, A.P);
   const iter_fn corr = corr_kernel(tpb), flow = flow_kernel(tpb);
-  for (int32_t it = 0; it < A.max_iters; it++) {
+  const bool fused = c->fused && A.mb_reps == 0 && A.W == 1;
+  if (fused) {
+    // every pair's whole adaptive loop in one launch; the events put its
+    // time in the flow-kernel slot
+    hipEvent_t *ev = c->itev;
+    if (timed)
+      for (int j = 0; j < 3; j++) HIPCHK(hipEventRecord(ev[j], st));
+    hipLaunchKernelGGL(round_kernel(tpb), dim3(blocks), dim3(tpb), 0, st, A);
+    if (timed)
+      for (int j = 3; j < 5; j++) HIPCHK(hipEventRecord(ev[j], st));
+  }
+  for (int32_t it = 0; it < (fused ? 0 : A.max_iters); it++) {
     hipEvent_t *ev = c->itev + 5 * it;
     if (timed) HIPCHK(hipEventRecord(ev[0], st));
     hipLaunchKernelGGL(k_iter_begin, dim3(1), dim3(1024), 0, st, A, it);
@@ -653,7 +688,7 @@ static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t s
     hipLaunchKernelGGL(k_mt, dim3(1), dim3(WAVE), 0, st, A);
   }
   HIPCHK(hipGetLastError());
-  c->timed_iters = timed ? A.max_iters : 0;
+  c->timed_iters = timed ? (fused ? 1 : A.max_iters) : 0;
   return FR_OK;
 }
 
@@ -888,7 +923,7 @@ static int32_t check_batch_args(const fr_context *c, const fr_graph *g, const in
 // learned factor or when switched off.
 static int32_t speculation_slots(const fr_context *c, const fr_params *p, int32_t npairs,
                                  int64_t n, int64_t narcs) {
-  if (!c->speculate || !p->adaptive || p->max_iters < 2) return 1;
+  if (!c->speculate || !p->adaptive || p->max_iters < 2 || fused_rounds(c, p)) return 1;
   int32_t W = 0;
   for (int32_t a = p->alpha_max; a >= 1; a >>= 1) W++;
   const int64_t slots = (int64_t)c->num_cus * c->tune.blocks_per_cu;

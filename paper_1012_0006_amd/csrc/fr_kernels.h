@@ -1006,6 +1006,53 @@ __global__ void __launch_bounds__(1024) k_iter_mid(KArgs A, int32_t it) {
 #define PS_WORK (((int)offsetof(PairState, work)) / 8)
 static_assert(sizeof(PairState) % 8 == 0, "PairState is summed as 8-byte words");
 
+// Items 0..N-1 of entry p over the workgroup, one lane each: f(p, item), with
+// p = -1 past the end; the trip count is uniform over each wave.
+template <typename F>
+__device__ __forceinline__ void pair_items(int32_t p, int64_t N, F &&f) {
+  BLOCK_WAVE_LOOP(i, N) f(i < N ? p : -1, i < N ? i : (int64_t)0);
+}
+
+// The boundary pass over the union lists (vertices of a and b) of the entries
+// that `items` hands out: f(p, slot) for union slot `slot` of entry p.
+template <typename Items>
+__device__ __forceinline__ void bnd_union(const KArgs &A, int32_t S, Items &&items) {
+  unsigned long long *acc = (unsigned long long *)A.pacc;
+  unsigned long long *psw = (unsigned long long *)A.ps;
+  // pair cut, boundary weight a / b, boundary count a / b, vertices, arcs
+  KeyedSums<7> sums;
+  auto out = [&](int j, int key, int64_t v) {
+    if (j < 5) wave_add_by_key(acc, PA_N, PA_CUT + j, key, v);
+    else wave_add_by_key(psw, PS_WORDS, PS_WORK + (j == 5 ? W_BND_VERTS : W_BND_ARCS), key, v);
+  };
+  items([&](int32_t p, int64_t slot) {
+    const bool on = p >= 0;
+    const int32_t a = on ? A.pairs[2 * p] : 0, b = on ? A.pairs[2 * p + 1] : 0;
+    // the union list is held by the pair's first entry
+    const int32_t u = on ? A.uvert[A.voff[A.blk2pair[a]] + slot] : 0;
+    const int side = on && A.part[u] == b;
+    const int32_t y = side ? a : b;
+    const int32_t e0 = on ? A.xadj[u] : 0, e1 = on ? A.xadj[u + 1] : 0;
+    bool bnd = false;
+    int64_t cw = 0;
+    for (int32_t e = e0; e < e1; e++) {
+      if (A.part[A.adjncy[e]] == y) {
+        bnd = true;
+        if (!side) cw += A.adjwgt[e];
+      }
+    }
+    const bool bl = on && bnd;
+    const int64_t w = bl ? A.vwgt[u] : 0;
+    if (bl) mark_of(A, p)[u] = S;
+    const int64_t x[7] = {cw, bl && !side ? w : 0, bl && side ? w : 0, bl && !side ? 1 : 0,
+                          bl && side ? 1 : 0, 1, e1 - e0};
+    sums.add(on ? p : -1, x, out);
+    const int pos = wave_append_by_key(A.pcnt, bl ? p : -1);
+    if (bl) put_bounded(A.LA + A.voff[p], pos, A.voff[p + 1] - A.voff[p], u, A.ctl);
+  });
+  sums.flush(out);
+}
+
 // ---- pair boundary (Sec. 4.1): vertices of a with a neighbour in b and vice
 //      versa become BFS level 0 (marked with the stamp S); also the pair cut
 //      and the boundary weight and size per side.
@@ -1074,37 +1121,7 @@ __global__ void __launch_bounds__(256) k_bnd(KArgs A, int32_t it) {
     sums.flush(out);
     return;
   }
-  auto out = [&](int j, int key, int64_t v) {
-    if (j < 5) wave_add_by_key(acc, PA_N, PA_CUT + j, key, v);
-    else wave_add_by_key(psw, PS_WORDS, PS_WORK + (j == 5 ? W_BND_VERTS : W_BND_ARCS), key, v);
-  };
-  grid_items(A, A.vpre, [&](int32_t p, int64_t slot) {
-    const bool on = p >= 0;
-    const int32_t a = on ? A.pairs[2 * p] : 0, b = on ? A.pairs[2 * p + 1] : 0;
-    // the union list is held by the pair's first entry
-    const int32_t u = on ? A.uvert[A.voff[A.blk2pair[a]] + slot] : 0;
-    const int side = on && A.part[u] == b;
-    const int32_t y = side ? a : b;
-    const int32_t e0 = on ? A.xadj[u] : 0, e1 = on ? A.xadj[u + 1] : 0;
-    bool bnd = false;
-    int64_t cw = 0;
-    for (int32_t e = e0; e < e1; e++) {
-      if (A.part[A.adjncy[e]] == y) {
-        bnd = true;
-        if (!side) cw += A.adjwgt[e];
-      }
-    }
-    const bool lead = on;
-    const bool bl = lead && bnd;
-    const int64_t w = bl ? A.vwgt[u] : 0;
-    if (bl) mark_of(A, p)[u] = S;
-    const int64_t x[7] = {cw, bl && !side ? w : 0, bl && side ? w : 0, bl && !side ? 1 : 0,
-                          bl && side ? 1 : 0, 1, e1 - e0};
-    sums.add(lead ? p : -1, x, out);
-    const int pos = wave_append_by_key(A.pcnt, bl ? p : -1);
-    if (bl) put_bounded(A.LA + A.voff[p], pos, A.voff[p + 1] - A.voff[p], u, A.ctl);
-  });
-  sums.flush(out);
+  bnd_union(A, S, [&](auto &&f) { grid_items(A, A.vpre, f); });
 }
 
 // Takes the next pair of the queue for launch `it`; -1 when the queue is
@@ -1127,6 +1144,136 @@ __device__ __forceinline__ int32_t next_pair(const KArgs &A, int32_t *queue,
 //      the boundary; a level that crosses the side's area bound is cut in
 //      ascending vertex id.  Taken vertices get local ids (lg, vmap).
 template <int TPB>
+__device__ __forceinline__ void corr_pair(const KArgs &A, int32_t S, int32_t p, SolveShared<TPB> &sh,
+                          PairState &st) {
+  const PairView V = make_view(A, p);
+  const int32_t a = V.a, b = V.b;
+  int32_t *mk = mark_of(A, p), *vm = vmap_of(A, p);
+  const int64_t *pa = A.pacc + (int64_t)p * PA_N;
+  int64_t t0 = wall_clock64();
+  if (threadIdx.x == 0) {
+    st = A.ps[p];
+    sh.cnt[0] = min(A.pcnt[p], (int32_t)V.nv);
+    sh.cnt[1] = sh.cnt[2] = 0;
+    sh.nr = 0;
+    sh.W[0] = sh.W[1] = 0;
+    sh.state[0] = sh.state[1] = 1;
+    const int64_t base = A.base[st.alpha];
+    sh.U[0] = base - st.cB > 0 ? base - st.cB : 0;
+    sh.U[1] = base - st.cA > 0 ? base - st.cA : 0;
+    if (st.cut0 < 0) st.cut0 = pa[PA_CUT];
+    st.cut = pa[PA_CUT];
+  }
+  if (threadIdx.x < W_COUNT) sh.work[threadIdx.x] = 0ull;
+  __syncthreads();
+  int64_t Lw[2] = {pa[PA_BW0], pa[PA_BW1]}, Lc[2] = {pa[PA_BC0], pa[PA_BC1]};
+  int32_t *cur = V.LA, *nxt = V.LB;
+  int cc = 0;  // counter of the current list
+  for (int32_t lev = 0;; lev++) {
+    const int32_t cnt = uni(min(sh.cnt[cc], (int32_t)V.nv));
+    if (threadIdx.x == 0) {
+      for (int s = 0; s < 2; s++) {
+        sh.mode[s] = 0;
+        if (!sh.state[s]) continue;
+        if (Lc[s] == 0) {
+          sh.state[s] = 0;
+          continue;
+        }
+        if (A.area_mode == FR_AREA_DEPTH) {
+          sh.mode[s] = 1;
+          sh.W[s] += Lw[s];
+          if (lev >= A.depth) sh.state[s] = 0;
+        } else if (sh.W[s] + Lw[s] <= sh.U[s]) {
+          sh.mode[s] = 1;
+          sh.W[s] += Lw[s];
+        } else {
+          sh.mode[s] = 2;  // the bound is crossed inside this level
+          sh.state[s] = 0;
+        }
+      }
+      sh.cnt[(cc + 1) % 3] = 0;
+      st.bfs_levels += 1;
+    }
+    __syncthreads();
+    for (int s = 0; s < 2; s++)
+      if (sh.mode[s] == 2) cut_level<TPB>(A, mk, s ? b : a, cur, cnt, sh.U[s] - sh.W[s], S, sh);
+    // the taken part of this level joins the corridor
+    BLOCK_WAVE_LOOP(i, cnt) {
+      bool take = false;
+      int32_t u = 0;
+      if (i < cnt) {
+        u = cur[i];
+        const int s = A.part[u] == b;
+        take = sh.mode[s] == 1 || (sh.mode[s] == 2 && mk[u] == S);
+      }
+      const int pos = wave_append(&sh.nr, take);
+      if (take) {
+        put_bounded(V.lg, pos, V.nv, u, A.ctl);
+        vm[u] = pos;
+      }
+    }
+    if (!sh.state[0] && !sh.state[1]) break;
+    // expand the sides that go on
+    int64_t acc2[4] = {0, 0, 0, 0};  // weight a, weight b, count a, count b
+    int32_t *ncnt = &sh.cnt[(cc + 1) % 3];
+    // GTF lanes per frontier vertex, KF arcs per lane: the neighbours'
+    // block, mark and weight are loaded together, ahead of the claims
+    for_groups<GTF>(cnt, [&](int item, bool valid, int gl) {
+      const int32_t u = valid ? cur[item] : 0;
+      const int32_t x = valid ? A.part[u] : -1;
+      const int32_t e0 = valid ? A.xadj[u] : 0, e1 = valid ? A.xadj[u + 1] : 0;
+      const int s = x == b;
+      const bool go = valid && sh.state[s];
+      count_work(sh, W_BFS_ITEMS, (go && gl == 0) ? 1 : 0);
+      count_work(sh, W_BFS_ARCS, (go && gl == 0) ? e1 - e0 : 0);
+      const int32_t ee = go ? e1 : e0;
+      for (int32_t c0 = e0; c0 < ee; c0 += GTF * KF) {
+        int32_t v[KF], xv[KF], mv[KF], wv[KF];
+#pragma unroll
+        for (int k = 0; k < KF; k++) {
+          const int32_t e = c0 + k * GTF + gl;
+          v[k] = e < ee ? A.adjncy[e] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < KF; k++) {
+          xv[k] = v[k] >= 0 ? A.part[v[k]] : -1;
+          mv[k] = v[k] >= 0 ? mk[v[k]] : S;
+          wv[k] = v[k] >= 0 ? A.vwgt[v[k]] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < KF; k++) {
+          bool claim = false;
+          if (v[k] >= 0 && xv[k] == x && mv[k] < S) claim = atomicMax(&mk[v[k]], S) < S;
+          const int pos = wave_append(ncnt, claim);
+          if (claim) {
+            put_bounded(nxt, pos, V.nv, v[k], A.ctl);
+            acc2[s] += wv[k];
+            acc2[2 + s] += 1;
+          }
+        }
+      }
+    });
+    block_sums<4>(acc2, sh.red);
+    Lw[0] = acc2[0];
+    Lw[1] = acc2[1];
+    Lc[0] = acc2[2];
+    Lc[1] = acc2[3];
+    int32_t *t = cur;
+    cur = nxt;
+    nxt = t;
+    cc = (cc + 1) % 3;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    st.nr = min(sh.nr, (int32_t)V.nv);
+    for (int j = 0; j < W_COUNT; j++) st.work[j] += (int64_t)sh.work[j];
+    st.t_corridor += wall_clock64() - t0;
+    A.ps[p] = st;
+  }
+  __syncthreads();
+}
+
+template <int TPB>
 __global__ void __launch_bounds__(TPB) k_corr(KArgs A, int32_t it) {
   __shared__ SolveShared<TPB> sh;
   __shared__ PairState st;
@@ -1134,131 +1281,7 @@ __global__ void __launch_bounds__(TPB) k_corr(KArgs A, int32_t it) {
   for (;;) {
     const int32_t p = next_pair<TPB>(A, A.queue + 2 * it, sh);
     if (p < 0) break;
-    const PairView V = make_view(A, p);
-    const int32_t a = V.a, b = V.b;
-    int32_t *mk = mark_of(A, p), *vm = vmap_of(A, p);
-    const int64_t *pa = A.pacc + (int64_t)p * PA_N;
-    int64_t t0 = wall_clock64();
-    if (threadIdx.x == 0) {
-      st = A.ps[p];
-      sh.cnt[0] = min(A.pcnt[p], (int32_t)V.nv);
-      sh.cnt[1] = sh.cnt[2] = 0;
-      sh.nr = 0;
-      sh.W[0] = sh.W[1] = 0;
-      sh.state[0] = sh.state[1] = 1;
-      const int64_t base = A.base[st.alpha];
-      sh.U[0] = base - st.cB > 0 ? base - st.cB : 0;
-      sh.U[1] = base - st.cA > 0 ? base - st.cA : 0;
-      if (st.cut0 < 0) st.cut0 = pa[PA_CUT];
-      st.cut = pa[PA_CUT];
-    }
-    if (threadIdx.x < W_COUNT) sh.work[threadIdx.x] = 0ull;
-    __syncthreads();
-    int64_t Lw[2] = {pa[PA_BW0], pa[PA_BW1]}, Lc[2] = {pa[PA_BC0], pa[PA_BC1]};
-    int32_t *cur = V.LA, *nxt = V.LB;
-    int cc = 0;  // counter of the current list
-    for (int32_t lev = 0;; lev++) {
-      const int32_t cnt = uni(min(sh.cnt[cc], (int32_t)V.nv));
-      if (threadIdx.x == 0) {
-        for (int s = 0; s < 2; s++) {
-          sh.mode[s] = 0;
-          if (!sh.state[s]) continue;
-          if (Lc[s] == 0) {
-            sh.state[s] = 0;
-            continue;
-          }
-          if (A.area_mode == FR_AREA_DEPTH) {
-            sh.mode[s] = 1;
-            sh.W[s] += Lw[s];
-            if (lev >= A.depth) sh.state[s] = 0;
-          } else if (sh.W[s] + Lw[s] <= sh.U[s]) {
-            sh.mode[s] = 1;
-            sh.W[s] += Lw[s];
-          } else {
-            sh.mode[s] = 2;  // the bound is crossed inside this level
-            sh.state[s] = 0;
-          }
-        }
-        sh.cnt[(cc + 1) % 3] = 0;
-        st.bfs_levels += 1;
-      }
-      __syncthreads();
-      for (int s = 0; s < 2; s++)
-        if (sh.mode[s] == 2) cut_level<TPB>(A, mk, s ? b : a, cur, cnt, sh.U[s] - sh.W[s], S, sh);
-      // the taken part of this level joins the corridor
-      BLOCK_WAVE_LOOP(i, cnt) {
-        bool take = false;
-        int32_t u = 0;
-        if (i < cnt) {
-          u = cur[i];
-          const int s = A.part[u] == b;
-          take = sh.mode[s] == 1 || (sh.mode[s] == 2 && mk[u] == S);
-        }
-        const int pos = wave_append(&sh.nr, take);
-        if (take) {
-          put_bounded(V.lg, pos, V.nv, u, A.ctl);
-          vm[u] = pos;
-        }
-      }
-      if (!sh.state[0] && !sh.state[1]) break;
-      // expand the sides that go on
-      int64_t acc2[4] = {0, 0, 0, 0};  // weight a, weight b, count a, count b
-      int32_t *ncnt = &sh.cnt[(cc + 1) % 3];
-      // GTF lanes per frontier vertex, KF arcs per lane: the neighbours'
-      // block, mark and weight are loaded together, ahead of the claims
-      for_groups<GTF>(cnt, [&](int item, bool valid, int gl) {
-        const int32_t u = valid ? cur[item] : 0;
-        const int32_t x = valid ? A.part[u] : -1;
-        const int32_t e0 = valid ? A.xadj[u] : 0, e1 = valid ? A.xadj[u + 1] : 0;
-        const int s = x == b;
-        const bool go = valid && sh.state[s];
-        count_work(sh, W_BFS_ITEMS, (go && gl == 0) ? 1 : 0);
-        count_work(sh, W_BFS_ARCS, (go && gl == 0) ? e1 - e0 : 0);
-        const int32_t ee = go ? e1 : e0;
-        for (int32_t c0 = e0; c0 < ee; c0 += GTF * KF) {
-          int32_t v[KF], xv[KF], mv[KF], wv[KF];
-#pragma unroll
-          for (int k = 0; k < KF; k++) {
-            const int32_t e = c0 + k * GTF + gl;
-            v[k] = e < ee ? A.adjncy[e] : -1;
-          }
-#pragma unroll
-          for (int k = 0; k < KF; k++) {
-            xv[k] = v[k] >= 0 ? A.part[v[k]] : -1;
-            mv[k] = v[k] >= 0 ? mk[v[k]] : S;
-            wv[k] = v[k] >= 0 ? A.vwgt[v[k]] : 0;
-          }
-#pragma unroll
-          for (int k = 0; k < KF; k++) {
-            bool claim = false;
-            if (v[k] >= 0 && xv[k] == x && mv[k] < S) claim = atomicMax(&mk[v[k]], S) < S;
-            const int pos = wave_append(ncnt, claim);
-            if (claim) {
-              put_bounded(nxt, pos, V.nv, v[k], A.ctl);
-              acc2[s] += wv[k];
-              acc2[2 + s] += 1;
-            }
-          }
-        }
-      });
-      block_sums<4>(acc2, sh.red);
-      Lw[0] = acc2[0];
-      Lw[1] = acc2[1];
-      Lc[0] = acc2[2];
-      Lc[1] = acc2[3];
-      int32_t *t = cur;
-      cur = nxt;
-      nxt = t;
-      cc = (cc + 1) % 3;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      st.nr = min(sh.nr, (int32_t)V.nv);
-      for (int j = 0; j < W_COUNT; j++) st.work[j] += (int64_t)sh.work[j];
-      st.t_corridor += wall_clock64() - t0;
-      A.ps[p] = st;
-    }
-    __syncthreads();
+    corr_pair<TPB>(A, S, p, sh, st);
   }
 }
 
@@ -1269,8 +1292,8 @@ __global__ void __launch_bounds__(TPB) k_corr(KArgs A, int32_t it) {
 //      outside the corridor is the capacity of s -> u (written as u's initial
 //      excess), the weight into b outside that of u -> t (written to SNK),
 //      and the old a-b edges with one end outside count as decided too.
-__global__ void __launch_bounds__(256) k_net_count(KArgs A, int32_t it) {
-  const int32_t S = A.stamp0 + 2 * it;
+template <typename Items>
+__device__ __forceinline__ void net_count(const KArgs &A, int32_t S, Items &&items) {
   const bool term = A.terminals != 0;
   unsigned long long *acc = (unsigned long long *)A.pacc;
   unsigned long long *psw = (unsigned long long *)A.ps;
@@ -1282,7 +1305,7 @@ __global__ void __launch_bounds__(256) k_net_count(KArgs A, int32_t it) {
     else if (j == 5) wave_add_by_key(acc, PA_N, PA_CS, key, v);
     else wave_add_by_key(psw, PS_WORDS, PS_WORK + (j == 3 ? W_NET_VERTS : W_NET_ARCS), key, v);
   };
-  grid_items(A, A.cpre, [&](int32_t p, int64_t item) {
+  items([&](int32_t p, int64_t item) {
     const int64_t i = p >= 0 ? A.voff[p] + item : 0;  // arena slot
     const bool on = p >= 0;
     const int32_t a = on ? A.pairs[2 * p] : 0, b = on ? A.pairs[2 * p + 1] : 0;
@@ -1325,13 +1348,14 @@ __global__ void __launch_bounds__(256) k_net_count(KArgs A, int32_t it) {
   sums.flush(out);
 }
 
+__global__ void __launch_bounds__(256) k_net_count(KArgs A, int32_t it) {
+  net_count(A, A.stamp0 + 2 * it, [&](auto &&f) { grid_items(A, A.cpre, f); });
+}
+
 // pass 2 (one block per pair): inclusive scan of the arc counts into CSR
 // offsets, 4 values per thread per tile
-__global__ void __launch_bounds__(1024) k_net_scan(KArgs A, int32_t it) {
-  __shared__ int64_t s_scan[17];
-  (void)it;
-  const int32_t p = blockIdx.x;
-  if (p >= A.P || A.ps[p].done) return;
+// s_scan: blockDim.x / 64 + 1 LDS words.  All threads call it.
+__device__ __forceinline__ void net_scan_pair(const KArgs &A, int32_t p, int64_t *s_scan) {
   const int32_t nr = uni(A.ps[p].nr);
   int32_t *lo = A.lo + A.voff[p] + p;
   int64_t carry = 0;
@@ -1360,10 +1384,18 @@ __global__ void __launch_bounds__(1024) k_net_scan(KArgs A, int32_t it) {
   }
 }
 
+__global__ void __launch_bounds__(1024) k_net_scan(KArgs A, int32_t it) {
+  __shared__ int64_t s_scan[17];
+  (void)it;
+  const int32_t p = blockIdx.x;
+  if (p >= A.P || A.ps[p].done) return;
+  net_scan_pair(A, p, s_scan);
+}
+
 // pass 3: arcs (local head and capacity) in the order of the global adjacency
-__global__ void __launch_bounds__(256) k_net_fill(KArgs A, int32_t it) {
-  const int32_t S = A.stamp0 + 2 * it;
-  grid_items(A, A.cpre, [&](int32_t p, int64_t item) {
+template <typename Items>
+__device__ __forceinline__ void net_fill(const KArgs &A, int32_t S, Items &&items) {
+  items([&](int32_t p, int64_t item) {
     if (p < 0) return;
     const int64_t i = A.voff[p] + item;  // arena slot
     const int32_t a = A.pairs[2 * p], b = A.pairs[2 * p + 1];
@@ -1404,11 +1436,15 @@ __global__ void __launch_bounds__(256) k_net_fill(KArgs A, int32_t it) {
   });
 }
 
+__global__ void __launch_bounds__(256) k_net_fill(KArgs A, int32_t it) {
+  net_fill(A, A.stamp0 + 2 * it, [&](auto &&f) { grid_items(A, A.cpre, f); });
+}
+
 // pass 4: reverse arcs, the initial preflow (every arc out of the source
 // border is saturated), cleared closure marks, the sink list
-__global__ void __launch_bounds__(256) k_net_rev(KArgs A, int32_t it) {
-  (void)it;
-  grid_items(A, A.cpre, [&](int32_t p, int64_t item64) {
+template <typename Items>
+__device__ __forceinline__ void net_rev(const KArgs &A, Items &&items) {
+  items([&](int32_t p, int64_t item64) {
     const bool on = p >= 0;
     const int32_t item = (int32_t)item64;
     bool overflow = false;
@@ -1465,8 +1501,286 @@ __global__ void __launch_bounds__(256) k_net_rev(KArgs A, int32_t it) {
   });
 }
 
+__global__ void __launch_bounds__(256) k_net_rev(KArgs A, int32_t it) {
+  (void)it;
+  net_rev(A, [&](auto &&f) { grid_items(A, A.cpre, f); });
+}
+
 // ---- maximum preflow, smallest source set, balance check, write-back and
 //      the adaptive factor (Sec. 4.1), one workgroup per pair
+template <int TPB>
+__device__ __forceinline__ void flow_pair(const KArgs &A, int32_t p, SolveShared<TPB> &sh,
+                                          PairState &st) {
+  const PairView V = make_view(A, p);
+  const int32_t a = V.a, b = V.b;
+  int64_t *pa = A.pacc + (int64_t)p * PA_N;
+  if (threadIdx.x == 0) {
+    st = A.ps[p];
+    sh.cnt[0] = sh.cnt[1] = sh.cnt[2] = 0;
+    sh.nsnk = min(A.pcnt[A.P + p], (int32_t)V.nv);
+  }
+  if (threadIdx.x < W_COUNT) sh.work[threadIdx.x] = 0ull;
+  __syncthreads();
+  const int32_t nr = uni(st.nr);
+  int64_t t0 = wall_clock64(), t1;
+  int64_t t_rel = 0, t_push = 0;
+  const int32_t NL = nr + 2;
+  const bool lds = nr <= 32 * FR_BM_WORDS;
+  const int32_t nw = (nr + 31) >> 5;
+  const bool overflow = pa[PA_RCAP] >= 0x7fffffffLL;
+  Rot R;
+  int64_t gr_levels = 0, sweeps = 0, relabels = 0, cl_levels = 0;
+  if (!overflow) {
+    // one relabel call site (the relabel is inlined; one copy keeps the
+    // kernel within its registers): at the start, when the active list
+    // runs dry and every relabel_period passes
+    int32_t cnt = 0;
+    ListRef cur, nxt;
+    int since = 0;
+    bool relabel = true;
+    for (;;) {
+      if (relabel) {
+        t1 = wall_clock64();
+        t_push += t1 - t0;
+        t0 = t1;
+        cnt = global_relabel<TPB>(A, V, nr, NL, sh, R, gr_levels, lds);
+        t1 = wall_clock64();
+        t_rel += t1 - t0;
+        t0 = t1;
+        relabels++;
+        cur = flist(V, sh, 0, lds);
+        nxt = flist(V, sh, 1, lds);
+        since = 0;
+        relabel = false;
+      }
+      if (cnt == 0) {
+        if (since == 0) break;  // an exact relabel found no active vertex
+        relabel = true;
+        continue;
+      }
+      if (sweeps >= A.max_sweeps) {
+        if (threadIdx.x == 0) {
+          A.ctl->err = FR_E_SOLVER_LIMIT;
+          A.ctl->diag = DIAG_SWEEPS;
+        }
+        break;
+      }
+      // queued marks of this pass in bm[(since + 1) & 1]; the other bitmap
+      // (the previous pass's marks, or the relabel's visited marks) is
+      // cleared now and serves the next pass
+      uint32_t *qbm = nullptr;
+      if (lds) {
+        qbm = sh.u.f.bm[(since + 1) & 1];
+        uint32_t *old = sh.u.f.bm[since & 1];
+        for (int w = threadIdx.x; w < nw; w += TPB) old[w] = 0u;
+      }
+      pr_sweep_any<TPB>(A, V, cur, cnt, nxt, &sh.cnt[(R.c + 1) % 3], NL, sh.work, qbm);
+      if (threadIdx.x == 0) sh.cnt[(R.c + 2) % 3] = 0;
+      __syncthreads();
+      R.c = (R.c + 1) % 3;
+      cnt = uni(min(sh.cnt[R.c], (int32_t)V.nv));
+      const ListRef t = cur;
+      cur = nxt;
+      nxt = t;
+      sweeps++;
+      if (++since >= A.relabel_period) relabel = true;
+    }
+    t1 = wall_clock64();
+    t_push += t1 - t0;
+    t0 = t1;
+    // ---- smallest source set (Sec. 4.1.1): closure of the source border
+    //      and of every vertex left with excess, over arcs with residual
+    //      capacity
+    {
+      uint32_t *vis = sh.u.f.bm[0];
+      cur = flist(V, sh, 0, lds);
+      nxt = flist(V, sh, 1, lds);
+      int32_t *ncnt = &sh.cnt[(R.c + 1) % 3];
+      BLOCK_WAVE_LOOP(i, nr) {
+        bool seed = false;
+        if (i < nr) {
+          const uint32_t f = V.fl[i];
+          seed = LF_SRC(f) || (!LF_SNK(f) && V.ex[i] > 0);
+          if (seed) V.ins[i] = 1;
+        }
+        if (lds) {
+          const unsigned long long m = __ballot(seed);
+          if (lane64() == 0) vis[i >> 5] = (uint32_t)m;
+          if (lane64() == 32) vis[i >> 5] = (uint32_t)(m >> 32);
+        }
+        const int pos = wave_append(ncnt, seed);
+        if (seed) lput(cur, pos, V.nv, (int32_t)i, A.ctl);
+      }
+      if (threadIdx.x == 0) sh.cnt[(R.c + 2) % 3] = 0;
+      __syncthreads();
+      R.c = (R.c + 1) % 3;
+      int32_t cnt2 = uni(min(sh.cnt[R.c], (int32_t)V.nv));
+      while (cnt2 > 0) {
+        int32_t *ncnt2 = &sh.cnt[(R.c + 1) % 3];
+        for_groups<GTF>(cnt2, [&](int item, bool valid, int gl) {
+          const int32_t u = valid ? lget(cur, item) : 0;
+          const int32_t e0 = valid ? V.lo[u] : 0, e1 = valid ? V.lo[u + 1] : 0;
+          count_work(sh, W_CL_ITEMS, (valid && gl == 0) ? 1 : 0);
+          count_work(sh, W_CL_ARCS, (valid && gl == 0) ? e1 - e0 : 0);
+          for (int32_t c0 = e0; c0 < e1; c0 += GTF * KF) {
+            int32_t v[KF], r[KF];
+#pragma unroll
+            for (int k = 0; k < KF; k++) {
+              const int32_t ar = c0 + k * GTF + gl;
+              Arc x = {0, 0, 0ull};
+              if (ar < e1) x = V.arc[ar];
+              r[k] = res_own(x.rc);
+              v[k] = x.lh;
+            }
+#pragma unroll
+            for (int k = 0; k < KF; k++) {
+              bool claim = false;
+              if (r[k] > 0) {
+                if (lds) {
+                  const bool seen = (vis[v[k] >> 5] >> (v[k] & 31)) & 1u;
+                  if (!seen) {
+                    claim = bm_claim(vis, v[k]);
+                    if (claim) V.ins[v[k]] = 1;
+                  }
+                } else if (V.ins[v[k]] == 0) {
+                  claim = atomicCAS(&V.ins[v[k]], 0, 1) == 0;
+                }
+              }
+              const int pos = wave_append(ncnt2, claim);
+              if (claim) lput(nxt, pos, V.nv, v[k], A.ctl);
+            }
+          }
+        });
+        if (threadIdx.x == 0) sh.cnt[(R.c + 2) % 3] = 0;
+        __syncthreads();
+        R.c = (R.c + 1) % 3;
+        cnt2 = uni(min(sh.cnt[R.c], (int32_t)V.nv));
+        const ListRef t = cur;
+        cur = nxt;
+        nxt = t;
+        cl_levels++;
+      }
+    }
+  }
+  t1 = wall_clock64();
+  const int64_t t_cl = t1 - t0;
+  t0 = t1;
+  // ---- candidate partition and its balance check (Sec. 2.1); for the most
+  //      balanced cut, also the free vertices (neither in the smallest
+  //      source set nor able to reach the sink: exact label NL), listed in
+  //      LB with LA[i] = i for them and -1 for every other corridor vertex
+  // flow, moved a->b, moved b->a, source side; the same three for the
+  // largest minimum source side (label >= NL: cannot reach the sink)
+  int64_t acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  const bool term = A.terminals != 0;
+  const bool mb = A.mb_reps > 0 && !overflow;
+  const int side_mode = (A.mb_reps > 0 || overflow) ? 0 : A.cut_side;
+  if (mb) {
+    if (threadIdx.x == 0) sh.nfree = 0;
+    __syncthreads();
+  }
+  if (!overflow) {
+    BLOCK_WAVE_LOOP(i, nr) {
+      bool fv = false;
+      if (i < nr) {
+        const uint32_t f = V.fl[i];
+        const int32_t w = A.vwgt[V.lg[i]];
+        const bool in = V.ins[i] != 0;
+        // the closure reached the sink: the preflow was not maximal
+        if (in && (term ? V.SNK[i] > 0 : LF_SNK(f))) {
+          A.ctl->err = FR_E_DEVICE;
+          A.ctl->diag = DIAG_CLOSURE;
+        }
+        // flow: what reached the sink border; contracted terminals: what
+        // left s and stayed nowhere in the corridor
+        if (term) acc[0] -= V.ex[i];
+        else if (LF_SNK(f)) acc[0] += V.ex[i];
+        if (!(f & LF_SIDE_B) && !in) acc[1] += w;
+        if ((f & LF_SIDE_B) && in) acc[2] += w;
+        acc[3] += in ? 1 : 0;
+        if (side_mode) {
+          const bool inx = V.lab[i] >= NL;
+          if (!(f & LF_SIDE_B) && !inx) acc[4] += w;
+          if ((f & LF_SIDE_B) && inx) acc[5] += w;
+          acc[6] += inx ? 1 : 0;
+        }
+        if (mb) {
+          fv = !in && !(f & LF_BORDER) && V.lab[i] == NL;
+          V.LA[i] = fv ? (int32_t)i : -1;
+        }
+      }
+      if (mb) {
+        const int pos = wave_append(&sh.nfree, fv);
+        if (fv) V.LB[pos] = (int32_t)i;
+      }
+    }
+  }
+  block_sums<7>(acc, sh.red);
+  // the record of this solve; the adaptive rule and the write-back run in
+  // k_select, over all slots of the pair
+  if (threadIdx.x == 0) {
+    st.sweeps += sweeps;
+    st.relabels += relabels;
+    st.gr_levels += gr_levels;
+    st.cl_levels += cl_levels;
+    for (int j = 0; j < W_COUNT; j++) st.work[j] += (int64_t)sh.work[j];
+    st.t_relabel += t_rel;
+    st.t_push += t_push;
+    st.t_closure += t_cl;
+    fr_solve rec;
+    const int64_t cut = st.cut;
+    rec.alpha = st.alpha;
+    if (term) acc[0] += pa[PA_CS];
+    rec.flow = acc[0];
+    rec.region_vertices = nr;
+    rec.region_edges = pa[PA_RARCS] / 2;
+    rec.source_side = acc[3];
+    rec.cut_before = cut;
+    int64_t cand = cut - pa[PA_RCIN] + acc[0];
+    int64_t wa = st.cA - acc[1] + acc[2];
+    int64_t wb = st.cB + acc[1] - acc[2];
+    sh.use_max = 0;
+    if (side_mode && cut != 0) {  // the largest minimum source side instead
+      const int64_t wa2 = st.cA - acc[4] + acc[5], wb2 = st.cB + acc[4] - acc[5];
+      const bool f1 = wa <= A.lmax && wb <= A.lmax, f2 = wa2 <= A.lmax && wb2 <= A.lmax;
+      if (side_mode == 1 || (!f1 && f2)) {
+        sh.use_max = 1;
+        wa = wa2;
+        wb = wb2;
+        rec.source_side = acc[6];
+      }
+    }
+    int dec;
+    if (cut == 0) {
+      dec = FR_DEC_NOT_ADJACENT;
+      cand = 0;
+      wa = st.cA;
+      wb = st.cB;
+      rec.flow = 0;
+    } else {
+      const bool feas = wa <= A.lmax && wb <= A.lmax;
+      dec = !feas ? FR_DEC_INFEASIBLE : (cand < cut ? FR_DEC_APPLY : FR_DEC_EQUAL);
+    }
+    rec.cut_candidate = cand;
+    rec.wa = wa;
+    rec.wb = wb;
+    rec.decision = dec;
+    A.srec[p] = rec;
+    st.t_finish += wall_clock64() - t0;
+    for (int j = 0; j < PA_N; j++) pa[j] = 0;
+    A.pcnt[p] = mb ? sh.nfree : 0;  // the most balanced cut kernel reads and clears it
+    A.pcnt[A.P + p] = 0;
+    A.ps[p] = st;
+  }
+  __syncthreads();
+  if (sh.use_max) {  // the source side becomes every vertex that cannot reach the sink
+    BLOCK_WAVE_LOOP(i, nr) {
+      if (i < nr) V.ins[i] = V.lab[i] >= NL ? 1 : 0;
+    }
+    __syncthreads();
+  }
+}
+
 template <int TPB>
 __global__ void __launch_bounds__(TPB) k_flow(KArgs A, int32_t it) {
   __shared__ SolveShared<TPB> sh;
@@ -1474,274 +1788,7 @@ __global__ void __launch_bounds__(TPB) k_flow(KArgs A, int32_t it) {
   for (;;) {
     const int32_t p = next_pair<TPB>(A, A.queue + 2 * it + 1, sh);
     if (p < 0) break;
-    const PairView V = make_view(A, p);
-    const int32_t a = V.a, b = V.b;
-    int64_t *pa = A.pacc + (int64_t)p * PA_N;
-    if (threadIdx.x == 0) {
-      st = A.ps[p];
-      sh.cnt[0] = sh.cnt[1] = sh.cnt[2] = 0;
-      sh.nsnk = min(A.pcnt[A.P + p], (int32_t)V.nv);
-    }
-    if (threadIdx.x < W_COUNT) sh.work[threadIdx.x] = 0ull;
-    __syncthreads();
-    const int32_t nr = uni(st.nr);
-    int64_t t0 = wall_clock64(), t1;
-    int64_t t_rel = 0, t_push = 0;
-    const int32_t NL = nr + 2;
-    const bool lds = nr <= 32 * FR_BM_WORDS;
-    const int32_t nw = (nr + 31) >> 5;
-    const bool overflow = pa[PA_RCAP] >= 0x7fffffffLL;
-    Rot R;
-    int64_t gr_levels = 0, sweeps = 0, relabels = 0, cl_levels = 0;
-    if (!overflow) {
-      // one relabel call site (the relabel is inlined; one copy keeps the
-      // kernel within its registers): at the start, when the active list
-      // runs dry and every relabel_period passes
-      int32_t cnt = 0;
-      ListRef cur, nxt;
-      int since = 0;
-      bool relabel = true;
-      for (;;) {
-        if (relabel) {
-          t1 = wall_clock64();
-          t_push += t1 - t0;
-          t0 = t1;
-          cnt = global_relabel<TPB>(A, V, nr, NL, sh, R, gr_levels, lds);
-          t1 = wall_clock64();
-          t_rel += t1 - t0;
-          t0 = t1;
-          relabels++;
-          cur = flist(V, sh, 0, lds);
-          nxt = flist(V, sh, 1, lds);
-          since = 0;
-          relabel = false;
-        }
-        if (cnt == 0) {
-          if (since == 0) break;  // an exact relabel found no active vertex
-          relabel = true;
-          continue;
-        }
-        if (sweeps >= A.max_sweeps) {
-          if (threadIdx.x == 0) {
-            A.ctl->err = FR_E_SOLVER_LIMIT;
-            A.ctl->diag = DIAG_SWEEPS;
-          }
-          break;
-        }
-        // queued marks of this pass in bm[(since + 1) & 1]; the other bitmap
-        // (the previous pass's marks, or the relabel's visited marks) is
-        // cleared now and serves the next pass
-        uint32_t *qbm = nullptr;
-        if (lds) {
-          qbm = sh.u.f.bm[(since + 1) & 1];
-          uint32_t *old = sh.u.f.bm[since & 1];
-          for (int w = threadIdx.x; w < nw; w += TPB) old[w] = 0u;
-        }
-        pr_sweep_any<TPB>(A, V, cur, cnt, nxt, &sh.cnt[(R.c + 1) % 3], NL, sh.work, qbm);
-        if (threadIdx.x == 0) sh.cnt[(R.c + 2) % 3] = 0;
-        __syncthreads();
-        R.c = (R.c + 1) % 3;
-        cnt = uni(min(sh.cnt[R.c], (int32_t)V.nv));
-        const ListRef t = cur;
-        cur = nxt;
-        nxt = t;
-        sweeps++;
-        if (++since >= A.relabel_period) relabel = true;
-      }
-      t1 = wall_clock64();
-      t_push += t1 - t0;
-      t0 = t1;
-      // ---- smallest source set (Sec. 4.1.1): closure of the source border
-      //      and of every vertex left with excess, over arcs with residual
-      //      capacity
-      {
-        uint32_t *vis = sh.u.f.bm[0];
-        cur = flist(V, sh, 0, lds);
-        nxt = flist(V, sh, 1, lds);
-        int32_t *ncnt = &sh.cnt[(R.c + 1) % 3];
-        BLOCK_WAVE_LOOP(i, nr) {
-          bool seed = false;
-          if (i < nr) {
-            const uint32_t f = V.fl[i];
-            seed = LF_SRC(f) || (!LF_SNK(f) && V.ex[i] > 0);
-            if (seed) V.ins[i] = 1;
-          }
-          if (lds) {
-            const unsigned long long m = __ballot(seed);
-            if (lane64() == 0) vis[i >> 5] = (uint32_t)m;
-            if (lane64() == 32) vis[i >> 5] = (uint32_t)(m >> 32);
-          }
-          const int pos = wave_append(ncnt, seed);
-          if (seed) lput(cur, pos, V.nv, (int32_t)i, A.ctl);
-        }
-        if (threadIdx.x == 0) sh.cnt[(R.c + 2) % 3] = 0;
-        __syncthreads();
-        R.c = (R.c + 1) % 3;
-        int32_t cnt2 = uni(min(sh.cnt[R.c], (int32_t)V.nv));
-        while (cnt2 > 0) {
-          int32_t *ncnt2 = &sh.cnt[(R.c + 1) % 3];
-          for_groups<GTF>(cnt2, [&](int item, bool valid, int gl) {
-            const int32_t u = valid ? lget(cur, item) : 0;
-            const int32_t e0 = valid ? V.lo[u] : 0, e1 = valid ? V.lo[u + 1] : 0;
-            count_work(sh, W_CL_ITEMS, (valid && gl == 0) ? 1 : 0);
-            count_work(sh, W_CL_ARCS, (valid && gl == 0) ? e1 - e0 : 0);
-            for (int32_t c0 = e0; c0 < e1; c0 += GTF * KF) {
-              int32_t v[KF], r[KF];
-#pragma unroll
-              for (int k = 0; k < KF; k++) {
-                const int32_t ar = c0 + k * GTF + gl;
-                Arc x = {0, 0, 0ull};
-                if (ar < e1) x = V.arc[ar];
-                r[k] = res_own(x.rc);
-                v[k] = x.lh;
-              }
-#pragma unroll
-              for (int k = 0; k < KF; k++) {
-                bool claim = false;
-                if (r[k] > 0) {
-                  if (lds) {
-                    const bool seen = (vis[v[k] >> 5] >> (v[k] & 31)) & 1u;
-                    if (!seen) {
-                      claim = bm_claim(vis, v[k]);
-                      if (claim) V.ins[v[k]] = 1;
-                    }
-                  } else if (V.ins[v[k]] == 0) {
-                    claim = atomicCAS(&V.ins[v[k]], 0, 1) == 0;
-                  }
-                }
-                const int pos = wave_append(ncnt2, claim);
-                if (claim) lput(nxt, pos, V.nv, v[k], A.ctl);
-              }
-            }
-          });
-          if (threadIdx.x == 0) sh.cnt[(R.c + 2) % 3] = 0;
-          __syncthreads();
-          R.c = (R.c + 1) % 3;
-          cnt2 = uni(min(sh.cnt[R.c], (int32_t)V.nv));
-          const ListRef t = cur;
-          cur = nxt;
-          nxt = t;
-          cl_levels++;
-        }
-      }
-    }
-    t1 = wall_clock64();
-    const int64_t t_cl = t1 - t0;
-    t0 = t1;
-    // ---- candidate partition and its balance check (Sec. 2.1); for the most
-    //      balanced cut, also the free vertices (neither in the smallest
-    //      source set nor able to reach the sink: exact label NL), listed in
-    //      LB with LA[i] = i for them and -1 for every other corridor vertex
-    // flow, moved a->b, moved b->a, source side; the same three for the
-    // largest minimum source side (label >= NL: cannot reach the sink)
-    int64_t acc[7] = {0, 0, 0, 0, 0, 0, 0};
-    const bool term = A.terminals != 0;
-    const bool mb = A.mb_reps > 0 && !overflow;
-    const int side_mode = (A.mb_reps > 0 || overflow) ? 0 : A.cut_side;
-    if (mb) {
-      if (threadIdx.x == 0) sh.nfree = 0;
-      __syncthreads();
-    }
-    if (!overflow) {
-      BLOCK_WAVE_LOOP(i, nr) {
-        bool fv = false;
-        if (i < nr) {
-          const uint32_t f = V.fl[i];
-          const int32_t w = A.vwgt[V.lg[i]];
-          const bool in = V.ins[i] != 0;
-          // the closure reached the sink: the preflow was not maximal
-          if (in && (term ? V.SNK[i] > 0 : LF_SNK(f))) {
-            A.ctl->err = FR_E_DEVICE;
-            A.ctl->diag = DIAG_CLOSURE;
-          }
-          // flow: what reached the sink border; contracted terminals: what
-          // left s and stayed nowhere in the corridor
-          if (term) acc[0] -= V.ex[i];
-          else if (LF_SNK(f)) acc[0] += V.ex[i];
-          if (!(f & LF_SIDE_B) && !in) acc[1] += w;
-          if ((f & LF_SIDE_B) && in) acc[2] += w;
-          acc[3] += in ? 1 : 0;
-          if (side_mode) {
-            const bool inx = V.lab[i] >= NL;
-            if (!(f & LF_SIDE_B) && !inx) acc[4] += w;
-            if ((f & LF_SIDE_B) && inx) acc[5] += w;
-            acc[6] += inx ? 1 : 0;
-          }
-          if (mb) {
-            fv = !in && !(f & LF_BORDER) && V.lab[i] == NL;
-            V.LA[i] = fv ? (int32_t)i : -1;
-          }
-        }
-        if (mb) {
-          const int pos = wave_append(&sh.nfree, fv);
-          if (fv) V.LB[pos] = (int32_t)i;
-        }
-      }
-    }
-    block_sums<7>(acc, sh.red);
-    // the record of this solve; the adaptive rule and the write-back run in
-    // k_select, over all slots of the pair
-    if (threadIdx.x == 0) {
-      st.sweeps += sweeps;
-      st.relabels += relabels;
-      st.gr_levels += gr_levels;
-      st.cl_levels += cl_levels;
-      for (int j = 0; j < W_COUNT; j++) st.work[j] += (int64_t)sh.work[j];
-      st.t_relabel += t_rel;
-      st.t_push += t_push;
-      st.t_closure += t_cl;
-      fr_solve rec;
-      const int64_t cut = st.cut;
-      rec.alpha = st.alpha;
-      if (term) acc[0] += pa[PA_CS];
-      rec.flow = acc[0];
-      rec.region_vertices = nr;
-      rec.region_edges = pa[PA_RARCS] / 2;
-      rec.source_side = acc[3];
-      rec.cut_before = cut;
-      int64_t cand = cut - pa[PA_RCIN] + acc[0];
-      int64_t wa = st.cA - acc[1] + acc[2];
-      int64_t wb = st.cB + acc[1] - acc[2];
-      sh.use_max = 0;
-      if (side_mode && cut != 0) {  // the largest minimum source side instead
-        const int64_t wa2 = st.cA - acc[4] + acc[5], wb2 = st.cB + acc[4] - acc[5];
-        const bool f1 = wa <= A.lmax && wb <= A.lmax, f2 = wa2 <= A.lmax && wb2 <= A.lmax;
-        if (side_mode == 1 || (!f1 && f2)) {
-          sh.use_max = 1;
-          wa = wa2;
-          wb = wb2;
-          rec.source_side = acc[6];
-        }
-      }
-      int dec;
-      if (cut == 0) {
-        dec = FR_DEC_NOT_ADJACENT;
-        cand = 0;
-        wa = st.cA;
-        wb = st.cB;
-        rec.flow = 0;
-      } else {
-        const bool feas = wa <= A.lmax && wb <= A.lmax;
-        dec = !feas ? FR_DEC_INFEASIBLE : (cand < cut ? FR_DEC_APPLY : FR_DEC_EQUAL);
-      }
-      rec.cut_candidate = cand;
-      rec.wa = wa;
-      rec.wb = wb;
-      rec.decision = dec;
-      A.srec[p] = rec;
-      st.t_finish += wall_clock64() - t0;
-      for (int j = 0; j < PA_N; j++) pa[j] = 0;
-      A.pcnt[p] = mb ? sh.nfree : 0;  // the most balanced cut kernel reads and clears it
-      A.pcnt[A.P + p] = 0;
-      A.ps[p] = st;
-    }
-    __syncthreads();
-    if (sh.use_max) {  // the source side becomes every vertex that cannot reach the sink
-      BLOCK_WAVE_LOOP(i, nr) {
-        if (i < nr) V.ins[i] = V.lab[i] >= NL ? 1 : 0;
-      }
-      __syncthreads();
-    }
+    flow_pair<TPB>(A, p, sh, st);
   }
 }
 
@@ -1751,15 +1798,14 @@ __global__ void __launch_bounds__(TPB) k_flow(KArgs A, int32_t it) {
 //      next slot holds that solve, a feasible solve that does not improve
 //      stops), record the walked solves, write the applied candidate back and
 //      set every slot's factor for the next launch
-__global__ void __launch_bounds__(1024) k_select(KArgs A, int32_t it) {
-  __shared__ int32_t s_chosen, s_v0;
-  (void)it;
-  const int32_t p = blockIdx.x;  // pair of the round
+// Pair p of the round (entries p * W ...); s_sel: 3 LDS words (chosen slot,
+// first entry, stopped).  All threads call it.
+__device__ __forceinline__ void select_pair(const KArgs &A, int32_t p, int32_t *s_sel) {
   const int32_t W = A.W;
   const int32_t v0 = p * W;
   if (A.ps[v0].done) return;
   if (threadIdx.x == 0) {
-    PairState R = A.ps[v0];
+    PairState &R = A.ps[v0];  // updated in place (a copy would live in scratch)
     bool stop = false;
     int chosen = -1;
     int32_t next_alpha = R.alpha;
@@ -1801,7 +1847,6 @@ __global__ void __launch_bounds__(1024) k_select(KArgs A, int32_t it) {
     }
     R.alpha = next_alpha;
     R.done = stop ? 1 : 0;
-    A.ps[v0] = R;
     for (int s = 1; s < W; s++) {
       PairState &q = A.ps[v0 + s];
       q.alpha = next_alpha >> s;
@@ -1810,18 +1855,63 @@ __global__ void __launch_bounds__(1024) k_select(KArgs A, int32_t it) {
       q.cB = R.cB;
       q.cut = R.cut;
     }
-    s_chosen = A.ctl->err == 0 ? chosen : -1;
-    s_v0 = v0;
+    s_sel[0] = A.ctl->err == 0 ? chosen : -1;
+    s_sel[1] = v0;
+    s_sel[2] = stop ? 1 : 0;
   }
   __syncthreads();
-  const int chosen = s_chosen;
+  const int chosen = s_sel[0];
   if (chosen < 0) return;
-  const int32_t vc = s_v0 + chosen;
+  const int32_t vc = s_sel[1] + chosen;
   const int32_t a = A.pairs[2 * vc], b = A.pairs[2 * vc + 1];
   const int64_t vb = A.voff[vc];
   const int32_t nr = A.ps[vc].nr;
   for (int32_t i = threadIdx.x; i < nr; i += blockDim.x)
     A.part[A.lg[vb + i]] = A.ins[vb + i] ? a : b;
+}
+
+__global__ void __launch_bounds__(1024) k_select(KArgs A, int32_t it) {
+  __shared__ int32_t s_sel[3];
+  (void)it;
+  select_pair(A, blockIdx.x, s_sel);
+}
+
+// ---- a whole round in one launch: each workgroup takes a pair (one entry
+//      per pair, W = 1) and runs its adaptive loop -- boundary, corridor,
+//      network, flow, the adaptive rule -- to the end without waiting for the
+//      other pairs.  The phases are the bodies of the per-iteration kernels
+//      over the pair's own items; a pair's buffers are touched by its
+//      workgroup only, so barriers order the phases.
+template <int TPB>
+__global__ void __launch_bounds__(TPB) k_round(KArgs A) {
+  __shared__ SolveShared<TPB> sh;
+  __shared__ PairState st;
+  __shared__ int32_t s_sel[3];
+  for (;;) {
+    const int32_t p = next_pair<TPB>(A, A.queue, sh);
+    if (p < 0) break;
+    const int64_t nu = A.voff[p + 1] - A.voff[p];
+    for (int32_t it = 0; it < A.max_iters; it++) {
+      const int32_t S = A.stamp0 + 2 * it;
+      bnd_union(A, S, [&](auto &&f) { pair_items(p, nu, f); });
+      __syncthreads();
+      corr_pair<TPB>(A, S, p, sh, st);
+      const int32_t nr = uni(st.nr);
+      net_count(A, S, [&](auto &&f) { pair_items(p, nr, f); });
+      __syncthreads();
+      net_scan_pair(A, p, sh.scan);
+      __syncthreads();
+      net_fill(A, S, [&](auto &&f) { pair_items(p, nr, f); });
+      __syncthreads();
+      net_rev(A, [&](auto &&f) { pair_items(p, nr, f); });
+      __syncthreads();
+      flow_pair<TPB>(A, p, sh, st);
+      __syncthreads();
+      select_pair(A, p, s_sel);
+      __syncthreads();
+      if (uni(s_sel[2])) break;
+    }
+  }
 }
 
 // side codes of the last solve of pair 0 (single-pair calls)

@@ -225,6 +225,7 @@ def test_random_rounds_all_options(gpu_lib, seed):
     try:
         c.set_speculation(bool(rng.integers(0, 2)))
         c.set_validation(bool(rng.integers(0, 2)))
+        c.set_fused(seed % 2 == 0)
         p["terminals"] = int(rng.integers(0, 2))
         dg = gpu_lib.DeviceGraph.from_host(g)
         if seed % 4 == 3:

@@ -92,7 +92,8 @@ def _merge(part, pairs, outs):
 def test_largest_round_every_pair(gpu_lib, ctx, cid):
     """The largest round of C3 (8 pairs) and of C5 (128 pairs) on the default
     path (pinned border, smallest source set, alpha' = 16 adaptive), as the
-    benchmark times it: every pair's result record and trace, and the whole
+    benchmark times it, with the fused round kernel and with the per-iteration
+    launch chains: every pair's result record and trace, and the whole
     partition, equal the oracle's."""
     import torch
 
@@ -104,18 +105,26 @@ def test_largest_round_every_pair(gpu_lib, ctx, cid):
     pairs = [tuple(e) for e, c in zip(edges.tolist(), colour.tolist()) if c == cls]
     p = {k: w.params[k] for k in ("area_mode", "depth", "alpha", "alpha_max", "adaptive",
                                   "max_iters", "eps_ppm")}
-    print(f"{cid} largest round, {len(pairs)} pairs, every pair", flush=True)
-    dpart = part0.clone()
-    res, trace = gpu_lib.flow_refine_batch(ctx, dg, dpart, w.k, pairs, gpu_lib.params(**p))
-    out = dpart.cpu().numpy()
     outs = _oracle_pairs(w, w.part, pairs, p)
-    for i, ((a, b), o) in enumerate(zip(pairs, outs)):
-        assert o.rc == 0
-        for key in KEYS:
-            assert res[i][key] == o.result[key], (cid, (a, b), key, res[i][key], o.result[key])
-        assert trace[i] == o.trace, (cid, (a, b))
-    assert np.array_equal(out, _merge(w.part, pairs, outs))
-    assert sum(r["applied"] > 0 for r in res) > 0
+    merged = _merge(w.part, pairs, outs)
+    try:
+        for fused in (True, False):
+            print(f"{cid} largest round, {len(pairs)} pairs, every pair, "
+                  f"{'fused round kernel' if fused else 'launch chains'}", flush=True)
+            ctx.set_fused(fused)
+            dpart = part0.clone()
+            res, trace = gpu_lib.flow_refine_batch(ctx, dg, dpart, w.k, pairs, gpu_lib.params(**p))
+            out = dpart.cpu().numpy()
+            for i, ((a, b), o) in enumerate(zip(pairs, outs)):
+                assert o.rc == 0
+                for key in KEYS:
+                    assert res[i][key] == o.result[key], (cid, fused, (a, b), key, res[i][key],
+                                                          o.result[key])
+                assert trace[i] == o.trace, (cid, fused, (a, b))
+            assert np.array_equal(out, merged)
+            assert sum(r["applied"] > 0 for r in res) > 0
+    finally:
+        ctx.set_fused(False)
 
 
 def test_c5_sweep_every_pair(gpu_lib, ctx):

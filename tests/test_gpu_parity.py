@@ -238,11 +238,13 @@ def test_error_paths(gpu_lib, ctx):
     assert e.value.code == -8
 
 
-@pytest.mark.parametrize("spec", [True, False])
-def test_speculation_on_off_match_oracle(gpu_lib, spec):
+@pytest.mark.parametrize("spec,fused", [(True, False), (False, False), (True, True)])
+def test_speculation_on_off_match_oracle(gpu_lib, spec, fused):
     """The adaptive loop with every factor of the halving chain solved at once
-    (speculation) and one solve per launch give the oracle's trace, result and
-    partition; with speculation the C2 pair runs its 5 factors side by side."""
+    (speculation, launch chains per iteration), one solve per launch, and the
+    fused round kernel (one solve at a time inside one launch) give the
+    oracle's trace, result and partition; with speculation the C2 pair runs
+    its 5 factors side by side."""
     import torch
 
     w = gen.config("C2", n_override=1 << 16)
@@ -250,6 +252,8 @@ def test_speculation_on_off_match_oracle(gpu_lib, spec):
     ctx = gpu_lib.Context()
     try:
         ctx.set_speculation(spec)
+        ctx.set_fused(fused)
+        spec = spec and not fused
         dg = gpu_lib.DeviceGraph.from_host(w.graph)
         dpart = torch.as_tensor(w.part.copy()).cuda()
         res, trace, side = gpu_lib.flow_refine_pair(ctx, dg, dpart, 2, 0, 1,
@@ -373,6 +377,7 @@ def test_boundary_pass_modes(gpu_lib, spec):
     c = gpu_lib.Context()
     try:
         c.set_speculation(spec)
+        c.set_fused(False)  # the boundary pass of the launch chains
         a, b = (int(x) for x in edges[0])
         _compare_pair(gpu_lib, c, g, part, 64, a, b, p)
         cls = int(np.argmax(np.bincount(colour)))

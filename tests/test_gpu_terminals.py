@@ -119,6 +119,7 @@ def test_speculation_on_off(gpu_lib, spec):
     c = gpu_lib.Context()
     try:
         c.set_speculation(spec)
+        c.set_fused(not spec)  # launch chains with speculation, else the fused round kernel
         _compare(gpu_lib, c, g, part, 2, 0, 1, p)
     finally:
         c.close()
