@@ -624,9 +624,15 @@ template <int TPB>
 __device__ void pr_sweep_any(const KArgs &A, const PairView &V, const ListRef &cur, int32_t cnt,
                              const ListRef &next, int32_t *next_cnt, int32_t NL,
                              unsigned long long *wcnt, uint32_t *qbm) {
-  // 1 and 16 lanes per vertex run as 2 and 8 (results do not depend on it)
-  if (A.tpv <= 2) pr_sweep<TPB, 2>(A, V, cur, cnt, next, next_cnt, NL, wcnt, qbm);
-  else if (A.tpv == 4) pr_sweep<TPB, 4>(A, V, cur, cnt, next, next_cnt, NL, wcnt, qbm);
+  // Lanes per vertex: the tuning's value (1 and 16 run as 2 and 8), lowered
+  // while the list would take more than one pass of the workgroup -- every
+  // extra pass costs the whole chain of dependent loads and atomics again,
+  // while 2 or 4 lanes still keep 8 arcs of a vertex in flight.  Results do
+  // not depend on it.
+  int t = A.tpv <= 2 ? 2 : (A.tpv == 4 ? 4 : 8);
+  while (t > 2 && (int64_t)cnt * t > TPB) t >>= 1;
+  if (t == 2) pr_sweep<TPB, 2>(A, V, cur, cnt, next, next_cnt, NL, wcnt, qbm);
+  else if (t == 4) pr_sweep<TPB, 4>(A, V, cur, cnt, next, next_cnt, NL, wcnt, qbm);
   else pr_sweep<TPB, 8>(A, V, cur, cnt, next, next_cnt, NL, wcnt, qbm);
 }
 
