@@ -84,6 +84,9 @@ struct fr_context {
   hipStream_t user_stream = nullptr;
   hipStream_t cs = nullptr;  // the library's own stream (graph capture needs a non-null one)
   int num_cus = 0;
+  // grids of the whole-graph passes: every workgroup resident at once (each
+  // wave walks one contiguous run of vertex chunks)
+  int g_bnd = 0, g_bstat = 0, g_fstat = 0, g_union = 0;
   fr_tuning tune{1024, 2, 8, 100, 1};
   int validate = 1;
   int mlp_loaded = 0;
@@ -196,7 +199,7 @@ static int32_t ensure_capacity(fr_context *c, int64_t n, int64_t narcs, int64_t 
     d.mtw = nullptr;
     d.mtchg = nullptr;
     d.mtkcap = 0;
-    if (dalloc(&d.blk2pair, k) != hipSuccess || dalloc(&d.bstat, 3 * k) != hipSuccess ||
+    if (dalloc(&d.blk2pair, 3 * k) != hipSuccess || dalloc(&d.bstat, 3 * k) != hipSuccess ||
         dalloc(&d.qadj, k * k) != hipSuccess)
       return FR_E_OOM;
     d.kcap = k;
@@ -301,6 +304,18 @@ extern "C" int32_t fr_create(int32_t device, void *hip_stream, fr_context **out)
     return FR_E_DEVICE;
   }
   c->num_cus = prop.multiProcessorCount;
+  {
+    auto resident = [&](const void *fn) {
+      int nb = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, 0) != hipSuccess || nb < 1)
+        nb = 4;
+      return std::min(nb * c->num_cus, 8192);
+    };
+    c->g_bnd = resident((const void *)k_bnd);
+    c->g_bstat = resident((const void *)k_block_stats);
+    c->g_fstat = resident((const void *)k_feature_stats);
+    c->g_union = resident((const void *)k_union);
+  }
   int rate = 0;
   if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, device) == hipSuccess && rate > 0)
     c->wall_khz = rate;
@@ -486,6 +501,7 @@ static KArgs call_args(fr_context *c, const DevBufs &d, const fr_graph *g, int32
   A.vwgt = g->vwgt;
   A.part = dpart;
   A.blk2pair = d.blk2pair;
+  A.binfo = d.blk2pair + k;  // the same allocation: [k] then [2k]
   A.bstat = d.bstat;
   A.queue = d.qctr;
   A.pacc = d.pacc;
@@ -622,9 +638,9 @@ static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t s
   const int sblocks = std::min(4 * c->num_cus, 8192);
   A.fstat = use_mlp ? d.fstat : nullptr;
   hipLaunchKernelGGL(k_round_init, dim3(1), dim3(1024), 0, st, A);
-  hipLaunchKernelGGL(k_block_stats, dim3(sblocks), dim3(256), 0, st, A);
+  hipLaunchKernelGGL(k_block_stats, dim3(c->g_bstat), dim3(256), 0, st, A);
   if (use_mlp) {
-    hipLaunchKernelGGL(k_feature_stats, dim3(sblocks), dim3(256), 0, st, A, d.fstat);
+    hipLaunchKernelGGL(k_feature_stats, dim3(c->g_fstat), dim3(256), 0, st, A, d.fstat);
     hipLaunchKernelGGL(k_features, dim3((A.P + 255) / 256), dim3(256), 0, st, A,
                        (const int64_t *)d.fstat, d.feats);
     hipLaunchKernelGGL(k_mlp_forward,
@@ -635,7 +651,7 @@ static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t s
                        (const float *)d.probs, A.P, A.alpha0);
   }
   hipLaunchKernelGGL(k_arena, dim3(1), dim3(1024), 0, st, A);
-  hipLaunchKernelGGL(k_union, dim3(sblocks), dim3(256), 0, st, A);
+  hipLaunchKernelGGL(k_union, dim3(c->g_union), dim3(256), 0, st, A);
   // pairwise FM before the flow iterations: gains grid-wide, then one
   // workgroup per pair
   if (A.fm_limit > 0) {
@@ -660,7 +676,7 @@ static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t s
     hipEvent_t *ev = c->itev + 5 * it;
     if (timed) HIPCHK(hipEventRecord(ev[0], st));
     hipLaunchKernelGGL(k_iter_begin, dim3(1), dim3(1024), 0, st, A, it);
-    hipLaunchKernelGGL(k_bnd, dim3(sblocks), dim3(256), 0, st, A, it);
+    hipLaunchKernelGGL(k_bnd, dim3(c->g_bnd), dim3(256), 0, st, A, it);
     hipLaunchKernelGGL(corr, dim3(blocks), dim3(tpb), 0, st, A, it);
     hipLaunchKernelGGL(k_iter_mid, dim3(1), dim3(1024), 0, st, A, it);
     if (timed) HIPCHK(hipEventRecord(ev[1], st));
@@ -1121,7 +1137,7 @@ extern "C" int32_t flow_refine_pair_static(fr_context *c, const fr_graph *g, int
   take(&v.partw, vn);
   take(&v.lflag, (size_t)n);
   take(&v.arc, sizeof(Arc) * (size_t)narcs);
-  take(&v.blk2pair, sizeof(int32_t) * (size_t)k);
+  take(&v.blk2pair, sizeof(int32_t) * 3 * (size_t)k);
   take(&v.bstat, sizeof(int64_t) * 3 * (size_t)k);
   if (!fits) return FR_E_SCRATCH_LIMIT;
   v.side = nullptr;
@@ -1577,8 +1593,8 @@ extern "C" int32_t fr_pair_features(fr_context *c, const fr_graph *g, const int3
   R.fstat = d.fstat;
   const int sblocks = std::min(4 * c->num_cus, 8192);
   hipLaunchKernelGGL(k_round_init, dim3(1), dim3(1024), 0, st, R);
-  hipLaunchKernelGGL(k_block_stats, dim3(sblocks), dim3(256), 0, st, R);
-  hipLaunchKernelGGL(k_feature_stats, dim3(sblocks), dim3(256), 0, st, R, d.fstat);
+  hipLaunchKernelGGL(k_block_stats, dim3(c->g_bstat), dim3(256), 0, st, R);
+  hipLaunchKernelGGL(k_feature_stats, dim3(c->g_fstat), dim3(256), 0, st, R, d.fstat);
   hipLaunchKernelGGL(k_features, dim3((npairs + 255) / 256), dim3(256), 0, st, R,
                      (const int64_t *)d.fstat, d.feats);
   HIPCHK(hipGetLastError());

@@ -103,6 +103,8 @@ struct KArgs {
   const int32_t *pairs;     // [2P]
   int32_t *order;           // [P] pairs in the order workgroups take them
   int32_t *blk2pair;        // [k]
+  int32_t *binfo;           // [2k] per block in the round: first entry of its pair while a
+                            // slot still iterates (else -1), (other block << 1) | (block is b)
   int32_t *alpha0;          // [P] start factor per pair
   PairState *ps;            // [P]
   fr_solve *trace;          // [P * max_iters] or null

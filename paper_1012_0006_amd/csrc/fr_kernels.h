@@ -159,6 +159,102 @@ __device__ __forceinline__ int wave_append_by_key(int32_t *counters, int key) {
   return slot;
 }
 
+// Per-lane running sums of N per-pair quantities, added to their per-pair
+// totals (dst[j][key * stride[j] + slot[j]]) only when the lane's pair
+// changes and at the end, so a kernel over many items of few pairs issues few
+// atomics.  Every lane of the wave calls add() and flush().
+template <int N>
+struct KeyedSums {
+  int key = -1;
+  int64_t v[N];
+  __device__ KeyedSums() {
+    for (int j = 0; j < N; j++) v[j] = 0;
+  }
+  template <typename Out>
+  __device__ __forceinline__ void add(int k, const int64_t (&x)[N], Out &&out) {
+    const bool change = key >= 0 && k >= 0 && k != key;
+    if (__ballot(change)) {
+      for (int j = 0; j < N; j++) out(j, change ? key : -1, v[j]);
+      if (change)
+        for (int j = 0; j < N; j++) v[j] = 0;
+    }
+    if (k >= 0) {
+      key = k;
+      for (int j = 0; j < N; j++) v[j] += x[j];
+    }
+  }
+  template <typename Out>
+  __device__ __forceinline__ void flush(Out &&out) {
+    for (int j = 0; j < N; j++) out(j, key, v[j]);
+  }
+};
+
+// Calls f(u0) for chunks of 64 consecutive vertices [u0, u0 + 64): each wave
+// walks a contiguous run of chunks, so sums keyed by block or pair change key
+// only at block borders and reach device memory a few times per wave.
+// Workgroups are dispatched round-robin over the 8 XCDs, so workgroup g
+// takes its runs from the (g mod 8)-th eighth of the vertex range, and
+// neighbouring vertices (whose blocks the arcs look up) stay in one XCD's
+// L2.  Wave-uniform; every wave of the grid calls it.
+template <typename F>
+__device__ __forceinline__ void wave_chunk_runs(int64_t n, F &&f) {
+  const int64_t nchunk = (n + 63) / 64;
+  const int xcd = (int)(blockIdx.x % 8u);
+  const int64_t nbx = ((int64_t)gridDim.x - xcd + 7) / 8;  // workgroups on this XCD
+  const int64_t per = (nchunk + 7) / 8;
+  const int wpb = (int)(blockDim.x >> 6);
+  const int64_t r_lo = min(nchunk, xcd * per), r_hi = min(nchunk, (xcd + 1) * per);
+  const int64_t nw = nbx * wpb;  // waves on this XCD
+  const int64_t run = (r_hi - r_lo + nw - 1) / nw;
+  const int64_t wi = (int64_t)(blockIdx.x / 8u) * wpb + (threadIdx.x >> 6);
+  const int64_t c_lo = min(r_hi, r_lo + wi * run), c_hi = min(r_hi, c_lo + run);
+  for (int64_t c = c_lo; c < c_hi; c++) f(c * 64);
+}
+
+// Boundary flag and cut weight of the 64 vertices of one chunk, one lane
+// each: the lane's vertex has arcs [x0, the next lane's x0), the chunk's
+// arcs are [E0, E1); with y2 >= 0 the vertex is a boundary vertex when a
+// neighbour lies in block y2 >> 1, and its cut weight sums the weights of
+// those arcs when y2 & 1 is 0 (lanes past the graph pass x0 = INT32_MAX and
+// y2 = -1).  The arcs are read coalesced, KB per lane in flight; each finds
+// its tail by a binary search over the lanes' range starts.  sb / scw: the
+// wave's 64 LDS slots.
+__device__ __forceinline__ void chunk_boundary(const KArgs &A, int32_t x0, int32_t y2, int32_t E0,
+                                               int32_t E1, uint32_t *sb,
+                                               unsigned long long *scw, bool &bnd,
+                                               int64_t &cw) {
+  const int lane = lane64();
+  sb[lane] = 0u;
+  scw[lane] = 0ull;
+  constexpr int KB = 4;
+  for (int32_t e0 = E0; e0 < E1; e0 += 64 * KB) {
+    int32_t o[KB], ty[KB], v[KB];
+#pragma unroll
+    for (int q = 0; q < KB; q++) {
+      const int32_t e = e0 + 64 * q + lane;
+      int l = 0;
+      for (int step = 32; step > 0; step >>= 1) {
+        const int32_t t = __shfl(x0, l + step);
+        if (t <= e) l += step;
+      }
+      o[q] = l;
+      ty[q] = __shfl(y2, l);
+      if (e >= E1) ty[q] = -1;
+      v[q] = ty[q] >= 0 ? A.adjncy[e] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < KB; q++) {
+      const int32_t e = e0 + 64 * q + lane;
+      if (ty[q] >= 0 && A.part[v[q]] == (ty[q] >> 1)) {
+        atomicOr(&sb[o[q]], 1u);
+        if (!(ty[q] & 1)) atomicAdd(&scw[o[q]], (unsigned long long)A.adjwgt[e]);
+      }
+    }
+  }
+  bnd = sb[lane] != 0u;
+  cw = (int64_t)scw[lane];
+}
+
 // c(V), max c(v) and the range check of the partition (once per call).
 __global__ void __launch_bounds__(256) k_graph_stats(KArgs A) {
   __shared__ int64_t s_red[16];
@@ -189,7 +285,11 @@ __global__ void __launch_bounds__(256) k_graph_stats(KArgs A) {
 // Start of a round (one block): block -> pair map, cleared block statistics,
 // union fill counters, pair queues, per-pair sums and list counters.
 __global__ void __launch_bounds__(1024) k_round_init(KArgs A) {
-  for (int i = threadIdx.x; i < A.k; i += blockDim.x) A.blk2pair[i] = -1;
+  for (int i = threadIdx.x; i < A.k; i += blockDim.x) {
+    A.blk2pair[i] = -1;
+    A.binfo[2 * i] = -1;
+    A.binfo[2 * i + 1] = 0;
+  }
   for (int i = threadIdx.x; i < 3 * A.k; i += blockDim.x) A.bstat[i] = 0;
   for (int i = threadIdx.x; i < A.P; i += blockDim.x) A.ucnt[i] = 0;
   if (A.fstat)
@@ -209,9 +309,12 @@ __global__ void __launch_bounds__(1024) k_round_init(KArgs A) {
 __global__ void __launch_bounds__(256) k_block_stats(KArgs A) {
   unsigned long long *bw = (unsigned long long *)A.bstat;
   unsigned long long *bc = bw + A.k, *ba = bw + 2 * A.k;
-  for (int64_t b0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) & ~(int64_t)63;
-       b0 < A.n; b0 += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t u = b0 + lane64();
+  KeyedSums<3> sums;
+  auto out = [&](int j, int key, int64_t v) {
+    wave_add_by_key(j == 0 ? bw : (j == 1 ? bc : ba), 1, 0, key, v);
+  };
+  wave_chunk_runs(A.n, [&](int64_t u0) {
+    const int64_t u = u0 + lane64();
     int key = -1;
     int32_t w = 0, deg = 0;
     if (u < A.n) {
@@ -222,10 +325,10 @@ __global__ void __launch_bounds__(256) k_block_stats(KArgs A) {
         deg = A.xadj[u + 1] - A.xadj[u];
       }
     }
-    wave_add_by_key(bw, 1, 0, key, w);
-    wave_add_by_key(bc, 1, 0, key, 1);
-    wave_add_by_key(ba, 1, 0, key, deg);
-  }
+    const int64_t x[3] = {w, 1, deg};
+    sums.add(key, x, out);
+  });
+  sums.flush(out);
 }
 
 // Arena slices (prefix sums of the pairs' vertex and arc counts), the
@@ -315,13 +418,12 @@ __global__ void __launch_bounds__(256) k_validate(KArgs A, int64_t narcs) {
 
 // vertices of the two blocks of every pair, gathered into the pair's arena
 __global__ void __launch_bounds__(256) k_union(KArgs A) {
-  for (int64_t b0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) & ~(int64_t)63;
-       b0 < A.n; b0 += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t u = b0 + lane64();
+  wave_chunk_runs(A.n, [&](int64_t u0) {
+    const int64_t u = u0 + lane64();
     const int32_t p = u < A.n ? A.blk2pair[A.part[u]] : -1;
     const int pos = wave_append_by_key(A.ucnt, p);
     if (p >= 0 && A.voff[p] + pos < A.voff[p + 1]) A.uvert[A.voff[p] + pos] = (int32_t)u;
-  }
+  });
 }
 
 // ------------------------------------------------------------------------
@@ -929,36 +1031,6 @@ __device__ __forceinline__ void grid_items(const KArgs &A, const int64_t *pre, F
   }
 }
 
-// Per-lane running sums of N per-pair quantities, added to their per-pair
-// totals (dst[j][key * stride[j] + slot[j]]) only when the lane's pair
-// changes and at the end, so a kernel over many items of few pairs issues few
-// atomics.  Every lane of the wave calls add() and flush().
-template <int N>
-struct KeyedSums {
-  int key = -1;
-  int64_t v[N];
-  __device__ KeyedSums() {
-    for (int j = 0; j < N; j++) v[j] = 0;
-  }
-  template <typename Out>
-  __device__ __forceinline__ void add(int k, const int64_t (&x)[N], Out &&out) {
-    const bool change = key >= 0 && k >= 0 && k != key;
-    if (__ballot(change)) {
-      for (int j = 0; j < N; j++) out(j, change ? key : -1, v[j]);
-      if (change)
-        for (int j = 0; j < N; j++) v[j] = 0;
-    }
-    if (k >= 0) {
-      key = k;
-      for (int j = 0; j < N; j++) v[j] += x[j];
-    }
-  }
-  template <typename Out>
-  __device__ __forceinline__ void flush(Out &&out) {
-    for (int j = 0; j < N; j++) out(j, key, v[j]);
-  }
-};
-
 // Start of launch `it` (one block): the pairs still iterating, compacted in
 // pair order, and the prefix sums of their union sizes.
 __global__ void __launch_bounds__(1024) k_iter_begin(KArgs A, int32_t it) {
@@ -986,6 +1058,18 @@ __global__ void __launch_bounds__(1024) k_iter_begin(KArgs A, int32_t it) {
   if (threadIdx.x == 0) {
     *A.nact = (int32_t)tc;
     A.vpre[tc] = ts;
+  }
+  // per block of the round: its pair's first entry while a slot still
+  // iterates, the other block and the side (the boundary pass's lookup)
+  for (int i = threadIdx.x; i < P; i += blockDim.x) {
+    if (i % A.W) continue;
+    bool live = false;
+    for (int32_t s = 0; s < A.W; s++) live = live || !A.ps[i + s].done;
+    const int32_t a = A.pairs[2 * i], b = A.pairs[2 * i + 1];
+    A.binfo[2 * a] = live ? i : -1;
+    A.binfo[2 * a + 1] = b << 1;
+    A.binfo[2 * b] = live ? i : -1;
+    A.binfo[2 * b + 1] = (a << 1) | 1;
   }
 }
 
@@ -1072,10 +1156,10 @@ __global__ void __launch_bounds__(256) k_bnd(KArgs A, int32_t it) {
   const int32_t S = A.stamp0 + 2 * it;
   unsigned long long *acc = (unsigned long long *)A.pacc;
   unsigned long long *psw = (unsigned long long *)A.ps;
-  // pair cut, boundary weight a / b, boundary count a / b, vertices, arcs
-  KeyedSums<7> sums;
   const int64_t total = A.vpre[*A.nact];  // union items of the live slots
   if (4 * total >= (int64_t)A.n) {
+    // pair cut, boundary weight a / b, boundary count a / b, vertices, arcs
+    KeyedSums<7> sums;
     // keyed by the pair's first entry; a flush adds to each live slot
     auto out = [&](int j, int key, int64_t v) {
       for (int32_t s = 0; s < A.W; s++) {
@@ -1084,38 +1168,35 @@ __global__ void __launch_bounds__(256) k_bnd(KArgs A, int32_t it) {
         else wave_add_by_key(psw, PS_WORDS, PS_WORK + (j == 5 ? W_BND_VERTS : W_BND_ARCS), q, v);
       }
     };
-    // one lane per vertex (64 vertices per wave): the chain of dependent
-    // loads per vertex is short, and many vertices are in flight per lane
-    for (int64_t b0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) & ~(int64_t)63; b0 < A.n;
-         b0 += (int64_t)gridDim.x * blockDim.x) {
-      const int64_t u = b0 + lane64();
-      int32_t p0 = -1, side = 0, deg = 0;
-      bool bnd = false;
-      int64_t cw = 0;
-      if (u < A.n) {
+    // per lane of the block: boundary flag and cut weight of its vertex
+    __shared__ uint32_t s_bnd[256];
+    __shared__ unsigned long long s_cw[256];
+    const int lane = lane64();
+    const int wl = (int)(threadIdx.x & ~63u);
+    wave_chunk_runs(A.n, [&](int64_t u0) {
+      const int64_t u = u0 + lane;
+      const int64_t last = min((int64_t)A.n, u0 + 64);
+      const bool in = u < last;
+      // the vertex's block -> its pair's first live entry, the other block
+      // and the side (binfo, set at the start of every iteration)
+      int32_t p0 = -1, y2 = -1, x0 = 0x7fffffff;
+      if (in) {
         const int32_t pv = A.part[u];
-        p0 = A.blk2pair[pv];
-        bool live = false;
-        for (int32_t s = 0; s < A.W && p0 >= 0 && !live; s++) live = !A.ps[p0 + s].done;
-        if (!live) p0 = -1;
-        if (p0 >= 0) {
-          const int32_t a = A.pairs[2 * p0], b = A.pairs[2 * p0 + 1];
-          side = pv == b;
-          const int32_t y = side ? a : b;
-          const int32_t e0 = A.xadj[u], e1 = A.xadj[u + 1];
-          deg = e1 - e0;
-          for (int32_t e = e0; e < e1; e++) {
-            if (A.part[A.adjncy[e]] == y) {
-              bnd = true;
-              if (!side) cw += A.adjwgt[e];
-            }
-          }
-        }
+        x0 = A.xadj[u];
+        p0 = A.binfo[2 * pv];
+        y2 = A.binfo[2 * pv + 1];
       }
+      if (p0 < 0) y2 = -1;
+      const int32_t E1 = A.xadj[last];
+      const int32_t x1 = u + 1 < last ? __shfl(x0, lane + 1) : E1;
+      bool bnd;
+      int64_t cw;
+      chunk_boundary(A, x0, y2, __shfl(x0, 0), E1, s_bnd + wl, s_cw + wl, bnd, cw);
       const bool bl = p0 >= 0 && bnd;
+      const int side = y2 & 1;
       const int64_t w = bl ? A.vwgt[u] : 0;
       const int64_t x[7] = {cw, bl && !side ? w : 0, bl && side ? w : 0, bl && !side ? 1 : 0,
-                            bl && side ? 1 : 0, 1, deg};
+                            bl && side ? 1 : 0, 1, in ? x1 - x0 : 0};
       sums.add(p0, x, out);
       for (int32_t s = 0; s < A.W; s++) {
         const int32_t p = bl && !A.ps[p0 + s].done ? p0 + s : -1;
@@ -1123,7 +1204,7 @@ __global__ void __launch_bounds__(256) k_bnd(KArgs A, int32_t it) {
         const int pos = wave_append_by_key(A.pcnt, p);
         if (p >= 0) put_bounded(A.LA + A.voff[p], pos, A.voff[p + 1] - A.voff[p], (int32_t)u, A.ctl);
       }
-    }
+    });
     sums.flush(out);
     return;
   }

@@ -30,34 +30,38 @@
 // Per-pair boundary statistics for the features: [P][4] = boundary vertices
 // of a, of b, boundary weight of a, pair cut.  Grid over all vertices.
 __global__ void __launch_bounds__(256) k_feature_stats(KArgs A, int64_t *acc) {
-  for (int64_t b0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) & ~(int64_t)63;
-       b0 < A.n; b0 += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t u = b0 + lane64();
-    int key = -1, side = 0;
-    bool bnd = false;
-    int64_t cw = 0, w = 0;
-    if (u < A.n) {
+  __shared__ uint32_t s_bnd[256];
+  __shared__ unsigned long long s_cw[256];
+  const int lane = lane64();
+  const int wl = (int)(threadIdx.x & ~63u);
+  unsigned long long *ac = (unsigned long long *)acc;
+  // boundary count a / b, boundary weight a, cut weight; keyed by pair
+  KeyedSums<4> sums;
+  auto out = [&](int j, int key, int64_t v) { wave_add_by_key(ac, 4, j, key, v); };
+  wave_chunk_runs(A.n, [&](int64_t u0) {
+    const int64_t u = u0 + lane;
+    const int64_t last = min((int64_t)A.n, u0 + 64);
+    int32_t p = -1, y2 = -1, x0 = 0x7fffffff;
+    int64_t w = 0;
+    if (u < last) {
       const int32_t x = A.part[u];
-      const int32_t p = A.blk2pair[x];
+      x0 = A.xadj[u];
+      p = A.blk2pair[x];
       if (p >= 0) {
         const int32_t a = A.pairs[2 * p], b = A.pairs[2 * p + 1];
-        side = x == b;
-        const int32_t y = side ? a : b;
-        for (int32_t e = A.xadj[u]; e < A.xadj[u + 1]; e++)
-          if (A.part[A.adjncy[e]] == y) {
-            bnd = true;
-            if (!side) cw += A.adjwgt[e];
-          }
-        key = p;
+        const int side = x == b;
+        y2 = ((side ? a : b) << 1) | side;
         w = A.vwgt[u];
       }
     }
-    unsigned long long *ac = (unsigned long long *)acc;
-    wave_add_by_key(ac, 4, 0, (bnd && !side) ? key : -1, 1);
-    wave_add_by_key(ac, 4, 1, (bnd && side) ? key : -1, 1);
-    wave_add_by_key(ac, 4, 2, (bnd && !side) ? key : -1, w);
-    wave_add_by_key(ac, 4, 3, key, cw);
-  }
+    bool bnd;
+    int64_t cw;
+    chunk_boundary(A, x0, y2, __shfl(x0, 0), A.xadj[last], s_bnd + wl, s_cw + wl, bnd, cw);
+    const int side = y2 & 1;
+    const int64_t x[4] = {bnd && !side ? 1 : 0, bnd && side ? 1 : 0, bnd && !side ? w : 0, cw};
+    sums.add(p, x, out);
+  });
+  sums.flush(out);
 }
 
 // The 8 features of every pair (FP32): log2(1+|dA|), log2(1+|dB|), c(A)/W,
