@@ -239,10 +239,13 @@ def run_learned(args, fr, torch, gen):
     edges_q, colour = fr.fr_quotient_matchings(ctx, dg, part0, w.k)
     classes = sorted(set(colour.tolist()))
     out = {}
-    for use in (0, 1):
-        prm = fr.params(**{k: w.params[k] for k in ("area_mode", "depth", "alpha", "alpha_max",
-                                                     "adaptive", "max_iters", "eps_ppm")},
-                        use_mlp=use)
+    runs = {"plain": (0, None), "constant_8": (0, 8), "constant_4": (0, 4), "learned": (1, None)}
+    for name, (use, alpha) in runs.items():
+        pc = {k: w.params[k] for k in ("area_mode", "depth", "alpha", "alpha_max", "adaptive",
+                                       "max_iters", "eps_ppm")}
+        if alpha is not None:
+            pc["alpha"] = alpha
+        prm = fr.params(**pc, use_mlp=use)
         dpart = part0.clone()
         solves = edges = 0
         torch.cuda.synchronize()
@@ -255,15 +258,18 @@ def run_learned(args, fr, torch, gen):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         import oracle  # cut accounting only (sum of cut edge weights)
-        out["learned" if use else "plain"] = {
+        out[name] = {
             "seconds": dt, "flow_solves": solves, "region_edges": edges,
             "region_edges_per_s": edges / dt,
             "total_cut": oracle.total_cut(w.graph, dpart.cpu().numpy())}
     ctx.close()
     out["workload"] = ("C4: 2D RGG n=2^22 mean degree 8, weights 1..10, k=64 RCB + 2% noise, "
-                       f"one sweep of {len(classes)} matching rounds, eps 3%, alpha' 16 adaptive")
-    out["validation_accuracy"] = report.get("validation_accuracy")
+                       f"one sweep of {len(classes)} matching rounds, eps 3%, alpha' 16 adaptive; "
+                       "starts: plain 16, constant 8, constant 4, learned")
+    out["training"] = {"loss": report.get("loss"), "cost_lambda": report.get("cost_lambda"),
+                       "held_out_sweeps": report.get("validation_sweeps")}
     out["speedup"] = out["plain"]["seconds"] / out["learned"]["seconds"]
+    out["speedup_vs_constant_8"] = out["constant_8"]["seconds"] / out["learned"]["seconds"]
     return out
 
 

@@ -409,6 +409,13 @@ int32_t fr_mlp_forward(fr_context *ctx, const float *x, int32_t n, float *probs)
  * (either output may be NULL). */
 int32_t fr_mlp_loss_grad(fr_context *ctx, const float *x, const int32_t *labels, int32_t n,
                          float *loss, float *grad);
+/* Mean expected cost of (x, costs) and its gradient (either output may be
+ * NULL): costs[n*5] holds every sample's cost of each class (finite), the loss
+ * is the mean over the samples of sum_c p_c costs_c with the softmax
+ * probabilities p (cost-sensitive classification: the class of least cost
+ * is the target, and near misses cost what the costs say). */
+int32_t fr_mlp_loss_grad_cost(fr_context *ctx, const float *x, const float *costs, int32_t n,
+                              float *loss, float *grad);
 /* Start factors alpha[n] in {1, 2, 4, 8, 16} for features x[n*8]: 2^c for the
  * most probable class c (the first on ties), as batch and sweep calls with
  * use_mlp take them. */
@@ -417,6 +424,11 @@ int32_t fr_mlp_predict(fr_context *ctx, const float *x, int32_t n, int32_t *alph
  * (optional) = mean cross-entropy over all n samples after each epoch. */
 int32_t fr_mlp_train(fr_context *ctx, const float *x, const int32_t *labels, int32_t n,
                      int32_t epochs, int32_t batch, float lr, uint64_t seed, float *epoch_loss);
+/* fr_mlp_train on the mean expected cost of per-class costs[n*5] (see
+ * fr_mlp_loss_grad_cost); epoch_loss gets that loss. */
+int32_t fr_mlp_train_cost(fr_context *ctx, const float *x, const float *costs, int32_t n,
+                          int32_t epochs, int32_t batch, float lr, uint64_t seed,
+                          float *epoch_loss);
 /* Features feats[npairs*8] of block-disjoint pairs: log2(1+|boundary a|),
  * log2(1+|boundary b|), c(a)/W, c(b)/W, log2(1+pair cut), (L_max-c(a))/W,
  * (L_max-c(b))/W, log2(1 + U_a(1)/c(boundary a)); W = c(V)/k. */

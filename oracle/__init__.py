@@ -378,6 +378,32 @@ def mlp_forward(params: dict, x: np.ndarray):
     return p, (x, a1, h1, a2, h2, z)
 
 
+def _mlp_backward(params: dict, cache, dz):
+    x, a1, h1, a2, h2, z = cache
+    g = {"W3": h2.T @ dz, "b3": dz.sum(axis=0)}
+    dh2 = dz @ params["W3"].T
+    da2 = dh2 * (a2 > 0)
+    g["W2"] = h1.T @ da2
+    g["b2"] = da2.sum(axis=0)
+    dh1 = da2 @ params["W2"].T
+    da1 = dh1 * (a1 > 0)
+    g["W1"] = x.T @ da1
+    g["b1"] = da1.sum(axis=0)
+    return g
+
+
+def mlp_loss_grad_cost(params: dict, x: np.ndarray, costs: np.ndarray):
+    """Mean expected cost over the samples, sum_c p_c costs_c with the softmax
+    p, and its gradient: dL/dz_j = p_j (costs_j - sum_c p_c costs_c) / n."""
+    p, cache = mlp_forward(params, x)
+    costs = np.asarray(costs, dtype=np.float64)
+    nrows = p.shape[0]
+    pc = (p * costs).sum(axis=1, keepdims=True)
+    loss = float(pc.mean())
+    dz = p * (costs - pc) / nrows
+    return loss, _mlp_backward(params, cache, dz)
+
+
 def mlp_loss_grad(params: dict, x: np.ndarray, labels: np.ndarray):
     """Mean softmax cross-entropy and its gradient (hand-written backward)."""
     p, (x, a1, h1, a2, h2, z) = mlp_forward(params, x)

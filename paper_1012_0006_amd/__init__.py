@@ -65,7 +65,7 @@ EXPORTS = ("fr_create", "fr_destroy", "fr_strerror", "flow_refine_pair",
            "fr_set_validation", "fr_set_speculation", "fr_set_fused", "fr_set_timing",
            "fr_last_stats",
            "fr_mlp_num_params", "fr_mlp_init", "fr_mlp_set_weights", "fr_mlp_get_weights", "fr_mlp_forward", "fr_mlp_loss_grad",
-           "fr_mlp_train", "fr_pair_features", "fr_autotune", "fr_mlp_predict", "fr_eps_to_ppm")
+           "fr_mlp_train", "fr_mlp_loss_grad_cost", "fr_mlp_train_cost", "fr_pair_features", "fr_autotune", "fr_mlp_predict", "fr_eps_to_ppm")
 ALPHAS = (1, 2, 4, 8, 16)
 
 
@@ -134,6 +134,11 @@ def load(path: str = LIB_PATH):
     lib.fr_mlp_loss_grad.argtypes = [vp, vp, vp, i32, vp, vp]
     lib.fr_mlp_train.restype = i32
     lib.fr_mlp_train.argtypes = [vp, vp, vp, i32, i32, i32, ctypes.c_float, ctypes.c_uint64, vp]
+    lib.fr_mlp_loss_grad_cost.restype = i32
+    lib.fr_mlp_loss_grad_cost.argtypes = [vp, vp, vp, i32, vp, vp]
+    lib.fr_mlp_train_cost.restype = i32
+    lib.fr_mlp_train_cost.argtypes = [vp, vp, vp, i32, i32, i32, ctypes.c_float, ctypes.c_uint64,
+                                      vp]
     lib.fr_pair_features.restype = i32
     lib.fr_pair_features.argtypes = [vp, P(FrGraph), vp, i32, vp, i32, i32, vp]
     lib.fr_autotune.restype = i32
@@ -450,6 +455,29 @@ def fr_mlp_train(ctx: Context, x, labels, epochs: int, batch: int, lr: float, se
     losses = np.zeros(epochs, dtype=np.float32)
     _check(ctx.lib.fr_mlp_train(ctx.handle, x.ctypes.data, y.ctypes.data, x.shape[0], epochs,
                                 batch, lr, seed, losses.ctypes.data), "fr_mlp_train")
+    return losses
+
+
+def fr_mlp_loss_grad_cost(ctx: Context, x, costs):
+    """Mean expected cost sum_c p_c costs_c (costs [n, 5]) and its gradient."""
+    x = _f32(x).reshape(-1, 8)
+    cs = _f32(costs).reshape(-1, 5)
+    assert cs.shape[0] == x.shape[0]
+    loss = np.zeros(1, dtype=np.float32)
+    g = np.zeros(fr_mlp_num_params(), dtype=np.float32)
+    _check(ctx.lib.fr_mlp_loss_grad_cost(ctx.handle, x.ctypes.data, cs.ctypes.data, x.shape[0],
+                                         loss.ctypes.data, g.ctypes.data), "fr_mlp_loss_grad_cost")
+    return float(loss[0]), g
+
+
+def fr_mlp_train_cost(ctx: Context, x, costs, epochs: int, batch: int, lr: float, seed: int):
+    x = _f32(x).reshape(-1, 8)
+    cs = _f32(costs).reshape(-1, 5)
+    assert cs.shape[0] == x.shape[0]
+    losses = np.zeros(epochs, dtype=np.float32)
+    _check(ctx.lib.fr_mlp_train_cost(ctx.handle, x.ctypes.data, cs.ctypes.data, x.shape[0],
+                                     epochs, batch, lr, seed, losses.ctypes.data),
+           "fr_mlp_train_cost")
     return losses
 
 

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <numeric>
 #include <random>
@@ -1433,37 +1434,42 @@ extern "C" int32_t fr_mlp_init(fr_context *c, uint64_t seed) {
   return fr_mlp_set_weights(c, w.data(), MLP_NPARAMS);
 }
 
-// Scratch for n samples: x, labels, probs, activations (4*64), backward (5+2*64).
+// Scratch for n samples: x, labels or per-class costs, probs, activations
+// (4*64), backward (5+2*64).
 struct MlpScratch {
   float *x = nullptr, *probs = nullptr, *act = nullptr, *dact = nullptr, *loss = nullptr;
   int32_t *labels = nullptr, *idx = nullptr;
   float *xb = nullptr;
   int32_t *lb = nullptr;
+  float *costs = nullptr, *cb = nullptr;
   ~MlpScratch() {
     dfree(x); dfree(probs); dfree(act); dfree(dact); dfree(loss); dfree(labels); dfree(idx);
-    dfree(xb); dfree(lb);
+    dfree(xb); dfree(lb); dfree(costs); dfree(cb);
   }
 };
 
-static int32_t mlp_alloc(MlpScratch &s, int64_t n, int64_t batch) {
+static int32_t mlp_alloc(MlpScratch &s, int64_t n, int64_t batch, bool with_costs = false) {
   const int64_t m = std::max(n, batch);
   if (dalloc(&s.x, n * MLP_IN) || dalloc(&s.probs, m * MLP_OUT) || dalloc(&s.act, m * 4 * MLP_H) ||
       dalloc(&s.dact, m * (MLP_OUT + 2 * MLP_H)) || dalloc(&s.loss, 1) || dalloc(&s.labels, n) ||
       dalloc(&s.idx, std::max<int64_t>(batch, 1)) || dalloc(&s.xb, batch * MLP_IN) ||
       dalloc(&s.lb, std::max<int64_t>(batch, 1)))
     return FR_E_OOM;
+  if (with_costs && (dalloc(&s.costs, n * MLP_OUT) || dalloc(&s.cb, batch * MLP_OUT)))
+    return FR_E_OOM;
   return FR_OK;
 }
 
-static int32_t mlp_fwd_bwd(fr_context *c, const float *x, const int32_t *labels, int32_t n,
-                           MlpScratch &s, bool backward) {
+// labels, or per-class costs when costs is not null
+static int32_t mlp_fwd_bwd(fr_context *c, const float *x, const int32_t *labels,
+                           const float *costs, int32_t n, MlpScratch &s, bool backward) {
   hipStream_t st = c->cs;
   const int fb = (n + MLP_SAMPLES_PER_BLOCK - 1) / MLP_SAMPLES_PER_BLOCK;
   hipLaunchKernelGGL(k_mlp_forward, dim3(fb), dim3(1024), 0, st, (const float *)c->d.mlp, x, n,
                      s.probs, s.act);
   if (backward) {
     hipLaunchKernelGGL(k_mlp_backward, dim3(fb), dim3(1024), 0, st, (const float *)c->d.mlp,
-                       (const float *)s.probs, labels, n, (const float *)s.act, s.dact);
+                       (const float *)s.probs, labels, costs, n, (const float *)s.act, s.dact);
     hipLaunchKernelGGL(k_mlp_grad, dim3((MLP_NPARAMS + 255) / 256), dim3(256), 0, st, x,
                        (const float *)s.act, (const float *)s.dact, n, c->d.mlp_g);
   }
@@ -1478,7 +1484,7 @@ extern "C" int32_t fr_mlp_forward(fr_context *c, const float *x, int32_t n, floa
   int32_t rc = mlp_alloc(s, n, 1);
   if (rc) return rc;
   HIPCHK(hipMemcpyAsync(s.x, x, sizeof(float) * MLP_IN * n, hipMemcpyHostToDevice, c->cs));
-  if ((rc = mlp_fwd_bwd(c, s.x, nullptr, n, s, false))) return rc;
+  if ((rc = mlp_fwd_bwd(c, s.x, nullptr, nullptr, n, s, false))) return rc;
   HIPCHK(hipMemcpyAsync(probs, s.probs, sizeof(float) * MLP_OUT * n, hipMemcpyDeviceToHost, c->cs));
   HIPCHK(hipStreamSynchronize(c->cs));
   return FR_OK;
@@ -1491,7 +1497,7 @@ extern "C" int32_t fr_mlp_predict(fr_context *c, const float *x, int32_t n, int3
   int32_t rc = mlp_alloc(s, n, 1);
   if (rc) return rc;
   HIPCHK(hipMemcpyAsync(s.x, x, sizeof(float) * MLP_IN * n, hipMemcpyHostToDevice, c->cs));
-  if ((rc = mlp_fwd_bwd(c, s.x, nullptr, n, s, false))) return rc;
+  if ((rc = mlp_fwd_bwd(c, s.x, nullptr, nullptr, n, s, false))) return rc;
   // the start factor of each sample, as the batch and sweep calls take it
   hipLaunchKernelGGL(k_alpha_from_probs, dim3((n + 255) / 256), dim3(256), 0, c->cs,
                      (const float *)s.probs, n, s.labels);
@@ -1507,20 +1513,36 @@ extern "C" int32_t fr_eps_to_ppm(double eps, int32_t *ppm) {
   return FR_OK;
 }
 
-extern "C" int32_t fr_mlp_loss_grad(fr_context *c, const float *x, const int32_t *labels, int32_t n,
-                                    float *loss, float *grad) {
-  if (!c || !x || !labels || n < 1 || !c->mlp_loaded) return FR_E_INVALID_ARG;
+// checks of the training targets: labels in [0, 5), or finite costs
+static bool mlp_targets_ok(const int32_t *labels, const float *costs, int32_t n) {
+  if (costs) {
+    for (int64_t i = 0; i < (int64_t)n * MLP_OUT; i++)
+      if (!std::isfinite(costs[i])) return false;
+    return true;
+  }
+  if (!labels) return false;
   for (int32_t i = 0; i < n; i++)
-    if (labels[i] < 0 || labels[i] >= MLP_OUT) return FR_E_INVALID_ARG;
+    if (labels[i] < 0 || labels[i] >= MLP_OUT) return false;
+  return true;
+}
+
+static int32_t mlp_loss_grad(fr_context *c, const float *x, const int32_t *labels,
+                             const float *costs, int32_t n, float *loss, float *grad) {
+  if (!c || !x || n < 1 || !c->mlp_loaded || !mlp_targets_ok(labels, costs, n))
+    return FR_E_INVALID_ARG;
   HIPCHK(hipSetDevice(c->device));
   MlpScratch s;
-  int32_t rc = mlp_alloc(s, n, 1);
+  int32_t rc = mlp_alloc(s, n, 1, costs != nullptr);
   if (rc) return rc;
   HIPCHK(hipMemcpyAsync(s.x, x, sizeof(float) * MLP_IN * n, hipMemcpyHostToDevice, c->cs));
-  HIPCHK(hipMemcpyAsync(s.labels, labels, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->cs));
-  if ((rc = mlp_fwd_bwd(c, s.x, s.labels, n, s, true))) return rc;
+  if (costs)
+    HIPCHK(hipMemcpyAsync(s.costs, costs, sizeof(float) * MLP_OUT * n, hipMemcpyHostToDevice, c->cs));
+  else
+    HIPCHK(hipMemcpyAsync(s.labels, labels, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->cs));
+  const float *dc = costs ? s.costs : nullptr;
+  if ((rc = mlp_fwd_bwd(c, s.x, s.labels, dc, n, s, true))) return rc;
   hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(256), 0, c->cs, (const float *)s.probs,
-                     (const int32_t *)s.labels, n, s.loss);
+                     (const int32_t *)s.labels, dc, n, s.loss);
   if (loss) HIPCHK(hipMemcpyAsync(loss, s.loss, sizeof(float), hipMemcpyDeviceToHost, c->cs));
   if (grad)
     HIPCHK(hipMemcpyAsync(grad, c->d.mlp_g, sizeof(float) * MLP_NPARAMS, hipMemcpyDeviceToHost, c->cs));
@@ -1528,23 +1550,39 @@ extern "C" int32_t fr_mlp_loss_grad(fr_context *c, const float *x, const int32_t
   return FR_OK;
 }
 
-// Minibatch Adam on the device; epoch_loss (optional, [epochs]) gets the mean
-// cross-entropy over all samples after each epoch.
-extern "C" int32_t fr_mlp_train(fr_context *c, const float *x, const int32_t *labels, int32_t n,
-                                int32_t epochs, int32_t batch, float lr, uint64_t seed,
-                                float *epoch_loss) {
-  if (!c || !x || !labels || n < 1 || epochs < 1 || batch < 1 || !(lr > 0.f) || !c->mlp_loaded)
+extern "C" int32_t fr_mlp_loss_grad(fr_context *c, const float *x, const int32_t *labels, int32_t n,
+                                    float *loss, float *grad) {
+  if (!labels) return FR_E_INVALID_ARG;
+  return mlp_loss_grad(c, x, labels, nullptr, n, loss, grad);
+}
+
+extern "C" int32_t fr_mlp_loss_grad_cost(fr_context *c, const float *x, const float *costs,
+                                         int32_t n, float *loss, float *grad) {
+  if (!costs) return FR_E_INVALID_ARG;
+  return mlp_loss_grad(c, x, nullptr, costs, n, loss, grad);
+}
+
+// Minibatch Adam on the device; epoch_loss (optional, [epochs]) gets the loss
+// over all samples after each epoch (cross-entropy, or expected cost).
+static int32_t mlp_train(fr_context *c, const float *x, const int32_t *labels, const float *costs,
+                         int32_t n, int32_t epochs, int32_t batch, float lr, uint64_t seed,
+                         float *epoch_loss) {
+  if (!c || !x || n < 1 || epochs < 1 || batch < 1 || !(lr > 0.f) || !c->mlp_loaded ||
+      !mlp_targets_ok(labels, costs, n))
     return FR_E_INVALID_ARG;
-  for (int32_t i = 0; i < n; i++)
-    if (labels[i] < 0 || labels[i] >= MLP_OUT) return FR_E_INVALID_ARG;
   HIPCHK(hipSetDevice(c->device));
   hipStream_t st = c->cs;
   batch = std::min(batch, n);
   MlpScratch s;
-  int32_t rc = mlp_alloc(s, n, batch);
+  int32_t rc = mlp_alloc(s, n, batch, costs != nullptr);
   if (rc) return rc;
   HIPCHK(hipMemcpyAsync(s.x, x, sizeof(float) * MLP_IN * n, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(s.labels, labels, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+  if (costs)
+    HIPCHK(hipMemcpyAsync(s.costs, costs, sizeof(float) * MLP_OUT * n, hipMemcpyHostToDevice, st));
+  else
+    HIPCHK(hipMemcpyAsync(s.labels, labels, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+  const float *dc = costs ? s.costs : nullptr;
+  const float *dcb = costs ? s.cb : nullptr;
   std::vector<int32_t> perm((size_t)n);
   std::iota(perm.begin(), perm.end(), 0);
   std::mt19937_64 rng(seed);
@@ -1554,23 +1592,37 @@ extern "C" int32_t fr_mlp_train(fr_context *c, const float *x, const int32_t *la
     for (int32_t b0 = 0; b0 + batch <= n; b0 += batch) {
       HIPCHK(hipMemcpyAsync(s.idx, perm.data() + b0, sizeof(int32_t) * batch, hipMemcpyHostToDevice, st));
       hipLaunchKernelGGL(k_gather_rows, dim3((batch * MLP_IN + 255) / 256), dim3(256), 0, st,
-                         (const float *)s.x, (const int32_t *)s.labels, (const int32_t *)s.idx,
-                         batch, s.xb, s.lb);
-      if ((rc = mlp_fwd_bwd(c, s.xb, s.lb, batch, s, true))) return rc;
+                         (const float *)s.x, (const int32_t *)s.labels, dc, (const int32_t *)s.idx,
+                         batch, s.xb, s.lb, s.cb);
+      if ((rc = mlp_fwd_bwd(c, s.xb, s.lb, dcb, batch, s, true))) return rc;
       hipLaunchKernelGGL(k_adam, dim3((MLP_NPARAMS + 255) / 256), dim3(256), 0, st, c->d.mlp,
                          (const float *)c->d.mlp_g, c->d.mlp_m, c->d.mlp_v, lr, 0.9f, 0.999f, 1e-8f,
                          ++t);
       HIPCHK(hipStreamSynchronize(st));  // the host batch indices are reused
     }
     if (epoch_loss) {
-      if ((rc = mlp_fwd_bwd(c, s.x, s.labels, n, s, false))) return rc;
+      if ((rc = mlp_fwd_bwd(c, s.x, s.labels, dc, n, s, false))) return rc;
       hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(256), 0, st, (const float *)s.probs,
-                         (const int32_t *)s.labels, n, s.loss);
+                         (const int32_t *)s.labels, dc, n, s.loss);
       HIPCHK(hipMemcpyAsync(&epoch_loss[ep], s.loss, sizeof(float), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
     }
   }
   return FR_OK;
+}
+
+extern "C" int32_t fr_mlp_train(fr_context *c, const float *x, const int32_t *labels, int32_t n,
+                                int32_t epochs, int32_t batch, float lr, uint64_t seed,
+                                float *epoch_loss) {
+  if (!labels) return FR_E_INVALID_ARG;
+  return mlp_train(c, x, labels, nullptr, n, epochs, batch, lr, seed, epoch_loss);
+}
+
+extern "C" int32_t fr_mlp_train_cost(fr_context *c, const float *x, const float *costs, int32_t n,
+                                     int32_t epochs, int32_t batch, float lr, uint64_t seed,
+                                     float *epoch_loss) {
+  if (!costs) return FR_E_INVALID_ARG;
+  return mlp_train(c, x, nullptr, costs, n, epochs, batch, lr, seed, epoch_loss);
 }
 
 // The 8 input features of each pair (host [npairs * 8]).

@@ -139,12 +139,14 @@ __global__ void __launch_bounds__(1024) k_mlp_forward(const float *prm, const fl
   }
 }
 
-// Backward through the activations of each sample for the mean softmax
-// cross-entropy: dz = (p - onehot) / n, da2 = (dz W3^T) * [a2 > 0],
-// da1 = (da2 W2^T) * [a1 > 0].  dact = dz [n][5], da2 [n][64], da1 [n][64].
+// Backward through the activations of each sample, for the mean softmax
+// cross-entropy (labels): dz = (p - onehot) / n; or, with per-class costs
+// [n][5], for the mean expected cost sum_c p_c cost_c: dz_j = p_j (cost_j -
+// sum_c p_c cost_c) / n.  Then da2 = (dz W3^T) * [a2 > 0], da1 = (da2 W2^T) *
+// [a1 > 0].  dact = dz [n][5], da2 [n][64], da1 [n][64].
 __global__ void __launch_bounds__(1024) k_mlp_backward(const float *prm, const float *probs,
-                                                       const int32_t *labels, int32_t n,
-                                                       const float *act, float *dact) {
+                                                       const int32_t *labels, const float *costs,
+                                                       int32_t n, const float *act, float *dact) {
   __shared__ float s_dz[MLP_SAMPLES_PER_BLOCK][MLP_OUT];
   __shared__ float s_da2[MLP_SAMPLES_PER_BLOCK][MLP_H];
   const int ls = threadIdx.x / MLP_H, j = threadIdx.x % MLP_H;
@@ -153,7 +155,14 @@ __global__ void __launch_bounds__(1024) k_mlp_backward(const float *prm, const f
   const int64_t stride = (int64_t)n * MLP_H;
   if (j < MLP_OUT) {
     float dz = 0.f;
-    if (ok) dz = (probs[(int64_t)s * MLP_OUT + j] - (labels[s] == j ? 1.f : 0.f)) / (float)n;
+    if (ok && costs) {
+      const float *pr = probs + (int64_t)s * MLP_OUT, *cs = costs + (int64_t)s * MLP_OUT;
+      float pc = 0.f;
+      for (int c = 0; c < MLP_OUT; c++) pc = fmaf(pr[c], cs[c], pc);
+      dz = pr[j] * (cs[j] - pc) / (float)n;
+    } else if (ok) {
+      dz = (probs[(int64_t)s * MLP_OUT + j] - (labels[s] == j ? 1.f : 0.f)) / (float)n;
+    }
     s_dz[ls][j] = dz;
     if (ok) dact[(int64_t)s * MLP_OUT + j] = dz;
   }
@@ -208,14 +217,20 @@ __global__ void __launch_bounds__(256) k_mlp_grad(const float *x, const float *a
   grad[t] = g;
 }
 
-// mean cross-entropy of n samples (one block)
+// mean cross-entropy of n samples (labels), or their mean expected cost
+// (costs [n][5]); one block
 __global__ void __launch_bounds__(256) k_mlp_loss(const float *probs, const int32_t *labels,
-                                                  int32_t n, float *loss) {
+                                                  const float *costs, int32_t n, float *loss) {
   __shared__ double s_red[256];
   double acc = 0.0;
   for (int s = threadIdx.x; s < n; s += blockDim.x) {
-    const float p = probs[(int64_t)s * MLP_OUT + labels[s]];
-    acc -= log((double)fmaxf(p, 1e-30f));
+    if (costs) {
+      for (int c = 0; c < MLP_OUT; c++)
+        acc += (double)probs[(int64_t)s * MLP_OUT + c] * (double)costs[(int64_t)s * MLP_OUT + c];
+    } else {
+      const float p = probs[(int64_t)s * MLP_OUT + labels[s]];
+      acc -= log((double)fmaxf(p, 1e-30f));
+    }
   }
   s_red[threadIdx.x] = acc;
   __syncthreads();
@@ -241,15 +256,21 @@ __global__ void __launch_bounds__(256) k_adam(float *prm, const float *grad, flo
   prm[i] -= lr * mh / (sqrtf(vh) + eps);
 }
 
-// rows idx[0..m) of (x, labels) into (xb, lb)
+// rows idx[0..m) of (x, labels or costs) into (xb, lb or cb)
+static_assert(MLP_IN >= MLP_OUT, "a row's costs are gathered by its feature lanes");
 __global__ void __launch_bounds__(256) k_gather_rows(const float *x, const int32_t *labels,
-                                                     const int32_t *idx, int32_t m, float *xb,
-                                                     int32_t *lb) {
+                                                     const float *costs, const int32_t *idx,
+                                                     int32_t m, float *xb, int32_t *lb,
+                                                     float *cb) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= m * MLP_IN) return;
   const int r = t / MLP_IN, c = t % MLP_IN;
   xb[t] = x[(int64_t)idx[r] * MLP_IN + c];
-  if (c == 0) lb[r] = labels[idx[r]];
+  if (costs) {
+    if (c < MLP_OUT) cb[r * MLP_OUT + c] = costs[(int64_t)idx[r] * MLP_OUT + c];
+  } else if (c == 0) {
+    lb[r] = labels[idx[r]];
+  }
 }
 
 // start factor of each pair from the predicted class (first maximum, i.e.

@@ -9,7 +9,12 @@ adaptive search is run from each start factor in {1, 2, 4, 8, 16} (alpha_max
 final pair cut of the five.  The partition then moves on with the result of
 the plain search from 16 before the next class.  The features are the
 library's 8 pair features, taken before the class is refined.  Training runs
-on the device (fr_mlp_train: Adam, softmax cross-entropy).
+on the device (Adam): by default on the expected cost of each start
+(fr_mlp_train_cost), the start's corridor edges over the mean corridor edges
+of the plain search plus lambda times its final pair cut above the pair's
+best; or on the labels (fr_mlp_train, softmax cross-entropy).  Per-class
+logit offsets then keep the summed final cut of the training pairs within
+0.01 % of the constant start at alpha' = 8's.
 
     python -m paper_1012_0006_amd.train_mlp --graphs 200 --out weights.json
 """
@@ -66,9 +71,10 @@ def label_graph(fr, ctx, torch, gen, seed, n, k, eps_ppm, alpha_max=16):
     return feats, labels, finals, works
 
 
-def one_sweep(fr, ctx, torch, gen, seed, n, k, use_mlp):
-    """One pass over the colour classes from the seeded start partition:
-    flow solves, corridor edges and the final total cut."""
+def one_sweep(fr, ctx, torch, gen, seed, n, k, use_mlp, alpha=16):
+    """One pass over the colour classes from the seeded start partition
+    (start factor alpha, or the learned one): flow solves, corridor edges and
+    the final total cut."""
     g = gen.rgg(n, 2, 8.0, seed=seed, wlo=1, whi=10)
     part = gen.rcb(g, k)
     gen.global_noise(g, part, 0.02, seed)
@@ -76,7 +82,7 @@ def one_sweep(fr, ctx, torch, gen, seed, n, k, use_mlp):
     cur = torch.as_tensor(part).cuda()
     edges, colour = fr.fr_quotient_matchings(ctx, dg, cur, k)
     solves = region = 0
-    prm = fr.params(alpha=16, alpha_max=16, adaptive=1, max_iters=16, eps_ppm=30000,
+    prm = fr.params(alpha=alpha, alpha_max=16, adaptive=1, max_iters=16, eps_ppm=30000,
                     use_mlp=use_mlp)
     for c in sorted(set(colour.tolist())):
         pairs = [tuple(e) for e, cc in zip(edges.tolist(), colour.tolist()) if cc == c]
@@ -103,30 +109,44 @@ def fold_normalisation(w, mu, sd):
     return w.astype(np.float32)
 
 
-def choose_offsets(logp, final, work, tol):
-    """Per-class logit offsets (a shift of the class priors toward larger
-    factors) that minimise the corridor edges of the predicted starts while
-    the summed final pair cut stays within (1 + tol) of the plain search from
-    the largest factor.  First the smallest linear shift beta * class that
-    meets the bound, then a coordinate refinement of each class offset."""
+def choose_offsets(logp, final, work, tol, ref_class=None):
+    """Per-class logit offsets that minimise the corridor edges of the
+    predicted starts while the summed final pair cut stays within (1 + tol)
+    of a reference: the plain search from the largest factor, or (ref_class)
+    the constant start at that class's factor.  From zero offsets, greedy
+    moves of one class offset buy the largest cut decrease per corridor edge
+    added until the bound holds; then a coordinate refinement of each class
+    offset keeps any move that lowers the edges within the bound."""
     idx = np.arange(len(logp))
     ncls = logp.shape[1]
     plain_cut = final[:, -1].sum()
-    bound = (1 + tol) * plain_cut
+    ref_cut = plain_cut if ref_class is None else final[:, ref_class].sum()
+    bound = (1 + tol) * ref_cut
 
     def cost(c):
         pick = np.argmax(logp + c, axis=1)
         return work[idx, pick].sum(), final[idx, pick].sum()
 
-    best = np.arange(ncls) * 50.0  # every pair at the largest factor: the plain search
+    best = np.zeros(ncls)
     bw, bc = cost(best)
-    for beta in np.arange(0.0, 8.0, 0.05):
-        c = beta * np.arange(ncls)
-        wv, cv = cost(c)
-        if cv <= bound:
-            if wv < bw:
-                best, bw, bc = c, wv, cv
+    steps = (0.02, 0.05, 0.1, 0.2, 0.5, 1.0, 2.0, 5.0)
+    while bc > bound:
+        move = None
+        for j in range(ncls):
+            for st in steps:
+                for sgn in (1.0, -1.0):
+                    c = best.copy()
+                    c[j] += sgn * st
+                    wv, cv = cost(c)
+                    if cv < bc:
+                        gain = (bc - cv) / max(1.0, float(wv - bw))
+                        if move is None or gain > move[0]:
+                            move = (gain, c, wv, cv)
+        if move is None:
+            best = np.arange(ncls) * 50.0  # every pair at the largest factor
+            bw, bc = cost(best)
             break
+        _, best, bw, bc = move
     grid = np.arange(-1.0, 1.01, 0.1)
     for _ in range(3):
         for j in range(1, ncls):
@@ -149,9 +169,17 @@ def main():
     ap.add_argument("--epochs", type=int, default=80)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--cut-tolerance", type=float, default=0.0025)
+    ap.add_argument("--cut-tolerance", type=float, default=0.0001)
+    ap.add_argument("--cut-reference", type=int, default=8,
+                    help="start factor whose constant-start cut bounds the learned start's "
+                         "(0: the plain search from 16 with --cut-tolerance)")
+    ap.add_argument("--loss", choices=("cost", "label"), default="cost")
+    ap.add_argument("--cost-lambda", type=float, default=0.4,
+                    help="weight of one unit of final pair cut above the pair's best start, "
+                         "against corridor edges in units of the plain search's mean")
     ap.add_argument("--out", default=WEIGHTS)
     ap.add_argument("--dump", default=None, help="also save the labelled samples (.npz)")
+    ap.add_argument("--load", default=None, help="labelled samples saved by --dump (no labelling)")
     args = ap.parse_args()
 
     import torch
@@ -163,7 +191,10 @@ def main():
     ctx.set_validation(False)
     t0 = time.time()
     X, Y, G, F, E = [], [], [], [], []
-    for gi in range(args.graphs):
+    if args.load:
+        with np.load(args.load) as z:
+            X, Y, G, F, E = (z[key] for key in ("X", "Y", "G", "F", "E"))
+    for gi in range(0 if args.load else args.graphs):
         f, y, fin, wk = label_graph(fr, ctx, torch, gen, args.first_seed + gi, args.n, args.k,
                                     30000)
         X += f
@@ -186,7 +217,13 @@ def main():
     sd = X[~val].std(0) + 1e-6
     Xn = ((X - mu) / sd).astype(np.float32)
     fr.fr_mlp_init(ctx, 2024)
-    losses = fr.fr_mlp_train(ctx, Xn[~val], Y[~val], args.epochs, args.batch, args.lr, seed=7)
+    if args.loss == "cost":
+        e_mean = E[~val][:, -1].mean()
+        C = (E / e_mean + args.cost_lambda * (F - F.min(1, keepdims=True))).astype(np.float32)
+        losses = fr.fr_mlp_train_cost(ctx, Xn[~val], C[~val], args.epochs, args.batch, args.lr,
+                                      seed=7)
+    else:
+        losses = fr.fr_mlp_train(ctx, Xn[~val], Y[~val], args.epochs, args.batch, args.lr, seed=7)
     w = fold_normalisation(fr.fr_mlp_get_weights(ctx), mu, sd)
     fr.fr_mlp_set_weights(ctx, w)
     Xf = X.astype(np.float32)
@@ -195,26 +232,37 @@ def main():
     acc_va = float(np.mean(np.argmax(probs[val], 1) == Y[val])) if val.any() else None
     logp = np.log(np.maximum(probs.astype(np.float64), 1e-30))
     # decision offsets are chosen on the training graphs and checked on the held-out ones
+    ref = fr.ALPHAS.index(args.cut_reference) if args.cut_reference else None
     c, w_tr, cut_tr, plain_cut_tr, plain_w_tr = choose_offsets(logp[~val], F[~val], E[~val],
-                                                               args.cut_tolerance)
+                                                               args.cut_tolerance, ref)
+    raw = np.argmax(logp, 1)
+    iv_all = np.arange(len(Y))
+    raw_stats = {name: {"edges": int(E[m][iv_all[:int(m.sum())], raw[m]].sum()),
+                        "cut": int(F[m][iv_all[:int(m.sum())], raw[m]].sum())}
+                 for name, m in (("train", ~val), ("validation", val))}
     w[OFF_B3:OFF_B3 + 5] += c.astype(np.float32)
     fr.fr_mlp_set_weights(ctx, w)
     pick = np.argmax(fr.fr_mlp_forward(ctx, Xf[val]), 1)
     iv = np.arange(int(val.sum()))
     hist = np.bincount(Y, minlength=5).tolist()
-    ev = {0: [0, 0, 0], 1: [0, 0, 0]}
+    # held-out sweeps: the plain search, constant starts 8 and 4, the learned start
+    runs = {"plain": (0, 16), "constant_8": (0, 8), "constant_4": (0, 4), "learned": (1, 16)}
+    ev = {name: [0, 0, 0] for name in runs}
     for gi in range(int(round(0.9 * args.graphs)), args.graphs):
-        for use in (0, 1):
-            r = one_sweep(fr, ctx, torch, gen, args.first_seed + gi, args.n, args.k, use)
-            ev[use] = [x + y for x, y in zip(ev[use], r)]
+        for name, (use, al) in runs.items():
+            r = one_sweep(fr, ctx, torch, gen, args.first_seed + gi, args.n, args.k, use, al)
+            ev[name] = [x + y for x, y in zip(ev[name], r)]
     report = {
         "graphs": args.graphs, "first_seed": args.first_seed, "n": args.n, "k": args.k,
         "samples": int(len(Y)), "label_histogram_alpha_1_2_4_8_16": hist,
         "majority_class_accuracy": float(max(hist) / max(1, len(Y))),
         "train_accuracy": acc_tr, "validation_accuracy": acc_va,
+        "loss": args.loss, "cost_lambda": args.cost_lambda if args.loss == "cost" else None,
         "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
         "loss_first_epoch": float(losses[0]), "loss_last_epoch": float(losses[-1]),
+        "no_offsets": raw_stats,
         "class_offsets": [float(v) for v in c], "cut_tolerance": args.cut_tolerance,
+        "cut_reference": args.cut_reference,
         "train_pairs": {"plain_edges": plain_w_tr, "learned_edges": w_tr,
                         "plain_cut": plain_cut_tr, "learned_cut": cut_tr},
         "validation_pairs": {"plain_edges": int(E[val][:, -1].sum()),
@@ -224,8 +272,8 @@ def main():
                              "best_cut": int(F[val].min(1).sum()),
                              "constant_start_edges": [int(v) for v in E[val].sum(0)],
                              "constant_start_cut": [int(v) for v in F[val].sum(0)]},
-        "validation_sweep_plain": dict(zip(("solves", "region_edges", "cut"), ev[0])),
-        "validation_sweep_learned": dict(zip(("solves", "region_edges", "cut"), ev[1])),
+        "validation_sweeps": {name: dict(zip(("solves", "region_edges", "cut"), v))
+                              for name, v in ev.items()},
         "seconds": time.time() - t0,
     }
     with open(args.out, "w") as fh:

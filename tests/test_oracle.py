@@ -452,6 +452,59 @@ def test_mlp_reference_matches_torch_autograd():
         assert np.allclose(T[k].grad.numpy(), grads[k], rtol=1e-10, atol=1e-12)
 
 
+def test_mlp_cost_reference_matches_torch_autograd():
+    """The expected-cost loss mean_i sum_c p_ic cost_ic and its hand-written
+    gradient against torch autograd on the same network."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(13)
+    P = _mlp_params(rng)
+    x = rng.normal(0, 1, (29, 8))
+    costs = rng.uniform(-1, 3, (29, 5))
+    loss, grads = oracle.mlp_loss_grad_cost(P, x, costs)
+    T = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in P.items()}
+    xt = torch.tensor(x)
+    h = torch.relu(xt @ T["W1"] + T["b1"])
+    h = torch.relu(h @ T["W2"] + T["b2"])
+    z = h @ T["W3"] + T["b3"]
+    lt = (torch.softmax(z, 1) * torch.tensor(costs)).sum(1).mean()
+    lt.backward()
+    assert abs(lt.item() - loss) < 1e-12
+    for k in P:
+        assert np.allclose(T[k].grad.numpy(), grads[k], rtol=1e-10, atol=1e-12)
+
+
+def test_mlp_cost_reference_invariants():
+    """Costs equal across the classes of a sample leave nothing to learn (loss
+    = their mean, gradient 0); adding a constant to a sample's costs moves
+    the loss by its mean share and leaves the gradient unchanged; central
+    differences agree with the gradient."""
+    rng = np.random.default_rng(14)
+    P = _mlp_params(rng)
+    x = rng.normal(0, 1, (11, 8))
+    flat = np.repeat(rng.uniform(0, 2, (11, 1)), 5, axis=1)
+    loss, grads = oracle.mlp_loss_grad_cost(P, x, flat)
+    assert abs(loss - flat[:, 0].mean()) < 1e-12
+    assert all(np.abs(g).max() < 1e-12 for g in grads.values())
+    costs = rng.uniform(0, 1, (11, 5))
+    shift = rng.uniform(-2, 2, (11, 1))
+    l0, g0 = oracle.mlp_loss_grad_cost(P, x, costs)
+    l1, g1 = oracle.mlp_loss_grad_cost(P, x, costs + shift)
+    assert abs((l1 - l0) - shift.mean()) < 1e-12
+    for k in P:
+        assert np.allclose(g0[k], g1[k], rtol=1e-9, atol=1e-12)
+    h = 1e-6
+    for k in P:
+        fl = P[k].reshape(-1)
+        for idx in itertools.islice(rng.permutation(fl.size), 4):
+            old = fl[idx]
+            fl[idx] = old + h
+            lp, _ = oracle.mlp_loss_grad_cost(P, x, costs)
+            fl[idx] = old - h
+            lm, _ = oracle.mlp_loss_grad_cost(P, x, costs)
+            fl[idx] = old
+            assert abs((lp - lm) / (2 * h) - g0[k].reshape(-1)[idx]) < 1e-6
+
+
 def test_mlp_reference_finite_differences():
     rng = np.random.default_rng(4)
     P = _mlp_params(rng)
