@@ -354,8 +354,13 @@ int32_t fr_set_speculation(fr_context *ctx, int32_t on);
  * network passes spread over the whole chip instead of one workgroup. */
 int32_t fr_set_fused(fr_context *ctx, int32_t on);
 
-/* Input checks of every call (CSR shape, ranges, symmetry: O(sum deg^2)) on
- * (1, the default) or off (0; malformed input then gives undefined results). */
+/* Input checks of every call on (1, the default) or off (0; malformed input
+ * then gives undefined results): CSR shape, ids and weights in range, no self
+ * loop or repeated neighbour, symmetry with equal weights.  Vertices of more
+ * than 16 arcs are checked through hash tables of their neighbours (device
+ * memory grown on demand), so the work is O(m) expected; the entry point
+ * that allocates nothing scans their lists instead (O(sum of deg^2) over
+ * those vertices). */
 int32_t fr_set_validation(fr_context *ctx, int32_t on);
 
 /* Per-phase timing of sweeps on (1) or off (0, the default).  On: the rounds

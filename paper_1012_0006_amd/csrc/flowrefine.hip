@@ -45,6 +45,10 @@ struct DevBufs {
   int8_t *side = nullptr;
   int32_t *mbq = nullptr;  // most balanced cut: quotient arcs, one per arc slot (lazy)
   int64_t mbqcap = 0;
+  // input checks: hub table offsets [n], table keys and weights
+  int64_t *vhdir = nullptr;
+  int32_t *vkey = nullptr, *vw = nullptr;
+  int64_t vhcap = 0, vtcap = 0;
   int32_t *mbc = nullptr;  // most balanced cut: large component graphs, 4 per vertex slot (lazy)
   int64_t mbccap = 0;
   int32_t *fmg = nullptr, *fmq = nullptr;  // 2-way FM: per-vertex gains, queue positions (lazy)
@@ -355,7 +359,7 @@ extern "C" int32_t fr_destroy(fr_context *c) {
   if (c->cs) (void)hipStreamSynchronize(c->cs);
   free_vertex_arc(c->d);
   DevBufs &d = c->d;
-  void *ptrs[] = {d.mtw,      d.mtchg,
+  void *ptrs[] = {d.mtw,      d.mtchg, d.vhdir, d.vkey, d.vw,
                   d.blk2pair, d.bstat, d.qadj, d.ps,    d.pairs, d.alpha0, d.order,
                   d.trace,    d.ucnt,  d.voff, d.aoff,  d.fstat, d.feats,  d.probs,
                   d.base,     d.scal,  d.ctl,  d.mlp,   d.mlp_m, d.mlp_v,  d.mlp_g,
@@ -577,15 +581,75 @@ static KArgs call_args(fr_context *c, const DevBufs &d, const fr_graph *g, int32
 // Per-call constants: input checks, c(V), max c(v), L_max and the area
 // bases floor((1 + alpha eps) c(V) / k) for alpha = 0..alpha_max (exact, in
 // 128-bit arithmetic on the host).  One host synchronisation.
-static int32_t call_constants(fr_context *c, KArgs &A, int64_t narcs, const fr_params *p) {
+// Sets n int32 words to v on the stream (a kernel, not a memset node, so the
+// work stays correct inside captured graphs).
+__global__ void __launch_bounds__(256) k_fill32(int32_t *x, int64_t n, int32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+// Input checks (k_validate).  With may_alloc, vertices of more than
+// FR_VAL_HUB arcs get hash tables of their neighbours first (device buffers
+// grown on demand); without it (the entry point that allocates nothing)
+// their lists are scanned instead.
+static int32_t validate_graph(fr_context *c, const KArgs &A, int64_t narcs, bool may_alloc) {
+  DevBufs &d = c->d;
+  hipStream_t st = c->cs;
+  const int sblocks = std::min(4 * c->num_cus, 8192);
+  const int64_t *hdir = nullptr;
+  const int32_t *tkey = nullptr, *tw = nullptr;
+  if (may_alloc) {
+    unsigned long long *ctr = (unsigned long long *)(d.scal + 2);
+    HIPCHK(hipMemsetAsync(ctr, 0, 2 * sizeof(unsigned long long), st));
+    hipLaunchKernelGGL(k_val_hub_size, dim3(sblocks), dim3(256), 0, st, A, narcs, ctr);
+    HIPCHK(hipGetLastError());
+    int64_t slots = 0;
+    HIPCHK(hipMemcpyAsync(&slots, ctr, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (slots > 0) {
+      if (d.vhcap < A.n) {
+        dfree(d.vhdir);
+        d.vhdir = nullptr;
+        d.vhcap = 0;
+        if (dalloc(&d.vhdir, A.n) != hipSuccess) return FR_E_OOM;
+        d.vhcap = A.n;
+      }
+      if (d.vtcap < slots) {
+        dfree(d.vkey);
+        dfree(d.vw);
+        d.vkey = d.vw = nullptr;
+        d.vtcap = 0;
+        if (dalloc(&d.vkey, slots) != hipSuccess || dalloc(&d.vw, slots) != hipSuccess)
+          return FR_E_OOM;
+        d.vtcap = slots;
+      }
+      hipLaunchKernelGGL(k_fill32, dim3(std::min<int64_t>((slots + 255) / 256, 4 * c->num_cus)),
+                         dim3(256), 0, st, d.vkey, slots, -1);
+      hipLaunchKernelGGL(k_val_hub_alloc, dim3(sblocks), dim3(256), 0, st, A, narcs, d.vhdir, ctr);
+      hipLaunchKernelGGL(k_val_hub_insert, dim3(sblocks), dim3(256), 0, st, A,
+                         (const int64_t *)d.vhdir, d.vkey, d.vw);
+      HIPCHK(hipGetLastError());
+      hdir = d.vhdir;
+      tkey = d.vkey;
+      tw = d.vw;
+    }
+  }
+  hipLaunchKernelGGL(k_validate, dim3(sblocks), dim3(256), 0, st, A, narcs, hdir, tkey, tw);
+  HIPCHK(hipGetLastError());
+  return FR_OK;
+}
+
+static int32_t call_constants(fr_context *c, KArgs &A, int64_t narcs, const fr_params *p,
+                              bool may_alloc = true) {
   DevBufs &d = c->d;
   hipStream_t st = c->cs;
   memset(c->h_ctl, 0, sizeof(Ctl));
   HIPCHK(hipMemcpyAsync(d.ctl, c->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
   const int sblocks = std::min(4 * c->num_cus, 8192);
   if (c->validate) {
-    hipLaunchKernelGGL(k_validate, dim3(sblocks), dim3(256), 0, st, A, narcs);
-    HIPCHK(hipGetLastError());
+    int32_t rc = validate_graph(c, A, narcs, may_alloc);
+    if (rc) return rc;
   }
   hipLaunchKernelGGL(k_graph_stats, dim3(sblocks), dim3(256), 0, st, A);
   HIPCHK(hipGetLastError());
@@ -972,13 +1036,6 @@ struct HostBuf {
   T &operator[](size_t i) { return p[i]; }
 };
 
-// Clears n int32 words on the stream (a kernel, not a memset node, so the
-// work stays correct inside captured graphs).
-__global__ void __launch_bounds__(256) k_fill32(int32_t *x, int64_t n, int32_t v) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    x[i] = v;
-}
 
 // One batched round of disjoint pairs.  carve = nullptr: the context's
 // buffers, grown on demand.  Otherwise the graph must be on the device, the
@@ -1016,7 +1073,7 @@ static int32_t refine(fr_context *c, const fr_graph *g, int32_t *part, int32_t k
   KArgs A = call_args(c, d, &s.g, d.partw, k, p);
   A.W = W;
   A.mstride = W > 1 ? n : 0;
-  if ((rc = call_constants(c, A, s.narcs, p))) return rc;
+  if ((rc = call_constants(c, A, s.narcs, p, carve == nullptr))) return rc;
   HostBuf<int32_t, 8> a0, vp;
   a0.resize((size_t)V);
   vp.resize((size_t)2 * V);

@@ -383,9 +383,92 @@ __global__ void __launch_bounds__(1024) k_arena(KArgs A) {
   }
 }
 
-// CSR checks: offsets monotone, ids in range, no self loop, no repeated
-// neighbour, weights in [1, 2^30), symmetric with equal weights.
-__global__ void __launch_bounds__(256) k_validate(KArgs A, int64_t narcs) {
+// ---- input checks (every call unless switched off): offsets monotone, ids
+//      in range, no self loop, no repeated neighbour, weights in [1, 2^30),
+//      symmetric with equal weights.  A vertex with at most FR_VAL_HUB arcs is
+//      checked by scanning its own list and its neighbours' lists.  A vertex
+//      with more arcs ("hub") gets an open-addressing hash table of its
+//      neighbours (key, weight): inserting finds its repeated neighbours, and
+//      the reverse-arc check of every arc into it probes the table.  Work is
+//      O(m FR_VAL_HUB) plus O(1) expected per hub arc, instead of O(sum deg^2).
+#define FR_VAL_HUB 16
+
+// table slots of a hub: a power of two at least twice its degree
+__device__ __forceinline__ int64_t hub_slots(int64_t deg) {
+  int64_t t = 64;
+  while (t < 2 * deg) t <<= 1;
+  return t;
+}
+
+__device__ __forceinline__ uint32_t hub_hash(int32_t key) {
+  return (uint32_t)key * 2654435761u;  // Knuth's multiplicative hash
+}
+
+// degree of u when its offsets are well formed, else -1 (reported by k_validate)
+__device__ __forceinline__ int64_t checked_degree(const KArgs &A, int64_t u, int64_t narcs) {
+  const int32_t b = A.xadj[u], e = A.xadj[u + 1];
+  if (b < 0 || e < b || e > narcs) return -1;
+  return (int64_t)e - b;
+}
+
+// pass 1: table slots of all hubs (ctr[0] += slots)
+__global__ void __launch_bounds__(256) k_val_hub_size(KArgs A, int64_t narcs,
+                                                      unsigned long long *ctr) {
+  unsigned long long acc = 0;
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < A.n;
+       u += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t deg = checked_degree(A, u, narcs);
+    if (deg > FR_VAL_HUB) acc += (unsigned long long)hub_slots(deg);
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if (lane64() == 0 && acc) atomicAdd(ctr, acc);
+}
+
+// pass 2: each hub's table offset (hdir, -1 for the other vertices), slots
+// handed out by ctr[1]
+__global__ void __launch_bounds__(256) k_val_hub_alloc(KArgs A, int64_t narcs, int64_t *hdir,
+                                                       unsigned long long *ctr) {
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < A.n;
+       u += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t deg = checked_degree(A, u, narcs);
+    hdir[u] = deg > FR_VAL_HUB ? (int64_t)atomicAdd(ctr + 1, (unsigned long long)hub_slots(deg))
+                               : -1;
+  }
+}
+
+// pass 3: one wave per hub inserts its arcs (keys start at -1 = empty)
+__global__ void __launch_bounds__(256) k_val_hub_insert(KArgs A, const int64_t *hdir,
+                                                        int32_t *tkey, int32_t *tw) {
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t u = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); u < A.n;
+       u += nw) {
+    const int64_t off = hdir[u];
+    if (off < 0) continue;
+    const int32_t b = A.xadj[u], e = A.xadj[u + 1];
+    const int64_t mask = hub_slots((int64_t)e - b) - 1;
+    for (int32_t j = b + lane64(); j < e; j += 64) {
+      const int32_t v = A.adjncy[j];
+      if (v < 0) continue;  // out of range: reported by k_validate
+      const int64_t h = (int64_t)(hub_hash(v) & (uint32_t)mask);
+      for (int64_t q = 0; q <= mask; q++) {
+        const int64_t slot = off + ((h + q) & mask);
+        const int32_t old = atomicCAS(&tkey[slot], -1, v);
+        if (old == -1) {
+          tw[slot] = A.adjwgt[j];
+          break;
+        }
+        if (old == v) {  // repeated neighbour
+          atomicOr(&A.ctl->bad_graph, 1);
+          break;
+        }
+      }
+    }
+  }
+}
+
+// The per-arc checks; hdir null: no hub tables (every list scanned).
+__global__ void __launch_bounds__(256) k_validate(KArgs A, int64_t narcs, const int64_t *hdir,
+                                                  const int32_t *tkey, const int32_t *tw) {
   for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < A.n;
        u += (int64_t)gridDim.x * blockDim.x) {
     const int32_t b = A.xadj[u], e = A.xadj[u + 1];
@@ -393,12 +476,29 @@ __global__ void __launch_bounds__(256) k_validate(KArgs A, int64_t narcs) {
       atomicOr(&A.ctl->bad_graph, 1);
       continue;
     }
+    const bool hub_u = hdir && hdir[u] >= 0;  // its repeats were checked on insertion
     for (int32_t j = b; j < e; j++) {
       const int32_t v = A.adjncy[j], w = A.adjwgt[j];
       bool ok = v >= 0 && v < A.n && v != (int32_t)u && w >= 1 && w < (1 << 30);
-      for (int32_t q = b; ok && q < j; q++)
+      for (int32_t q = b; ok && !hub_u && q < j; q++)
         if (A.adjncy[q] == v) ok = false;
-      if (ok) {
+      if (ok && hdir && hdir[v] >= 0) {
+        // the reverse arc in v's table
+        const int64_t off = hdir[v];
+        const int64_t mask = hub_slots((int64_t)A.xadj[v + 1] - A.xadj[v]) - 1;
+        const int64_t h = (int64_t)(hub_hash((int32_t)u) & (uint32_t)mask);
+        bool found = false;
+        for (int64_t q = 0; q <= mask; q++) {
+          const int64_t slot = off + ((h + q) & mask);
+          const int32_t key = tkey[slot];
+          if (key == (int32_t)u) {
+            found = tw[slot] == w;
+            break;
+          }
+          if (key == -1) break;
+        }
+        ok = found;
+      } else if (ok) {
         bool found = false;
         const int32_t vb = A.xadj[v], ve = A.xadj[v + 1];
         for (int32_t q = vb; q < ve && q < narcs && q >= 0; q++)
