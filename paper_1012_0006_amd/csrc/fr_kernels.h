@@ -869,6 +869,24 @@ __device__ __forceinline__ void for_groups(int32_t N, F &&f) {
   }
 }
 
+// Lanes per item of a corridor BFS level: GTF while the level fits one pass
+// of the workgroup, else 2, else 1 -- every extra pass would pay the level's
+// chain of dependent loads again; each item keeps 8 arcs in flight at any
+// width.  f(Lanes<G>) runs the level; results do not depend on G.  (The flow
+// phases' searches keep GTF lanes: their levels are short, and one
+// instantiation keeps that kernel within its registers.)
+template <int G>
+struct Lanes {
+  static constexpr int g = G, k = 8 / G;
+};
+
+template <typename F>
+__device__ __forceinline__ void by_width(int32_t cnt, F &&f) {
+  if ((int64_t)cnt * GTF <= (int64_t)blockDim.x) f(Lanes<GTF>{});
+  else if ((int64_t)cnt * 2 <= (int64_t)blockDim.x) f(Lanes<2>{});
+  else f(Lanes<1>{});
+}
+
 // Sets the bitmap words of vertices 0..nr-1 to the ballot of pred(i) (one
 // store per 32 vertices; words past nr come out 0).  All threads call it.
 template <typename P>
@@ -1405,40 +1423,43 @@ __device__ __forceinline__ void corr_pair(const KArgs &A, int32_t S, int32_t p, 
     int32_t *ncnt = &sh.cnt[(cc + 1) % 3];
     // GTF lanes per frontier vertex, KF arcs per lane: the neighbours'
     // block, mark and weight are loaded together, ahead of the claims
-    for_groups<GTF>(cnt, [&](int item, bool valid, int gl) {
-      const int32_t u = valid ? cur[item] : 0;
-      const int32_t x = valid ? A.part[u] : -1;
-      const int32_t e0 = valid ? A.xadj[u] : 0, e1 = valid ? A.xadj[u + 1] : 0;
-      const int s = x == b;
-      const bool go = valid && sh.state[s];
-      count_work(sh, W_BFS_ITEMS, (go && gl == 0) ? 1 : 0);
-      count_work(sh, W_BFS_ARCS, (go && gl == 0) ? e1 - e0 : 0);
-      const int32_t ee = go ? e1 : e0;
-      for (int32_t c0 = e0; c0 < ee; c0 += GTF * KF) {
-        int32_t v[KF], xv[KF], mv[KF], wv[KF];
+    by_width(cnt, [&](auto L) {
+      constexpr int GW = decltype(L)::g, KW = decltype(L)::k;
+      for_groups<GW>(cnt, [&](int item, bool valid, int gl) {
+        const int32_t u = valid ? cur[item] : 0;
+        const int32_t x = valid ? A.part[u] : -1;
+        const int32_t e0 = valid ? A.xadj[u] : 0, e1 = valid ? A.xadj[u + 1] : 0;
+        const int s = x == b;
+        const bool go = valid && sh.state[s];
+        count_work(sh, W_BFS_ITEMS, (go && gl == 0) ? 1 : 0);
+        count_work(sh, W_BFS_ARCS, (go && gl == 0) ? e1 - e0 : 0);
+        const int32_t ee = go ? e1 : e0;
+        for (int32_t c0 = e0; c0 < ee; c0 += GW * KW) {
+          int32_t v[KW], xv[KW], mv[KW], wv[KW];
 #pragma unroll
-        for (int k = 0; k < KF; k++) {
-          const int32_t e = c0 + k * GTF + gl;
-          v[k] = e < ee ? A.adjncy[e] : -1;
-        }
+          for (int k = 0; k < KW; k++) {
+            const int32_t e = c0 + k * GW + gl;
+            v[k] = e < ee ? A.adjncy[e] : -1;
+          }
 #pragma unroll
-        for (int k = 0; k < KF; k++) {
-          xv[k] = v[k] >= 0 ? A.part[v[k]] : -1;
-          mv[k] = v[k] >= 0 ? mk[v[k]] : S;
-          wv[k] = v[k] >= 0 ? A.vwgt[v[k]] : 0;
-        }
+          for (int k = 0; k < KW; k++) {
+            xv[k] = v[k] >= 0 ? A.part[v[k]] : -1;
+            mv[k] = v[k] >= 0 ? mk[v[k]] : S;
+            wv[k] = v[k] >= 0 ? A.vwgt[v[k]] : 0;
+          }
 #pragma unroll
-        for (int k = 0; k < KF; k++) {
-          bool claim = false;
-          if (v[k] >= 0 && xv[k] == x && mv[k] < S) claim = atomicMax(&mk[v[k]], S) < S;
-          const int pos = wave_append(ncnt, claim);
-          if (claim) {
-            put_bounded(nxt, pos, V.nv, v[k], A.ctl);
-            acc2[s] += wv[k];
-            acc2[2 + s] += 1;
+          for (int k = 0; k < KW; k++) {
+            bool claim = false;
+            if (v[k] >= 0 && xv[k] == x && mv[k] < S) claim = atomicMax(&mk[v[k]], S) < S;
+            const int pos = wave_append(ncnt, claim);
+            if (claim) {
+              put_bounded(nxt, pos, V.nv, v[k], A.ctl);
+              acc2[s] += wv[k];
+              acc2[2 + s] += 1;
+            }
           }
         }
-      }
+      });
     });
     block_sums<4>(acc2, sh.red);
     Lw[0] = acc2[0];
