@@ -109,7 +109,7 @@ def c2_params(fr, w):
 def run_plain(args, fr, torch, gen):
     w = gen.config("C2")
     ctx = fr.Context()
-    ctx.set_validation(False)  # inputs are generated valid; validation is O(sum deg^2)
+    ctx.set_validation(False)  # inputs are generated valid
     dg = fr.DeviceGraph.from_host(w.graph)
     part0 = torch.as_tensor(w.part).cuda()
     dpart = part0.clone()
@@ -599,10 +599,13 @@ def summarize(argv):
     """Summaries of rocprofv3 output under profiles/ (runs on the host only):
       stats WORKLOAD DIR CMD...  -- the --kernel-trace --stats table of DIR
           -> profiles/k_flow_WORKLOAD_kernel_stats.md
-      pmc WORKLOAD FETCH_DIR WRITE_DIR CMD...  -- two --pmc runs (FETCH_SIZE,
-          then WRITE_SIZE) of a command with --copy-probe: the mean per
-          k_flow dispatch, each scaled by the ratio of the true byte count of
-          the 512 MiB copy to what the same counter read for it
+      pmc WORKLOAD FETCH_DIR WRITE_DIR STATS_DIR CMD...  -- two --pmc runs
+          (FETCH_SIZE, then WRITE_SIZE) of a command with --copy-probe: the
+          mean per k_flow dispatch, each scaled by the ratio of the true byte
+          count of the 512 MiB copy to what the same counter read for it; and
+          the same for every other kernel, with its mean duration from the
+          --kernel-trace --stats run of the same command in STATS_DIR (GB/s
+          against the 8 TB/s peak)
           -> profiles/k_flow_WORKLOAD_traffic.{md,json}
     CMD is the command line that produced the output, recorded verbatim."""
     kind, work = argv[0], argv[1]
@@ -626,7 +629,7 @@ def summarize(argv):
         return
     if kind != "pmc":
         raise SystemExit("summarize: stats or pmc")
-    fdir, wdir, cmd = argv[2], argv[3], " ".join(argv[4:])
+    fdir, wdir, sdir, cmd = argv[2], argv[3], argv[4], " ".join(argv[5:])
 
     def per_dispatch(root, counter):
         vals, names = {}, {}
@@ -656,6 +659,28 @@ def summarize(argv):
          "copy_fetch_kib": res["FETCH_SIZE"][2], "copy_write_kib": res["WRITE_SIZE"][2],
          "fetch_scale": fscale, "write_scale": wscale, "hbm_bytes_per_launch": hbm,
          "kernel_source_hash": kernel_source_hash(), "command": cmd}
+    # every kernel: scaled HBM bytes per launch, mean duration, bandwidth
+    fv, fn = per_dispatch(fdir, "FETCH_SIZE")
+    wv, wn = per_dispatch(wdir, "WRITE_SIZE")
+    per_k = {}
+    for vals, names, scale, slot in ((fv, fn, fscale, 0), (wv, wn, wscale, 1)):
+        for dsp, v in vals.items():
+            e = per_k.setdefault(names[dsp], [0.0, 0.0, 0, 0])
+            e[slot] += v * scale * 1024
+            e[2 + slot] += 1
+    avg_ns = {_col(r, "Name"): float(_col(r, "AverageNs")) for r in _csv_rows(sdir, "kernel_stats.csv")}
+    kernels = []
+    for name, (fb, wb, nf, nw) in per_k.items():
+        if "copy" in name.lower() or nf == 0:
+            continue
+        b = fb / nf + (wb / nw if nw else 0.0)
+        t = avg_ns.get(name)
+        kernels.append({"kernel": name, "launches": nf, "hbm_bytes_per_launch": b,
+                        "avg_us": t / 1e3 if t else None,
+                        "gb_per_s": b / t if t else None,
+                        "frac_of_peak": b / t / 8000.0 if t else None})
+    kernels.sort(key=lambda e: -(e["hbm_bytes_per_launch"] * e["launches"]))
+    d["kernels"] = kernels
     with open(os.path.join(out_dir, f"k_flow_{work}_traffic.json"), "w") as f:
         json.dump(d, f, indent=1)
     md = [f"# HBM traffic of {kname}, {work}", "",
@@ -667,10 +692,28 @@ def summarize(argv):
           f"| scale to true bytes | {fscale:.3f} | {wscale:.3f} |",
           f"| {kname}, mean per launch ({nl} launches) | {fk:.1f} | {wk:.1f} |", "",
           f"HBM bytes per launch (scaled): {hbm / 1e6:.2f} MB.", "",
-          f"Kernel sources hash: {d['kernel_source_hash']}."]
+          "Every kernel of the run (scaled FETCH_SIZE + WRITE_SIZE per launch; mean duration from "
+          "the `--kernel-trace --stats` run of the same command; the peak is 8 TB/s):", "",
+          "| kernel | launches | HBM MB per launch | mean us | GB/s | % of peak |",
+          "|---|---:|---:|---:|---:|---:|"]
+    for e in kernels:
+        md.append(f"| {e['kernel']} | {e['launches']} | {e['hbm_bytes_per_launch'] / 1e6:.2f} | "
+                  + (f"{e['avg_us']:.1f} | {e['gb_per_s']:.0f} | {100 * e['frac_of_peak']:.1f} |"
+                     if e["avg_us"] else "| | |"))
+    md += ["", f"Kernel sources hash: {d['kernel_source_hash']}."]
     with open(os.path.join(out_dir, f"k_flow_{work}_traffic.md"), "w") as f:
         f.write("\n".join(md) + "\n")
     print(json.dumps(d))
+
+
+def copy_probe(torch):
+    """One device copy of COPY_PROBE_BYTES: the byte counters' calibration."""
+    x = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
 
 
 def main():
@@ -689,6 +732,8 @@ def main():
     ap.add_argument("--no-multitry", action="store_true")
     ap.add_argument("--mt-configs", default="C3")
     ap.add_argument("--max-sweeps", type=int, default=64)
+    ap.add_argument("--c2-only", action="store_true",
+                    help="only the C2 pair leg, printed as its own JSON line (for profiling it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one device copy of 512 MiB (calibrates HBM byte counters)")
     ap.add_argument("--summarize", nargs="+", metavar="ARG",
@@ -714,16 +759,18 @@ def main():
         sys.exit(1)
     fr.load()  # fails loudly when the HIP library is not built
 
+    if args.c2_only:
+        c2 = c2_leg(argparse.Namespace(**dict(vars(args), steps=args.c2_steps, warmup=2)), fr,
+                    torch, gen)
+        if args.copy_probe:
+            copy_probe(torch)
+        print(json.dumps({"c2_plain": c2}), flush=True)
+        return
     h = run_c5_headline(args, fr, torch, gen)
     progress(f"C5 headline: {h['wall'] * 1e3 / args.steps:.0f} ms per step, "
              f"cut {h['cut0']} -> {h['cut']}")
     if args.copy_probe:
-        x = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.int32, device="cuda")
-        y = torch.empty_like(x)
-        torch.cuda.synchronize()
-        y.copy_(x)
-        torch.cuda.synchronize()
-        del x, y
+        copy_probe(torch)
     line = {
         "metric": METRIC,
         "value": h["edges"] / h["wall"],
