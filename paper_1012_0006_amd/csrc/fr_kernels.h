@@ -1234,7 +1234,8 @@ __device__ __forceinline__ void bnd_union(const KArgs &A, int32_t S, Items &&ite
     else wave_add_by_key(psw, PS_WORDS, PS_WORK + (j == 5 ? W_BND_VERTS : W_BND_ARCS), key, v);
   };
   items([&](int32_t p, int64_t slot) {
-    const bool on = p >= 0;
+    // one pass per pair: the first entry's (the other slots copy it)
+    const bool on = p >= 0 && p % A.W == 0;
     const int32_t a = on ? A.pairs[2 * p] : 0, b = on ? A.pairs[2 * p + 1] : 0;
     // the union list is held by the pair's first entry
     const int32_t u = on ? A.uvert[A.voff[A.blk2pair[a]] + slot] : 0;
@@ -1256,7 +1257,7 @@ __device__ __forceinline__ void bnd_union(const KArgs &A, int32_t S, Items &&ite
                           bl && side ? 1 : 0, 1, e1 - e0};
     sums.add(on ? p : -1, x, out);
     const int pos = wave_append_by_key(A.pcnt, bl ? p : -1);
-    if (bl) put_bounded(A.LA + A.voff[p], pos, A.voff[p + 1] - A.voff[p], u, A.ctl);
+    if (bl) put_bounded(A.SNK + A.voff[p], pos, A.voff[p + 1] - A.voff[p], u, A.ctl);
   });
   sums.flush(out);
 }
@@ -1264,12 +1265,14 @@ __device__ __forceinline__ void bnd_union(const KArgs &A, int32_t S, Items &&ite
 // ---- pair boundary (Sec. 4.1): vertices of a with a neighbour in b and vice
 //      versa become BFS level 0 (marked with the stamp S); also the pair cut
 //      and the boundary weight and size per side.
-//      Every slot of a pair solves the same partition, so the boundary of a
-//      vertex is the same for all of them.  While the pairs still iterating
-//      cover a large part of the graph, the kernel walks the vertices once in
-//      id order (coalesced; the pair from the block) and hands each result to
-//      every live slot (one lane per vertex); late in a round, with few pairs
-//      left, it walks only their union lists, one item per slot.
+//      Every slot of a pair solves the same partition, so the boundary is
+//      computed once, for the pair's first entry: its sums, its marks and its
+//      list (in the entry's SNK slice, which nothing reads before the network
+//      build); each slot's corridor copies the list and marks it in its own
+//      marks.  While the pairs still iterating cover a large part of the
+//      graph, the kernel walks all vertices in chunks of 64 (coalesced arcs,
+//      the pair from the block); late in a round, with few pairs left, it
+//      walks only their union lists.
 __global__ void __launch_bounds__(256) k_bnd(KArgs A, int32_t it) {
   const int32_t S = A.stamp0 + 2 * it;
   unsigned long long *acc = (unsigned long long *)A.pacc;
@@ -1278,13 +1281,11 @@ __global__ void __launch_bounds__(256) k_bnd(KArgs A, int32_t it) {
   if (4 * total >= (int64_t)A.n) {
     // pair cut, boundary weight a / b, boundary count a / b, vertices, arcs
     KeyedSums<7> sums;
-    // keyed by the pair's first entry; a flush adds to each live slot
+    // keyed by the pair's first entry (live: binfo), which the other slots
+    // copy from at the corridor's start
     auto out = [&](int j, int key, int64_t v) {
-      for (int32_t s = 0; s < A.W; s++) {
-        const int32_t q = key >= 0 && !A.ps[key + s].done ? key + s : -1;
-        if (j < 5) wave_add_by_key(acc, PA_N, PA_CUT + j, q, v);
-        else wave_add_by_key(psw, PS_WORDS, PS_WORK + (j == 5 ? W_BND_VERTS : W_BND_ARCS), q, v);
-      }
+      if (j < 5) wave_add_by_key(acc, PA_N, PA_CUT + j, key, v);
+      else wave_add_by_key(psw, PS_WORDS, PS_WORK + (j == 5 ? W_BND_VERTS : W_BND_ARCS), key, v);
     };
     // per lane of the block: boundary flag and cut weight of its vertex
     __shared__ uint32_t s_bnd[256];
@@ -1316,12 +1317,10 @@ __global__ void __launch_bounds__(256) k_bnd(KArgs A, int32_t it) {
       const int64_t x[7] = {cw, bl && !side ? w : 0, bl && side ? w : 0, bl && !side ? 1 : 0,
                             bl && side ? 1 : 0, 1, in ? x1 - x0 : 0};
       sums.add(p0, x, out);
-      for (int32_t s = 0; s < A.W; s++) {
-        const int32_t p = bl && !A.ps[p0 + s].done ? p0 + s : -1;
-        if (p >= 0) mark_of(A, p)[u] = S;
-        const int pos = wave_append_by_key(A.pcnt, p);
-        if (p >= 0) put_bounded(A.LA + A.voff[p], pos, A.voff[p + 1] - A.voff[p], (int32_t)u, A.ctl);
-      }
+      const int32_t p = bl ? p0 : -1;
+      if (p >= 0) mark_of(A, p)[u] = S;
+      const int pos = wave_append_by_key(A.pcnt, p);
+      if (p >= 0) put_bounded(A.SNK + A.voff[p], pos, A.voff[p + 1] - A.voff[p], (int32_t)u, A.ctl);
     });
     sums.flush(out);
     return;
@@ -1354,11 +1353,14 @@ __device__ __forceinline__ void corr_pair(const KArgs &A, int32_t S, int32_t p, 
   const PairView V = make_view(A, p);
   const int32_t a = V.a, b = V.b;
   int32_t *mk = mark_of(A, p), *vm = vmap_of(A, p);
-  const int64_t *pa = A.pacc + (int64_t)p * PA_N;
+  // the boundary pass ran once per pair, for its first entry p0: its sums,
+  // and its list in p0's SNK slice (untouched until the network build)
+  const int32_t p0 = p - p % A.W;
+  const int64_t *pa = A.pacc + (int64_t)p0 * PA_N;
   int64_t t0 = wall_clock64();
   if (threadIdx.x == 0) {
     st = A.ps[p];
-    sh.cnt[0] = min(A.pcnt[p], (int32_t)V.nv);
+    sh.cnt[0] = min(A.pcnt[p0], (int32_t)V.nv);
     sh.cnt[1] = sh.cnt[2] = 0;
     sh.nr = 0;
     sh.W[0] = sh.W[1] = 0;
@@ -1371,6 +1373,19 @@ __device__ __forceinline__ void corr_pair(const KArgs &A, int32_t S, int32_t p, 
   }
   if (threadIdx.x < W_COUNT) sh.work[threadIdx.x] = 0ull;
   __syncthreads();
+  {
+    // level 0: the pair's boundary list into this entry's list, the other
+    // slots also marking it in their own corridor marks (the first entry's
+    // marks were set by the boundary pass)
+    const int32_t *bl = A.SNK + A.voff[p0];
+    const int32_t n0 = uni(sh.cnt[0]);
+    for (int32_t i = threadIdx.x; i < n0; i += TPB) {
+      const int32_t u = bl[i];
+      V.LA[i] = u;
+      if (p != p0) mk[u] = S;
+    }
+    __syncthreads();
+  }
   int64_t Lw[2] = {pa[PA_BW0], pa[PA_BW1]}, Lc[2] = {pa[PA_BC0], pa[PA_BC1]};
   int32_t *cur = V.LA, *nxt = V.LB;
   int cc = 0;  // counter of the current list
