@@ -189,15 +189,19 @@ struct KeyedSums {
   }
 };
 
-// Calls f(u0) for chunks of 64 consecutive vertices [u0, u0 + 64): each wave
+// Calls f for chunks of 64 consecutive vertices [u0, u0 + 64): each wave
 // walks a contiguous run of chunks, so sums keyed by block or pair change key
 // only at block borders and reach device memory a few times per wave.
 // Workgroups are dispatched round-robin over the 8 XCDs, so workgroup g
 // takes its runs from the (g mod 8)-th eighth of the vertex range, and
 // neighbouring vertices (whose blocks the arcs look up) stay in one XCD's
 // L2.  Wave-uniform; every wave of the grid calls it.
+// f(u0, pv, x0) also gets the lane's vertex's block part[u] and arc start
+// xadj[u] (-1 and INT32_MAX past the graph), loaded one chunk ahead so that
+// their latency overlaps the previous chunk's work.
 template <typename F>
-__device__ __forceinline__ void wave_chunk_runs(int64_t n, F &&f) {
+__device__ __forceinline__ void wave_chunk_runs(const KArgs &A, F &&f) {
+  const int64_t n = A.n;
   const int64_t nchunk = (n + 63) / 64;
   const int xcd = (int)(blockIdx.x % 8u);
   const int64_t nbx = ((int64_t)gridDim.x - xcd + 7) / 8;  // workgroups on this XCD
@@ -208,7 +212,21 @@ __device__ __forceinline__ void wave_chunk_runs(int64_t n, F &&f) {
   const int64_t run = (r_hi - r_lo + nw - 1) / nw;
   const int64_t wi = (int64_t)(blockIdx.x / 8u) * wpb + (threadIdx.x >> 6);
   const int64_t c_lo = min(r_hi, r_lo + wi * run), c_hi = min(r_hi, c_lo + run);
-  for (int64_t c = c_lo; c < c_hi; c++) f(c * 64);
+  auto load = [&](int64_t c, int32_t &pv, int32_t &x0) {
+    const int64_t u = c * 64 + lane64();
+    const bool in = c < c_hi && u < n;
+    pv = in ? A.part[u] : -1;
+    x0 = in ? A.xadj[u] : 0x7fffffff;
+  };
+  int32_t pv, x0;
+  load(c_lo, pv, x0);
+  for (int64_t c = c_lo; c < c_hi; c++) {
+    int32_t pn, xn;
+    load(c + 1, pn, xn);
+    f(c * 64, pv, x0);
+    pv = pn;
+    x0 = xn;
+  }
 }
 
 // Boundary flag and cut weight of the 64 vertices of one chunk, one lane
@@ -226,7 +244,7 @@ __device__ __forceinline__ void chunk_boundary(const KArgs &A, int32_t x0, int32
   const int lane = lane64();
   sb[lane] = 0u;
   scw[lane] = 0ull;
-  constexpr int KB = 4;
+  constexpr int KB = 2;
   for (int32_t e0 = E0; e0 < E1; e0 += 64 * KB) {
     int32_t o[KB], ty[KB], v[KB];
 #pragma unroll
@@ -313,17 +331,14 @@ __global__ void __launch_bounds__(256) k_block_stats(KArgs A) {
   auto out = [&](int j, int key, int64_t v) {
     wave_add_by_key(j == 0 ? bw : (j == 1 ? bc : ba), 1, 0, key, v);
   };
-  wave_chunk_runs(A.n, [&](int64_t u0) {
+  wave_chunk_runs(A, [&](int64_t u0, int32_t blk, int32_t x0) {
     const int64_t u = u0 + lane64();
     int key = -1;
     int32_t w = 0, deg = 0;
-    if (u < A.n) {
-      const int32_t x = A.part[u];
-      if (A.blk2pair[x] >= 0) {
-        key = x;
-        w = A.vwgt[u];
-        deg = A.xadj[u + 1] - A.xadj[u];
-      }
+    if (blk >= 0 && A.blk2pair[blk] >= 0) {
+      key = blk;
+      w = A.vwgt[u];
+      deg = A.xadj[u + 1] - x0;
     }
     const int64_t x[3] = {w, 1, deg};
     sums.add(key, x, out);
@@ -518,9 +533,9 @@ __global__ void __launch_bounds__(256) k_validate(KArgs A, int64_t narcs, const 
 
 // vertices of the two blocks of every pair, gathered into the pair's arena
 __global__ void __launch_bounds__(256) k_union(KArgs A) {
-  wave_chunk_runs(A.n, [&](int64_t u0) {
+  wave_chunk_runs(A, [&](int64_t u0, int32_t x, int32_t) {
     const int64_t u = u0 + lane64();
-    const int32_t p = u < A.n ? A.blk2pair[A.part[u]] : -1;
+    const int32_t p = x >= 0 ? A.blk2pair[x] : -1;
     const int pos = wave_append_by_key(A.ucnt, p);
     if (p >= 0 && A.voff[p] + pos < A.voff[p + 1]) A.uvert[A.voff[p] + pos] = (int32_t)u;
   });
@@ -1292,16 +1307,14 @@ __global__ void __launch_bounds__(256) k_bnd(KArgs A, int32_t it) {
     __shared__ unsigned long long s_cw[256];
     const int lane = lane64();
     const int wl = (int)(threadIdx.x & ~63u);
-    wave_chunk_runs(A.n, [&](int64_t u0) {
+    wave_chunk_runs(A, [&](int64_t u0, int32_t pv, int32_t x0) {
       const int64_t u = u0 + lane;
       const int64_t last = min((int64_t)A.n, u0 + 64);
       const bool in = u < last;
       // the vertex's block -> its pair's first live entry, the other block
       // and the side (binfo, set at the start of every iteration)
-      int32_t p0 = -1, y2 = -1, x0 = 0x7fffffff;
+      int32_t p0 = -1, y2 = -1;
       if (in) {
-        const int32_t pv = A.part[u];
-        x0 = A.xadj[u];
         p0 = A.binfo[2 * pv];
         y2 = A.binfo[2 * pv + 1];
       }

@@ -38,14 +38,13 @@ __global__ void __launch_bounds__(256) k_feature_stats(KArgs A, int64_t *acc) {
   // boundary count a / b, boundary weight a, cut weight; keyed by pair
   KeyedSums<4> sums;
   auto out = [&](int j, int key, int64_t v) { wave_add_by_key(ac, 4, j, key, v); };
-  wave_chunk_runs(A.n, [&](int64_t u0) {
+  wave_chunk_runs(A, [&](int64_t u0, int32_t blk, int32_t x0) {
     const int64_t u = u0 + lane;
     const int64_t last = min((int64_t)A.n, u0 + 64);
-    int32_t p = -1, y2 = -1, x0 = 0x7fffffff;
+    int32_t p = -1, y2 = -1;
     int64_t w = 0;
     if (u < last) {
-      const int32_t x = A.part[u];
-      x0 = A.xadj[u];
+      const int32_t x = blk;
       p = A.blk2pair[x];
       if (p >= 0) {
         const int32_t a = A.pairs[2 * p], b = A.pairs[2 * p + 1];
