@@ -230,7 +230,10 @@ typedef struct {
   int32_t blocks_per_cu;   /* persistent per-pair workgroups per compute unit: 1..8 */
   int32_t tpv;             /* lanes per vertex in push/relabel sweeps: 1, 2, 4, 8 or 16
                               (1 runs as 2, 16 as 8) */
-  int32_t relabel_period;  /* push/relabel sweeps between global relabels, 1..10^6 */
+  int32_t relabel_period;  /* global relabel interval, 1..10^6: after a global relabel
+                              whose search took L levels, the next one follows after
+                              L/2 push/relabel sweeps, clamped to [period/4 (at least
+                              1), 2 period], or when the active list runs dry */
   int32_t mb_lds;          /* most balanced cut: 1 = component graph in LDS when it fits,
                               0 = always in device memory */
 } fr_tuning;

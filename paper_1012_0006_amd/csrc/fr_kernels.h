@@ -1769,17 +1769,26 @@ __device__ __forceinline__ void flow_pair(const KArgs &A, int32_t p, SolveShared
   if (!overflow) {
     // one relabel call site (the relabel is inlined; one copy keeps the
     // kernel within its registers): at the start, when the active list
-    // runs dry and every relabel_period passes
+    // runs dry and after rp_eff passes
     int32_t cnt = 0;
     ListRef cur, nxt;
     int since = 0;
+    // sweeps until the next global relabel: half the last relabel's BFS
+    // depth (a deep corridor's relabel costs more), within [period / 4,
+    // 2 period] of the tuning's period
+    int32_t rp_eff = A.relabel_period;
+    const int32_t rp_lo = max(1, A.relabel_period / 4), rp_hi = 2 * A.relabel_period;
     bool relabel = true;
     for (;;) {
       if (relabel) {
         t1 = wall_clock64();
         t_push += t1 - t0;
         t0 = t1;
-        cnt = global_relabel<TPB>(A, V, nr, NL, sh, R, gr_levels, lds);
+        {
+          const int64_t lev0 = gr_levels;
+          cnt = global_relabel<TPB>(A, V, nr, NL, sh, R, gr_levels, lds);
+          rp_eff = (int32_t)min((int64_t)rp_hi, max((int64_t)rp_lo, (gr_levels - lev0) / 2));
+        }
         t1 = wall_clock64();
         t_rel += t1 - t0;
         t0 = t1;
@@ -1819,7 +1828,7 @@ __device__ __forceinline__ void flow_pair(const KArgs &A, int32_t p, SolveShared
       cur = nxt;
       nxt = t;
       sweeps++;
-      if (++since >= A.relabel_period) relabel = true;
+      if (++since >= rp_eff) relabel = true;
     }
     t1 = wall_clock64();
     t_push += t1 - t0;
