@@ -50,7 +50,7 @@ class OrParams(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int32) for f in
                 ("area_mode", "depth", "alpha", "alpha_max", "adaptive", "max_iters", "eps_ppm",
                  "mb_reps", "mb_seed", "fm_limit", "fm_seed", "active_blocks", "cut_side",
-                 "terminals", "mt_alpha", "mt_seed")]
+                 "terminals", "mt_alpha", "mt_seed", "restart_alpha")]
 
 
 class OrSolve(ctypes.Structure):
@@ -134,7 +134,7 @@ def _params(p: dict) -> OrParams:
                     p["adaptive"], p["max_iters"], p["eps_ppm"], p.get("mb_reps", 0),
                     _i32(p.get("mb_seed", 0)), p.get("fm_limit", 0), _i32(p.get("fm_seed", 0)),
                     p.get("active_blocks", 0), p.get("cut_side", 0), p.get("terminals", 0),
-                    p.get("mt_alpha", 0), _i32(p.get("mt_seed", 0)))
+                    p.get("mt_alpha", 0), _i32(p.get("mt_seed", 0)), p.get("restart_alpha", 0))
 
 
 def _struct_dict(s) -> dict:

@@ -35,6 +35,11 @@
  *   R6  adaptive loop: start at the given alpha; apply => alpha=min(2a,amax);
  *       reject => alpha=max(a/2,1) (stop if it was 1); feasible and not
  *       improving => stop; at most max_iters solves
+ *   R6b restart_alpha > 0 (set with a learned start, which the paper does
+ *       not have): a search that started below min(restart_alpha, amax),
+ *       has applied nothing and meets a feasible, non-improving solve
+ *       continues once from that factor instead of stopping, within the
+ *       same max_iters, so the plain search decides before the pair gives up
  *   R8  the first block of the pair is the source side
  *   R9  DEPTH mode includes BFS distance <= depth from the boundary
  *   R12 2-way FM before the flow (Sec. 2.2, KaPPa's local search with TopGain):
@@ -95,6 +100,7 @@ typedef struct {
   int32_t mt_alpha; /* 0: no multi-try FM; > 0: after the pairwise improvements of a batch, one
                        multi-try round per pair (Sec. 4.2), stopping rule parameter alpha */
   int32_t mt_seed;  /* seed of the multi-try keys (its 32 bits, zero-extended) */
+  int32_t restart_alpha; /* 0: none; > 0: the one restart of rule R6b from this factor */
 } or_params;
 
 /* one flow solve */
@@ -1335,7 +1341,7 @@ static int32_t refine_pair_core(const or_graph *g, int32_t *part, int32_t k, int
   if (p->alpha < 1 || p->alpha_max < 1 || p->max_iters < 1 || p->eps_ppm < 0 ||
       (p->area_mode != 0 && p->area_mode != 1) || p->depth < 0 || p->mb_reps < 0 ||
       p->fm_limit < 0 || p->cut_side < 0 || p->cut_side > 2 ||
-      (p->terminals != 0 && p->terminals != 1) || p->mt_alpha < 0)
+      (p->terminals != 0 && p->terminals != 1) || p->mt_alpha < 0 || p->restart_alpha < 0)
     return -8;
   int64_t w_a = 0, w_b = 0;
   for (int32_t u = 0; u < g->n; u++) {
@@ -1362,6 +1368,9 @@ static int32_t refine_pair_core(const or_graph *g, int32_t *part, int32_t k, int
   int32_t alpha = p->alpha < p->alpha_max ? p->alpha : p->alpha_max;
   int32_t last = 0;
   int stopped = 0;
+  const int32_t restart = p->restart_alpha < p->alpha_max ? p->restart_alpha : p->alpha_max;
+  const int32_t start = alpha;
+  int restarted = 0;
   for (int32_t it = 0; it < p->max_iters; it++) {
     or_solve rec;
     if (solve_once(g, part, k, a, b, p, alpha, &rec, side_out) != 0) return -7;
@@ -1379,6 +1388,9 @@ static int32_t refine_pair_core(const or_graph *g, int32_t *part, int32_t k, int
     } else if (rec.decision == DEC_INFEASIBLE) {
       if (!p->adaptive || alpha == 1) { stopped = 1; break; }
       alpha = alpha / 2 > 1 ? alpha / 2 : 1;
+    } else if (rec.decision == DEC_EQUAL && res->applied == 0 && !restarted && start < restart) {
+      restarted = 1; /* R6b: once, from the plain search's start */
+      alpha = restart;
     } else {
       stopped = 1; /* feasible and not improving, or not adjacent */
       break;

@@ -286,6 +286,82 @@ def test_adaptive_rule_traces():
         assert o.result["region_edges"] == sum(r["region_edges"] for r in tr)
 
 
+def _wavy(seed, amp, f):
+    """A 2D RGG (n = 3000) split along x = 0.5 + amp sin(2 pi f y): a long
+    boundary that small corridors cannot straighten."""
+    g = gen.rgg(3000, 2, 8.0, seed=seed, wlo=1, whi=int([1, 10][seed % 2]))
+    x, y = g.coords[:, 0], g.coords[:, 1]
+    return g, (x > 0.5 + amp * np.sin(2 * np.pi * f * y)).astype(np.int32)
+
+
+def _swapped(seed):
+    g = gen.rgg(3000, 2, 8.0, seed=seed, wlo=1, whi=int([1, 10][seed % 2]))
+    part = gen.rcb(g, 2, force_axis=seed % 2)
+    gen.pair_swap_noise(g, part, [0.002, 0.01, 0.05][(seed - 700) % 3], seed - 700)
+    return g, part
+
+
+def test_restart_rule_composes():
+    """R6b (the one restart of a learned start): when a search that started
+    below the restart factor applies nothing and meets a feasible,
+    non-improving solve, the
+    restarted call is that search followed by the plain search from the
+    restart factor on the same partition with the iterations left; records,
+    result and partition are those of the two calls in sequence."""
+    cases = [(_wavy(902, 0.2, 1), 1), (_wavy(911, 0.2, 1), 1), (_swapped(715), 1)]
+    for (g, part), a0 in cases:
+        p = dict(area_mode=0, depth=0, alpha=a0, alpha_max=16, adaptive=1, max_iters=8,
+                 eps_ppm=30000)
+        first = oracle.refine_pair(g, part, 2, 0, 1, p)
+        assert first.result["applied"] == 0 and first.trace[-1]["decision"] == oracle.DEC_EQUAL
+        assert first.trace[-1]["alpha"] < 16
+        used = len(first.trace)
+        second = oracle.refine_pair(g, part, 2, 0, 1, dict(p, alpha=16, max_iters=8 - used))
+        both = oracle.refine_pair(g, part, 2, 0, 1, dict(p, restart_alpha=16))
+        assert both.trace == first.trace + second.trace
+        assert both.trace[used]["alpha"] == 16
+        assert np.array_equal(both.part, second.part)
+        for key in ("applied", "cut_after", "weight_a", "weight_b", "final_alpha", "iter_cap"):
+            assert both.result[key] == second.result[key], key
+        assert both.result["iters"] == used + second.result["iters"]
+        assert both.result["region_edges"] == (first.result["region_edges"] +
+                                               second.result["region_edges"])
+        assert both.result["cut_after"] < first.result["cut_after"]
+        # capped below the restart factor by alpha_max: the restart runs from 8
+        capped = oracle.refine_pair(g, part, 2, 0, 1, dict(p, alpha_max=8, restart_alpha=16))
+        assert capped.trace[used]["alpha"] == 8
+
+
+def test_restart_rule_leaves_other_searches_alone():
+    """R6b changes nothing for a search that applied a cut, ended on an
+    infeasible cut at factor 1 or started at the restart factor; with no
+    iteration left it changes only the iteration-cap flag; a negative
+    restart factor is rejected."""
+    seen = set()
+    for seed in range(700, 712):
+        g, part = _swapped(seed)
+        for a0 in (1, 2, 16):
+            p = dict(area_mode=0, depth=0, alpha=a0, alpha_max=16, adaptive=1, max_iters=8,
+                     eps_ppm=30000)
+            o = oracle.refine_pair(g, part, 2, 0, 1, p)
+            last = o.trace[-1]["decision"]
+            if o.result["applied"] > 0 or last != oracle.DEC_EQUAL or a0 == 16:
+                q = oracle.refine_pair(g, part, 2, 0, 1, dict(p, restart_alpha=16))
+                assert q.trace == o.trace and np.array_equal(q.part, o.part)
+                seen.add("start" if a0 == 16 else ("applied" if o.result["applied"] else last))
+    assert "applied" in seen and "start" in seen
+    g, part = _wavy(902, 0.2, 1)
+    p = dict(area_mode=0, depth=0, alpha=1, alpha_max=16, adaptive=1, max_iters=1, eps_ppm=30000)
+    o = oracle.refine_pair(g, part, 2, 0, 1, p)
+    q = oracle.refine_pair(g, part, 2, 0, 1, dict(p, restart_alpha=16))
+    # the restart is due but no iteration is left: the same solve, and the
+    # iteration cap reports the search as cut off
+    assert len(q.trace) == 1 and q.trace == o.trace
+    assert o.result["iter_cap"] == 0 and q.result["iter_cap"] == 1
+    assert np.array_equal(q.part, o.part)
+    assert oracle.refine_pair(g, part, 2, 0, 1, dict(p, restart_alpha=-1)).rc == -8
+
+
 def test_c1_closed_form():
     """128x128 unit grid, depth-8 corridor: 128 row-disjoint paths join the
     pinned borders and a straight column cut costs 128, so the flow is 128
