@@ -364,7 +364,8 @@ def run_c5_cpu_baseline(args, fr, torch, w):
     def one(i):
         a, b = pairs[i]
         return oracle.refine_pair(w.graph, w.part, w.k, a, b,
-                                  dict(base, alpha=res[i]["start_alpha"]), want_side=False)
+                                  dict(base, alpha=res[i]["start_alpha"],
+                                       restart_alpha=base["alpha"]), want_side=False)
 
     try:
         avail = len(os.sched_getaffinity(0))

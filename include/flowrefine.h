@@ -109,7 +109,11 @@ typedef struct {
   int32_t adaptive;  /* 0: one flow solve; 1: adaptive flow iterations */
   int32_t max_iters; /* flow solves per pair, in [1, 64] */
   int32_t eps_ppm;   /* imbalance eps in parts per million (3 % = 30000), >= 0 */
-  int32_t use_mlp;   /* start each pair at the learned factor (needs loaded weights) */
+  int32_t use_mlp;   /* start each pair at the learned factor (needs loaded weights).
+                      * A pair that started below alpha, has applied nothing
+                      * and meets a feasible cut without improvement then
+                      * continues once from alpha (the plain search's start)
+                      * within the same max_iters, instead of stopping there. */
   /* Most balanced minimum cut (Sec. 4.1.1; "balanced adaptive flow
    * iterations" when adaptive = 1).  0: the candidate is the smallest source
    * set.  r > 0: after each max flow, the strongly connected components of
@@ -392,7 +396,8 @@ int32_t fr_set_timing(fr_context *ctx, int32_t on);
  *   [11] solves whose component graph (more than 2,048 components) was kept
  *   in device memory instead of LDS; [12] FM moves made, [13] FM moves kept;
  *   [14] flow-kernel launches (one per adaptive iteration of each round),
- *   or round-kernel launches (one per round) with fused rounds;
+ *   or round-kernel launches (one per round) with fused rounds; [15] pairs
+ *   whose learned start was restarted from alpha (use_mlp);
  *   [28] multi-try searches, [29] multi-try moves made, [30] kept;
  *   [16..27] vertices and arcs touched: boundary scan, corridor BFS, network
  *   build, push/relabel sweeps, global relabels, residual closure (vertices

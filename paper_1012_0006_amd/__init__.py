@@ -274,7 +274,8 @@ def stats_dict(ctx) -> dict:
              sweeps=cnt[0], relabels=cnt[1], bfs_levels=cnt[2], gr_levels=cnt[3],
              cl_levels=cnt[4], workgroups=cnt[5], diag=cnt[6], slots=cnt[7],
              mb_kernel_ms=cnt[8] / 1e6, mb_free=cnt[9], mb_comp=cnt[10], mb_big=cnt[11],
-             fm_steps=cnt[12], fm_kept=cnt[13], flow_launches=cnt[14], mt_searches=cnt[28],
+             fm_steps=cnt[12], fm_kept=cnt[13], flow_launches=cnt[14], restarts=cnt[15],
+             mt_searches=cnt[28],
              mt_moves=cnt[29], mt_kept=cnt[30])
     d.update({k: cnt[16 + i] for i, k in enumerate(WORK_KEYS)})
     return d

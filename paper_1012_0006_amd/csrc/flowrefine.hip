@@ -524,6 +524,7 @@ static KArgs call_args(fr_context *c, const DevBufs &d, const fr_graph *g, int32
     A.area_mode = p->area_mode;
     A.depth = p->depth;
     A.alpha_max = p->alpha_max;
+    A.restart_alpha = p->use_mlp ? std::min(p->alpha, p->alpha_max) : 0;
     A.adaptive = p->adaptive;
     A.max_iters = p->max_iters;
     A.eps_ppm = p->eps_ppm;
@@ -831,6 +832,7 @@ static void add_entry_stats(fr_context *c, const PairState *ps, size_t count) {
     C[11] += s.mb_big;
     C[12] += s.fm_steps;
     C[13] += s.fm_kept;
+    C[15] += s.restarted;
     C[28] += s.mt_searches;
     C[29] += s.mt_moves;
     C[30] += s.mt_kept;

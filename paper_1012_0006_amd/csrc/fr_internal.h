@@ -27,7 +27,7 @@ struct PairState {
   int32_t nr;           // corridor vertices of the current solve
   int32_t done;         // the adaptive loop has stopped (a slot: not solved this launch)
   int32_t last_slot;    // slot of the pair's last recorded solve
-  int32_t spare;
+  int32_t restarted;    // the one restart of a learned start has happened
   int64_t cA, cB;       // current block weights
   int64_t cut;          // current pair cut
   int64_t cut0;         // pair cut at call start
@@ -129,6 +129,10 @@ struct KArgs {
   int64_t lmax;
   // parameters
   int32_t area_mode, depth, alpha_max, adaptive, max_iters, eps_ppm;
+  // learned start: a search that started below this factor, applied nothing
+  // and met a feasible cut without improvement continues once from it (the
+  // plain search's start; 0 = never)
+  int32_t restart_alpha;
   int32_t stamp0;           // corridor mark of the first solve (even)
   // most balanced minimum cut: sweeps (0 = smallest source set), key seed,
   // component graph in LDS when it fits, quotient arcs (one slot per arc slot)

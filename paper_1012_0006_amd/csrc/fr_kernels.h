@@ -2081,6 +2081,10 @@ __device__ __forceinline__ void select_pair(const KArgs &A, int32_t p, int32_t *
       } else if (rec.decision == FR_DEC_INFEASIBLE) {
         if (!A.adaptive || rec.alpha == 1) stop = true;
         else next_alpha = rec.alpha / 2 > 1 ? rec.alpha / 2 : 1;
+      } else if (rec.decision == FR_DEC_EQUAL && R.applied == 0 && !R.restarted &&
+                 R.start_alpha < A.restart_alpha) {
+        R.restarted = 1;  // the plain search decides before the pair gives up
+        next_alpha = A.restart_alpha;
       } else {
         stop = true;
       }
@@ -2088,7 +2092,7 @@ __device__ __forceinline__ void select_pair(const KArgs &A, int32_t p, int32_t *
         stop = true;
         R.iter_cap = 1;
       }
-      if (stop || rec.decision == FR_DEC_APPLY) break;
+      if (stop || rec.decision != FR_DEC_INFEASIBLE) break;
     }
     R.alpha = next_alpha;
     R.done = stop ? 1 : 0;

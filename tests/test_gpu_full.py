@@ -54,7 +54,7 @@ def _round_vs_oracle(gpu_lib, ctx, w, sample, use_mlp=0, extra=None):
     picks = order[:1] + order[1:][:: max(1, (len(order) - 1) // max(1, sample - 1))][: sample - 1]
     for i in picks:
         a, b = pairs[i]
-        q = dict(p, alpha=res[i]["start_alpha"]) if use_mlp else p
+        q = dict(p, alpha=res[i]["start_alpha"], restart_alpha=p["alpha"]) if use_mlp else p
         o = oracle.refine_pair(w.graph, w.part, w.k, a, b, q, want_side=False)
         for key in KEYS:
             assert res[i][key] == o.result[key], (w.name, (a, b), key)

@@ -140,7 +140,8 @@ def test_learned_start(gpu_lib, ctx):
                                         _prm(gpu_lib, dict(p, use_mlp=1)))
     cur = part.copy()
     for i, (a, b) in enumerate(pairs):
-        o = oracle.refine_pair(g, part, 16, a, b, dict(p, alpha=res[i]["start_alpha"]))
+        o = oracle.refine_pair(g, part, 16, a, b,
+                               dict(p, alpha=res[i]["start_alpha"], restart_alpha=16))
         for key in RESULT_KEYS:
             assert res[i][key] == o.result[key], ((a, b), key)
         assert tr[i] == o.trace

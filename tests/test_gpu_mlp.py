@@ -162,7 +162,8 @@ def test_training_reduces_loss(gpu_lib, ctx):
 
 def test_batch_with_learned_factor_matches_oracle(gpu_lib, ctx):
     """Flows stay exact under the learned start factor: the oracle, started at
-    the factor the device chose for each pair, gives the same results."""
+    the factor the device chose for each pair (with the one restart from the
+    plain start, rule R6b), gives the same results."""
     import torch
 
     gpu_lib.fr_mlp_init(ctx, 21)
@@ -182,7 +183,8 @@ def test_batch_with_learned_factor_matches_oracle(gpu_lib, ctx):
         assert res[i]["start_alpha"] == gpu_lib.ALPHAS[int(np.argmax(probs[i]))]
     cur = part.copy()
     for i, (a, b) in enumerate(pairs):
-        o = oracle.refine_pair(g, cur, k, a, b, dict(p, alpha=res[i]["start_alpha"]),
+        o = oracle.refine_pair(g, cur, k, a, b,
+                               dict(p, alpha=res[i]["start_alpha"], restart_alpha=p["alpha"]),
                                want_side=False)
         for key in KEYS:
             assert res[i][key] == o.result[key], (i, key)
@@ -247,3 +249,41 @@ def test_trained_factor_gain(gpu_lib, ctx):
     assert tot["learned"][2] <= 1.01 * tot["plain"][2]
     assert tot["learned"][1] < tot["constant_8"][1]
     assert tot["learned"][2] <= 1.001 * tot["constant_8"][2]
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_learned_start_restart_matches_oracle(gpu_lib, fused):
+    """The restart of a learned start (R6b) on the device: a network whose
+    output is always class 0 starts every pair at factor 1; on the wavy and
+    swapped 2-block cases that search stops without improvement, the pair
+    restarts from 16 and reaches a lower cut, exactly as the oracle's
+    restarted search does (records, result, partition), with the launch
+    chains (speculative slots after the restart) and with fused rounds."""
+    import torch
+    from tests.test_oracle import _swapped, _wavy
+
+    c = gpu_lib.Context()
+    try:
+        c.set_fused(fused)
+        w = np.zeros(gpu_lib.fr_mlp_num_params(), dtype=np.float32)
+        w[-5] = 10.0  # b3: class 0 (factor 1) wins on every input
+        gpu_lib.fr_mlp_set_weights(c, w)
+        p = dict(area_mode=0, depth=0, alpha=16, alpha_max=16, adaptive=1, max_iters=8,
+                 eps_ppm=30000)
+        for g, part in (_wavy(902, 0.2, 1), _wavy(911, 0.2, 1), _swapped(715)):
+            print(f"restart case n={g.n} fused={fused}", flush=True)
+            o = oracle.refine_pair(g, part, 2, 0, 1, dict(p, alpha=1, restart_alpha=16),
+                                   want_side=False)
+            plain1 = oracle.refine_pair(g, part, 2, 0, 1, dict(p, alpha=1), want_side=False)
+            assert o.result["cut_after"] < plain1.result["cut_after"]
+            dpart = torch.as_tensor(part.copy()).cuda()
+            res, tr = gpu_lib.flow_refine_batch(c, gpu_lib.DeviceGraph.from_host(g), dpart, 2,
+                                                [(0, 1)], gpu_lib.params(**p, use_mlp=1))
+            assert res[0]["start_alpha"] == 1
+            for key in KEYS:
+                assert res[0][key] == o.result[key], key
+            assert tr[0] == o.trace
+            assert np.array_equal(dpart.cpu().numpy(), o.part)
+            assert gpu_lib.stats_dict(c)["restarts"] == 1
+    finally:
+        c.close()
