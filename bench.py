@@ -227,9 +227,9 @@ def run_batched(args, fr, torch, gen, cid="C3"):
 
 def run_learned(args, fr, torch, gen):
     """One matching-round sweep of C4 (2D RGG n=2^22, mean degree 8, weights
-    1..10, k=64 RCB + 2 % noise): every colour class batched, once with the
-    plain adaptive search from alpha' = 16 and once starting at the learned
-    factor."""
+    1..10, k=64 RCB + 2 % noise): every colour class batched, with the plain
+    adaptive search from alpha' = 16, from constant starts 8 and 4, and from
+    the learned factor with and without the restart from alpha'."""
     w = gen.config("C4")
     ctx = fr.Context()
     ctx.set_validation(False)
@@ -239,15 +239,16 @@ def run_learned(args, fr, torch, gen):
     edges_q, colour = fr.fr_quotient_matchings(ctx, dg, part0, w.k)
     classes = sorted(set(colour.tolist()))
     out = {}
-    runs = {"plain": (0, None), "constant_8": (0, 8), "constant_4": (0, 4), "learned": (1, None)}
-    for name, (use, alpha) in runs.items():
+    runs = {"plain": (0, None, 0), "constant_8": (0, 8, 0), "constant_4": (0, 4, 0),
+            "learned": (1, None, 1), "learned_no_restart": (1, None, 0)}
+    for name, (use, alpha, restart) in runs.items():
         pc = {k: w.params[k] for k in ("area_mode", "depth", "alpha", "alpha_max", "adaptive",
                                        "max_iters", "eps_ppm")}
         if alpha is not None:
             pc["alpha"] = alpha
-        prm = fr.params(**pc, use_mlp=use)
+        prm = fr.params(**pc, use_mlp=use, mlp_restart=restart)
         dpart = part0.clone()
-        solves = edges = 0
+        solves = edges = restarts = 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for c in classes:
@@ -255,17 +256,19 @@ def run_learned(args, fr, torch, gen):
             res, _ = fr.flow_refine_batch(ctx, dg, dpart, w.k, pairs, prm)
             solves += sum(r["iters"] for r in res)
             edges += sum(r["region_edges"] for r in res)
+            restarts += fr.stats_dict(ctx)["restarts"]
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         import oracle  # cut accounting only (sum of cut edge weights)
         out[name] = {
-            "seconds": dt, "flow_solves": solves, "region_edges": edges,
+            "seconds": dt, "flow_solves": solves, "region_edges": edges, "restarts": restarts,
             "region_edges_per_s": edges / dt,
             "total_cut": oracle.total_cut(w.graph, dpart.cpu().numpy())}
     ctx.close()
     out["workload"] = ("C4: 2D RGG n=2^22 mean degree 8, weights 1..10, k=64 RCB + 2% noise, "
                        f"one sweep of {len(classes)} matching rounds, eps 3%, alpha' 16 adaptive; "
-                       "starts: plain 16, constant 8, constant 4, learned")
+                       "starts: plain 16, constant 8, constant 4, learned with and without "
+                       "the restart from 16")
     out["training"] = {"loss": report.get("loss"), "cost_lambda": report.get("cost_lambda"),
                        "held_out_sweeps": report.get("validation_sweeps")}
     out["speedup"] = out["plain"]["seconds"] / out["learned"]["seconds"]
@@ -274,14 +277,15 @@ def run_learned(args, fr, torch, gen):
 
 
 C5_WORKLOAD = ("C5: 2D RGG n=2^24 mean degree 6 unit weights, k=256 RCB + 1% noise, eps 3%, "
-               "alpha' 16 adaptive with learned start, batched rounds over the quotient-graph "
+               "alpha' 16 adaptive with learned start (restarted from 16 where it stops without "
+               "improvement), batched rounds over the quotient-graph "
                "colour classes, swept until no pair improves")
 
 
-def c5_params(fr, w, use_mlp):
+def c5_params(fr, w, use_mlp, restart=1):
     return fr.params(**{k: w.params[k] for k in ("area_mode", "depth", "alpha", "alpha_max",
                                                  "adaptive", "max_iters", "eps_ppm")},
-                     use_mlp=use_mlp)
+                     use_mlp=use_mlp, mlp_restart=restart)
 
 
 def run_c5_headline(args, fr, torch, gen):
@@ -335,6 +339,24 @@ def run_c5_headline(args, fr, torch, gen):
     ctx.close()
     return dict(w=w, wall=wall, step_ms=step_ms, cut0=int(oracle.total_cut(w.graph, w.part)),
                 cut=int(cut), repeatable=same, part=first, **tot)
+
+
+def run_c5_no_restart(args, fr, torch, w):
+    """The headline's sweep once more without the restart of learned starts:
+    the learned start's saving and its cut loss on this family."""
+    ctx = fr.Context()
+    ctx.set_validation(False)
+    fr.load_trained_mlp(ctx)
+    dg = fr.DeviceGraph.from_host(w.graph)
+    dpart = torch.as_tensor(w.part).cuda()
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    cut, stats = fr.flow_refine_sweep(ctx, dg, dpart, w.k, c5_params(fr, w, 1, restart=0),
+                                      args.max_sweeps)
+    out = {"ms": (time.perf_counter() - ts) * 1e3, "cut_after": int(cut), "sweeps": int(stats[0]),
+           "flow_solves": int(stats[1]), "region_edges": int(stats[3])}
+    ctx.close()
+    return out
 
 
 def run_c5_cpu_baseline(args, fr, torch, w):
@@ -808,6 +830,9 @@ def main():
         line["bit_exact_vs_oracle"] = line["cpu_baseline"]["bit_exact_vs_gpu_round"]
         progress(f"C5 CPU baseline: {line['cpu_baseline']['seconds']:.1f} s on "
                  f"{line['cpu_baseline']['cores']} threads, bit-exact {line['bit_exact_vs_oracle']}")
+    if not args.no_learned:
+        line["c5_learned_without_restart"] = run_c5_no_restart(args, fr, torch, h["w"])
+        progress("C5 sweep without restarts done")
     del h
     if not args.no_c2:
         line["c2_plain"] = c2_leg(argparse.Namespace(**dict(vars(args), steps=args.c2_steps,

@@ -109,11 +109,7 @@ typedef struct {
   int32_t adaptive;  /* 0: one flow solve; 1: adaptive flow iterations */
   int32_t max_iters; /* flow solves per pair, in [1, 64] */
   int32_t eps_ppm;   /* imbalance eps in parts per million (3 % = 30000), >= 0 */
-  int32_t use_mlp;   /* start each pair at the learned factor (needs loaded weights).
-                      * A pair that started below alpha, has applied nothing
-                      * and meets a feasible cut without improvement then
-                      * continues once from alpha (the plain search's start)
-                      * within the same max_iters, instead of stopping there. */
+  int32_t use_mlp;   /* start each pair at the learned factor (needs loaded weights) */
   /* Most balanced minimum cut (Sec. 4.1.1; "balanced adaptive flow
    * iterations" when adaptive = 1).  0: the candidate is the smallest source
    * set.  r > 0: after each max flow, the strongly connected components of
@@ -192,6 +188,13 @@ typedef struct {
    * (else FR_E_OVERFLOW).  The paper uses a = 10. */
   int32_t mt_alpha;
   int32_t mt_seed;
+  /* With use_mlp, 1: a pair that started below alpha, has applied nothing and
+   * meets a feasible cut without improvement continues once from alpha (the
+   * plain search's start) within the same max_iters, so the learned start
+   * never ends a pair's search that the plain search would have continued
+   * from a larger corridor; 0: it stops there (the adaptive rule of
+   * Sec. 4.1 as is).  Must be 0 or 1. */
+  int32_t mlp_restart;
 } fr_params;
 
 #define FR_TERM_PINNED 0

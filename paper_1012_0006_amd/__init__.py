@@ -38,7 +38,7 @@ class FrParams(ctypes.Structure):
     _fields_ = [(f, i32) for f in ("area_mode", "depth", "alpha", "alpha_max", "adaptive",
                                    "max_iters", "eps_ppm", "use_mlp", "mb_reps", "mb_seed",
                                    "fm_limit", "fm_seed", "active_blocks", "cut_side",
-                                   "terminals", "mt_alpha", "mt_seed")]
+                                   "terminals", "mt_alpha", "mt_seed", "mlp_restart")]
 
 
 class FrResult(ctypes.Structure):
@@ -162,7 +162,7 @@ def params(**kw) -> FrParams:
     bits are used)."""
     d = dict(area_mode=0, depth=0, alpha=16, alpha_max=16, adaptive=1, max_iters=16,
              eps_ppm=30000, use_mlp=0, mb_reps=0, mb_seed=0, fm_limit=0, fm_seed=0,
-             active_blocks=0, cut_side=0, terminals=0, mt_alpha=0, mt_seed=0)
+             active_blocks=0, cut_side=0, terminals=0, mt_alpha=0, mt_seed=0, mlp_restart=1)
     d.update(kw)
     for f in ("mb_seed", "fm_seed", "mt_seed"):
         seed = int(d[f]) & 0xFFFFFFFF

@@ -439,7 +439,7 @@ static int32_t check_params(const fr_params *p) {
       p->max_iters < 1 || p->max_iters > FR_MAX_ITERS || p->eps_ppm < 0 || p->eps_ppm > 100000000 ||
       p->mb_reps < 0 || p->mb_reps > FR_MB_MAX_REPS || p->fm_limit < 0 || p->cut_side < 0 ||
       p->cut_side > 2 || (p->terminals != FR_TERM_PINNED && p->terminals != FR_TERM_CONTRACTED) ||
-      p->mt_alpha < 0)
+      p->mt_alpha < 0 || (p->mlp_restart != 0 && p->mlp_restart != 1))
     return FR_E_INVALID_ARG;
   return FR_OK;
 }
@@ -524,7 +524,7 @@ static KArgs call_args(fr_context *c, const DevBufs &d, const fr_graph *g, int32
     A.area_mode = p->area_mode;
     A.depth = p->depth;
     A.alpha_max = p->alpha_max;
-    A.restart_alpha = p->use_mlp ? std::min(p->alpha, p->alpha_max) : 0;
+    A.restart_alpha = p->use_mlp && p->mlp_restart ? std::min(p->alpha, p->alpha_max) : 0;
     A.adaptive = p->adaptive;
     A.max_iters = p->max_iters;
     A.eps_ppm = p->eps_ppm;
