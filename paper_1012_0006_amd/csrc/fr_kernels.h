@@ -1320,7 +1320,10 @@ __global__ void __launch_bounds__(256) k_bnd(KArgs A, int32_t it) {
       }
       if (p0 < 0) y2 = -1;
       const int32_t E1 = A.xadj[last];
-      const int32_t x1 = u + 1 < last ? __shfl(x0, lane + 1) : E1;
+      // the next lane's arc start, shuffled by the whole wave (a lane that
+      // reads an inactive lane gets 0)
+      const int32_t xn = __shfl(x0, (lane + 1) & 63);
+      const int32_t x1 = u + 1 < last ? xn : E1;
       bool bnd;
       int64_t cw;
       chunk_boundary(A, x0, y2, __shfl(x0, 0), E1, s_bnd + wl, s_cw + wl, bnd, cw);

@@ -365,8 +365,22 @@ def test_boundary_pass_modes(gpu_lib, spec):
     live slot) while the live pairs cover at least a quarter of the graph, and
     the live pairs' vertex lists otherwise: one pair of a 64-way partition
     without speculation takes the lists, a whole matching round the vertex
-    walk (and the lists once most pairs stopped); both against the oracle."""
+    walk (and the lists once most pairs stopped); both against the oracle.
+    The pass's work counters count each live pair's vertices and arcs of its
+    two blocks once per launch: for one pair, arcs over vertices is exactly
+    that pair's ratio; for the round, it lies within the degree range."""
     import torch
+
+    def counters_ok(c, g, part, pairs):
+        st = gpu_lib.stats_dict(c)
+        deg = np.diff(g.xadj)
+        nv, na = st["bnd_verts"], st["bnd_arcs"]
+        assert nv > 0 and na > 0
+        if len(pairs) == 1:
+            mine = np.isin(part, pairs[0])
+            assert na * int(mine.sum()) == nv * int(deg[mine].sum())
+        else:
+            assert nv * int(deg.min()) <= na <= nv * int(deg.max())
 
     g = gen.rgg(1 << 14, 2, 8.0, 57, 1, 4)
     part = gen.rcb(g, 64)
@@ -380,6 +394,12 @@ def test_boundary_pass_modes(gpu_lib, spec):
         c.set_fused(False)  # the boundary pass of the launch chains
         a, b = (int(x) for x in edges[0])
         _compare_pair(gpu_lib, c, g, part, 64, a, b, p)
+        counters_ok(c, g, part, [(a, b)])
+        # the 64 blocks merged into two halves: the pair covers the graph, so
+        # every pass walks all vertices
+        part2 = (part >= 32).astype(np.int32)
+        _compare_pair(gpu_lib, c, g, part2, 2, 0, 1, p)
+        counters_ok(c, g, part2, [(0, 1)])
         cls = int(np.argmax(np.bincount(colour)))
         pairs = [tuple(e) for e, cc in zip(edges.tolist(), colour) if cc == cls]
         print(f"round of {len(pairs)} pairs, speculation {spec}", flush=True)
@@ -393,5 +413,6 @@ def test_boundary_pass_modes(gpu_lib, spec):
                 assert res[i][key] == ores[i][key], (i, key)
             assert trace[i] == otr[i]
         assert np.array_equal(dpart.cpu().numpy(), opart)
+        counters_ok(c, g, part, pairs)
     finally:
         c.close()
