@@ -309,7 +309,7 @@ def run_c5_headline(args, fr, torch, gen):
         fr.flow_refine_sweep(ctx, dg, dpart, w.k, prm, args.max_sweeps)
     torch.cuda.synchronize()
     tot = dict(edges=0, kern_ms=0.0, bytes=0, launches=0, solves=0, sweeps=0, corridor_ms=0.0,
-               build_ms=0.0, sweeps_pr=0, relabels=0)
+               build_ms=0.0, sweeps_pr=0, relabels=0, gr_levels=0)
     step_ms, first, cut = [], None, None
     same = True
     t0 = time.perf_counter()
@@ -329,6 +329,7 @@ def run_c5_headline(args, fr, torch, gen):
         tot["build_ms"] += st["build_ms"]
         tot["sweeps_pr"] += st["sweeps"]
         tot["relabels"] += st["relabels"]
+        tot["gr_levels"] += st["gr_levels"]
         out = dpart.cpu().numpy()
         if first is None:
             first = out
@@ -576,6 +577,11 @@ def c2_leg(args, fr, torch, gen):
         "solves_per_step": plain["result"]["iters"],
         "sweeps_per_step": plain["stats"]["sweeps"],
         "relabels_per_step": plain["stats"]["relabels"],
+        "relabel_bfs_levels_per_step": plain["stats"]["gr_levels"],
+        "per_recorded_solve": {
+            "push_relabel_sweeps": plain["stats"]["sweeps"] / plain["result"]["iters"],
+            "global_relabels": plain["stats"]["relabels"] / plain["result"]["iters"],
+            "relabel_bfs_levels": plain["stats"]["gr_levels"] / plain["result"]["iters"]},
         "roofline": roofline(plain["bytes"], plain["kern_ms"], plain["launches"],
                              load_traffic("C2")),
         "whole_path_gb_per_s": plain["path_bytes"] / (plain["path_ms"] / 1e3) / 1e9,
@@ -824,6 +830,11 @@ def main():
                               "flow_kernel": h["kern_ms"] / args.steps},
         "push_relabel_sweeps_per_step": h["sweeps_pr"] // args.steps,
         "global_relabels_per_step": h["relabels"] // args.steps,
+        # over the recorded solves; the work of discarded speculative solves
+        # is included in the sums
+        "per_recorded_solve": {"push_relabel_sweeps": h["sweeps_pr"] / max(1, h["solves"]),
+                      "global_relabels": h["relabels"] / max(1, h["solves"]),
+                      "relabel_bfs_levels": h["gr_levels"] / max(1, h["solves"])},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = run_c5_cpu_baseline(args, fr, torch, h["w"])
