@@ -243,6 +243,18 @@ typedef struct {
                               1), 2 period], or when the active list runs dry */
   int32_t mb_lds;          /* most balanced cut: 1 = component graph in LDS when it fits,
                               0 = always in device memory */
+  int32_t slice_us;        /* sliced rounds, 0..10^7 us (0 = off): a flow-kernel launch
+                              gives each solve this much device time, then stops it at
+                              the next global relabel that is due anyway, if by then at
+                              most a quarter of the launch's solves still run; it
+                              continues in the next launch of the chain, while the pairs
+                              whose solves ended start their next adaptive iteration,
+                              so they no longer wait for the round's slowest pair.  The
+                              chain then runs until every pair has stopped (the host
+                              reads the count back every four launches after the first
+                              max_iters).  Rounds of one pair, captured sweeps, most
+                              balanced cuts, fused rounds and the entry point without
+                              device allocation run unsliced. */
 } fr_tuning;
 
 typedef struct fr_context fr_context;
@@ -398,10 +410,12 @@ int32_t fr_set_timing(fr_context *ctx, int32_t on);
  *   kernels time in ns, [9] free vertices, [10] their residual components,
  *   [11] solves whose component graph (more than 2,048 components) was kept
  *   in device memory instead of LDS; [12] FM moves made, [13] FM moves kept;
- *   [14] flow-kernel launches (one per adaptive iteration of each round),
- *   or round-kernel launches (one per round) with fused rounds; [15] pairs
+ *   [14] flow-kernel launches (one per adaptive iteration of each round,
+ *   more with sliced rounds), or round-kernel launches (one per round) with
+ *   fused rounds; [15] pairs
  *   whose learned start was restarted from alpha (use_mlp);
- *   [28] multi-try searches, [29] multi-try moves made, [30] kept;
+ *   [28] multi-try searches, [29] multi-try moves made, [30] kept; [31]
+ *   solves continued in a later launch (sliced rounds);
  *   [16..27] vertices and arcs touched: boundary scan, corridor BFS, network
  *   build, push/relabel sweeps, global relabels, residual closure (vertices
  *   then arcs for each); the rest 0. */

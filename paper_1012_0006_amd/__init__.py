@@ -56,7 +56,7 @@ class FrSolve(ctypes.Structure):
 
 class FrTuning(ctypes.Structure):
     _fields_ = [(f, i32) for f in ("block_threads", "blocks_per_cu", "tpv", "relabel_period",
-                                   "mb_lds")]
+                                   "mb_lds", "slice_us")]
 
 
 EXPORTS = ("fr_create", "fr_destroy", "fr_strerror", "flow_refine_pair",
@@ -232,8 +232,8 @@ class Context:
 
     # -- tuning ---------------------------------------------------------
     def set_tuning(self, block_threads=1024, blocks_per_cu=2, tpv=8, relabel_period=100,
-                   mb_lds=1):
-        t = FrTuning(block_threads, blocks_per_cu, tpv, relabel_period, mb_lds)
+                   mb_lds=1, slice_us=8000):
+        t = FrTuning(block_threads, blocks_per_cu, tpv, relabel_period, mb_lds, slice_us)
         _check(self.lib.fr_set_tuning(self.handle, ctypes.byref(t)), "fr_set_tuning")
 
     def get_tuning(self) -> dict:
@@ -276,7 +276,7 @@ def stats_dict(ctx) -> dict:
              mb_kernel_ms=cnt[8] / 1e6, mb_free=cnt[9], mb_comp=cnt[10], mb_big=cnt[11],
              fm_steps=cnt[12], fm_kept=cnt[13], flow_launches=cnt[14], restarts=cnt[15],
              mt_searches=cnt[28],
-             mt_moves=cnt[29], mt_kept=cnt[30])
+             mt_moves=cnt[29], mt_kept=cnt[30], slices=cnt[31])
     d.update({k: cnt[16 + i] for i, k in enumerate(WORK_KEYS)})
     return d
 
@@ -499,7 +499,8 @@ def fr_autotune(ctx: Context, graph: DeviceGraph, part, k: int, pairs, prm: FrPa
     kept in the context.  Returns (best index, per-candidate ms)."""
     gs = graph.struct()
     pr = _i32(pairs).reshape(-1)
-    cand = (FrTuning * len(candidates))(*[FrTuning(**{"mb_lds": 1, **c}) for c in candidates])
+    cand = (FrTuning * len(candidates))(*[FrTuning(**{"mb_lds": 1, "slice_us": 8000, **c})
+                                          for c in candidates])
     ms = (ctypes.c_double * len(candidates))()
     best = i32(-1)
     _check(ctx.lib.fr_autotune(ctx.handle, ctypes.byref(gs), _part_arg(part, True), k,
@@ -509,12 +510,15 @@ def fr_autotune(ctx: Context, graph: DeviceGraph, part, k: int, pairs, prm: FrPa
 
 
 DEFAULT_CANDIDATES = (
-    dict(block_threads=1024, blocks_per_cu=2, tpv=8, relabel_period=100),
-    dict(block_threads=1024, blocks_per_cu=2, tpv=8, relabel_period=70),
-    dict(block_threads=1024, blocks_per_cu=2, tpv=4, relabel_period=200),
-    dict(block_threads=1024, blocks_per_cu=2, tpv=2, relabel_period=200),
-    dict(block_threads=512, blocks_per_cu=4, tpv=4, relabel_period=200),
-    dict(block_threads=256, blocks_per_cu=8, tpv=4, relabel_period=200),
+    dict(block_threads=1024, blocks_per_cu=2, tpv=8, relabel_period=100, slice_us=8000),
+    dict(block_threads=1024, blocks_per_cu=2, tpv=8, relabel_period=70, slice_us=8000),
+    dict(block_threads=1024, blocks_per_cu=2, tpv=8, relabel_period=100, slice_us=0),
+    dict(block_threads=1024, blocks_per_cu=2, tpv=8, relabel_period=100, slice_us=2000),
+    dict(block_threads=1024, blocks_per_cu=2, tpv=8, relabel_period=100, slice_us=16000),
+    dict(block_threads=1024, blocks_per_cu=2, tpv=4, relabel_period=200, slice_us=8000),
+    dict(block_threads=1024, blocks_per_cu=2, tpv=2, relabel_period=200, slice_us=8000),
+    dict(block_threads=512, blocks_per_cu=4, tpv=4, relabel_period=200, slice_us=8000),
+    dict(block_threads=256, blocks_per_cu=8, tpv=4, relabel_period=200, slice_us=8000),
 )
 
 

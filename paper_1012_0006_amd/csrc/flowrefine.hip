@@ -92,7 +92,7 @@ struct fr_context {
   // grids of the whole-graph passes: every workgroup resident at once (each
   // wave walks one contiguous run of vertex chunks)
   int g_bnd = 0, g_bstat = 0, g_fstat = 0, g_union = 0;
-  fr_tuning tune{1024, 2, 8, 100, 1};
+  fr_tuning tune{1024, 2, 8, 100, 1, 8000};
   int validate = 1;
   int mlp_loaded = 0;
   DevBufs d;
@@ -100,7 +100,7 @@ struct fr_context {
   int32_t stamp = 2;
   double wall_khz = 100000.0;  // device constant-rate clock
   int64_t graph_launches = 0;
-  hipEvent_t itev[5 * FR_MAX_ITERS] = {};
+  std::vector<hipEvent_t> itev;  // five per launch of the per-iteration chain (timed calls)
   int32_t timed_iters = 0;
   int speculate = 1;
   int fused = 0;  // rounds as one persistent launch (k_round) where possible
@@ -329,7 +329,7 @@ extern "C" int32_t fr_create(int32_t device, void *hip_stream, fr_context **out)
 #define A_(p, cnt) \
   if (e == hipSuccess) e = dalloc(&d.p, cnt)
   A_(trace, (int64_t)FR_MAX_PAIRS * FR_MAX_ITERS); A_(ucnt, FR_MAX_PAIRS);
-  A_(qctr, 2 * FR_MAX_ITERS); A_(pcnt, 2 * FR_MAX_PAIRS); A_(pacc, (int64_t)PA_N * FR_MAX_PAIRS);
+  A_(qctr, 4 * FR_MAX_ITERS); A_(pcnt, 2 * FR_MAX_PAIRS); A_(pacc, (int64_t)PA_N * FR_MAX_PAIRS);
   A_(act, FR_MAX_PAIRS); A_(nact, 1); A_(vpre, FR_MAX_PAIRS + 1); A_(cpre, FR_MAX_PAIRS + 1);
   A_(mpre, FR_MAX_PAIRS + 1);
   A_(srec, FR_MAX_PAIRS);
@@ -340,7 +340,8 @@ extern "C" int32_t fr_create(int32_t device, void *hip_stream, fr_context **out)
 #undef A_
   if (e == hipSuccess) e = hipHostMalloc((void **)&c->h_ctl, sizeof(Ctl), hipHostMallocDefault);
   for (int i = 0; i < 4 && e == hipSuccess; i++) e = hipEventCreate(&c->ev[i]);
-  for (int i = 0; i < 5 * FR_MAX_ITERS && e == hipSuccess; i++) e = hipEventCreate(&c->itev[i]);
+  c->itev.assign(5 * FR_MAX_ITERS, nullptr);
+  for (size_t i = 0; i < c->itev.size() && e == hipSuccess; i++) e = hipEventCreate(&c->itev[i]);
   if (e != hipSuccess) {
     fr_destroy(c);
     return FR_E_OOM;
@@ -369,8 +370,8 @@ extern "C" int32_t fr_destroy(fr_context *c) {
   if (c->h_ctl) (void)hipHostFree(c->h_ctl);
   for (int i = 0; i < 4; i++)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
-  for (int i = 0; i < 5 * FR_MAX_ITERS; i++)
-    if (c->itev[i]) (void)hipEventDestroy(c->itev[i]);
+  for (hipEvent_t ev : c->itev)
+    if (ev) (void)hipEventDestroy(ev);
   if (c->cs) (void)hipStreamDestroy(c->cs);
   delete c;
   return FR_OK;
@@ -385,6 +386,7 @@ extern "C" int32_t fr_set_tuning(fr_context *c, const fr_tuning *t) {
     return FR_E_INVALID_ARG;
   if (t->relabel_period < 1 || t->relabel_period > 1000000) return FR_E_INVALID_ARG;
   if (t->mb_lds != 0 && t->mb_lds != 1) return FR_E_INVALID_ARG;
+  if (t->slice_us < 0 || t->slice_us > 10000000) return FR_E_INVALID_ARG;
   c->tune = *t;
   return FR_OK;
 }
@@ -574,6 +576,7 @@ static KArgs call_args(fr_context *c, const DevBufs &d, const fr_graph *g, int32
   A.ctl = d.ctl;
   A.tpv = c->tune.tpv;
   A.relabel_period = c->tune.relabel_period;
+  A.slice_ticks = (int64_t)((double)c->tune.slice_us * c->wall_khz / 1000.0);
   A.max_sweeps = 4 * ((int64_t)g->n + 16) + 1000000;
   A.side_out = d.side;
   return A;
@@ -728,18 +731,47 @@ static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t s
   const int blocks = blocks_of(c, A.P);
   const iter_fn corr = corr_kernel(tpb), flow = flow_kernel(tpb);
   const bool fused = c->fused && A.mb_reps == 0 && A.W == 1;
+  // sliced rounds need the host between launches (how many follow is read
+  // back), so a captured round passes slice_ticks = 0; a round of one pair
+  // has no other pair to wait for
+  const bool sliced = A.slice_ticks > 0 && !fused && A.mb_reps == 0 && A.P / A.W > 1;
+  if (!sliced) A.slice_ticks = 0;
   if (fused) {
     // every pair's whole adaptive loop in one launch; the events put its
     // time in the flow-kernel slot
-    hipEvent_t *ev = c->itev;
+    hipEvent_t *ev = c->itev.data();
     if (timed)
       for (int j = 0; j < 3; j++) HIPCHK(hipEventRecord(ev[j], st));
     hipLaunchKernelGGL(round_kernel(tpb), dim3(blocks), dim3(tpb), 0, st, A);
     if (timed)
       for (int j = 3; j < 5; j++) HIPCHK(hipEventRecord(ev[j], st));
   }
-  for (int32_t it = 0; it < (fused ? 0 : A.max_iters); it++) {
-    hipEvent_t *ev = c->itev + 5 * it;
+  // launches of the per-iteration chain: max_iters when every launch runs
+  // its solves out (each is one adaptive iteration of every pair still
+  // iterating); sliced, a pair's iteration may span launches, so more
+  // follow, four at a time, while an entry still iterates
+  int32_t launches = fused ? 0 : A.max_iters;
+  const int32_t max_launches = 256 * A.max_iters;
+  for (int32_t it = 0;; it++) {
+    if (it >= launches) {
+      if (!sliced) break;
+      hipLaunchKernelGGL(k_live, dim3(1), dim3(1024), 0, st, A);
+      HIPCHK(hipMemcpyAsync(&c->h_ctl->live, &c->d.ctl->live, sizeof(int32_t),
+                            hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (c->h_ctl->live == 0) break;
+      if (it >= max_launches) {
+        c->timed_iters = timed ? it : 0;
+        return FR_E_SOLVER_LIMIT;
+      }
+      launches = it + 4;
+    }
+    if (timed && (size_t)(5 * it + 5) > c->itev.size()) {
+      const size_t n0 = c->itev.size();
+      c->itev.resize(n0 + 5 * FR_MAX_ITERS, nullptr);
+      for (size_t i = n0; i < c->itev.size(); i++) HIPCHK(hipEventCreate(&c->itev[i]));
+    }
+    hipEvent_t *ev = timed ? c->itev.data() + 5 * it : nullptr;
     if (timed) HIPCHK(hipEventRecord(ev[0], st));
     hipLaunchKernelGGL(k_iter_begin, dim3(1), dim3(1024), 0, st, A, it);
     hipLaunchKernelGGL(k_bnd, dim3(c->g_bnd), dim3(256), 0, st, A, it);
@@ -770,7 +802,7 @@ static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t s
     hipLaunchKernelGGL(k_mt, dim3(1), dim3(WAVE), 0, st, A);
   }
   HIPCHK(hipGetLastError());
-  c->timed_iters = timed ? (fused ? 1 : A.max_iters) : 0;
+  c->timed_iters = timed ? (fused ? 1 : launches) : 0;
   return FR_OK;
 }
 
@@ -780,7 +812,7 @@ static void iteration_times(fr_context *c, double out[4]) {
   out[0] = out[1] = out[2] = out[3] = 0.0;
   for (int it = 0; it < c->timed_iters; it++) {
     float t = 0.f;
-    hipEvent_t *ev = c->itev + 5 * it;
+    hipEvent_t *ev = c->itev.data() + 5 * it;
     for (int j = 0; j < 4; j++)
       if (hipEventElapsedTime(&t, ev[j], ev[j + 1]) == hipSuccess) out[j] += t;
   }
@@ -833,6 +865,7 @@ static void add_entry_stats(fr_context *c, const PairState *ps, size_t count) {
     C[12] += s.fm_steps;
     C[13] += s.fm_kept;
     C[15] += s.restarted;
+    C[31] += s.slices;
     C[28] += s.mt_searches;
     C[29] += s.mt_moves;
     C[30] += s.mt_kept;
@@ -1103,6 +1136,7 @@ static int32_t refine(fr_context *c, const fr_graph *g, int32_t *part, int32_t k
   }
   KArgs R = round_args(c, A, 0, V, stamp0, true);
   R.mt_stamp0 = mts;
+  if (carve) R.slice_ticks = 0;
   (void)hipEventRecord(c->ev[1], st);
   if ((rc = enqueue_round(c, R, p->use_mlp != 0, st, true))) return rc;
   (void)hipEventRecord(c->ev[2], st);
@@ -1393,6 +1427,7 @@ extern "C" int32_t flow_refine_sweep(fr_context *c, const fr_graph *g, int32_t *
         KArgs R = round_args(c, A, offs[r], offs[r + 1] - offs[r],
                              stamp0 + r * (2 * p->max_iters + 2), false);
         R.mt_stamp0 = mts[(size_t)r];
+        R.slice_ticks = 0;  // captured: no host between the launches
         cap_rc = enqueue_round(c, R, p->use_mlp != 0, st, false);
       }
       hipError_t ce = hipStreamEndCapture(st, &graph);

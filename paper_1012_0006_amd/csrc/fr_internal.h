@@ -45,7 +45,14 @@ struct PairState {
   // multi-try FM after the round (kept on the pair's first entry): searches
   // started, moves made, moves kept after the rollbacks
   int64_t mt_searches, mt_moves, mt_kept;
-  int64_t spare2;
+  // sliced rounds: the phase of the entry's current iteration (0 corridor
+  // due, 1 flow under way, 2 solved, waiting for the pair's other slots),
+  // the iterations it started (its corridor marks' stamp), the sweeps and
+  // relabel interval of a solve that spans launches, and how often its
+  // solves continued in a later launch
+  int32_t phase, iter;
+  int64_t solve_sweeps;
+  int32_t rp_eff, slices;
 };
 
 // work counters: the data each phase of a solve touches
@@ -85,7 +92,7 @@ struct Ctl {
   int32_t diag;         // which internal check raised err (DIAG_*)
   int32_t bad_part;     // part[] holds an id outside [0, k)
   int32_t bad_graph;    // set by the validation kernel
-  int32_t pad;
+  int32_t live;         // entries still iterating (sliced rounds, read by the host)
   int64_t cV;           // total vertex weight
   int64_t maxc;         // max vertex weight
 };
@@ -177,6 +184,9 @@ struct KArgs {
   Ctl *ctl;
   // launch
   int32_t tpv, relabel_period;
+  // sliced rounds: device-clock ticks an entry's flow may run in one launch
+  // before it stops at the next due global relabel (0: run to the end)
+  int64_t slice_ticks;
   int64_t max_sweeps;
   int8_t *side_out;
 };

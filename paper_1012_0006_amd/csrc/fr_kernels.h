@@ -312,7 +312,7 @@ __global__ void __launch_bounds__(1024) k_round_init(KArgs A) {
   for (int i = threadIdx.x; i < A.P; i += blockDim.x) A.ucnt[i] = 0;
   if (A.fstat)
     for (int i = threadIdx.x; i < 4 * A.P; i += blockDim.x) A.fstat[i] = 0;
-  for (int i = threadIdx.x; i < 2 * A.max_iters; i += blockDim.x) A.queue[i] = 0;
+  for (int i = threadIdx.x; i < 4 * A.max_iters; i += blockDim.x) A.queue[i] = 0;
   for (int i = threadIdx.x; i < A.P * PA_N; i += blockDim.x) A.pacc[i] = 0;
   for (int i = threadIdx.x; i < 2 * A.P; i += blockDim.x) A.pcnt[i] = 0;
   __syncthreads();
@@ -574,6 +574,7 @@ struct SolveShared {
   int32_t nr;                     // corridor size
   int32_t nsnk;                   // sink-border vertices
   int32_t pair;                   // queue slot
+  int32_t slice_end;              // the flow stops here until the next launch
   int32_t state[2];               // BFS: 1 = still expanding
   int32_t mode[2];                // BFS: level take mode (0 none, 1 all, 2 prefix)
   int32_t digit;
@@ -1133,6 +1134,11 @@ __device__ __forceinline__ PairView make_view(const KArgs &A, int32_t p) {
 }
 
 // corridor marks and local ids of entry p (its slot's arrays)
+// Corridor mark stamp of entry p's current iteration (two per iteration:
+// S in the corridor, S + 1 cut off from it)
+__device__ __forceinline__ int32_t stamp_of(const KArgs &A, int32_t p) {
+  return A.stamp0 + 2 * A.ps[p].iter;
+}
 __device__ __forceinline__ int32_t *mark_of(const KArgs &A, int32_t p) {
   return A.mark + (int64_t)(p % A.W) * A.mstride;
 }
@@ -1168,13 +1174,18 @@ __device__ __forceinline__ void grid_items(const KArgs &A, const int64_t *pre, F
 // pair order, and the prefix sums of their union sizes.
 __global__ void __launch_bounds__(1024) k_iter_begin(KArgs A, int32_t it) {
   __shared__ int64_t s_scan[17];
-  (void)it;
   const int P = A.P;
+  // this launch's counters (a ring over max_iters launches): the corridor
+  // and flow queues, the flow's running and started entries
+  if (threadIdx.x < 4) A.queue[4 * (it % A.max_iters) + threadIdx.x] = 0;
   const int per = (P + blockDim.x - 1) / blockDim.x;
   const int lo = threadIdx.x * per, hi = min(lo + per, P);
+  // the entries whose next corridor is due (the others are idle, or in a
+  // solve that continues from an earlier launch)
+  auto due = [&](int i) { return !A.ps[i].done && A.ps[i].phase == 0; };
   int64_t cnt = 0, sz = 0;
   for (int i = lo; i < hi; i++)
-    if (!A.ps[i].done) {
+    if (due(i)) {
       cnt++;
       sz += A.voff[i + 1] - A.voff[i];
     }
@@ -1182,7 +1193,7 @@ __global__ void __launch_bounds__(1024) k_iter_begin(KArgs A, int32_t it) {
   int64_t rc = block_exscan64(cnt, &tc, s_scan);
   int64_t rs = block_exscan64(sz, &ts, s_scan);
   for (int i = lo; i < hi; i++)
-    if (!A.ps[i].done) {
+    if (due(i)) {
       A.act[rc] = i;
       A.vpre[rc] = rs;
       rc++;
@@ -1192,12 +1203,12 @@ __global__ void __launch_bounds__(1024) k_iter_begin(KArgs A, int32_t it) {
     *A.nact = (int32_t)tc;
     A.vpre[tc] = ts;
   }
-  // per block of the round: its pair's first entry while a slot still
-  // iterates, the other block and the side (the boundary pass's lookup)
+  // per block of the round: its pair's first entry while a slot's corridor
+  // is due, the other block and the side (the boundary pass's lookup)
   for (int i = threadIdx.x; i < P; i += blockDim.x) {
     if (i % A.W) continue;
     bool live = false;
-    for (int32_t s = 0; s < A.W; s++) live = live || !A.ps[i + s].done;
+    for (int32_t s = 0; s < A.W; s++) live = live || due(i + s);
     const int32_t a = A.pairs[2 * i], b = A.pairs[2 * i + 1];
     A.binfo[2 * a] = live ? i : -1;
     A.binfo[2 * a + 1] = b << 1;
@@ -1239,7 +1250,7 @@ __device__ __forceinline__ void pair_items(int32_t p, int64_t N, F &&f) {
 // The boundary pass over the union lists (vertices of a and b) of the entries
 // that `items` hands out: f(p, slot) for union slot `slot` of entry p.
 template <typename Items>
-__device__ __forceinline__ void bnd_union(const KArgs &A, int32_t S, Items &&items) {
+__device__ __forceinline__ void bnd_union(const KArgs &A, Items &&items) {
   unsigned long long *acc = (unsigned long long *)A.pacc;
   unsigned long long *psw = (unsigned long long *)A.ps;
   // pair cut, boundary weight a / b, boundary count a / b, vertices, arcs
@@ -1267,7 +1278,7 @@ __device__ __forceinline__ void bnd_union(const KArgs &A, int32_t S, Items &&ite
     }
     const bool bl = on && bnd;
     const int64_t w = bl ? A.vwgt[u] : 0;
-    if (bl) mark_of(A, p)[u] = S;
+    if (bl) mark_of(A, p)[u] = stamp_of(A, p);
     const int64_t x[7] = {cw, bl && !side ? w : 0, bl && side ? w : 0, bl && !side ? 1 : 0,
                           bl && side ? 1 : 0, 1, e1 - e0};
     sums.add(on ? p : -1, x, out);
@@ -1289,7 +1300,7 @@ __device__ __forceinline__ void bnd_union(const KArgs &A, int32_t S, Items &&ite
 //      the pair from the block); late in a round, with few pairs left, it
 //      walks only their union lists.
 __global__ void __launch_bounds__(256) k_bnd(KArgs A, int32_t it) {
-  const int32_t S = A.stamp0 + 2 * it;
+  (void)it;
   unsigned long long *acc = (unsigned long long *)A.pacc;
   unsigned long long *psw = (unsigned long long *)A.ps;
   const int64_t total = A.vpre[*A.nact];  // union items of the live slots
@@ -1334,21 +1345,23 @@ __global__ void __launch_bounds__(256) k_bnd(KArgs A, int32_t it) {
                             bl && side ? 1 : 0, 1, in ? x1 - x0 : 0};
       sums.add(p0, x, out);
       const int32_t p = bl ? p0 : -1;
-      if (p >= 0) mark_of(A, p)[u] = S;
+      if (p >= 0) mark_of(A, p)[u] = stamp_of(A, p);
       const int pos = wave_append_by_key(A.pcnt, p);
       if (p >= 0) put_bounded(A.SNK + A.voff[p], pos, A.voff[p + 1] - A.voff[p], (int32_t)u, A.ctl);
     });
     sums.flush(out);
     return;
   }
-  bnd_union(A, S, [&](auto &&f) { grid_items(A, A.vpre, f); });
+  bnd_union(A, [&](auto &&f) { grid_items(A, A.vpre, f); });
 }
 
 // Takes the next pair of the queue for launch `it`; -1 when the queue is
 // empty.  Pairs that stopped are skipped.  All threads call it.
+// Entries in the phase `upto` or below qualify: 0 for a corridor that is
+// due, 1 for a flow that starts or continues.
 template <int TPB>
 __device__ __forceinline__ int32_t next_pair(const KArgs &A, int32_t *queue,
-                                             SolveShared<TPB> &sh) {
+                                             SolveShared<TPB> &sh, int32_t upto) {
   for (;;) {
     if (threadIdx.x == 0) sh.pair = atomicAdd(queue, 1);
     __syncthreads();
@@ -1356,7 +1369,7 @@ __device__ __forceinline__ int32_t next_pair(const KArgs &A, int32_t *queue,
     __syncthreads();
     if (q >= A.P) return -1;
     const int32_t p = uni(A.order[q]);
-    if (!A.ps[p].done) return p;
+    if (!A.ps[p].done && A.ps[p].phase <= upto) return p;
   }
 }
 
@@ -1516,11 +1529,10 @@ template <int TPB>
 __global__ void __launch_bounds__(TPB) k_corr(KArgs A, int32_t it) {
   __shared__ SolveShared<TPB> sh;
   __shared__ PairState st;
-  const int32_t S = A.stamp0 + 2 * it;
   for (;;) {
-    const int32_t p = next_pair<TPB>(A, A.queue + 2 * it, sh);
+    const int32_t p = next_pair<TPB>(A, A.queue + 4 * (it % A.max_iters), sh, 0);
     if (p < 0) break;
-    corr_pair<TPB>(A, S, p, sh, st);
+    corr_pair<TPB>(A, stamp_of(A, p), p, sh, st);
   }
 }
 
@@ -1532,7 +1544,7 @@ __global__ void __launch_bounds__(TPB) k_corr(KArgs A, int32_t it) {
 //      excess), the weight into b outside that of u -> t (written to SNK),
 //      and the old a-b edges with one end outside count as decided too.
 template <typename Items>
-__device__ __forceinline__ void net_count(const KArgs &A, int32_t S, Items &&items) {
+__device__ __forceinline__ void net_count(const KArgs &A, Items &&items) {
   const bool term = A.terminals != 0;
   unsigned long long *acc = (unsigned long long *)A.pacc;
   unsigned long long *psw = (unsigned long long *)A.ps;
@@ -1551,6 +1563,7 @@ __device__ __forceinline__ void net_count(const KArgs &A, int32_t S, Items &&ite
     const int32_t u = on ? A.lg[i] : 0;
     const int side = on && A.part[u] == b;
     const int32_t *mk = on ? mark_of(A, p) : A.mark;
+    const int32_t S = on ? stamp_of(A, p) : 0;
     const int32_t e0 = on ? A.xadj[u] : 0, e1 = on ? A.xadj[u + 1] : 0;
     int64_t cnt = 0, cap = 0, cin = 0, cs = 0, ct = 0;
     bool border = false;
@@ -1588,7 +1601,8 @@ __device__ __forceinline__ void net_count(const KArgs &A, int32_t S, Items &&ite
 }
 
 __global__ void __launch_bounds__(256) k_net_count(KArgs A, int32_t it) {
-  net_count(A, A.stamp0 + 2 * it, [&](auto &&f) { grid_items(A, A.cpre, f); });
+  (void)it;
+  net_count(A, [&](auto &&f) { grid_items(A, A.cpre, f); });
 }
 
 // pass 2 (one block per pair): inclusive scan of the arc counts into CSR
@@ -1627,15 +1641,16 @@ __global__ void __launch_bounds__(1024) k_net_scan(KArgs A, int32_t it) {
   __shared__ int64_t s_scan[17];
   (void)it;
   const int32_t p = blockIdx.x;
-  if (p >= A.P || A.ps[p].done) return;
+  if (p >= A.P || A.ps[p].done || A.ps[p].phase != 0) return;
   net_scan_pair(A, p, s_scan);
 }
 
 // pass 3: arcs (local head and capacity) in the order of the global adjacency
 template <typename Items>
-__device__ __forceinline__ void net_fill(const KArgs &A, int32_t S, Items &&items) {
+__device__ __forceinline__ void net_fill(const KArgs &A, Items &&items) {
   items([&](int32_t p, int64_t item) {
     if (p < 0) return;
+    const int32_t S = stamp_of(A, p);
     const int64_t i = A.voff[p] + item;  // arena slot
     const int32_t a = A.pairs[2 * p], b = A.pairs[2 * p + 1];
     const int32_t u = A.lg[i];
@@ -1676,7 +1691,8 @@ __device__ __forceinline__ void net_fill(const KArgs &A, int32_t S, Items &&item
 }
 
 __global__ void __launch_bounds__(256) k_net_fill(KArgs A, int32_t it) {
-  net_fill(A, A.stamp0 + 2 * it, [&](auto &&f) { grid_items(A, A.cpre, f); });
+  (void)it;
+  net_fill(A, [&](auto &&f) { grid_items(A, A.cpre, f); });
 }
 
 // pass 4: reverse arcs, the initial preflow (every arc out of the source
@@ -1746,10 +1762,11 @@ __global__ void __launch_bounds__(256) k_net_rev(KArgs A, int32_t it) {
 }
 
 // ---- maximum preflow, smallest source set, balance check, write-back and
-//      the adaptive factor (Sec. 4.1), one workgroup per pair
+//      the adaptive factor (Sec. 4.1), one workgroup per pair.
+//      lc (sliced rounds): this launch's running and started flow entries.
 template <int TPB>
 __device__ __forceinline__ void flow_pair(const KArgs &A, int32_t p, SolveShared<TPB> &sh,
-                                          PairState &st) {
+                                          PairState &st, const int32_t *lc = nullptr) {
   const PairView V = make_view(A, p);
   const int32_t a = V.a, b = V.b;
   int64_t *pa = A.pacc + (int64_t)p * PA_N;
@@ -1757,11 +1774,17 @@ __device__ __forceinline__ void flow_pair(const KArgs &A, int32_t p, SolveShared
     st = A.ps[p];
     sh.cnt[0] = sh.cnt[1] = sh.cnt[2] = 0;
     sh.nsnk = min(A.pcnt[A.P + p], (int32_t)V.nv);
+    if (st.phase == 0) {  // a new solve (else it continues from a sliced launch)
+      st.solve_sweeps = 0;
+      st.rp_eff = A.relabel_period;
+    }
   }
   if (threadIdx.x < W_COUNT) sh.work[threadIdx.x] = 0ull;
   __syncthreads();
   const int32_t nr = uni(st.nr);
   int64_t t0 = wall_clock64(), t1;
+  const int64_t t_start = t0;
+  bool sliced = false;
   int64_t t_rel = 0, t_push = 0;
   const int32_t NL = nr + 2;
   const bool lds = nr <= 32 * FR_BM_WORDS;
@@ -1779,10 +1802,31 @@ __device__ __forceinline__ void flow_pair(const KArgs &A, int32_t p, SolveShared
     // sweeps until the next global relabel: half the last relabel's BFS
     // depth (a deep corridor's relabel costs more), within [period / 4,
     // 2 period] of the tuning's period
-    int32_t rp_eff = A.relabel_period;
+    int32_t rp_eff = uni(st.rp_eff);
     const int32_t rp_lo = max(1, A.relabel_period / 4), rp_hi = 2 * A.relabel_period;
+    const int64_t sweeps0 = uni(st.solve_sweeps);  // of this solve, in earlier launches
     bool relabel = true;
     for (;;) {
+      if (relabel && A.slice_ticks > 0 && relabels > 0) {
+        // sliced rounds: once this launch's time is used up, stop where a
+        // global relabel is due anyway; the next launch starts with it
+        // (only while at most a quarter of the launch's entries still run:
+        // the others are waiting for it)
+        if (threadIdx.x == 0) {
+          int32_t stop = 0;
+          if (lc && wall_clock64() - t_start >= A.slice_ticks) {
+            const int32_t run = __hip_atomic_load(lc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int32_t sta =
+                __hip_atomic_load(lc + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            stop = 4 * run <= sta ? 1 : 0;
+          }
+          sh.slice_end = stop;
+        }
+        __syncthreads();
+        sliced = uni(sh.slice_end) != 0;
+        __syncthreads();
+        if (sliced) break;
+      }
       if (relabel) {
         t1 = wall_clock64();
         t_push += t1 - t0;
@@ -1806,7 +1850,7 @@ __device__ __forceinline__ void flow_pair(const KArgs &A, int32_t p, SolveShared
         relabel = true;
         continue;
       }
-      if (sweeps >= A.max_sweeps) {
+      if (sweeps0 + sweeps >= A.max_sweeps) {
         if (threadIdx.x == 0) {
           A.ctl->err = FR_E_SOLVER_LIMIT;
           A.ctl->diag = DIAG_SWEEPS;
@@ -1836,6 +1880,25 @@ __device__ __forceinline__ void flow_pair(const KArgs &A, int32_t p, SolveShared
     t1 = wall_clock64();
     t_push += t1 - t0;
     t0 = t1;
+    if (sliced) {
+      // the solve continues in the next launch: its counters so far, its
+      // relabel interval; the network, labels and excesses stay in place
+      if (threadIdx.x == 0) {
+        st.sweeps += sweeps;
+        st.relabels += relabels;
+        st.gr_levels += gr_levels;
+        for (int j = 0; j < W_COUNT; j++) st.work[j] += (int64_t)sh.work[j];
+        st.t_relabel += t_rel;
+        st.t_push += t_push;
+        st.solve_sweeps = sweeps0 + sweeps;
+        st.rp_eff = rp_eff;
+        st.phase = 1;
+        st.slices++;
+        A.ps[p] = st;
+      }
+      __syncthreads();
+      return;
+    }
     // ---- smallest source set (Sec. 4.1.1): closure of the source border
     //      and of every vertex left with excess, over arcs with residual
     //      capacity
@@ -2018,6 +2081,7 @@ __device__ __forceinline__ void flow_pair(const KArgs &A, int32_t p, SolveShared
     for (int j = 0; j < PA_N; j++) pa[j] = 0;
     A.pcnt[p] = mb ? sh.nfree : 0;  // the most balanced cut kernel reads and clears it
     A.pcnt[A.P + p] = 0;
+    st.phase = 2;
     A.ps[p] = st;
   }
   __syncthreads();
@@ -2034,9 +2098,15 @@ __global__ void __launch_bounds__(TPB) k_flow(KArgs A, int32_t it) {
   __shared__ SolveShared<TPB> sh;
   __shared__ PairState st;
   for (;;) {
-    const int32_t p = next_pair<TPB>(A, A.queue + 2 * it + 1, sh);
+    int32_t *lc = A.queue + 4 * (it % A.max_iters) + 2;  // running, started
+    const int32_t p = next_pair<TPB>(A, lc - 1, sh, 1);
     if (p < 0) break;
-    flow_pair<TPB>(A, p, sh, st);
+    if (threadIdx.x == 0 && A.slice_ticks > 0) {
+      atomicAdd(lc, 1);
+      atomicAdd(lc + 1, 1);
+    }
+    flow_pair<TPB>(A, p, sh, st, lc);
+    if (threadIdx.x == 0 && A.slice_ticks > 0) atomicSub(lc, 1);
   }
 }
 
@@ -2052,6 +2122,13 @@ __device__ __forceinline__ void select_pair(const KArgs &A, int32_t p, int32_t *
   const int32_t W = A.W;
   const int32_t v0 = p * W;
   if (A.ps[v0].done) return;
+  // sliced rounds: the pair moves on once every slot it runs has solved
+  bool ready = true;
+  for (int s = 0; s < W; s++) ready = ready && (A.ps[v0 + s].done || A.ps[v0 + s].phase == 2);
+  if (!ready) {
+    if (threadIdx.x == 0) s_sel[2] = 0;
+    return;
+  }
   if (threadIdx.x == 0) {
     PairState &R = A.ps[v0];  // updated in place (a copy would live in scratch)
     bool stop = false;
@@ -2099,6 +2176,8 @@ __device__ __forceinline__ void select_pair(const KArgs &A, int32_t p, int32_t *
     }
     R.alpha = next_alpha;
     R.done = stop ? 1 : 0;
+    R.phase = 0;
+    R.iter++;
     for (int s = 1; s < W; s++) {
       PairState &q = A.ps[v0 + s];
       q.alpha = next_alpha >> s;
@@ -2106,6 +2185,8 @@ __device__ __forceinline__ void select_pair(const KArgs &A, int32_t p, int32_t *
       q.cA = R.cA;
       q.cB = R.cB;
       q.cut = R.cut;
+      q.phase = 0;
+      q.iter = R.iter;
     }
     s_sel[0] = A.ctl->err == 0 ? chosen : -1;
     s_sel[1] = v0;
@@ -2120,6 +2201,19 @@ __device__ __forceinline__ void select_pair(const KArgs &A, int32_t p, int32_t *
   const int32_t nr = A.ps[vc].nr;
   for (int32_t i = threadIdx.x; i < nr; i += blockDim.x)
     A.part[A.lg[vb + i]] = A.ins[vb + i] ? a : b;
+}
+
+// Entries still iterating, for the host's count of further launches of a
+// sliced round (0 once a device error stopped the round).  One block.
+__global__ void __launch_bounds__(1024) k_live(KArgs A) {
+  __shared__ int32_t s_live;
+  if (threadIdx.x == 0) s_live = 0;
+  __syncthreads();
+  int32_t cnt = 0;
+  for (int32_t i = threadIdx.x; i < A.P; i += blockDim.x) cnt += A.ps[i].done ? 0 : 1;
+  if (cnt) atomicAdd(&s_live, cnt);
+  __syncthreads();
+  if (threadIdx.x == 0) A.ctl->live = A.ctl->err != 0 ? 0 : s_live;
 }
 
 __global__ void __launch_bounds__(1024) k_select(KArgs A, int32_t it) {
@@ -2140,20 +2234,19 @@ __global__ void __launch_bounds__(TPB) k_round(KArgs A) {
   __shared__ PairState st;
   __shared__ int32_t s_sel[3];
   for (;;) {
-    const int32_t p = next_pair<TPB>(A, A.queue, sh);
+    const int32_t p = next_pair<TPB>(A, A.queue, sh, 1);
     if (p < 0) break;
     const int64_t nu = A.voff[p + 1] - A.voff[p];
     for (int32_t it = 0; it < A.max_iters; it++) {
-      const int32_t S = A.stamp0 + 2 * it;
-      bnd_union(A, S, [&](auto &&f) { pair_items(p, nu, f); });
+      bnd_union(A, [&](auto &&f) { pair_items(p, nu, f); });
       __syncthreads();
-      corr_pair<TPB>(A, S, p, sh, st);
+      corr_pair<TPB>(A, stamp_of(A, p), p, sh, st);
       const int32_t nr = uni(st.nr);
-      net_count(A, S, [&](auto &&f) { pair_items(p, nr, f); });
+      net_count(A, [&](auto &&f) { pair_items(p, nr, f); });
       __syncthreads();
       net_scan_pair(A, p, sh.scan);
       __syncthreads();
-      net_fill(A, S, [&](auto &&f) { pair_items(p, nr, f); });
+      net_fill(A, [&](auto &&f) { pair_items(p, nr, f); });
       __syncthreads();
       net_rev(A, [&](auto &&f) { pair_items(p, nr, f); });
       __syncthreads();

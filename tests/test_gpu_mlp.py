@@ -207,7 +207,7 @@ def test_autotune_keeps_results(gpu_lib, ctx):
     prm = gpu_lib.params()
     best, ms = gpu_lib.fr_autotune(ctx, dg, dpart, k, pairs, prm, cands, reps=1)
     assert 0 <= best < 3 and all(m > 0 for m in ms)
-    assert ctx.get_tuning() == dict(cands[best], mb_lds=1)
+    assert ctx.get_tuning() == dict(cands[best], mb_lds=1, slice_us=8000)
     assert np.array_equal(dpart.cpu().numpy(), part)  # the partition is not modified
     ctx.set_tuning()
 
