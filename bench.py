@@ -118,7 +118,7 @@ def run_plain(args, fr, torch, gen):
         dpart.copy_(part0)
         fr.flow_refine_pair(ctx, dg, dpart, w.k, 0, 1, prm)
     torch.cuda.synchronize()
-    edges, kern_ms, byts, path_ms, path_bytes = 0, 0.0, 0, 0.0, 0
+    edges, kern_ms, byts, path_ms, path_bytes, launches = 0, 0.0, 0, 0.0, 0, 0
     results = []
     step_s = []
     t0 = time.perf_counter()
@@ -133,6 +133,7 @@ def run_plain(args, fr, torch, gen):
         byts += flow_bytes(st)
         path_ms += st["round_ms"]
         path_bytes += algorithmic_bytes(st, res["region_edges"])
+        launches += st["flow_launches"]
         results.append((res, trace))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -140,7 +141,7 @@ def run_plain(args, fr, torch, gen):
     ctx.close()
     return dict(w=w, edges=edges, wall=wall, kern_ms=kern_ms, bytes=byts, result=results[-1][0],
                 trace=results[-1][1], part=final_part, stats=st, path_ms=path_ms,
-                path_bytes=path_bytes, launches=args.steps * w.params["max_iters"],
+                path_bytes=path_bytes, launches=launches,
                 step_ms=[t * 1e3 for t in step_s])
 
 

@@ -702,7 +702,8 @@ static int blocks_of(const fr_context *c, int32_t P) {
 // One round: setup kernels, then max_iters launches of the per-iteration
 // chain (pairs that stopped are skipped inside).  With timed set, events
 // around the phases of each iteration give the per-phase times.
-static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t st, bool timed) {
+static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t st, bool timed,
+                             bool captured) {
   DevBufs &d = c->d;
   const int sblocks = std::min(4 * c->num_cus, 8192);
   A.fstat = use_mlp ? d.fstat : nullptr;
@@ -746,15 +747,19 @@ static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t s
     if (timed)
       for (int j = 3; j < 5; j++) HIPCHK(hipEventRecord(ev[j], st));
   }
-  // launches of the per-iteration chain: max_iters when every launch runs
-  // its solves out (each is one adaptive iteration of every pair still
-  // iterating); sliced, a pair's iteration may span launches, so more
-  // follow, four at a time, while an entry still iterates
-  int32_t launches = fused ? 0 : A.max_iters;
+  // launches of the per-iteration chain.  Unsliced, each is one adaptive
+  // iteration of every pair still iterating, at most max_iters of them; a
+  // captured round runs all max_iters (a stopped pair skips the rest).  Not
+  // captured, the host reads the number of entries still iterating back
+  // after 2, 4 and 8 launches and then every 4, and the chain ends at 0;
+  // sliced, a pair's iteration may span launches, so it may run past
+  // max_iters.
+  const bool host = !captured && !fused;
+  int32_t launches = fused ? 0 : (host ? std::min(2, A.max_iters) : A.max_iters);
   const int32_t max_launches = 256 * A.max_iters;
   for (int32_t it = 0;; it++) {
     if (it >= launches) {
-      if (!sliced) break;
+      if (!host || (!sliced && it >= A.max_iters)) break;
       hipLaunchKernelGGL(k_live, dim3(1), dim3(1024), 0, st, A);
       HIPCHK(hipMemcpyAsync(&c->h_ctl->live, &c->d.ctl->live, sizeof(int32_t),
                             hipMemcpyDeviceToHost, st));
@@ -764,7 +769,8 @@ static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t s
         c->timed_iters = timed ? it : 0;
         return FR_E_SOLVER_LIMIT;
       }
-      launches = it + 4;
+      launches = it < 8 ? 2 * it : it + 4;
+      if (!sliced) launches = std::min(launches, A.max_iters);
     }
     if (timed && (size_t)(5 * it + 5) > c->itev.size()) {
       const size_t n0 = c->itev.size();
@@ -1138,7 +1144,7 @@ static int32_t refine(fr_context *c, const fr_graph *g, int32_t *part, int32_t k
   R.mt_stamp0 = mts;
   if (carve) R.slice_ticks = 0;
   (void)hipEventRecord(c->ev[1], st);
-  if ((rc = enqueue_round(c, R, p->use_mlp != 0, st, true))) return rc;
+  if ((rc = enqueue_round(c, R, p->use_mlp != 0, st, true, false))) return rc;
   (void)hipEventRecord(c->ev[2], st);
   if ((rc = device_error(c))) return rc;
   if (side_out) {
@@ -1414,7 +1420,7 @@ extern "C" int32_t flow_refine_sweep(fr_context *c, const fr_graph *g, int32_t *
         KArgs R = round_args(c, A, offs[r], offs[r + 1] - offs[r],
                              stamp0 + r * (2 * p->max_iters + 2), false);
         R.mt_stamp0 = mts[(size_t)r];
-        if ((rc = enqueue_round(c, R, p->use_mlp != 0, st, true))) return rc;
+        if ((rc = enqueue_round(c, R, p->use_mlp != 0, st, true, false))) return rc;
         HIPCHK(hipStreamSynchronize(st));
         add_round_times(c);
       }
@@ -1428,7 +1434,7 @@ extern "C" int32_t flow_refine_sweep(fr_context *c, const fr_graph *g, int32_t *
                              stamp0 + r * (2 * p->max_iters + 2), false);
         R.mt_stamp0 = mts[(size_t)r];
         R.slice_ticks = 0;  // captured: no host between the launches
-        cap_rc = enqueue_round(c, R, p->use_mlp != 0, st, false);
+        cap_rc = enqueue_round(c, R, p->use_mlp != 0, st, false, true);
       }
       hipError_t ce = hipStreamEndCapture(st, &graph);
       if (cap_rc != FR_OK || ce != hipSuccess) {

@@ -84,7 +84,6 @@ def test_matching_rounds(gpu_lib, ctx, seed, n, k, dim):
         pairs = [tuple(e) for e, cc in zip(edges.tolist(), colour) if cc == c]
         _, st = _batch_vs_oracle(gpu_lib, ctx, g, part, k, pairs, p)
         slices.append(st["slices"])
-        assert st["flow_launches"] >= 16
     if ctx.get_tuning()["slice_us"] == 1:
         assert max(slices) > 0, slices
 
