@@ -249,12 +249,13 @@ typedef struct {
                               most a quarter of the launch's solves still run; it
                               continues in the next launch of the chain, while the pairs
                               whose solves ended start their next adaptive iteration,
-                              so they no longer wait for the round's slowest pair.  The
-                              chain then runs until every pair has stopped (the host
-                              reads the count back every four launches after the first
-                              max_iters).  Rounds of one pair, captured sweeps, most
-                              balanced cuts, fused rounds and the entry point without
-                              device allocation run unsliced. */
+                              so they no longer wait for the round's slowest pair; the
+                              chain may then run past max_iters launches.  Rounds of
+                              one pair, captured sweeps, most balanced cuts, fused
+                              rounds and the entry point without device allocation run
+                              unsliced.  (Every call that is not captured ends its chain
+                              once no pair iterates: the host reads the count back after
+                              2, 4 and 8 launches and then every 4.) */
 } fr_tuning;
 
 typedef struct fr_context fr_context;
@@ -369,7 +370,8 @@ int32_t fr_set_speculation(fr_context *ctx, int32_t on);
  * round's other pairs between its iterations; every solve is then one factor
  * (no speculative factors, fr_set_speculation has no effect).  With 0, every
  * iteration of the round is a chain of launches over all pairs, and a pair's
- * next iteration waits for the slowest pair's current one.  Calls with the
+ * next iteration waits for the slowest pair's current one unless its solves
+ * are sliced (fr_tuning.slice_us).  Calls with the
  * most balanced cut (mb_reps > 0) always run the launch chains.  Results are
  * identical either way.  The launch chains are the faster choice wherever
  * measured: they keep the speculative factors, and their boundary and
@@ -410,9 +412,9 @@ int32_t fr_set_timing(fr_context *ctx, int32_t on);
  *   kernels time in ns, [9] free vertices, [10] their residual components,
  *   [11] solves whose component graph (more than 2,048 components) was kept
  *   in device memory instead of LDS; [12] FM moves made, [13] FM moves kept;
- *   [14] flow-kernel launches (one per adaptive iteration of each round,
- *   more with sliced rounds), or round-kernel launches (one per round) with
- *   fused rounds; [15] pairs
+ *   [14] flow-kernel launches (one per launch of a round's chain: the chain
+ *   ends once no pair iterates, a captured sweep runs max_iters per round),
+ *   or round-kernel launches (one per round) with fused rounds; [15] pairs
  *   whose learned start was restarted from alpha (use_mlp);
  *   [28] multi-try searches, [29] multi-try moves made, [30] kept; [31]
  *   solves continued in a later launch (sliced rounds);

@@ -697,11 +697,13 @@ static int blocks_of(const fr_context *c, int32_t P) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(P, slots));
 }
 
-// All kernels of one matching round; device-only work, so a sequence of
-// rounds can be captured into a graph.
-// One round: setup kernels, then max_iters launches of the per-iteration
-// chain (pairs that stopped are skipped inside).  With timed set, events
-// around the phases of each iteration give the per-phase times.
+// All kernels of one matching round: setup kernels, then the launches of
+// the per-iteration chain (pairs that stopped are skipped inside).  With
+// captured set, device-only work (max_iters launches, no host read-back),
+// so a sequence of rounds can be captured into a graph; otherwise the host
+// ends the chain once no pair iterates and may slice long solves.  With
+// timed set, events around the phases of each launch give the per-phase
+// times.
 static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t st, bool timed,
                              bool captured) {
   DevBufs &d = c->d;
