@@ -286,7 +286,7 @@ extern "C" const char *fr_strerror(int32_t code) {
     case FR_E_DEVICE: return "HIP device error";
     case FR_E_OOM: return "out of memory";
     case FR_E_INVALID_ARG: return "invalid argument";
-    case FR_E_SOLVER_LIMIT: return "push/relabel sweep limit reached";
+    case FR_E_SOLVER_LIMIT: return "push/relabel sweep limit or round launch limit reached";
     case FR_E_SCRATCH_LIMIT: return "graph too large for the static scratch of flow_refine_pair_static";
     default: return "unknown error";
   }
