@@ -66,7 +66,8 @@ extern "C" {
 #define FR_E_OOM (-7)                /* device or host allocation failed */
 #define FR_E_INVALID_ARG (-8)        /* NULL pointer, bad parameter value */
 #define FR_E_SOLVER_LIMIT (-9)       /* push-relabel exceeded its sweep safety cap, or a
-                                        sliced round its cap of 256 * max_iters launches */
+                                        sliced round ran more than max(256 max_iters,
+                                        65,536) launches */
 #define FR_E_SCRATCH_LIMIT (-10)     /* flow_refine_pair_static: graph beyond its static scratch */
 
 /* ---- per-pair status (fr_result.status) --------------------------------- */

@@ -758,7 +758,9 @@ static int32_t enqueue_round(fr_context *c, KArgs A, bool use_mlp, hipStream_t s
   // max_iters.
   const bool host = !captured && !fused;
   int32_t launches = fused ? 0 : (host ? std::min(2, A.max_iters) : A.max_iters);
-  const int32_t max_launches = 256 * A.max_iters;
+  // a backstop only: every slice but a solve's last makes at least one sweep,
+  // so the solves' sweep cap already bounds the chain
+  const int32_t max_launches = std::max(256 * A.max_iters, 1 << 16);
   for (int32_t it = 0;; it++) {
     if (it >= launches) {
       if (!host || (!sliced && it >= A.max_iters)) break;
