@@ -175,7 +175,7 @@ def run_batched(args, fr, torch, gen, cid="C3"):
 
         with tempfile.TemporaryDirectory() as tmp:
             tuning = fr.autotune_cached(ctx, dg, part0, w.k, pairs, prm,
-                                        cache_path=os.path.join(tmp, "tuning.json"), reps=1)
+                                        cache_path=os.path.join(tmp, "tuning.json"), reps=2)
     dpart = part0.clone()
     reps = max(1, args.batch_reps)
     # batched: the median of at least three timed calls (one call is short)
