@@ -12,6 +12,7 @@ from scipy.sparse import csr_matrix
 from scipy.sparse.csgraph import maximum_flow
 
 import gen
+from gen import Graph
 import oracle
 from tests.helpers import (area_bound, brute_force_min_cut, corridor_by_sorting, csr_from_edges,
                            edges_of, edmonds_karp, l_max, pair_network, random_graph)
@@ -360,6 +361,35 @@ def test_restart_rule_leaves_other_searches_alone():
     assert o.result["iter_cap"] == 0 and q.result["iter_cap"] == 1
     assert np.array_equal(q.part, o.part)
     assert oracle.refine_pair(g, part, 2, 0, 1, dict(p, restart_alpha=-1)).rc == -8
+
+
+def test_restart_rule_in_batches():
+    """R6b inside a batch: two wavy cases side by side as one graph (k = 4,
+    the same balance bound as each alone with k = 2).  The batch with a
+    restart factor equals the pairs refined one after the other with it, and
+    each pair ends exactly as its case refined alone."""
+    (g1, p1), (g2, p2) = _wavy(902, 0.2, 1), _wavy(911, 0.2, 1)
+    n1 = g1.n
+    xadj = np.concatenate([g1.xadj, g2.xadj[1:] + g1.xadj[-1]]).astype(np.int32)
+    adj = np.concatenate([g1.adjncy, g2.adjncy + n1]).astype(np.int32)
+    g = Graph(xadj, adj, np.concatenate([g1.adjwgt, g2.adjwgt]).astype(np.int32),
+              np.concatenate([g1.vwgt, g2.vwgt]).astype(np.int32))
+    part = np.concatenate([p1, p2 + 2]).astype(np.int32)
+    p = dict(area_mode=0, depth=0, alpha=1, alpha_max=16, adaptive=1, max_iters=8,
+             eps_ppm=30000, restart_alpha=16)
+    pairs = [(0, 1), (2, 3)]
+    rc, res, tr, bpart = oracle.refine_batch(g, part, 4, pairs, p)
+    assert rc == 0
+    cur = part.copy()
+    for i, (a, b) in enumerate(pairs):
+        o = oracle.refine_pair(g, cur, 4, a, b, p)
+        assert o.result == res[i] and o.trace == tr[i]
+        cur = o.part
+    assert np.array_equal(cur, bpart)
+    for i, (gi, pi) in enumerate(((g1, p1), (g2, p2))):
+        alone = oracle.refine_pair(gi, pi, 2, 0, 1, p)
+        assert alone.trace == tr[i] and alone.result["cut_after"] == res[i]["cut_after"]
+        assert len(tr[i]) > 1 and tr[i][1]["alpha"] == 16  # the restart fired
 
 
 def test_c1_closed_form():
